@@ -1,0 +1,183 @@
+"""Plain CPU oracle for the restless sieve fingerprint (ctypes over oracle.c).
+
+TEST INFRASTRUCTURE ONLY. Only the test suite, ``__graft_entry__.smoke()`` and
+the CPU-baseline leg of ``bench.py`` import this package. It shares no code
+with the GPU library and the GPU library never imports it.
+
+The C source follows arXiv 2010.08423: Eq. (poly-enc:1) (restless-walk
+generating function), Eq. (multilinear:1)-(multilinear:3) (sieving with
+colour shades), Alg. 1 (sum over subsets L), the exhaustive temporal DFS of
+Sec. 5.3 and the determinant closed form of the sieve.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_SO = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+_u32p = ctypes.POINTER(ctypes.c_uint32)
+_u64p = ctypes.POINTER(ctypes.c_uint64)
+_u8p = ctypes.POINTER(ctypes.c_uint8)
+
+
+def build() -> str:
+    """Compile oracle.c into liboracle.so with gcc (plain C, OpenMP for the
+    optional iteration-parallel timing variant)."""
+    cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-o", _SO + ".tmp", _SRC]
+    subprocess.run(cmd, check=True)
+    os.replace(_SO + ".tmp", _SO)
+    return _SO
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_SO):
+        build()
+    lib = ctypes.CDLL(_SO)
+    u64 = ctypes.c_uint64
+    lib.orc_gf_mul.restype = u64
+    lib.orc_gf_mul.argtypes = [u64, u64]
+    lib.orc_gf_mul_nibble.restype = u64
+    lib.orc_gf_mul_nibble.argtypes = [u64, u64]
+    lib.orc_gf_pow.restype = u64
+    lib.orc_gf_pow.argtypes = [u64, u64]
+    lib.orc_gf_inv.restype = u64
+    lib.orc_gf_inv.argtypes = [u64]
+    lib.orc_mix64.restype = u64
+    lib.orc_mix64.argtypes = [u64]
+    lib.orc_hash.restype = u64
+    lib.orc_hash.argtypes = [u64, u64, _u64p, ctypes.c_int]
+    lib.orc_z_table.restype = ctypes.c_int
+    lib.orc_z_table.argtypes = [ctypes.c_uint32, _u8p, ctypes.c_uint32, ctypes.c_uint32, _u8p, u64, _u64p]
+    graph_args = [ctypes.c_uint32, u64, _u32p, _u32p, _u32p, _u8p, ctypes.c_uint32, ctypes.c_uint32, _u32p, _u8p]
+    lib.orc_sieve.restype = ctypes.c_int
+    lib.orc_sieve.argtypes = graph_args + [u64, u64, u64, ctypes.c_int, _u64p, _u64p]
+    lib.orc_closed_form.restype = ctypes.c_int
+    lib.orc_closed_form.argtypes = graph_args + [u64, _u64p, _u64p]
+    lib.orc_count_paths.restype = ctypes.c_int
+    lib.orc_count_paths.argtypes = graph_args + [_u64p]
+    lib.orc_gf_det.restype = u64
+    lib.orc_gf_det.argtypes = [_u64p, ctypes.c_int]
+    lib.orc_gf_det_leibniz.restype = u64
+    lib.orc_gf_det_leibniz.argtypes = [_u64p, ctypes.c_int]
+    _lib = lib
+    return lib
+
+
+def _ptr(a, typ):
+    return a.ctypes.data_as(typ) if a is not None else None
+
+
+# --- field and hash -------------------------------------------------------
+
+def gf_mul(a: int, b: int) -> int:
+    return _load().orc_gf_mul(a, b)
+
+
+def gf_mul_nibble(a: int, b: int) -> int:
+    return _load().orc_gf_mul_nibble(a, b)
+
+
+def gf_pow(a: int, e: int) -> int:
+    return _load().orc_gf_pow(a, e)
+
+
+def gf_inv(a: int) -> int:
+    return _load().orc_gf_inv(a)
+
+
+def mix64(x: int) -> int:
+    return _load().orc_mix64(x)
+
+
+def keyed_hash(seed: int, tag: int, words) -> int:
+    w = np.ascontiguousarray(np.asarray(words, dtype=np.uint64))
+    return _load().orc_hash(seed, tag, _ptr(w, _u64p), len(w))
+
+
+def gf_det(mat) -> int:
+    a = np.ascontiguousarray(np.asarray(mat, dtype=np.uint64))
+    return _load().orc_gf_det(_ptr(a, _u64p), a.shape[0])
+
+
+def gf_det_leibniz(mat) -> int:
+    a = np.ascontiguousarray(np.asarray(mat, dtype=np.uint64))
+    return _load().orc_gf_det_leibniz(_ptr(a, _u64p), a.shape[0])
+
+
+# --- graph queries ----------------------------------------------------------
+
+def _graph_args(n, src, dst, t, colour, n_colours, k, delta, motif):
+    src = np.ascontiguousarray(src, dtype=np.uint32)
+    dst = np.ascontiguousarray(dst, dtype=np.uint32)
+    t = np.ascontiguousarray(t, dtype=np.uint32)
+    if not (len(src) == len(dst) == len(t)):
+        raise ValueError("src, dst, t must have equal length")
+    if np.isscalar(delta):
+        delta = np.full(max(n, 1), int(delta), dtype=np.uint32)
+    delta = np.ascontiguousarray(delta, dtype=np.uint32)
+    col = None if colour is None else np.ascontiguousarray(colour, dtype=np.uint8)
+    mot = None if motif is None else np.ascontiguousarray(motif, dtype=np.uint8)
+    keep = (src, dst, t, delta, col, mot)
+    args = [n, len(src), _ptr(src, _u32p), _ptr(dst, _u32p), _ptr(t, _u32p), _ptr(col, _u8p),
+            int(n_colours), int(k), _ptr(delta, _u32p), _ptr(mot, _u8p)]
+    return args, keep
+
+
+def z_table(n, k, seed, colour=None, n_colours=0, motif=None) -> np.ndarray:
+    z = np.zeros((max(n, 1), k), dtype=np.uint64)
+    col = None if colour is None else np.ascontiguousarray(colour, dtype=np.uint8)
+    mot = None if motif is None else np.ascontiguousarray(motif, dtype=np.uint8)
+    rc = _load().orc_z_table(n, _ptr(col, _u8p), n_colours, k, _ptr(mot, _u8p), seed, _ptr(z, _u64p))
+    if rc:
+        raise ValueError(f"orc_z_table rejected the query (rc={rc})")
+    return z[:n]
+
+
+def sieve(n, src, dst, t, k, delta, seed, colour=None, n_colours=0, motif=None,
+          it_begin=0, it_end=0, threads=1, per_iteration=False):
+    """Fingerprint F over iterations [it_begin, it_end) (0, 0 = all 2^k).
+    With per_iteration=True returns (F, array of f_L for the range)."""
+    args, keep = _graph_args(n, src, dst, t, colour, n_colours, k, delta, motif)
+    F = ctypes.c_uint64(0)
+    span = (it_end - it_begin) if (it_begin or it_end) else (1 << k)
+    per = np.zeros(max(span, 1), dtype=np.uint64) if per_iteration else None
+    rc = _load().orc_sieve(*args, seed, it_begin, it_end, threads, ctypes.byref(F), _ptr(per, _u64p))
+    del keep
+    if rc:
+        raise ValueError(f"orc_sieve rejected the query (rc={rc})")
+    if per_iteration:
+        return F.value, per[:span]
+    return F.value
+
+
+def closed_form(n, src, dst, t, k, delta, seed, colour=None, n_colours=0, motif=None):
+    """(F, number of restless paths enumerated) from the determinant closed form."""
+    args, keep = _graph_args(n, src, dst, t, colour, n_colours, k, delta, motif)
+    F = ctypes.c_uint64(0)
+    cnt = ctypes.c_uint64(0)
+    rc = _load().orc_closed_form(*args, seed, ctypes.byref(F), ctypes.byref(cnt))
+    del keep
+    if rc:
+        raise ValueError(f"orc_closed_form rejected the query (rc={rc})")
+    return F.value, cnt.value
+
+
+def count_paths(n, src, dst, t, k, delta, colour=None, n_colours=0, motif=None) -> int:
+    """Number of restless paths with k vertices (agreeing with the motif)."""
+    args, keep = _graph_args(n, src, dst, t, colour, n_colours, k, delta, motif)
+    cnt = ctypes.c_uint64(0)
+    rc = _load().orc_count_paths(*args, ctypes.byref(cnt))
+    del keep
+    if rc:
+        raise ValueError(f"orc_count_paths rejected the query (rc={rc})")
+    return cnt.value
