@@ -1,0 +1,247 @@
+/*
+ * librestless_sieve: GF(2^64) multilinear sieve for k-RestlessPath and
+ * k-RestlessMotif queries on one MI355X (gfx950) GPU.
+ *
+ * Method: Thejaswi, Lauri, Gionis, "Restless reachability problems in
+ * temporal graphs" (arXiv 2010.08423).
+ *   - Restless walk / path: Sec. 2 (consecutive edges (u,v,j), (v,w,j') with
+ *     0 <= j' - j <= delta(v); a path repeats no vertex).
+ *   - k-RestlessPath (a restless path with k vertices) and k-RestlessMotif
+ *     (k vertices whose colours equal the multiset M): Sec. 3. The queries
+ *     here ask whether such a path exists anywhere in the graph.
+ *   - Evaluation: the restless-walk generating function, Eq. (poly-enc:1),
+ *     sieved over all subsets L of [k], Eq. (multilinear:1); motif queries use
+ *     colour shades, Eq. (multilinear:3) and Eq. (multilinear:2); the sum over
+ *     L is the loop of Alg. 1. All arithmetic is in GF(2^64) (Sec. 5.1, b = 64)
+ *     with modulus x^64 + x^4 + x^3 + x + 1.
+ *
+ * Result: fingerprint F = XOR over L of f_L, where f_L sums the level-k
+ * evaluation over every end vertex and end time. F equals, over the same field,
+ *     XOR over restless paths P (motif: colour-agreeing) of
+ *     (prod_{p=1}^{k-1} y_{e_p,p}) * det [z_{v_p,j}]_{p,j},
+ * so F != 0 implies such a path exists (no false positives). If one exists,
+ * F == 0 with probability at most (3k-1)/2^64 (Schwartz-Zippel).
+ *
+ * The random values are a deterministic function of the query seed:
+ *   mix64 = SplitMix64 output finalizer; G = 0x9E3779B97F4A7C15;
+ *   H(seed, tag, w_1..w_r): h = mix64(seed + tag*G); h = mix64(h ^ (w_i + G)).
+ *   z_{u,j}   = H(seed, 'Z', u | j<<32)           j = 1..k   (path queries)
+ *   gamma_{u,d} = H(seed, 'G', u | d<<32)         d = shade 0..k-1
+ *   omega_{d,j} = H(seed, 'W', d | j<<32)
+ *   motif: z_{u,j} = sum over shades d of colour c(u) of gamma_{u,d} * omega_{d,j};
+ *          shades are numbered contiguously per colour, colours ascending.
+ *   y_{e,p}   = H(seed, 'Y', src | dst<<32, t | p<<32)   p = 1..k-1
+ *   iteration i in [0, 2^k) <-> L(i) = { j : bit j-1 of i is set }.
+ *
+ * Conventions for every call:
+ *   - Returns RS_OK (0) or a negative rs_status. No C++ exception crosses
+ *     this boundary. Errors leave outputs untouched unless stated.
+ *   - "host" pointers are read during the call only and never retained;
+ *     "device" pointers are device (HBM) addresses, e.g. a torch tensor's
+ *     data_ptr(), read during the call only.
+ *   - hip_stream is a hipStream_t (NULL = the null stream). Calls that return
+ *     a result synchronise that stream before returning.
+ *   - Graph objects are immutable after creation. Query calls on one graph
+ *     are serialised internally (they share a cached device workspace).
+ */
+#ifndef RESTLESS_SIEVE_RS_H
+#define RESTLESS_SIEVE_RS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t rs_status;
+#define RS_OK 0
+#define RS_EINVAL (-1)     /* invalid argument (sizes, ids, k, motif) */
+#define RS_ENOMEM (-2)     /* device or host allocation failed / over budget */
+#define RS_EDEVICE (-3)    /* HIP runtime error or a kernel-side failure flag */
+#define RS_EBUSY (-4)      /* server: not admitted yet / queue full */
+#define RS_ECANCELED (-5)  /* server: query cancelled */
+#define RS_ENOTFOUND (-6)  /* server: unknown ticket or graph id */
+#define RS_ETIMEOUT (-7)   /* server: poll wait expired before completion */
+
+#define RS_MAX_K 16
+#define RS_MAX_COLOURS 256
+
+/* Human-readable name of a status code (static storage). */
+const char* rs_status_str(rs_status s);
+
+/* Library version string, including the GPU target it was built for. */
+const char* rs_version(void);
+
+/* Text of the last error seen by the calling thread (HIP call and message),
+ * or "" (static thread-local storage, valid until the next call). */
+const char* rs_last_error(void);
+
+/* ------------------------------------------------------------------------
+ * Graphs (Sec. 2: a directed temporal graph is a SET of triples (u, v, j)
+ * with j >= 1; N_j(v) is the set of in-neighbours of v at time j).
+ * ---------------------------------------------------------------------- */
+typedef struct rs_graph rs_graph;
+
+typedef struct {
+  uint32_t n;               /* vertices */
+  uint64_t m_input;         /* edges passed in */
+  uint64_t m;               /* distinct non-loop edges kept */
+  uint64_t self_loops;      /* removed (a self-loop lies on no path) */
+  uint64_t duplicates;      /* removed (E is a set) */
+  uint32_t t_min, t_max;    /* timestamp range of the input edges (0,0 if none kept) */
+  uint32_t n_colours;       /* 0 = uncoloured graph */
+  uint32_t max_in_degree;
+  uint64_t device_bytes;    /* HBM held by the graph (excluding workspaces) */
+} rs_graph_info;
+
+/* Upload a temporal graph. src, dst, t: host arrays of m entries; vertex ids
+ * < n, timestamps >= 1 (else RS_EINVAL). colour: host array of n entries with
+ * values < n_colours, or NULL (then n_colours must be 0). Duplicated triples
+ * and self-loops are dropped. The edges are deduplicated, sorted by
+ * (dst, t, src) and indexed on the device. On success *out owns device memory
+ * until rs_graph_destroy. Requires n < 2^31 and m + n < 2^32. */
+rs_status rs_graph_create(uint32_t n, uint64_t m, const uint32_t* src, const uint32_t* dst,
+                          const uint32_t* t, const uint8_t* colour, uint32_t n_colours,
+                          void* hip_stream, rs_graph** out);
+
+/* As rs_graph_create, with src/dst/t/colour given as DEVICE pointers. */
+rs_status rs_graph_create_device(uint32_t n, uint64_t m, const uint32_t* src, const uint32_t* dst,
+                                 const uint32_t* t, const uint8_t* colour, uint32_t n_colours,
+                                 void* hip_stream, rs_graph** out);
+
+rs_status rs_graph_get_info(const rs_graph* g, rs_graph_info* out);
+
+/* Copy the canonical (deduplicated, (dst,t,src)-sorted) edge list to host
+ * arrays of info.m entries each (any may be NULL). */
+rs_status rs_graph_edges(const rs_graph* g, uint32_t* src, uint32_t* dst, uint32_t* t);
+
+/* Frees the graph and its workspaces. NULL is accepted. */
+rs_status rs_graph_destroy(rs_graph* g);
+
+/* ------------------------------------------------------------------------
+ * Queries.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+  uint32_t k;                 /* vertices on the path, 2..RS_MAX_K */
+  uint32_t delta;             /* resting time delta(v), the same at every vertex */
+  const uint8_t* motif_count; /* NULL = k-RestlessPath; else host array of
+                                 n_colours multiplicities mu(s) summing to k
+                                 (k-RestlessMotif). Copied during the call. */
+  uint64_t seed;              /* selects the random substitution */
+  uint64_t it_begin, it_end;  /* sieve iterations [it_begin, it_end) of the
+                                 2^k; (0, 0) = all. A range yields the partial
+                                 fingerprint; partials XOR to the whole. */
+} rs_query;
+
+typedef struct {
+  uint64_t fingerprint;  /* F over the requested iteration range */
+  uint32_t yes;          /* F != 0 (meaningful for the full range) */
+  rs_status status;      /* per-query status (batched and served calls) */
+  float device_ms;       /* device time of the query (hipEvents), or of the
+                            whole batch for rs_run_batch */
+} rs_result;
+
+/* Launch-shape knobs; zero fields mean "choose automatically". */
+typedef struct {
+  uint32_t edges_per_tile;     /* edges per wavefront tile in the scan levels: 8 or 16 */
+  uint32_t top_edges_per_tile; /* edges per wavefront in the last level: 16..256 */
+  uint32_t chunks_per_launch;  /* 64-iteration chunks processed per launch */
+  uint32_t waves_per_block;    /* 1, 2 or 4 */
+} rs_tuning;
+
+/* HBM bytes rs_run needs for this query on this graph beyond the graph
+ * itself: window indices 4m, substitution table 8nk, per-level products
+ * 8m*kq*(k-1) (kq = k rounded up to a multiple of 4), two prefix-state
+ * buffers 2*8*(m+n)*64 per concurrent chunk, look-back state and 8*2^k of
+ * per-iteration sums. */
+rs_status rs_query_footprint(const rs_graph* g, const rs_query* q, uint64_t* bytes);
+
+/* Plain path: one query, kernels launched one level at a time on hip_stream.
+ * Validation (RS_EINVAL): q != NULL; 2 <= k <= RS_MAX_K; motif only on a
+ * coloured graph, counts sum to k; it_begin <= it_end <= 2^k. k > n is not an
+ * error (F = 0). */
+rs_status rs_run(const rs_graph* g, const rs_query* q, rs_result* r, void* hip_stream);
+
+/* As rs_run with explicit launch knobs (NULL = automatic) and, if
+ * per_iteration != NULL, the per-iteration values f_L for every iteration of
+ * the range copied to that host array (it_end - it_begin entries; 2^k for the
+ * full range). */
+rs_status rs_run_ex(const rs_graph* g, const rs_query* q, const rs_tuning* tune,
+                    uint64_t* per_iteration, rs_result* r, void* hip_stream);
+
+/* Batched path: nq queries, each on its own graph (graphs[i]; graphs may
+ * repeat), evaluated by one persistent kernel that pulls work items
+ * (query, 64-iteration chunk, level, edge tile) from a device queue. The
+ * per-query setup kernels and the persistent kernel are captured once into a
+ * hipGraph and replayed. results[i].status holds each query's status; the
+ * call returns the first error, or RS_OK. tune == NULL uses the tuning found
+ * by rs_autotune for the first graph (or a default). Results are bit-identical
+ * to rs_run. */
+rs_status rs_run_batch(const rs_graph* const* graphs, const rs_query* queries, uint32_t nq,
+                       rs_result* results, const rs_tuning* tune, void* hip_stream);
+
+/* Times candidate launch shapes on the sample queries and returns the
+ * fastest; the choice is cached per (graph, k class) for later NULL-tuning
+ * calls. */
+rs_status rs_autotune(const rs_graph* g, const rs_query* sample, uint32_t ns, rs_tuning* out);
+
+/* ------------------------------------------------------------------------
+ * Kernel timing (hipEvents recorded around the launches of each kernel
+ * class on the launch stream while enabled). Classes: "level_scan" (prefix
+ * levels 2..k-1), "level_top" (level k), "qtable", "ztable", "window",
+ * "persistent".
+ * ---------------------------------------------------------------------- */
+rs_status rs_profile_enable(int on);
+rs_status rs_profile_reset(void);
+/* launches and summed milliseconds of a kernel class since the last reset. */
+rs_status rs_profile_get(const char* kernel_class, uint64_t* launches, double* total_ms,
+                         double* algorithmic_bytes);
+
+/* ------------------------------------------------------------------------
+ * Server: continuous batching over resident graphs.
+ * A worker thread keeps the graphs and per-slot device buffers resident,
+ * admits queued queries while their footprint fits the HBM budget, and runs
+ * epochs of the batched kernel over the admitted work; queries arriving
+ * while an epoch runs join the next epoch. Long queries are split into
+ * iteration ranges across epochs. All server calls are thread-safe.
+ * ---------------------------------------------------------------------- */
+typedef struct rs_server rs_server;
+
+typedef struct {
+  uint32_t max_inflight;       /* queries admitted at once (0 = 64) */
+  uint64_t epoch_edge_updates; /* work per epoch before new arrivals are
+                                  admitted (0 = automatic) */
+  uint32_t streams;            /* concurrent device streams (0 = 2) */
+} rs_server_opts;
+
+typedef struct {
+  uint64_t submitted, completed, admitted, deferred, cancelled, rejected;
+  uint64_t queued, inflight;   /* at the time of the call */
+  double qps;                  /* completed / seconds since creation */
+  double p50_ms, p99_ms;       /* latency submit -> completion of completed queries */
+  double busy_ms;              /* device time spent in epochs */
+  uint64_t epochs;
+} rs_server_stats;
+
+/* hbm_budget: bytes of HBM the server may hold for query workspaces. */
+rs_status rs_server_create(uint64_t hbm_budget, const rs_server_opts* opts, rs_server** out);
+/* The graph must outlive the server. */
+rs_status rs_server_add_graph(rs_server* s, const rs_graph* g, uint32_t* graph_id);
+/* Non-blocking. Copies the query (and its motif). RS_EINVAL for invalid
+ * queries, RS_ENOMEM if its footprint can never fit the budget. */
+rs_status rs_server_submit(rs_server* s, uint32_t graph_id, const rs_query* q, uint64_t* ticket);
+/* Wait up to wait_ms (0 = don't wait, <0 = forever). RS_OK with the result,
+ * RS_ETIMEOUT if not yet complete, RS_ENOTFOUND for unknown or already
+ * collected tickets. */
+rs_status rs_server_poll(rs_server* s, uint64_t ticket, rs_result* r, int32_t wait_ms);
+rs_status rs_server_cancel(rs_server* s, uint64_t ticket);
+rs_status rs_server_stats_get(rs_server* s, rs_server_stats* out);
+/* Stops the worker after in-flight epochs finish; pending queries are
+ * cancelled. */
+rs_status rs_server_destroy(rs_server* s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

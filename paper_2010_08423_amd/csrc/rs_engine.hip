@@ -1,0 +1,466 @@
+// Query engine and C ABI: graph lifetime, query validation, the plain
+// level-by-level launch sequence, device workspaces and kernel timing.
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "rs_internal.h"
+
+namespace rs {
+
+rs_status graph_build(uint32_t n, uint64_t m, const uint32_t* src, const uint32_t* dst,
+                      const uint32_t* t, const uint8_t* colour, uint32_t n_colours, bool host_ptrs,
+                      hipStream_t st, rs_graph** out);
+
+static thread_local std::string g_last_error;
+void set_last_error(const std::string& s) { g_last_error = s; }
+
+// ---------------------------------------------------------------------------
+// DevBuf
+// ---------------------------------------------------------------------------
+rs_status DevBuf::reserve(size_t need, hipStream_t st, bool zero) {
+  if (need <= bytes && p) return RS_OK;
+  release();
+  if (need == 0) need = 8;
+  void* q = nullptr;
+  if (hipMalloc(&q, need) != hipSuccess) {
+    (void)hipGetLastError();
+    return RS_ENOMEM;
+  }
+  p = q;
+  bytes = need;
+  if (zero) {
+    hipError_t e = launch_fill64(static_cast<uint64_t*>(p), 0, need / 8, st);
+    if (e == hipSuccess && need % 8) e = hipMemsetAsync(static_cast<char*>(p) + (need & ~size_t(7)), 0, need % 8, st);
+    if (e != hipSuccess) return RS_EDEVICE;
+  }
+  return RS_OK;
+}
+
+void DevBuf::release() {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+  bytes = 0;
+}
+
+// ---------------------------------------------------------------------------
+// Kernel timing
+// ---------------------------------------------------------------------------
+static const char* kClassNames[KC_COUNT] = {"level_scan", "level_top", "qtable", "ztable", "window", "persistent"};
+static std::mutex g_prof_mu;
+static std::atomic<bool> g_prof_on{false};
+struct PendingEv {
+  KernelClass kc;
+  hipEvent_t e0, e1;
+  double bytes;
+};
+static std::vector<PendingEv> g_pending;
+static uint64_t g_launches[KC_COUNT];
+static double g_ms[KC_COUNT];
+static double g_bytes[KC_COUNT];
+
+bool profiling_on() { return g_prof_on.load(std::memory_order_relaxed); }
+
+ProfScope::ProfScope(KernelClass k, hipStream_t s, double b) : kc(k), st(s), bytes(b) {
+  if (!profiling_on()) return;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    e0 = e1 = nullptr;
+    return;
+  }
+  (void)hipEventRecord(e0, st);
+}
+
+ProfScope::~ProfScope() {
+  if (!e0) return;
+  (void)hipEventRecord(e1, st);
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  g_pending.push_back({kc, e0, e1, bytes});
+}
+
+void profile_flush() {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  std::vector<PendingEv> keep;
+  for (auto& p : g_pending) {
+    if (hipEventQuery(p.e1) != hipSuccess) {
+      keep.push_back(p);
+      continue;
+    }
+    float ms = 0;
+    if (hipEventElapsedTime(&ms, p.e0, p.e1) == hipSuccess) {
+      g_launches[p.kc]++;
+      g_ms[p.kc] += ms;
+      g_bytes[p.kc] += p.bytes;
+    }
+    (void)hipEventDestroy(p.e0);
+    (void)hipEventDestroy(p.e1);
+  }
+  g_pending.swap(keep);
+}
+
+// ---------------------------------------------------------------------------
+// Query planning
+// ---------------------------------------------------------------------------
+static uint32_t round_kq(uint32_t k) { return (k + 3) / 4 * 4; }
+
+rs_status plan_query(const rs_graph* g, const rs_query* q, QueryPlan& qp) {
+  if (!g || !q) return RS_EINVAL;
+  if (q->k < 2 || q->k > RS_MAX_K) return RS_EINVAL;
+  const uint64_t total = 1ull << q->k;
+  qp = QueryPlan();
+  qp.k = q->k;
+  qp.kq = round_kq(q->k);
+  qp.delta = q->delta;
+  qp.seed = q->seed;
+  qp.it_begin = q->it_begin;
+  qp.it_end = q->it_end;
+  if (qp.it_begin == 0 && qp.it_end == 0) qp.it_end = total;
+  if (qp.it_begin > qp.it_end || qp.it_end > total) return RS_EINVAL;
+  if (q->motif_count) {
+    const uint32_t nc = g->info.n_colours;
+    if (nc == 0) return RS_EINVAL;
+    uint32_t s = 0;
+    for (uint32_t c = 0; c < nc; ++c) {
+      qp.mu[c] = q->motif_count[c];
+      qp.shade_off[c] = (uint8_t)s;
+      s += q->motif_count[c];
+    }
+    if (s != q->k) return RS_EINVAL;
+    qp.motif = true;
+  }
+  qp.chunk_first = qp.it_begin / 64;
+  qp.chunk_last = (qp.it_end + 63) / 64;
+  return RS_OK;
+}
+
+Tuning resolve_tuning(const rs_graph* g, uint32_t k, const rs_tuning* t) {
+  Tuning tu;
+  if (g && g->has_tuned[k]) tu = g->tuned[k];
+  if (t) {
+    if (t->edges_per_tile) tu.edges_per_tile = t->edges_per_tile;
+    if (t->top_edges_per_tile) tu.top_edges_per_tile = t->top_edges_per_tile;
+    if (t->chunks_per_launch) tu.chunks_per_launch = t->chunks_per_launch;
+    if (t->waves_per_block) tu.waves_per_block = t->waves_per_block;
+  }
+  if (tu.edges_per_tile != 8 && tu.edges_per_tile != 16) tu.edges_per_tile = 16;
+  tu.top_edges_per_tile = std::min(std::max(tu.top_edges_per_tile, 1u), 4096u);
+  if (tu.waves_per_block != 1 && tu.waves_per_block != 2 && tu.waves_per_block != 4) tu.waves_per_block = 4;
+  if (tu.chunks_per_launch < 1) tu.chunks_per_launch = 1;
+  return tu;
+}
+
+static uint64_t chunks_of(const QueryPlan& qp) { return qp.chunk_last - qp.chunk_first; }
+
+uint64_t plain_footprint(const rs_graph* g, const QueryPlan& qp, const Tuning& tu) {
+  const uint64_t m = g->g.m, n = g->g.n;
+  const uint64_t cpl = std::min<uint64_t>(tu.chunks_per_launch, std::max<uint64_t>(chunks_of(qp), 1));
+  const uint64_t tiles = (m + tu.edges_per_tile - 1) / tu.edges_per_tile;
+  uint64_t b = 4 * m + 8 * n * qp.kq + 8 * m * qp.kq * (qp.k - 1);
+  b += 2 * 8 * (m + n) * 64 * cpl;
+  b += cpl * tiles * (4 + 2 * 512) + 4 * cpl * RS_MAX_K;
+  b += 8 * (1ull << qp.k) + 64;
+  return b;
+}
+
+// Algorithmic HBM bytes of one prefix-level launch: per edge and chunk two
+// 512-byte window gathers (one z row at level 2) and one 512-byte prefix
+// store, plus the edge's indices and q row.
+double scan_bytes(uint64_t m, uint32_t kq, uint64_t chunks, bool first) {
+  const double per = (first ? 8.0 * kq : 1024.0) + 512.0 + 12.0 + 8.0 * kq;
+  return per * (double)m * (double)chunks;
+}
+double top_bytes(uint64_t m, uint32_t kq, uint64_t chunks, bool first) {
+  const double per = (first ? 8.0 * kq : 1024.0) + 8.0 + 8.0 * kq;
+  return per * (double)m * (double)chunks;
+}
+
+// ---------------------------------------------------------------------------
+// Plain path: setup kernels, then per chunk group levels 2..k.
+// ---------------------------------------------------------------------------
+rs_status run_plain(rs_graph* g, const QueryPlan& qp, const Tuning& tu, uint64_t* per_it_host,
+                    rs_result* r, hipStream_t st) {
+  auto& ws = g->ws;
+  const GraphDev& G = g->g;
+  const uint64_t m = G.m, n = G.n;
+  const uint64_t span = qp.it_end - qp.it_begin;
+  if (!ws.ev0) {
+    RS_HIP(hipEventCreate(&ws.ev0));
+    RS_HIP(hipEventCreate(&ws.ev1));
+  }
+  RS_HIP(hipEventRecord(ws.ev0, st));
+  uint64_t F = 0;
+  // No path with k distinct vertices can exist: F is exactly 0.
+  const bool trivial = m == 0 || qp.k > n || span == 0;
+  if (!trivial) {
+    const uint32_t k = qp.k, kq = qp.kq;
+    const uint64_t nchunks = chunks_of(qp);
+    const uint64_t cpl = std::min<uint64_t>(tu.chunks_per_launch, nchunks);
+    const uint32_t E = tu.edges_per_tile;
+    const uint64_t tiles = (m + E - 1) / E;
+    const uint64_t p_elems = (m + n) * 64;
+    if (ws.p_elems_per_chunk != p_elems) {  // slot layout differs: rezero
+      ws.p0.release();
+      ws.p1.release();
+      ws.p_elems_per_chunk = p_elems;
+    }
+    if (ws.lo.reserve(4 * m, st, false) || ws.z.reserve(8 * n * kq, st, false) ||
+        ws.q.reserve(8 * m * kq * (k - 1), st, false) || ws.p0.reserve(8 * p_elems * cpl, st, true) ||
+        ws.p1.reserve(8 * p_elems * cpl, st, true) || ws.counters.reserve(4 * cpl * RS_MAX_K, st, false) ||
+        ws.agg.reserve(512 * cpl * tiles, st, false) || ws.incl.reserve(512 * cpl * tiles, st, false) ||
+        ws.fsum.reserve(8 * (1ull << k), st, false) || ws.out.reserve(64, st, false) ||
+        ws.err.reserve(64, st, true))
+      return RS_ENOMEM;
+    if (ws.flags.bytes < 4 * cpl * tiles) {
+      if (ws.flags.reserve(4 * cpl * tiles, st, true)) return RS_ENOMEM;
+      ws.epoch = 0;
+    }
+    {
+      ProfScope ps(KC_ZTABLE, st, 8.0 * n * kq);
+      RS_HIP(launch_ztable(ws.z.as<uint64_t>(), (uint32_t)n, qp, G.colour.as<uint8_t>(), st));
+    }
+    {
+      ProfScope ps(KC_WINDOW, st, 16.0 * m);
+      RS_HIP(launch_window(G.e_src.as<uint32_t>(), G.e_t.as<uint32_t>(), G.in_off.as<uint32_t>(),
+                           ws.lo.as<uint32_t>(), (uint32_t)m, qp.delta, st));
+    }
+    {
+      ProfScope ps(KC_QTABLE, st, (double)m * (12.0 + 8.0 * kq * (k - 1)));
+      RS_HIP(launch_qtable(G.e_src.as<uint32_t>(), G.e_dst.as<uint32_t>(), G.e_t.as<uint32_t>(),
+                           ws.z.as<uint64_t>(), ws.q.as<uint64_t>(), (uint32_t)m, qp, st));
+    }
+    RS_HIP(launch_fill64(ws.fsum.as<uint64_t>(), 0, 1ull << k, st));
+    for (uint64_t c0 = qp.chunk_first; c0 < qp.chunk_last; c0 += cpl) {
+      const uint32_t gc = (uint32_t)std::min<uint64_t>(cpl, qp.chunk_last - c0);
+      RS_HIP(launch_fill32(ws.counters.as<uint32_t>(), 0, (uint64_t)cpl * RS_MAX_K, st));
+      uint64_t* prev = ws.p0.as<uint64_t>();
+      uint64_t* cur = ws.p1.as<uint64_t>();
+      for (uint32_t l = 2; l <= k; ++l) {
+        const uint64_t* ql = ws.q.as<uint64_t>() + (uint64_t)(l - 2) * m * kq;
+        const bool first = l == 2;
+        if (l < k) {
+          if (++ws.epoch >= (1u << 30)) {
+            RS_HIP(launch_fill32(ws.flags.as<uint32_t>(), 0, ws.flags.bytes / 4, st));
+            ws.epoch = 1;
+          }
+          ScanArgs a;
+          a.e_src = G.e_src.as<uint32_t>();
+          a.e_out = G.e_out.as<uint32_t>();
+          a.hi = G.hi.as<uint32_t>();
+          a.lo = ws.lo.as<uint32_t>();
+          a.q = ql;
+          a.z = ws.z.as<uint64_t>();
+          a.p_prev = prev;
+          a.p_cur = cur;
+          a.p_stride = p_elems;
+          a.chunk_base = c0 * 64;
+          a.m = (uint32_t)m;
+          a.n_tiles = (uint32_t)tiles;
+          a.k = k;
+          a.epoch = ws.epoch;
+          a.tile_counter = ws.counters.as<uint32_t>() + (uint64_t)(l - 2) * cpl;
+          a.flags = ws.flags.as<uint32_t>();
+          a.agg = ws.agg.as<uint64_t>();
+          a.incl = ws.incl.as<uint64_t>();
+          a.err = ws.err.as<uint32_t>();
+          ProfScope ps(KC_SCAN, st, scan_bytes(m, kq, gc, first));
+          RS_HIP(launch_scan(a, first, kq, gc, tu, st));
+          std::swap(prev, cur);
+        } else {
+          TopArgs a;
+          a.e_src = G.e_src.as<uint32_t>();
+          a.hi = G.hi.as<uint32_t>();
+          a.lo = ws.lo.as<uint32_t>();
+          a.q = ql;
+          a.z = ws.z.as<uint64_t>();
+          a.p_prev = prev;
+          a.p_stride = p_elems;
+          a.chunk_base = c0 * 64;
+          a.it_begin = qp.it_begin;
+          a.it_end = qp.it_end;
+          a.m = (uint32_t)m;
+          a.edges_per_wave = tu.top_edges_per_tile;
+          a.k = k;
+          a.fsum = ws.fsum.as<uint64_t>();
+          ProfScope ps(KC_TOP, st, top_bytes(m, kq, gc, first));
+          RS_HIP(launch_top(a, first, kq, gc, tu, st));
+        }
+      }
+    }
+    RS_HIP(launch_xor_reduce(ws.fsum.as<uint64_t>(), qp.it_begin, qp.it_end, ws.out.as<uint64_t>(), st));
+    uint32_t err = 0;
+    RS_HIP(hipMemcpyAsync(&F, ws.out.p, 8, hipMemcpyDeviceToHost, st));
+    RS_HIP(hipMemcpyAsync(&err, ws.err.p, 4, hipMemcpyDeviceToHost, st));
+    if (per_it_host)
+      RS_HIP(hipMemcpyAsync(per_it_host, ws.fsum.as<uint64_t>() + qp.it_begin, 8 * span,
+                            hipMemcpyDeviceToHost, st));
+    RS_HIP(hipEventRecord(ws.ev1, st));
+    RS_HIP(hipStreamSynchronize(st));
+    if (err) {
+      set_last_error("kernel reported a look-back failure (flag " + std::to_string(err) + ")");
+      uint32_t zero = 0;
+      (void)hipMemcpy(ws.err.p, &zero, 4, hipMemcpyHostToDevice);
+      return RS_EDEVICE;
+    }
+  } else {
+    if (per_it_host)
+      for (uint64_t i = 0; i < span; ++i) per_it_host[i] = 0;
+    RS_HIP(hipEventRecord(ws.ev1, st));
+    RS_HIP(hipStreamSynchronize(st));
+  }
+  float ms = 0;
+  (void)hipEventElapsedTime(&ms, ws.ev0, ws.ev1);
+  if (profiling_on()) profile_flush();
+  r->fingerprint = F;
+  r->yes = F != 0;
+  r->status = RS_OK;
+  r->device_ms = ms;
+  return RS_OK;
+}
+
+}  // namespace rs
+
+using namespace rs;
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char* rs_status_str(rs_status s) {
+  switch (s) {
+    case RS_OK: return "RS_OK";
+    case RS_EINVAL: return "RS_EINVAL: invalid argument";
+    case RS_ENOMEM: return "RS_ENOMEM: out of memory or over budget";
+    case RS_EDEVICE: return "RS_EDEVICE: device error";
+    case RS_EBUSY: return "RS_EBUSY: busy";
+    case RS_ECANCELED: return "RS_ECANCELED: cancelled";
+    case RS_ENOTFOUND: return "RS_ENOTFOUND: not found";
+    case RS_ETIMEOUT: return "RS_ETIMEOUT: timed out";
+    default: return "unknown rs_status";
+  }
+}
+
+const char* rs_version(void) { return "librestless_sieve 0.1 (gfx950)"; }
+
+const char* rs_last_error(void) { return g_last_error.c_str(); }
+
+rs_status rs_graph_create(uint32_t n, uint64_t m, const uint32_t* src, const uint32_t* dst,
+                          const uint32_t* t, const uint8_t* colour, uint32_t n_colours,
+                          void* hip_stream, rs_graph** out) {
+  try {
+    return graph_build(n, m, src, dst, t, colour, n_colours, true, (hipStream_t)hip_stream, out);
+  } catch (...) {
+    return RS_ENOMEM;
+  }
+}
+
+rs_status rs_graph_create_device(uint32_t n, uint64_t m, const uint32_t* src, const uint32_t* dst,
+                                 const uint32_t* t, const uint8_t* colour, uint32_t n_colours,
+                                 void* hip_stream, rs_graph** out) {
+  try {
+    return graph_build(n, m, src, dst, t, colour, n_colours, false, (hipStream_t)hip_stream, out);
+  } catch (...) {
+    return RS_ENOMEM;
+  }
+}
+
+rs_status rs_graph_get_info(const rs_graph* g, rs_graph_info* out) {
+  if (!g || !out) return RS_EINVAL;
+  *out = g->info;
+  return RS_OK;
+}
+
+rs_status rs_graph_edges(const rs_graph* g, uint32_t* src, uint32_t* dst, uint32_t* t) {
+  if (!g) return RS_EINVAL;
+  const uint64_t m = g->g.m;
+  if (!m) return RS_OK;
+  if (src) RS_HIP(hipMemcpy(src, g->g.e_src.p, 4 * m, hipMemcpyDeviceToHost));
+  if (dst) RS_HIP(hipMemcpy(dst, g->g.e_dst.p, 4 * m, hipMemcpyDeviceToHost));
+  if (t) RS_HIP(hipMemcpy(t, g->g.e_t.p, 4 * m, hipMemcpyDeviceToHost));
+  return RS_OK;
+}
+
+rs_status rs_graph_destroy(rs_graph* g) {
+  if (!g) return RS_OK;
+  (void)hipDeviceSynchronize();
+  for (DevBuf* b : {&g->g.e_src, &g->g.e_dst, &g->g.e_t, &g->g.e_out, &g->g.hi, &g->g.in_off, &g->g.colour,
+                    &g->ws.lo, &g->ws.z, &g->ws.q, &g->ws.p0, &g->ws.p1, &g->ws.counters, &g->ws.flags,
+                    &g->ws.agg, &g->ws.incl, &g->ws.fsum, &g->ws.out, &g->ws.err})
+    b->release();
+  if (g->ws.ev0) (void)hipEventDestroy(g->ws.ev0);
+  if (g->ws.ev1) (void)hipEventDestroy(g->ws.ev1);
+  delete g;
+  return RS_OK;
+}
+
+rs_status rs_query_footprint(const rs_graph* g, const rs_query* q, uint64_t* bytes) {
+  if (!bytes) return RS_EINVAL;
+  QueryPlan qp;
+  RS_TRY(plan_query(g, q, qp));
+  *bytes = plain_footprint(g, qp, resolve_tuning(g, qp.k, nullptr));
+  return RS_OK;
+}
+
+rs_status rs_run_ex(const rs_graph* gc, const rs_query* q, const rs_tuning* tune,
+                    uint64_t* per_iteration, rs_result* r, void* hip_stream) {
+  if (!r) return RS_EINVAL;
+  QueryPlan qp;
+  rs_status s = plan_query(gc, q, qp);
+  if (s != RS_OK) {
+    r->status = s;
+    return s;
+  }
+  rs_graph* g = const_cast<rs_graph*>(gc);
+  try {
+    std::lock_guard<std::mutex> lk(g->mu);
+    s = run_plain(g, qp, resolve_tuning(g, qp.k, tune), per_iteration, r, (hipStream_t)hip_stream);
+  } catch (...) {
+    s = RS_ENOMEM;
+  }
+  r->status = s;
+  return s;
+}
+
+rs_status rs_run(const rs_graph* g, const rs_query* q, rs_result* r, void* hip_stream) {
+  return rs_run_ex(g, q, nullptr, nullptr, r, hip_stream);
+}
+
+rs_status rs_profile_enable(int on) {
+  g_prof_on.store(on != 0);
+  return RS_OK;
+}
+
+rs_status rs_profile_reset(void) {
+  (void)hipDeviceSynchronize();
+  profile_flush();
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  for (int i = 0; i < KC_COUNT; ++i) {
+    g_launches[i] = 0;
+    g_ms[i] = 0;
+    g_bytes[i] = 0;
+  }
+  return RS_OK;
+}
+
+rs_status rs_profile_get(const char* kernel_class, uint64_t* launches, double* total_ms,
+                         double* algorithmic_bytes) {
+  if (!kernel_class) return RS_EINVAL;
+  profile_flush();
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  for (int i = 0; i < KC_COUNT; ++i) {
+    if (strcmp(kernel_class, kClassNames[i]) == 0) {
+      if (launches) *launches = g_launches[i];
+      if (total_ms) *total_ms = g_ms[i];
+      if (algorithmic_bytes) *algorithmic_bytes = g_bytes[i];
+      return RS_OK;
+    }
+  }
+  return RS_ENOTFOUND;
+}
+
+}  // extern "C"

@@ -1,0 +1,175 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <atomic>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/rs.h"
+
+namespace rs {
+
+// ---------------------------------------------------------------------------
+// Errors
+// ---------------------------------------------------------------------------
+void set_last_error(const std::string& s);
+
+#define RS_HIP(expr)                                                       \
+  do {                                                                     \
+    hipError_t _e = (expr);                                                \
+    if (_e != hipSuccess) {                                                \
+      ::rs::set_last_error(std::string(#expr) + ": " + hipGetErrorString(_e)); \
+      return RS_EDEVICE;                                                   \
+    }                                                                      \
+  } while (0)
+
+#define RS_TRY(expr)              \
+  do {                            \
+    rs_status _s = (expr);        \
+    if (_s != RS_OK) return _s;   \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// Device buffers
+// ---------------------------------------------------------------------------
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  // Grows to at least `need` bytes; new memory is zero-filled on `st`.
+  rs_status reserve(size_t need, hipStream_t st, bool zero = true);
+  void release();
+  template <class T>
+  T* as() const {
+    return static_cast<T*>(p);
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Kernel launch shapes and per-query plan
+// ---------------------------------------------------------------------------
+constexpr uint32_t kFlagAgg = 1;   // tile published the XOR of its open segment part
+constexpr uint32_t kFlagIncl = 2;  // tile published the full prefix of its open segment
+constexpr uint32_t kSpinLimit = 1u << 26;
+
+struct Tuning {
+  uint32_t edges_per_tile = 16;      // scan levels: 8 or 16
+  uint32_t top_edges_per_tile = 64;  // last level
+  uint32_t chunks_per_launch = 1;
+  uint32_t waves_per_block = 4;
+};
+
+struct QueryPlan {
+  uint32_t k = 0, kq = 0, delta = 0;
+  bool motif = false;
+  uint64_t seed = 0;
+  uint64_t it_begin = 0, it_end = 0;
+  uint64_t chunk_first = 0, chunk_last = 0;  // 64-iteration chunks [first, last)
+  uint8_t mu[RS_MAX_COLOURS] = {0};          // motif multiplicities
+  uint8_t shade_off[RS_MAX_COLOURS] = {0};
+};
+
+// Arguments of the prefix levels (2..k-1).
+struct ScanArgs {
+  const uint32_t* e_src;
+  const uint32_t* e_out;  // P slot written by edge e: e + dst(e) + 1
+  const uint32_t* hi;     // P slot of the window end
+  const uint32_t* lo;     // P slot of the window start
+  const uint64_t* q;      // [m][kq] products z_{dst,j} * y_{e,l-1} for this level
+  const uint64_t* z;      // [n][kq] (level 2 only)
+  const uint64_t* p_prev; // [(m+n)*64] per chunk
+  uint64_t* p_cur;
+  uint64_t p_stride;      // elements between consecutive chunks' P arrays
+  uint64_t chunk_base;    // first iteration index of chunk 0 of this launch
+  uint32_t m;
+  uint32_t n_tiles;
+  uint32_t k;
+  uint32_t epoch;
+  uint32_t* tile_counter;  // [chunks]
+  uint32_t* flags;         // [chunks][n_tiles]
+  uint64_t* agg;           // [chunks][n_tiles][64]
+  uint64_t* incl;          // [chunks][n_tiles][64]
+  uint32_t* err;
+};
+
+// Arguments of the last level k.
+struct TopArgs {
+  const uint32_t* e_src;
+  const uint32_t* hi;
+  const uint32_t* lo;
+  const uint64_t* q;
+  const uint64_t* z;
+  const uint64_t* p_prev;
+  uint64_t p_stride;
+  uint64_t chunk_base;
+  uint64_t it_begin, it_end;
+  uint32_t m;
+  uint32_t edges_per_wave;
+  uint32_t k;
+  uint64_t* fsum;  // [2^k] per-iteration sums (XOR-accumulated)
+};
+
+// Launchers (rs_kernels.hip). All enqueue on `st` and return hipGetLastError.
+hipError_t launch_ztable(uint64_t* z, uint32_t n, const QueryPlan& qp, const uint8_t* colour_d,
+                         hipStream_t st);
+hipError_t launch_window(const uint32_t* e_src, const uint32_t* e_t, const uint32_t* in_off,
+                         uint32_t* lo, uint32_t m, uint32_t delta, hipStream_t st);
+hipError_t launch_qtable(const uint32_t* e_src, const uint32_t* e_dst, const uint32_t* e_t,
+                         const uint64_t* z, uint64_t* q, uint32_t m, const QueryPlan& qp,
+                         hipStream_t st);
+hipError_t launch_scan(const ScanArgs& a, bool first_level, uint32_t kq, uint32_t chunks,
+                       const Tuning& tu, hipStream_t st);
+hipError_t launch_top(const TopArgs& a, bool first_level, uint32_t kq, uint32_t chunks,
+                      const Tuning& tu, hipStream_t st);
+hipError_t launch_fill32(uint32_t* p, uint32_t value, uint64_t count, hipStream_t st);
+hipError_t launch_fill64(uint64_t* p, uint64_t value, uint64_t count, hipStream_t st);
+hipError_t launch_xor_reduce(const uint64_t* f, uint64_t begin, uint64_t end, uint64_t* out,
+                             hipStream_t st);
+
+// Graph construction kernels (rs_graph.hip).
+struct GraphDev {
+  uint32_t n = 0;
+  uint64_t m = 0;
+  uint32_t n_colours = 0;
+  DevBuf e_src, e_dst, e_t, e_out, hi, in_off, colour;
+};
+
+// ---------------------------------------------------------------------------
+// Profiling (rs_engine.hip)
+// ---------------------------------------------------------------------------
+enum KernelClass { KC_SCAN = 0, KC_TOP, KC_QTABLE, KC_ZTABLE, KC_WINDOW, KC_PERSISTENT, KC_COUNT };
+bool profiling_on();
+struct ProfScope {
+  // Records events around one launch of class `kc` on `st` when profiling is on.
+  ProfScope(KernelClass kc, hipStream_t st, double algorithmic_bytes);
+  ~ProfScope();
+  KernelClass kc;
+  hipStream_t st;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  double bytes;
+};
+void profile_flush();  // folds completed event pairs into the totals
+
+}  // namespace rs
+
+// Opaque graph handle.
+struct rs_graph {
+  int device = 0;
+  rs::GraphDev g;
+  rs_graph_info info{};
+  // Query workspace cached on the graph; guarded by mu.
+  std::mutex mu;
+  struct Workspace {
+    rs::DevBuf lo, z, q, p0, p1, counters, flags, agg, incl, fsum, out, err;
+    uint32_t epoch = 0;
+    uint64_t p_elems_per_chunk = 0;
+    uint32_t flag_tiles = 0, flag_chunks = 0;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  } ws;
+  // Autotuned launch shapes per k (index k), 0 = not tuned.
+  rs::Tuning tuned[RS_MAX_K + 1];
+  bool has_tuned[RS_MAX_K + 1] = {false};
+};
