@@ -162,7 +162,7 @@ uint64_t plain_footprint(const rs_graph* g, const QueryPlan& qp, const Tuning& t
   const uint64_t tiles = (m + tu.edges_per_tile - 1) / tu.edges_per_tile;
   uint64_t b = 4 * m + 8 * n * qp.kq + 8 * m * qp.kq * (qp.k - 1);
   b += 2 * 8 * (m + n) * 64 * cpl;
-  b += cpl * tiles * (4 + 2 * 512) + 4 * cpl * RS_MAX_K;
+  b += cpl * tiles * 2 * 1024 + cpl * 512 * 4096;
   b += 8 * (1ull << qp.k) + 64;
   return b;
 }
@@ -208,15 +208,22 @@ rs_status run_plain(rs_graph* g, const QueryPlan& qp, const Tuning& tu, uint64_t
       ws.p1.release();
       ws.p_elems_per_chunk = p_elems;
     }
+    TopArgs ta{};
+    ta.m = (uint32_t)m;
+    ta.edges_per_wave = tu.top_edges_per_tile;
+    // Rows per chunk of the last level's partial sums; the single-chunk launch
+    // bounds every group: gc * blocks(gc) <= cpl * blocks(1).
+    const uint32_t tblocks = top_blocks(ta, k == 2, kq, 1, tu);
     if (ws.lo.reserve(4 * m, st, false) || ws.z.reserve(8 * n * kq, st, false) ||
         ws.q.reserve(8 * m * kq * (k - 1), st, false) || ws.p0.reserve(8 * p_elems * cpl, st, true) ||
-        ws.p1.reserve(8 * p_elems * cpl, st, true) || ws.counters.reserve(4 * cpl * RS_MAX_K, st, false) ||
-        ws.agg.reserve(512 * cpl * tiles, st, false) || ws.incl.reserve(512 * cpl * tiles, st, false) ||
-        ws.fsum.reserve(8 * (1ull << k), st, false) || ws.out.reserve(64, st, false) ||
-        ws.err.reserve(64, st, true))
+        ws.p1.reserve(8 * p_elems * cpl, st, true) ||
+        ws.partial.reserve(8 * 64 * cpl * (uint64_t)tblocks, st, false) ||
+        ws.fsum.reserve(8 * (1ull << k), st, false) || ws.out.reserve(64, st, false))
       return RS_ENOMEM;
-    if (ws.flags.bytes < 4 * cpl * tiles) {
-      if (ws.flags.reserve(4 * cpl * tiles, st, true)) return RS_ENOMEM;
+    if (ws.agg.bytes < 1024 * cpl * tiles || ws.incl.bytes < 1024 * cpl * tiles) {
+      // tagged records start at epoch 0, which no launch uses
+      if (ws.agg.reserve(1024 * cpl * tiles, st, true) || ws.incl.reserve(1024 * cpl * tiles, st, true))
+        return RS_ENOMEM;
       ws.epoch = 0;
     }
     {
@@ -236,7 +243,6 @@ rs_status run_plain(rs_graph* g, const QueryPlan& qp, const Tuning& tu, uint64_t
     RS_HIP(launch_fill64(ws.fsum.as<uint64_t>(), 0, 1ull << k, st));
     for (uint64_t c0 = qp.chunk_first; c0 < qp.chunk_last; c0 += cpl) {
       const uint32_t gc = (uint32_t)std::min<uint64_t>(cpl, qp.chunk_last - c0);
-      RS_HIP(launch_fill32(ws.counters.as<uint32_t>(), 0, (uint64_t)cpl * RS_MAX_K, st));
       uint64_t* prev = ws.p0.as<uint64_t>();
       uint64_t* cur = ws.p1.as<uint64_t>();
       for (uint32_t l = 2; l <= k; ++l) {
@@ -244,7 +250,8 @@ rs_status run_plain(rs_graph* g, const QueryPlan& qp, const Tuning& tu, uint64_t
         const bool first = l == 2;
         if (l < k) {
           if (++ws.epoch >= (1u << 30)) {
-            RS_HIP(launch_fill32(ws.flags.as<uint32_t>(), 0, ws.flags.bytes / 4, st));
+            RS_HIP(launch_fill64(ws.agg.as<uint64_t>(), 0, ws.agg.bytes / 8, st));
+            RS_HIP(launch_fill64(ws.incl.as<uint64_t>(), 0, ws.incl.bytes / 8, st));
             ws.epoch = 1;
           }
           ScanArgs a;
@@ -262,11 +269,8 @@ rs_status run_plain(rs_graph* g, const QueryPlan& qp, const Tuning& tu, uint64_t
           a.n_tiles = (uint32_t)tiles;
           a.k = k;
           a.epoch = ws.epoch;
-          a.tile_counter = ws.counters.as<uint32_t>() + (uint64_t)(l - 2) * cpl;
-          a.flags = ws.flags.as<uint32_t>();
           a.agg = ws.agg.as<uint64_t>();
           a.incl = ws.incl.as<uint64_t>();
-          a.err = ws.err.as<uint32_t>();
           ProfScope ps(KC_SCAN, st, scan_bytes(m, kq, gc, first));
           RS_HIP(launch_scan(a, first, kq, gc, tu, st));
           std::swap(prev, cur);
@@ -285,6 +289,7 @@ rs_status run_plain(rs_graph* g, const QueryPlan& qp, const Tuning& tu, uint64_t
           a.m = (uint32_t)m;
           a.edges_per_wave = tu.top_edges_per_tile;
           a.k = k;
+          a.partial = ws.partial.as<uint64_t>();
           a.fsum = ws.fsum.as<uint64_t>();
           ProfScope ps(KC_TOP, st, top_bytes(m, kq, gc, first));
           RS_HIP(launch_top(a, first, kq, gc, tu, st));
@@ -292,20 +297,12 @@ rs_status run_plain(rs_graph* g, const QueryPlan& qp, const Tuning& tu, uint64_t
       }
     }
     RS_HIP(launch_xor_reduce(ws.fsum.as<uint64_t>(), qp.it_begin, qp.it_end, ws.out.as<uint64_t>(), st));
-    uint32_t err = 0;
     RS_HIP(hipMemcpyAsync(&F, ws.out.p, 8, hipMemcpyDeviceToHost, st));
-    RS_HIP(hipMemcpyAsync(&err, ws.err.p, 4, hipMemcpyDeviceToHost, st));
     if (per_it_host)
       RS_HIP(hipMemcpyAsync(per_it_host, ws.fsum.as<uint64_t>() + qp.it_begin, 8 * span,
                             hipMemcpyDeviceToHost, st));
     RS_HIP(hipEventRecord(ws.ev1, st));
     RS_HIP(hipStreamSynchronize(st));
-    if (err) {
-      set_last_error("kernel reported a look-back failure (flag " + std::to_string(err) + ")");
-      uint32_t zero = 0;
-      (void)hipMemcpy(ws.err.p, &zero, 4, hipMemcpyHostToDevice);
-      return RS_EDEVICE;
-    }
   } else {
     if (per_it_host)
       for (uint64_t i = 0; i < span; ++i) per_it_host[i] = 0;
@@ -389,8 +386,8 @@ rs_status rs_graph_destroy(rs_graph* g) {
   if (!g) return RS_OK;
   (void)hipDeviceSynchronize();
   for (DevBuf* b : {&g->g.e_src, &g->g.e_dst, &g->g.e_t, &g->g.e_out, &g->g.hi, &g->g.in_off, &g->g.colour,
-                    &g->ws.lo, &g->ws.z, &g->ws.q, &g->ws.p0, &g->ws.p1, &g->ws.counters, &g->ws.flags,
-                    &g->ws.agg, &g->ws.incl, &g->ws.fsum, &g->ws.out, &g->ws.err})
+                    &g->ws.lo, &g->ws.z, &g->ws.q, &g->ws.p0, &g->ws.p1, &g->ws.partial,
+                    &g->ws.agg, &g->ws.incl, &g->ws.fsum, &g->ws.out})
     b->release();
   if (g->ws.ev0) (void)hipEventDestroy(g->ws.ev0);
   if (g->ws.ev1) (void)hipEventDestroy(g->ws.ev1);

@@ -9,7 +9,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/rs.h"
+#include "rs.h"  // include/ is on the include path
 
 namespace rs {
 
@@ -51,13 +51,12 @@ struct DevBuf {
 // ---------------------------------------------------------------------------
 // Kernel launch shapes and per-query plan
 // ---------------------------------------------------------------------------
-constexpr uint32_t kFlagAgg = 1;   // tile published the XOR of its open segment part
-constexpr uint32_t kFlagIncl = 2;  // tile published the full prefix of its open segment
-constexpr uint32_t kSpinLimit = 1u << 26;
+constexpr uint32_t kFlagAgg = 1;   // record: XOR of the tile's open segment part
+constexpr uint32_t kFlagIncl = 2;  // record: full prefix of that segment
 
 struct Tuning {
   uint32_t edges_per_tile = 16;      // scan levels: 8 or 16
-  uint32_t top_edges_per_tile = 64;  // last level
+  uint32_t top_edges_per_tile = 16;  // last level
   uint32_t chunks_per_launch = 1;
   uint32_t waves_per_block = 4;
 };
@@ -88,11 +87,8 @@ struct ScanArgs {
   uint32_t n_tiles;
   uint32_t k;
   uint32_t epoch;
-  uint32_t* tile_counter;  // [chunks]
-  uint32_t* flags;         // [chunks][n_tiles]
-  uint64_t* agg;           // [chunks][n_tiles][64]
-  uint64_t* incl;          // [chunks][n_tiles][64]
-  uint32_t* err;
+  uint64_t* agg;           // [chunks][n_tiles][64][2] tagged records
+  uint64_t* incl;          // [chunks][n_tiles][64][2]
 };
 
 // Arguments of the last level k.
@@ -109,8 +105,11 @@ struct TopArgs {
   uint32_t m;
   uint32_t edges_per_wave;
   uint32_t k;
-  uint64_t* fsum;  // [2^k] per-iteration sums (XOR-accumulated)
+  uint64_t* partial;  // [chunks][blocks][64] per-block sums
+  uint64_t* fsum;     // [2^k] per-iteration sums
 };
+// Rows of `partial` one launch_top call writes per chunk.
+uint32_t top_blocks(const TopArgs& a, bool first_level, uint32_t kq, uint32_t chunks, const Tuning& tu);
 
 // Launchers (rs_kernels.hip). All enqueue on `st` and return hipGetLastError.
 hipError_t launch_ztable(uint64_t* z, uint32_t n, const QueryPlan& qp, const uint8_t* colour_d,
@@ -163,7 +162,7 @@ struct rs_graph {
   // Query workspace cached on the graph; guarded by mu.
   std::mutex mu;
   struct Workspace {
-    rs::DevBuf lo, z, q, p0, p1, counters, flags, agg, incl, fsum, out, err;
+    rs::DevBuf lo, z, q, p0, p1, partial, agg, incl, fsum, out;
     uint32_t epoch = 0;
     uint64_t p_elems_per_chunk = 0;
     uint32_t flag_tiles = 0, flag_chunks = 0;

@@ -1,126 +1,21 @@
-// Sieve kernels for gfx950.
-//
-// Layout (one query, one 64-iteration chunk):
-//   * Edges are sorted by (dst, t, src); the in-edges of vertex u form the
-//     segment [in_off[u], in_off[u+1]) ordered by time.
-//   * The prefix state P of a level has m + n slots. Slot in_off[u] + u holds 0;
-//     slot e + dst(e) + 1 holds the XOR of the level's values over the edges of
-//     dst(e)'s segment up to and including e. Each slot stores 64 uint64, one
-//     per sieve iteration of the chunk (lane = iteration), 512 contiguous bytes.
-//   * For edge e = (v -> u, t) the restless window of Eq. (poly-enc:1) - the
-//     arrivals at v with time in [t - delta, t] - is P[hi(e)] ^ P[lo(e)], with
-//     hi/lo the slots bounding that time range in v's segment.
-//
-// Level step (Eq. poly-enc:1 with y per edge and position): for level l and
-// iteration L, c_l(e) = z^L_u * y_{e,l-1} * W where W = z^L_v at level 2 and the
-// window sum at level >= 3. The factor z^L_u * y_{e,l-1} equals
-// XOR_{j in L} q_j(e) with q_j(e) = z_{u,j} * y_{e,l-1} precomputed per edge and
-// level; within a wavefront the edge is uniform, so q_j is loaded once per
-// wave and each lane forms its own subset XOR (6 lane bits + chunk bits).
-// One GF(2^64) product remains per edge-update.
-//
-// Prefix levels keep a running XOR per lane along a tile of E consecutive
-// edges; a segment that crosses tiles receives its carry through a decoupled
-// look-back on per-tile flags (cache-bypassing device-scope stores and loads,
-// ordered with s_waitcnt, no L2 writeback fence).
-#include "rs_device.h"
-#include "rs_internal.h"
+// Per-level sieve kernels for gfx950 (the plain path): setup tables, the
+// prefix levels 2..k-1, the last level k and small utilities. The level-step
+// arithmetic and data layout are described in rs_level.h.
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <tuple>
+
+#include "rs_level.h"
 
 namespace rs {
 
 // ---------------------------------------------------------------------------
-// Device-coherent accesses for the look-back state.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ void st_dev64(uint64_t* p, uint64_t v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ uint64_t ld_dev64(uint64_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void st_dev32(uint32_t* p, uint32_t v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ uint32_t ld_dev32(uint32_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-// Orders this wave's earlier memory operations before later ones by waiting
-// for them to complete (vmcnt = 0); no cache writeback or invalidation.
-__device__ __forceinline__ void order_release() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-  __builtin_amdgcn_s_waitcnt(0xF70);
-}
-__device__ __forceinline__ void order_acquire() {
-  __builtin_amdgcn_s_waitcnt(0xF70);
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-}
-
-// Per-lane subset XOR  XOR_{j in L} row[j]  for the iteration L = cb + lane
-// (cb a multiple of 64): bits 0..5 of L come from the lane, higher bits from cb.
-template <int KQ>
-__device__ __forceinline__ uint64_t subset_xor(const uint64_t* __restrict__ row, uint64_t cb,
-                                               const uint32_t (&mk)[6]) {
-  uint64_t h = 0;  // wave-uniform: chunk bits select row entries 6..KQ-1
-#pragma unroll
-  for (int j = 6; j < KQ; ++j) h ^= row[j] & (0ull - ((cb >> j) & 1ull));
-  uint32_t lo = lo32(h), hi = hi32(h);
-#pragma unroll
-  for (int b = 0; b < 6 && b < KQ; ++b) {
-    const uint64_t v = row[b];
-    lo = and_xor(lo32(v), mk[b], lo);
-    hi = and_xor(hi32(v), mk[b], hi);
-  }
-  return mk64(lo, hi);
-}
-
-__device__ __forceinline__ void lane_masks(uint32_t lane, uint32_t (&mk)[6]) {
-#pragma unroll
-  for (int b = 0; b < 6; ++b) mk[b] = ((lane >> b) & 1u) ? 0xFFFFFFFFu : 0u;
-}
-
-__device__ __forceinline__ void publish(uint64_t* __restrict__ vals, uint32_t* __restrict__ flags,
-                                        uint64_t fi, uint32_t lane, uint64_t v, uint32_t state,
-                                        uint32_t epoch) {
-  st_dev64(&vals[fi * kLanes + lane], v);
-  order_release();
-  if (lane == 0) st_dev32(&flags[fi], (epoch << 2) | state);
-}
-
-// XOR of the level values of the segment part preceding tile `tile`.
-__device__ uint64_t look_back(uint32_t tile, uint64_t row0, uint32_t lane, uint32_t epoch,
-                              uint32_t* __restrict__ flags, uint64_t* __restrict__ agg,
-                              uint64_t* __restrict__ incl, uint32_t* __restrict__ err) {
-  uint64_t carry = 0;
-  uint32_t j = tile - 1;
-  uint32_t spins = 0;
-  while (true) {
-    const uint64_t fi = row0 + j;
-    const uint32_t f = uniform(ld_dev32(&flags[fi]));
-    if ((f >> 2) == epoch) {
-      order_acquire();
-      if ((f & 3u) == kFlagIncl) {
-        carry ^= ld_dev64(&incl[fi * kLanes + lane]);
-        break;
-      }
-      carry ^= ld_dev64(&agg[fi * kLanes + lane]);
-      if (j == 0) {  // tile 0 always starts a segment; reaching here is a bug
-        if (lane == 0) atomicOr(err, 2u);
-        break;
-      }
-      --j;
-      spins = 0;
-      continue;
-    }
-    if (++spins > kSpinLimit) {
-      if (lane == 0) atomicOr(err, 1u);
-      break;
-    }
-    __builtin_amdgcn_s_sleep(1);
-  }
-  return carry;
-}
-
-// ---------------------------------------------------------------------------
-// Prefix levels 2..k-1.
+// Prefix levels 2..k-1. The grid holds about as many waves as fit on the GPU;
+// wave w takes tiles w, w + W, w + 2W, ... (W waves in all), so a tile's
+// predecessor is normally being processed by the neighbouring wave in the
+// same round. No atomics: a tile whose predecessor has not published yet
+// waits a bounded time and then recomputes it (see look_back).
 // ---------------------------------------------------------------------------
 template <int KQ, int E, bool FIRST>
 __global__ __launch_bounds__(256) void k_scan(
@@ -129,116 +24,104 @@ __global__ __launch_bounds__(256) void k_scan(
     const uint64_t* __restrict__ q, const uint64_t* __restrict__ z,
     const uint64_t* __restrict__ p_prev, uint64_t* __restrict__ p_cur, uint64_t p_stride,
     uint64_t chunk_base, uint32_t m, uint32_t n_tiles, uint32_t epoch,
-    uint32_t* __restrict__ tile_counter, uint32_t* __restrict__ flags, uint64_t* __restrict__ agg,
-    uint64_t* __restrict__ incl, uint32_t* __restrict__ err) {
-  extern __shared__ uint64_t dyn_lds[];  // [waves][16][64]
+    uint64_t* __restrict__ agg, uint64_t* __restrict__ incl) {
+  extern __shared__ uint64_t dyn_lds[];  // [waves][16][64]; starts at LDS address 0
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t wv = threadIdx.x >> 6;
   uint64_t* tab = dyn_lds + wv * 16 * kLanes + lane;
   tab[0] = 0;
 
   const uint32_t chunk = blockIdx.y;
-  uint32_t tile = 0;
-  if (lane == 0) tile = atomicAdd(&tile_counter[chunk], 1u);
-  tile = uniform(tile);
-  if (tile >= n_tiles) return;
-
-  const uint64_t cb = chunk_base + (uint64_t)chunk * kLanes;
   uint32_t mk[6];
   lane_masks(lane, mk);
-  const uint64_t* __restrict__ pp = p_prev + (uint64_t)chunk * p_stride;
-  uint64_t* __restrict__ pc = p_cur + (uint64_t)chunk * p_stride;
-
-  const uint32_t e0 = tile * (uint32_t)E;
-  const uint32_t ne = min((uint32_t)E, m - e0);
-  const bool cont = e0 > 0 && e_out[e0] == e_out[e0 - 1] + 1u;
-
-  uint64_t pref[E];
-  uint32_t slot[E];
-  uint64_t acc = 0;
-  uint32_t first_len = 0;
-  bool started = !cont;
-  uint32_t last_slot = 0;
-#pragma unroll
-  for (int i = 0; i < E; ++i) {
-    pref[i] = 0;
-    slot[i] = 0;
-    if ((uint32_t)i < ne) {
-      const uint32_t e = e0 + (uint32_t)i;
-      const uint32_t s = e_out[e];
-      if (i > 0 && s != last_slot + 1u) {
-        acc = 0;
-        started = true;
-      }
-      if (!started) first_len = (uint32_t)i + 1u;
-      const uint64_t aL = subset_xor<KQ>(q + (uint64_t)e * KQ, cb, mk);
-      uint64_t w;
-      if (FIRST) {
-        w = subset_xor<KQ>(z + (uint64_t)e_src[e] * KQ, cb, mk);
-      } else {
-        w = pp[(uint64_t)hi_idx[e] * kLanes + lane] ^ pp[(uint64_t)lo_idx[e] * kLanes + lane];
-      }
-      acc ^= gf_mul(tab, aL, w);
-      pref[i] = acc;
-      slot[i] = s;
-      last_slot = s;
-    }
-  }
-
-  const uint32_t e_end = e0 + ne;
-  const bool next_cont = e_end < m && e_out[e_end] == last_slot + 1u;
-  const uint64_t row0 = (uint64_t)chunk * n_tiles;
-  const uint64_t fi = row0 + tile;
-  if (next_cont) publish(started ? incl : agg, flags, fi, lane, acc, started ? kFlagIncl : kFlagAgg, epoch);
-  uint64_t carry = 0;
-  if (cont) {
-    carry = look_back(tile, row0, lane, epoch, flags, agg, incl, err);
-    if (next_cont && !started) publish(incl, flags, fi, lane, carry ^ acc, kFlagIncl, epoch);
-  }
-#pragma unroll
-  for (int i = 0; i < E; ++i)
-    if ((uint32_t)i < ne) pc[(uint64_t)slot[i] * kLanes + lane] = pref[i] ^ ((uint32_t)i < first_len ? carry : 0);
+  TileCtx c;
+  c.e_src = e_src;
+  c.e_out = e_out;
+  c.hi = hi_idx;
+  c.lo = lo_idx;
+  c.q = q;
+  c.z = z;
+  c.pp = p_prev + (uint64_t)chunk * p_stride;
+  c.pc = p_cur + (uint64_t)chunk * p_stride;
+  c.cb = chunk_base + (uint64_t)chunk * kLanes;
+  c.m = m;
+  c.n_tiles = n_tiles;
+  c.epoch = epoch;
+  c.row0 = (uint64_t)chunk * n_tiles;
+  c.agg = agg;
+  c.incl = incl;
+  const uint32_t waves = gridDim.x * (blockDim.x >> 6);
+  scan_tiles<KQ, E, FIRST, false>(c, blockIdx.x * (blockDim.x >> 6) + wv, waves, lane, mk, tab);
 }
 
 // ---------------------------------------------------------------------------
-// Last level k: per-lane XOR of all edge values, one atomic per lane per wave.
+// Last level k: grid-stride over edge ranges, per-lane sums XORed across the
+// block in LDS, one partial row per block (no contended atomics); k_top_fold
+// folds the rows into the per-iteration sums.
 // ---------------------------------------------------------------------------
 template <int KQ, bool FIRST>
 __global__ __launch_bounds__(256) void k_top(
     const uint32_t* __restrict__ e_src, const uint32_t* __restrict__ hi_idx,
     const uint32_t* __restrict__ lo_idx, const uint64_t* __restrict__ q,
     const uint64_t* __restrict__ z, const uint64_t* __restrict__ p_prev, uint64_t p_stride,
-    uint64_t chunk_base, uint64_t it_begin, uint64_t it_end, uint32_t m, uint32_t edges_per_wave,
-    uint64_t* __restrict__ fsum) {
-  extern __shared__ uint64_t dyn_lds[];  // [waves][16][64]
+    uint64_t chunk_base, uint32_t m, uint32_t edges_per_wave, uint64_t* __restrict__ partial) {
+  extern __shared__ uint64_t dyn_lds[];  // [waves][16][64]; starts at LDS address 0
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t wv = threadIdx.x >> 6;
+  const uint32_t nw = blockDim.x >> 6;
   uint64_t* tab = dyn_lds + wv * 16 * kLanes + lane;
   tab[0] = 0;
   const uint32_t chunk = blockIdx.y;
-  const uint64_t wave_id = (uint64_t)blockIdx.x * (blockDim.x >> 6) + wv;
-  const uint64_t e0 = wave_id * edges_per_wave;
-  if (e0 >= m) return;
-  const uint32_t e1 = (uint32_t)min((uint64_t)m, e0 + edges_per_wave);
   const uint64_t cb = chunk_base + (uint64_t)chunk * kLanes;
   uint32_t mk[6];
   lane_masks(lane, mk);
-  const uint64_t* __restrict__ pp = p_prev + (uint64_t)chunk * p_stride;
+  const uint64_t waves = (uint64_t)gridDim.x * nw;
   Acc128 r = {0, 0, 0, 0};
-  for (uint32_t e = (uint32_t)e0; e < e1; ++e) {
-    const uint64_t aL = subset_xor<KQ>(q + (uint64_t)e * KQ, cb, mk);
-    uint64_t w;
-    if (FIRST) {
-      w = subset_xor<KQ>(z + (uint64_t)e_src[e] * KQ, cb, mk);
-    } else {
-      w = pp[(uint64_t)hi_idx[e] * kLanes + lane] ^ pp[(uint64_t)lo_idx[e] * kLanes + lane];
-    }
-    gf_table(tab, w);
-    gf_comb_acc(lds_addr(tab), aL, r);
+  for (uint64_t wave_id = (uint64_t)blockIdx.x * nw + wv; wave_id * edges_per_wave < m; wave_id += waves) {
+    const uint64_t e0 = wave_id * edges_per_wave;
+    const uint32_t e1 = (uint32_t)min((uint64_t)m, e0 + edges_per_wave);
+    top_range<KQ, FIRST, false>(e_src, hi_idx, lo_idx, q, z, p_prev + (uint64_t)chunk * p_stride, cb,
+                                (uint32_t)e0, e1, lane, mk, tab, r);
   }
   const uint64_t f = gf_reduce(r);
-  const uint64_t it = cb + lane;
-  if (it >= it_begin && it < it_end && f) atomicXor((unsigned long long*)&fsum[it], (unsigned long long)f);
+  // XOR the block's waves through LDS entry T[1] of each wave's table.
+  __syncthreads();
+  tab[kLanes] = f;
+  __syncthreads();
+  if (wv == 0) {
+    uint64_t s = 0;
+    for (uint32_t k2 = 0; k2 < nw; ++k2) s ^= dyn_lds[k2 * 16 * kLanes + kLanes + lane];
+    partial[((uint64_t)chunk * gridDim.x + blockIdx.x) * kLanes + lane] = s;
+  }
+}
+
+// fsum[cb + lane] = XOR over blocks of partial[chunk][block][lane], for the
+// iterations of [it_begin, it_end). One block of 1024 threads per chunk: 16
+// groups of 64 lanes stride over the rows with four independent loads in
+// flight each, then the groups are XORed in LDS.
+__global__ __launch_bounds__(1024) void k_top_fold(const uint64_t* __restrict__ partial, uint32_t blocks,
+                                                   uint64_t chunk_base, uint64_t it_begin, uint64_t it_end,
+                                                   uint64_t* __restrict__ fsum) {
+  __shared__ uint64_t part[16][kLanes];
+  const uint32_t chunk = blockIdx.x, lane = threadIdx.x & 63u, grp = threadIdx.x >> 6;
+  const uint64_t* rows = partial + (uint64_t)chunk * blocks * kLanes + lane;
+  uint64_t s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+  uint32_t b = grp;
+  for (; b + 48 < blocks; b += 64) {
+    s0 ^= rows[(uint64_t)b * kLanes];
+    s1 ^= rows[(uint64_t)(b + 16) * kLanes];
+    s2 ^= rows[(uint64_t)(b + 32) * kLanes];
+    s3 ^= rows[(uint64_t)(b + 48) * kLanes];
+  }
+  for (; b < blocks; b += 16) s0 ^= rows[(uint64_t)b * kLanes];
+  part[grp][lane] = s0 ^ s1 ^ s2 ^ s3;
+  __syncthreads();
+  if (grp == 0) {
+    uint64_t s = 0;
+    for (uint32_t g = 0; g < 16; ++g) s ^= part[g][lane];
+    const uint64_t it = chunk_base + (uint64_t)chunk * kLanes + lane;
+    if (it >= it_begin && it < it_end) fsum[it] = s;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -361,6 +244,25 @@ __global__ __launch_bounds__(1024) void k_xor_reduce(const uint64_t* __restrict_
 // ---------------------------------------------------------------------------
 static inline uint32_t div_up(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
 
+// Blocks of `kern` that fit on the whole GPU at once (cached per kernel and
+// block shape).
+static uint32_t resident_blocks(const void* kern, uint32_t threads, size_t lds) {
+  static std::mutex mu;
+  static std::map<std::tuple<const void*, uint32_t, size_t>, uint32_t> cache;
+  std::lock_guard<std::mutex> lk(mu);
+  auto key = std::make_tuple(kern, threads, lds);
+  auto it = cache.find(key);
+  if (it != cache.end()) return it->second;
+  int dev = 0, cus = 0, per_cu = 0;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, (int)threads, lds) != hipSuccess || per_cu < 1)
+    per_cu = 1;
+  const uint32_t v = (uint32_t)std::max(cus, 1) * (uint32_t)per_cu;
+  cache[key] = v;
+  return v;
+}
+
 hipError_t launch_ztable(uint64_t* z, uint32_t n, const QueryPlan& qp, const uint8_t* colour_d,
                          hipStream_t st) {
   ShadeTable sh;
@@ -399,10 +301,12 @@ hipError_t launch_qtable(const uint32_t* e_src, const uint32_t* e_dst, const uin
 
 template <int KQ, int E, bool FIRST>
 static void scan_one(const ScanArgs& a, uint32_t chunks, uint32_t wpb, hipStream_t st) {
-  dim3 g(div_up(a.n_tiles, wpb), chunks), b(64 * wpb);
-  hipLaunchKernelGGL((k_scan<KQ, E, FIRST>), g, b, wpb * 16 * kLanes * 8, st, a.e_src, a.e_out, a.hi, a.lo, a.q, a.z,
-                     a.p_prev, a.p_cur, a.p_stride, a.chunk_base, a.m, a.n_tiles, a.epoch,
-                     a.tile_counter, a.flags, a.agg, a.incl, a.err);
+  const size_t lds = (size_t)wpb * 16 * kLanes * 8;
+  const uint32_t fit = std::max(1u, resident_blocks((const void*)k_scan<KQ, E, FIRST>, 64 * wpb, lds) / chunks);
+  dim3 g(std::min(div_up(a.n_tiles, wpb), fit), chunks), b(64 * wpb);
+  hipLaunchKernelGGL((k_scan<KQ, E, FIRST>), g, b, lds, st, a.e_src, a.e_out, a.hi, a.lo, a.q, a.z,
+                     a.p_prev, a.p_cur, a.p_stride, a.chunk_base, a.m, a.n_tiles, a.epoch, a.agg,
+                     a.incl);
 }
 
 template <int KQ>
@@ -433,29 +337,53 @@ hipError_t launch_scan(const ScanArgs& a, bool first_level, uint32_t kq, uint32_
   return hipGetLastError();
 }
 
+// Blocks of the last-level launch (also the number of partial rows per chunk).
 template <int KQ>
-static void top_kq(const TopArgs& a, bool first, uint32_t chunks, uint32_t wpb, hipStream_t st) {
+static uint32_t top_blocks_kq(const TopArgs& a, bool first, uint32_t chunks, uint32_t wpb) {
   const uint32_t waves = div_up(a.m, a.edges_per_wave);
-  dim3 g(div_up(waves, wpb), chunks), b(64 * wpb);
+  const size_t lds = (size_t)wpb * 16 * kLanes * 8;
+  const void* kern = first ? (const void*)k_top<KQ, true> : (const void*)k_top<KQ, false>;
+  const uint32_t fit = std::max(1u, resident_blocks(kern, 64 * wpb, lds) / chunks);
+  return std::min(div_up(waves, wpb), fit);
+}
+
+template <int KQ>
+static void top_kq(const TopArgs& a, bool first, uint32_t chunks, uint32_t wpb, uint32_t blocks, hipStream_t st) {
+  const size_t lds = (size_t)wpb * 16 * kLanes * 8;
+  dim3 g(blocks, chunks), b(64 * wpb);
   if (first)
-    hipLaunchKernelGGL((k_top<KQ, true>), g, b, wpb * 16 * kLanes * 8, st, a.e_src, a.hi, a.lo, a.q, a.z, a.p_prev,
-                       a.p_stride, a.chunk_base, a.it_begin, a.it_end, a.m, a.edges_per_wave, a.fsum);
+    hipLaunchKernelGGL((k_top<KQ, true>), g, b, lds, st, a.e_src, a.hi, a.lo, a.q, a.z, a.p_prev,
+                       a.p_stride, a.chunk_base, a.m, a.edges_per_wave, a.partial);
   else
-    hipLaunchKernelGGL((k_top<KQ, false>), g, b, wpb * 16 * kLanes * 8, st, a.e_src, a.hi, a.lo, a.q, a.z, a.p_prev,
-                       a.p_stride, a.chunk_base, a.it_begin, a.it_end, a.m, a.edges_per_wave, a.fsum);
+    hipLaunchKernelGGL((k_top<KQ, false>), g, b, lds, st, a.e_src, a.hi, a.lo, a.q, a.z, a.p_prev,
+                       a.p_stride, a.chunk_base, a.m, a.edges_per_wave, a.partial);
+}
+
+uint32_t top_blocks(const TopArgs& a, bool first, uint32_t kq, uint32_t chunks, const Tuning& tu) {
+  switch (kq) {
+    case 4: return top_blocks_kq<4>(a, first, chunks, tu.waves_per_block);
+    case 8: return top_blocks_kq<8>(a, first, chunks, tu.waves_per_block);
+    case 12: return top_blocks_kq<12>(a, first, chunks, tu.waves_per_block);
+    default: return top_blocks_kq<16>(a, first, chunks, tu.waves_per_block);
+  }
 }
 
 hipError_t launch_top(const TopArgs& a, bool first_level, uint32_t kq, uint32_t chunks,
                       const Tuning& tu, hipStream_t st) {
   if (!a.m) return hipSuccess;
   const uint32_t wpb = tu.waves_per_block;
+  const uint32_t blocks = top_blocks(a, first_level, kq, chunks, tu);
   switch (kq) {
-    case 4: top_kq<4>(a, first_level, chunks, wpb, st); break;
-    case 8: top_kq<8>(a, first_level, chunks, wpb, st); break;
-    case 12: top_kq<12>(a, first_level, chunks, wpb, st); break;
-    case 16: top_kq<16>(a, first_level, chunks, wpb, st); break;
+    case 4: top_kq<4>(a, first_level, chunks, wpb, blocks, st); break;
+    case 8: top_kq<8>(a, first_level, chunks, wpb, blocks, st); break;
+    case 12: top_kq<12>(a, first_level, chunks, wpb, blocks, st); break;
+    case 16: top_kq<16>(a, first_level, chunks, wpb, blocks, st); break;
     default: return hipErrorInvalidValue;
   }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_top_fold, dim3(chunks), dim3(1024), 0, st, a.partial, blocks, a.chunk_base, a.it_begin,
+                     a.it_end, a.fsum);
   return hipGetLastError();
 }
 

@@ -1,0 +1,402 @@
+// Level-step device code shared by the per-level kernels and the persistent
+// batch kernel.
+//
+// Layout (one query, one 64-iteration chunk):
+//   * Edges are sorted by (dst, t, src); the in-edges of vertex u form the
+//     segment [in_off[u], in_off[u+1]) ordered by time.
+//   * The prefix state P of a level has m + n slots. Slot in_off[u] + u holds 0;
+//     slot e + dst(e) + 1 holds the XOR of the level's values over the edges of
+//     dst(e)'s segment up to and including e. Each slot stores 64 uint64, one
+//     per sieve iteration of the chunk (lane = iteration), 512 contiguous bytes.
+//   * For edge e = (v -> u, t) the restless window of Eq. (poly-enc:1) - the
+//     arrivals at v with time in [t - delta, t] - is P[hi(e)] ^ P[lo(e)], with
+//     hi/lo the slots bounding that time range in v's segment.
+//
+// Level step (Eq. poly-enc:1 with y per edge and position): for level l and
+// iteration L, c_l(e) = z^L_u * y_{e,l-1} * W where W = z^L_v at level 2 and the
+// window sum at level >= 3. The factor z^L_u * y_{e,l-1} equals
+// XOR_{j in L} q_j(e) with q_j(e) = z_{u,j} * y_{e,l-1} precomputed per edge and
+// level; within a wavefront the edge is uniform, so the q row is one scalar
+// load and each lane forms its own subset XOR (6 lane bits + chunk bits).
+// One GF(2^64) product remains per edge-update.
+//
+// Prefix levels keep a running XOR per lane along a tile of E consecutive
+// edges; a segment that crosses tiles receives its carry through a decoupled
+// look-back on self-validating per-tile records (device-scope atomic stores
+// and loads that bypass the per-XCD L2; no fences, no atomic read-modify-write).
+#pragma once
+
+#include "rs_device.h"
+#include "rs_internal.h"
+
+namespace rs {
+
+// Read-only per-edge and per-vertex arrays are read through the constant
+// address space so that wave-uniform accesses become scalar loads.
+typedef __attribute__((address_space(4))) const uint64_t cu64;
+typedef __attribute__((address_space(4))) const uint32_t cu32;
+__device__ __forceinline__ cu64* as_const(const uint64_t* p) { return (cu64*)p; }
+__device__ __forceinline__ cu32* as_const(const uint32_t* p) { return (cu32*)p; }
+
+// ---------------------------------------------------------------------------
+// Device-coherent accesses (bypass the per-XCD L2's non-coherent caching).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void st_dev64(uint64_t* p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t ld_dev64(const uint64_t* p) {
+  return __hip_atomic_load(const_cast<uint64_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_dev32(uint32_t* p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t ld_dev32(const uint32_t* p) {
+  return __hip_atomic_load(const_cast<uint32_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// Orders this wave's earlier memory operations before later ones by waiting
+// for them to complete (vmcnt = 0); no cache writeback or invalidation.
+__device__ __forceinline__ void order_release() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_s_waitcnt(0xF70);
+}
+__device__ __forceinline__ void order_acquire() {
+  __builtin_amdgcn_s_waitcnt(0xF70);
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// P-state accesses: plain (kernel boundaries order levels) or device-coherent
+// (levels ordered inside one persistent kernel).
+template <bool COHERENT>
+__device__ __forceinline__ uint64_t p_load(const uint64_t* p) {
+  if (COHERENT) return ld_dev64(p);
+  return *p;
+}
+template <bool COHERENT>
+__device__ __forceinline__ void p_store(uint64_t* p, uint64_t v) {
+  if (COHERENT)
+    st_dev64(p, v);
+  else
+    *p = v;
+}
+
+// Per-lane subset XOR  XOR_{j in L} row[j]  for the iteration L = cb + lane
+// (cb a multiple of 64): bits 0..5 of L come from the lane, higher bits from cb.
+template <int KQ>
+__device__ __forceinline__ uint64_t subset_xor(cu64* row, uint64_t cb, const uint32_t (&mk)[6]) {
+  uint64_t h = 0;  // wave-uniform: chunk bits select row entries 6..KQ-1
+#pragma unroll
+  for (int j = 6; j < KQ; ++j) h ^= row[j] & (0ull - ((cb >> j) & 1ull));
+  uint32_t lo = lo32(h), hi = hi32(h);
+#pragma unroll
+  for (int b = 0; b < 6 && b < KQ; ++b) {
+    const uint64_t v = row[b];
+    lo = and_xor(lo32(v), mk[b], lo);
+    hi = and_xor(hi32(v), mk[b], hi);
+  }
+  return mk64(lo, hi);
+}
+
+__device__ __forceinline__ void lane_masks(uint32_t lane, uint32_t (&mk)[6]) {
+#pragma unroll
+  for (int b = 0; b < 6; ++b) mk[b] = ((lane >> b) & 1u) ? 0xFFFFFFFFu : 0u;
+}
+
+// Look-back records. A tile publishes, per lane, two 64-bit words each holding
+// 32 bits of its 64-bit value and a 32-bit tag (epoch << 2 | state), written
+// with device-scope atomic stores. A reader accepts a record only when both
+// of its lane's words carry the expected tag, so no fence or separate flag
+// is needed and publishing never waits.
+__device__ __forceinline__ uint32_t rec_tag(uint32_t epoch, uint32_t state) { return (epoch << 2) | state; }
+
+__device__ __forceinline__ void publish(uint64_t* rec, uint64_t fi, uint32_t lane, uint64_t v, uint32_t tag) {
+  uint64_t* p = rec + (fi * kLanes + lane) * 2;
+  st_dev64(p, (uint64_t)lo32(v) | ((uint64_t)tag << 32));
+  st_dev64(p + 1, (uint64_t)hi32(v) | ((uint64_t)tag << 32));
+}
+
+// Lane's value of record fi if both words carry `tag`.
+__device__ __forceinline__ bool read_rec(const uint64_t* rec, uint64_t fi, uint32_t lane, uint32_t tag,
+                                         uint64_t* v) {
+  const uint64_t* p = rec + (fi * kLanes + lane) * 2;
+  const uint64_t w0 = ld_dev64(p), w1 = ld_dev64(p + 1);
+  *v = mk64(lo32(w0), lo32(w1));
+  return hi32(w0) == tag && hi32(w1) == tag;
+}
+
+// Everything one prefix-level tile needs; all fields wave-uniform.
+struct TileCtx {
+  const uint32_t* e_src;
+  const uint32_t* e_out;
+  const uint32_t* hi;
+  const uint32_t* lo;
+  const uint64_t* q;   // this level's [m][KQ] rows
+  const uint64_t* z;   // [n][KQ] rows (level 2)
+  const uint64_t* pp;  // previous level, this chunk
+  uint64_t* pc;        // this level, this chunk
+  uint64_t cb;         // first iteration of the chunk
+  uint32_t m;
+  uint32_t n_tiles;
+  uint32_t epoch;
+  uint64_t row0;       // record row of this (chunk, level)
+  uint64_t* agg;       // [tiles][64][2] records: XOR of the tile's open segment part
+  uint64_t* incl;      // [tiles][64][2] records: inclusive prefix of that segment
+};
+
+// Loads the tile's indices (scalar) and issues all of its window gathers at
+// once. Slots past the tile end read edge e0 so every load stays in bounds.
+template <int KQ, int E, bool FIRST, bool COHERENT>
+__device__ __forceinline__ void tile_inputs(const TileCtx& c, uint32_t e0, uint32_t ne, uint32_t lane,
+                                            uint32_t (&slot)[E], uint32_t (&ia)[E], uint64_t (&w)[E]) {
+  cu32* e_out = as_const(c.e_out);
+  cu32* hi_idx = as_const(c.hi);
+  cu32* lo_idx = as_const(c.lo);
+  cu32* e_src = as_const(c.e_src);
+  uint32_t ib[E];
+#pragma unroll
+  for (int i = 0; i < E; ++i) {
+    const uint32_t e = (uint32_t)i < ne ? e0 + (uint32_t)i : e0;
+    slot[i] = e_out[e];
+    if (FIRST) {
+      ia[i] = e_src[e];
+      ib[i] = 0;
+    } else {
+      ia[i] = hi_idx[e];
+      ib[i] = lo_idx[e];
+    }
+  }
+  if (!FIRST) {
+#pragma unroll
+    for (int i = 0; i < E; ++i)
+      w[i] = p_load<COHERENT>(c.pp + (uint64_t)ia[i] * kLanes + lane) ^
+             p_load<COHERENT>(c.pp + (uint64_t)ib[i] * kLanes + lane);
+  }
+}
+
+// c_l(e) for edge i of the tile.
+template <int KQ, int E, bool FIRST>
+__device__ __forceinline__ uint64_t edge_value(const TileCtx& c, uint32_t e, uint32_t a, uint64_t w,
+                                               const uint32_t (&mk)[6], uint64_t* tab) {
+  const uint64_t aL = subset_xor<KQ>(as_const(c.q) + (uint64_t)e * KQ, c.cb, mk);
+  const uint64_t wv = FIRST ? subset_xor<KQ>(as_const(c.z) + (uint64_t)a * KQ, c.cb, mk) : w;
+  return gf_mul(tab, aL, wv);
+}
+
+// What tile j publishes, recomputed by a waiting successor: the XOR of the
+// level values over the tile's open segment part (from the last segment start
+// inside the tile, else from the tile start). *started tells whether a
+// segment starts inside the tile, i.e. whether the value is inclusive. A
+// rarely taken path, written edge by edge to keep register use low.
+template <int KQ, int E, bool FIRST, bool COHERENT>
+__device__ uint64_t tile_open_part(const TileCtx& c, uint32_t j, uint32_t lane, const uint32_t (&mk)[6],
+                                   uint64_t* tab, bool* started) {
+  cu32* e_out = as_const(c.e_out);
+  cu32* hi_idx = as_const(c.hi);
+  cu32* lo_idx = as_const(c.lo);
+  cu32* e_src = as_const(c.e_src);
+  const uint32_t e0 = j * (uint32_t)E;
+  const uint32_t e1 = min(e0 + (uint32_t)E, c.m);
+  bool st = !(e0 > 0 && e_out[e0] == e_out[e0 - 1] + 1u);
+  uint64_t acc = 0;
+#pragma unroll 1
+  for (uint32_t e = e0; e < e1; ++e) {
+    if (e > e0 && e_out[e] != e_out[e - 1] + 1u) {
+      acc = 0;
+      st = true;
+    }
+    const uint64_t w = FIRST ? 0
+                             : p_load<COHERENT>(c.pp + (uint64_t)hi_idx[e] * kLanes + lane) ^
+                                   p_load<COHERENT>(c.pp + (uint64_t)lo_idx[e] * kLanes + lane);
+    acc ^= edge_value<KQ, E, FIRST>(c, e, FIRST ? e_src[e] : 0u, w, mk, tab);
+  }
+  *started = st;
+  return acc;
+}
+
+// Spins (each a flag round trip plus a short sleep) before a waiting tile
+// stops relying on its predecessor and recomputes that tile's part itself.
+constexpr uint32_t kFallbackSpins = 256;
+
+// XOR of the level values of the segment part preceding tile `tile`. Each
+// round probes the 64 predecessor tiles tile-1-lane at once (lane l reads the
+// tags of tile top-l's lane-0 words), then absorbs the leading run of
+// published tiles up to and including the nearest one that published its
+// inclusive prefix, every lane validating its own record words; a carry that
+// has to cross d tiles costs about d/64 memory round trips. A predecessor
+// that stays unpublished is recomputed here, so every wait is bounded
+// whatever order the tiles run in.
+template <int KQ, int E, bool FIRST, bool COHERENT>
+__device__ uint64_t look_back(const TileCtx& c, uint32_t tile, uint32_t lane, const uint32_t (&mk)[6],
+                              uint64_t* tab) {
+  uint64_t carry = 0;
+  int64_t top = (int64_t)tile - 1;  // nearest tile not absorbed yet
+  uint32_t spins = 0;
+  const uint32_t t_agg = rec_tag(c.epoch, kFlagAgg), t_inc = rec_tag(c.epoch, kFlagIncl);
+  while (top >= 0) {
+    const int64_t j = top - (int64_t)lane;
+    bool ready = false, inc = false;
+    if (j >= 0) {
+      const uint64_t fi = c.row0 + (uint64_t)j;
+      inc = hi32(ld_dev64(c.incl + fi * kLanes * 2)) == t_inc;
+      ready = inc || hi32(ld_dev64(c.agg + fi * kLanes * 2)) == t_agg;
+    }
+    const uint64_t ready_mask = __ballot(ready);
+    const uint64_t inc_mask = __ballot(inc);
+    const uint32_t lead = ready_mask == ~0ull ? 64u : (uint32_t)__builtin_ctzll(~ready_mask);
+    const uint32_t first_inc = inc_mask ? (uint32_t)__builtin_ctzll(inc_mask) : 64u;
+    const bool ends = first_inc < lead;
+    const uint32_t take = ends ? first_inc + 1 : lead;
+    if (take > 0) {
+      uint64_t part = 0;
+      bool ok = true;
+      // 4 records per step, all loads of a step in flight together
+      for (uint32_t i0 = 0; i0 < take; i0 += 4) {
+#pragma unroll
+        for (uint32_t d = 0; d < 4; ++d) {
+          const uint32_t i = i0 + d;
+          if (i < take) {
+            const bool use_inc = ends && i == first_inc;
+            uint64_t v;
+            ok &= read_rec(use_inc ? c.incl : c.agg, c.row0 + (uint64_t)(top - i), lane,
+                           use_inc ? t_inc : t_agg, &v);
+            part ^= v;
+          }
+        }
+      }
+      if (__ballot(!ok) == 0) {  // every lane's words were complete
+        carry ^= part;
+        if (ends) break;
+        top -= take;
+        spins = 0;
+        continue;
+      }
+    }
+    if (++spins > kFallbackSpins) {
+      bool started = false;
+      carry ^= tile_open_part<KQ, E, FIRST, COHERENT>(c, (uint32_t)top, lane, mk, tab, &started);
+      if (started) break;
+      --top;
+      spins = 0;
+      continue;
+    }
+    __builtin_amdgcn_s_sleep(2);
+  }
+  return carry;
+}
+
+// Inputs of one tile: indices and window sums, loaded ahead of its compute.
+template <int E>
+struct TileIn {
+  uint32_t slot[E], ia[E];
+  uint64_t w[E];
+};
+
+template <int KQ, int E, bool FIRST, bool COHERENT>
+__device__ __forceinline__ void load_tile(const TileCtx& c, uint32_t tile, uint32_t lane, TileIn<E>& in) {
+  const uint32_t e0 = tile * (uint32_t)E;
+  const uint32_t ne = min((uint32_t)E, c.m - e0);
+  tile_inputs<KQ, E, FIRST, COHERENT>(c, e0, ne, lane, in.slot, in.ia, in.w);
+}
+
+// One tile of E edges of a prefix level (2..k-1), inputs already loaded.
+template <int KQ, int E, bool FIRST, bool COHERENT>
+__device__ __forceinline__ void scan_tile(const TileCtx& c, uint32_t tile, const TileIn<E>& in,
+                                          uint32_t lane, const uint32_t (&mk)[6], uint64_t* tab) {
+  cu32* e_out = as_const(c.e_out);
+  const uint32_t m = c.m;
+  const uint32_t e0 = tile * (uint32_t)E;
+  const uint32_t ne = min((uint32_t)E, m - e0);
+  const bool cont = e0 > 0 && e_out[e0] == e_out[e0 - 1] + 1u;
+
+  uint64_t pref[E];
+  uint64_t acc = 0;
+  uint32_t first_len = 0;
+  bool started = !cont;
+  uint32_t last_slot = 0;
+#pragma unroll
+  for (int i = 0; i < E; ++i) {
+    pref[i] = 0;
+    if ((uint32_t)i < ne) {
+      if (i > 0 && in.slot[i] != last_slot + 1u) {
+        acc = 0;
+        started = true;
+      }
+      if (!started) first_len = (uint32_t)i + 1u;
+      acc ^= edge_value<KQ, E, FIRST>(c, e0 + (uint32_t)i, in.ia[i], in.w[i], mk, tab);
+      pref[i] = acc;
+      last_slot = in.slot[i];
+    }
+  }
+
+  const uint32_t e_end = e0 + ne;
+  const bool next_cont = e_end < m && e_out[e_end] == last_slot + 1u;
+  const uint64_t fi = c.row0 + tile;
+  if (next_cont)
+    publish(started ? c.incl : c.agg, fi, lane, acc, rec_tag(c.epoch, started ? kFlagIncl : kFlagAgg));
+  uint64_t carry = 0;
+  if (cont) {
+    carry = look_back<KQ, E, FIRST, COHERENT>(c, tile, lane, mk, tab);
+    if (next_cont && !started) publish(c.incl, fi, lane, carry ^ acc, rec_tag(c.epoch, kFlagIncl));
+  }
+#pragma unroll
+  for (int i = 0; i < E; ++i)
+    if ((uint32_t)i < ne)
+      p_store<COHERENT>(c.pc + (uint64_t)in.slot[i] * kLanes + lane, pref[i] ^ ((uint32_t)i < first_len ? carry : 0));
+}
+
+// Tiles first, first + stride, ... below n_tiles. (Loading the next tile's
+// inputs during this tile's compute was measured slower: the extra live
+// registers cost more occupancy than the overlap gains.)
+template <int KQ, int E, bool FIRST, bool COHERENT>
+__device__ __forceinline__ void scan_tiles(const TileCtx& c, uint32_t first, uint32_t stride, uint32_t lane,
+                                           const uint32_t (&mk)[6], uint64_t* tab) {
+  for (uint32_t tile = first; tile < c.n_tiles; tile += stride) {
+    TileIn<E> in;
+    load_tile<KQ, E, FIRST, COHERENT>(c, tile, lane, in);
+    scan_tile<KQ, E, FIRST, COHERENT>(c, tile, in, lane, mk, tab);
+  }
+}
+
+// Last level k over edges [e0, e1): unreduced per-lane sum of c_k(e) into r.
+template <int KQ, bool FIRST, bool COHERENT>
+__device__ __forceinline__ void top_range(const uint32_t* e_src_p, const uint32_t* hi_p,
+                                          const uint32_t* lo_p, const uint64_t* q_p,
+                                          const uint64_t* z_p, const uint64_t* pp, uint64_t cb,
+                                          uint32_t e0, uint32_t e1, uint32_t lane,
+                                          const uint32_t (&mk)[6], uint64_t* tab, Acc128& r) {
+  cu32* e_src = as_const(e_src_p);
+  cu32* hi_idx = as_const(hi_p);
+  cu32* lo_idx = as_const(lo_p);
+  cu64* q = as_const(q_p);
+  cu64* z = as_const(z_p);
+  const uint32_t base = lds_addr(tab);
+  constexpr int B = 8;  // edges per batch; the next batch's gathers fly during this one
+  uint64_t w[B], wn[B];
+  auto gather = [&](uint32_t eb, uint64_t(&dst)[B]) {
+    if (!FIRST) {
+#pragma unroll
+      for (int i = 0; i < B; ++i) {
+        const uint32_t e = eb + (uint32_t)i < e1 ? eb + (uint32_t)i : eb;
+        dst[i] = p_load<COHERENT>(pp + (uint64_t)hi_idx[e] * kLanes + lane) ^
+                 p_load<COHERENT>(pp + (uint64_t)lo_idx[e] * kLanes + lane);
+      }
+    }
+  };
+  if (e0 < e1) gather(e0, w);
+  for (uint32_t eb = e0; eb < e1; eb += B) {
+    if (eb + B < e1) gather(eb + B, wn);
+#pragma unroll
+    for (int i = 0; i < B; ++i) {
+      const uint32_t e = eb + (uint32_t)i;
+      if (e < e1) {
+        const uint64_t aL = subset_xor<KQ>(q + (uint64_t)e * KQ, cb, mk);
+        const uint64_t wv = FIRST ? subset_xor<KQ>(z + (uint64_t)e_src[e] * KQ, cb, mk) : w[i];
+        gf_table(tab, wv);
+        gf_comb_acc(base, aL, r);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < B; ++i) w[i] = wn[i];
+  }
+}
+
+}  // namespace rs
