@@ -145,9 +145,16 @@ typedef struct {
 /* Launch-shape knobs; zero fields mean "choose automatically". */
 typedef struct {
   uint32_t edges_per_tile;     /* edges per wavefront tile in the scan levels: 8 or 16 */
-  uint32_t top_edges_per_tile; /* edges per wavefront in the last level: 16..256 */
-  uint32_t chunks_per_launch;  /* 64-iteration chunks processed per launch */
+  uint32_t top_edges_per_tile; /* edges per wavefront in the last level: 1..4096 */
+  uint32_t chunks_per_launch;  /* plain path: 64-iteration chunks per launch
+                                  (the batched path ignores it) */
   uint32_t waves_per_block;    /* 1, 2 or 4 */
+  uint32_t max_slots;          /* batched path: at most this many chunks
+                                  resident per round; 0 = as many as the
+                                  HBM budget allows */
+  uint32_t no_graph;           /* batched path: 1 = enqueue the launches
+                                  directly instead of replaying a captured
+                                  hipGraph */
 } rs_tuning;
 
 /* HBM bytes rs_run needs for this query on this graph beyond the graph
@@ -171,13 +178,17 @@ rs_status rs_run_ex(const rs_graph* g, const rs_query* q, const rs_tuning* tune,
                     uint64_t* per_iteration, rs_result* r, void* hip_stream);
 
 /* Batched path: nq queries, each on its own graph (graphs[i]; graphs may
- * repeat), evaluated by one persistent kernel that pulls work items
- * (query, 64-iteration chunk, level, edge tile) from a device queue. The
- * per-query setup kernels and the persistent kernel are captured once into a
- * hipGraph and replayed. results[i].status holds each query's status; the
- * call returns the first error, or RS_OK. tune == NULL uses the tuning found
- * by rs_autotune for the first graph (or a default). Results are bit-identical
- * to rs_run. */
+ * repeat), evaluated together. Every (query, 64-iteration chunk) is a unit
+ * with its own prefix-state buffers; units are packed into rounds that fit
+ * the HBM budget (a third of free device memory, or max_slots units), and a
+ * round runs level l of all its units in shared launches (one per product-row
+ * width), each walking a device table of unit descriptors. The launch
+ * sequence is captured once per batch shape into a hipGraph and replayed with
+ * new descriptors (tune->no_graph = 1 enqueues it directly).
+ * results[i].status holds each query's status (RS_EINVAL for an invalid
+ * query, which is skipped); the call returns the first error, or RS_OK.
+ * tune == NULL uses the shape rs_autotune chose for graphs[0] (or a default).
+ * Results are bit-identical to rs_run. Calls are serialised internally. */
 rs_status rs_run_batch(const rs_graph* const* graphs, const rs_query* queries, uint32_t nq,
                        rs_result* results, const rs_tuning* tune, void* hip_stream);
 
@@ -189,8 +200,8 @@ rs_status rs_autotune(const rs_graph* g, const rs_query* sample, uint32_t ns, rs
 /* ------------------------------------------------------------------------
  * Kernel timing (hipEvents recorded around the launches of each kernel
  * class on the launch stream while enabled). Classes: "level_scan" (prefix
- * levels 2..k-1), "level_top" (level k), "qtable", "ztable", "window",
- * "persistent".
+ * levels 2..k-1), "level_top" (level k), "qtable", "ztable", "window" (plain
+ * path), "batch" (one whole rs_run_batch launch sequence).
  * ---------------------------------------------------------------------- */
 rs_status rs_profile_enable(int on);
 rs_status rs_profile_reset(void);

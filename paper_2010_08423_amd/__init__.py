@@ -54,7 +54,8 @@ class _Result(ctypes.Structure):
 
 class _Tuning(ctypes.Structure):
     _fields_ = [("edges_per_tile", ctypes.c_uint32), ("top_edges_per_tile", ctypes.c_uint32),
-                ("chunks_per_launch", ctypes.c_uint32), ("waves_per_block", ctypes.c_uint32)]
+                ("chunks_per_launch", ctypes.c_uint32), ("waves_per_block", ctypes.c_uint32),
+                ("max_slots", ctypes.c_uint32), ("no_graph", ctypes.c_uint32)]
 
 
 class _GraphInfo(ctypes.Structure):
@@ -188,9 +189,12 @@ class Tuning:
     top_edges_per_tile: int = 0
     chunks_per_launch: int = 0
     waves_per_block: int = 0
+    max_slots: int = 0
+    no_graph: int = 0
 
     def _c(self):
-        return _Tuning(self.edges_per_tile, self.top_edges_per_tile, self.chunks_per_launch, self.waves_per_block)
+        return _Tuning(self.edges_per_tile, self.top_edges_per_tile, self.chunks_per_launch, self.waves_per_block,
+                       self.max_slots, self.no_graph)
 
 
 class Graph:
@@ -302,7 +306,7 @@ def run(graph: Graph, k, delta, seed, motif=None, it_begin=0, it_end=0, tuning: 
 
 
 def run_batch(graphs, queries, tuning: Tuning | None = None, stream=None):
-    """rs_run_batch: queries[i] on graphs[i] in one persistent launch.
+    """rs_run_batch: queries[i] on graphs[i], evaluated together in shared level launches.
     Returns (list of Result, overall status)."""
     nq = len(queries)
     handles = (ctypes.c_void_p * max(nq, 1))(*[g.handle.value for g in graphs])
@@ -330,7 +334,8 @@ def autotune(graph: Graph, sample_queries) -> Tuning:
     out = _Tuning()
     _check(_load().rs_autotune(graph.handle, qs, ns, ctypes.byref(out)), "rs_autotune")
     del keep
-    return Tuning(out.edges_per_tile, out.top_edges_per_tile, out.chunks_per_launch, out.waves_per_block)
+    return Tuning(out.edges_per_tile, out.top_edges_per_tile, out.chunks_per_launch, out.waves_per_block,
+                  out.max_slots, out.no_graph)
 
 
 # --- kernel timing -------------------------------------------------------------

@@ -1,0 +1,887 @@
+// Batched queries: many queries, each with its own graph, k, delta, motif and
+// seed, evaluated together so that small queries share launches and fill the
+// GPU.
+//
+// Work decomposition. A query's 2^k sieve iterations form 64-iteration chunks
+// (one wave lane per iteration). Each (query, chunk) is a unit with its own
+// prefix-state buffers. Units are packed into rounds whose buffers fit the
+// HBM budget; a round runs levels 2..kmax, and level l is one launch per
+// product-row width kq (4, 8, 12, 16): a prefix launch over the edge tiles of
+// every unit whose query has k > l, and a last-level launch over the edge
+// ranges of every unit whose query has k == l. Levels are ordered by kernel
+// boundaries only: inside a launch the sole cross-wave dependency is the
+// bounded look-back of rs_level.h.
+//
+// Each launch walks a device work table: units[] (descriptors uploaded per
+// call) and ubegin[] (the first flat work index of each unit). The grid holds
+// about as many waves as are resident; wave w takes flat indices w, w + W, ...
+// and locates the unit by a binary search that is only repeated when the
+// index leaves the current unit. The whole launch sequence (per-query setup,
+// the level launches of every round, per-query reductions) is captured once
+// per batch shape into a hipGraph; later calls with the same shape upload new
+// descriptors and replay it.
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "rs_level.h"
+
+namespace rs {
+
+rs_status plan_query(const rs_graph* g, const rs_query* q, QueryPlan& qp);
+Tuning resolve_tuning(const rs_graph* g, uint32_t k, const rs_tuning* t);
+
+// Per-query descriptor of the setup kernels and the final reduction.
+struct BQuery {
+  const uint32_t* e_src;
+  const uint32_t* e_dst;
+  const uint32_t* e_t;
+  const uint32_t* e_out;
+  const uint32_t* hi;
+  const uint32_t* in_off;
+  const uint8_t* colour;
+  uint32_t* lo;
+  uint64_t* z;
+  uint64_t* q;
+  uint64_t* fsum;
+  uint64_t seed, it_begin, it_end;
+  uint32_t n, m, k, kq, delta, motif;
+  uint8_t mu[RS_MAX_COLOURS];
+  uint8_t off[RS_MAX_COLOURS];
+};
+
+// One (query, chunk) of one level launch; every field is wave-uniform.
+struct MUnit {
+  const uint32_t* e_src;
+  const uint32_t* e_out;
+  const uint32_t* hi;
+  const uint32_t* lo;
+  const uint64_t* q;   // this level's [m][kq] product rows
+  const uint64_t* z;   // [n][kq] substitution rows (level 2)
+  const uint64_t* pp;  // previous level's prefix state
+  uint64_t* pc;        // this level's prefix state (prefix launches)
+  uint64_t* fsum;      // per-iteration sums (last-level launches)
+  uint64_t cb;         // first iteration of the chunk
+  uint64_t it_begin, it_end;
+  uint64_t row0;       // first look-back record row
+  uint32_t m;
+  uint32_t n_items;    // edge tiles or edge ranges
+  uint32_t epoch;      // record tag epoch of this launch
+  uint32_t pad;
+};
+static_assert(sizeof(MUnit) == 120, "MUnit layout");
+// Units are read through the constant address space: scalar loads into SGPRs.
+typedef __attribute__((address_space(4))) const MUnit cMUnit;
+
+// ---------------------------------------------------------------------------
+// Per-query setup kernels (descriptors read from device memory).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void kb_ztable(const BQuery* __restrict__ qs, uint32_t qi) {
+  __shared__ uint64_t lds[4][16][kLanes];
+  const BQuery& Q = qs[qi];
+  const uint32_t lane = threadIdx.x & 63u;
+  uint64_t* tab = &lds[threadIdx.x >> 6][0][lane];
+  tab[0] = 0;
+  const uint64_t idx = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (uint64_t)Q.n * Q.kq) return;
+  const uint32_t u = (uint32_t)(idx / Q.kq), j = (uint32_t)(idx % Q.kq);
+  uint64_t v = 0;
+  if (j < Q.k) {
+    const uint64_t jj = (uint64_t)(j + 1) << 32;
+    if (!Q.motif) {
+      v = hash1(Q.seed, 'Z', (uint64_t)u | jj);
+    } else {
+      const uint32_t s = Q.colour[u];
+      for (uint32_t r = 0; r < Q.mu[s]; ++r) {
+        const uint64_t d = (uint64_t)Q.off[s] + r;
+        v ^= gf_mul(tab, hash1(Q.seed, 'G', (uint64_t)u | (d << 32)), hash1(Q.seed, 'W', d | jj));
+      }
+    }
+  }
+  Q.z[idx] = v;
+}
+
+__global__ __launch_bounds__(256) void kb_window(const BQuery* __restrict__ qs, uint32_t qi) {
+  const BQuery& Q = qs[qi];
+  const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= Q.m) return;
+  const uint32_t v = Q.e_src[e];
+  const uint32_t t = Q.e_t[e];
+  const uint32_t thr = t > Q.delta ? t - Q.delta : 0u;
+  uint32_t a = Q.in_off[v], b = Q.in_off[v + 1];
+  while (a < b) {
+    const uint32_t mid = a + ((b - a) >> 1);
+    if (Q.e_t[mid] < thr)
+      a = mid + 1;
+    else
+      b = mid;
+  }
+  Q.lo[e] = a + v;
+}
+
+template <int KQ>
+__global__ __launch_bounds__(256) void kb_qtable(const BQuery* __restrict__ qs, uint32_t qi) {
+  __shared__ uint64_t lds[4][16][kLanes];
+  const BQuery& Q = qs[qi];
+  const uint32_t lane = threadIdx.x & 63u;
+  uint64_t* tab = &lds[threadIdx.x >> 6][0][lane];
+  tab[0] = 0;
+  const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= Q.m) return;
+  const uint32_t src = Q.e_src[e], dst = Q.e_dst[e], t = Q.e_t[e];
+  uint64_t zr[KQ];
+#pragma unroll
+  for (int j = 0; j < KQ; ++j) zr[j] = Q.z[(uint64_t)dst * KQ + j];
+  const uint64_t w0 = (uint64_t)src | ((uint64_t)dst << 32);
+  for (uint32_t p = 1; p < Q.k; ++p) {
+    const uint64_t y = hash2(Q.seed, 'Y', w0, (uint64_t)t | ((uint64_t)p << 32));
+    gf_table(tab, y);
+    uint64_t* out = Q.q + ((uint64_t)(p - 1) * Q.m + e) * KQ;
+#pragma unroll
+    for (int j = 0; j < KQ; ++j) {
+      Acc128 r = {0, 0, 0, 0};
+      gf_comb_acc(lds_addr(tab), zr[j], r);
+      out[j] = gf_reduce(r);
+    }
+  }
+}
+
+__global__ void kb_clear_fsum(const BQuery* __restrict__ qs, uint32_t qi) {
+  const BQuery& Q = qs[qi];
+  const uint64_t total = 1ull << Q.k;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (uint64_t)gridDim.x * blockDim.x)
+    Q.fsum[i] = 0;
+}
+
+// out[qi] = XOR of the query's per-iteration sums over its range.
+__global__ __launch_bounds__(256) void kb_reduce(const BQuery* __restrict__ qs, uint64_t* __restrict__ out) {
+  __shared__ uint64_t part[256];
+  const BQuery& Q = qs[blockIdx.x];
+  uint64_t acc = 0;
+  for (uint64_t i = Q.it_begin + threadIdx.x; i < Q.it_end; i += blockDim.x) acc ^= Q.fsum[i];
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  for (uint32_t s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) part[threadIdx.x] ^= part[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[blockIdx.x] = part[0];
+}
+
+// ---------------------------------------------------------------------------
+// Level launches over the work table.
+// ---------------------------------------------------------------------------
+
+// Index of the unit holding flat work index t, searching [from, nunits); the
+// caller guarantees ubegin[from] <= t. Wave-uniform (scalar loads).
+__device__ __forceinline__ uint32_t find_unit(cu32* ubegin, uint32_t from, uint32_t nunits, uint32_t t) {
+  uint32_t lo = from, hi = nunits;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (ubegin[mid] <= t)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+// Prefix level: flat index = (unit, edge tile).
+template <int KQ, int E, bool FIRST>
+__global__ __launch_bounds__(256) void kb_scan(const MUnit* __restrict__ units, const uint32_t* __restrict__ ubegin_p,
+                                               uint32_t nunits, uint32_t total, uint64_t* __restrict__ agg,
+                                               uint64_t* __restrict__ incl) {
+  extern __shared__ uint64_t dyn_lds[];  // [waves][16][64]; starts at LDS address 0
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t wv = threadIdx.x >> 6;
+  uint64_t* tab = dyn_lds + wv * 16 * kLanes + lane;
+  tab[0] = 0;
+  uint32_t mk[6];
+  lane_masks(lane, mk);
+  cu32* ubegin = as_const(ubegin_p);
+  const uint32_t waves = gridDim.x * (blockDim.x >> 6);
+  uint32_t u = 0, u_begin = 0, u_end = 0;  // empty until the first search
+  TileCtx c;
+  c.agg = agg;
+  c.incl = incl;
+  for (uint32_t t = blockIdx.x * (blockDim.x >> 6) + wv; t < total; t += waves) {
+    if (t >= u_end) {
+      u = find_unit(ubegin, u_end == 0 ? 0u : u + 1, nunits, t);
+      u_begin = ubegin[u];
+      u_end = u + 1 < nunits ? ubegin[u + 1] : total;
+      cMUnit& U = ((cMUnit*)units)[u];
+      c.e_src = U.e_src;
+      c.e_out = U.e_out;
+      c.hi = U.hi;
+      c.lo = U.lo;
+      c.q = U.q;
+      c.z = U.z;
+      c.pp = U.pp;
+      c.pc = U.pc;
+      c.cb = U.cb;
+      c.m = U.m;
+      c.n_tiles = U.n_items;
+      c.epoch = U.epoch;
+      c.row0 = U.row0;
+    }
+    const uint32_t tile = t - u_begin;
+    TileIn<E> in;
+    load_tile<KQ, E, FIRST, false>(c, tile, lane, in);
+    scan_tile<KQ, E, FIRST, false>(c, tile, in, lane, mk, tab);
+  }
+}
+
+// Last level: flat index = (unit, edge range of top_edges edges). A wave keeps
+// its unreduced sum while it stays in one unit and XORs it into the unit's
+// per-iteration sums when it leaves.
+template <int KQ, bool FIRST>
+__global__ __launch_bounds__(256) void kb_top(const MUnit* __restrict__ units, const uint32_t* __restrict__ ubegin_p,
+                                              uint32_t nunits, uint32_t total, uint32_t top_edges) {
+  extern __shared__ uint64_t dyn_lds[];  // [waves][16][64]; starts at LDS address 0
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t wv = threadIdx.x >> 6;
+  uint64_t* tab = dyn_lds + wv * 16 * kLanes + lane;
+  tab[0] = 0;
+  uint32_t mk[6];
+  lane_masks(lane, mk);
+  cu32* ubegin = as_const(ubegin_p);
+  const uint32_t waves = gridDim.x * (blockDim.x >> 6);
+  uint32_t u = 0, u_begin = 0, u_end = 0;
+  const uint32_t *e_src = nullptr, *hi = nullptr, *lo = nullptr;
+  const uint64_t *q = nullptr, *z = nullptr, *pp = nullptr;
+  uint64_t* fsum = nullptr;
+  uint64_t cb = 0, it_begin = 0, it_end = 0;
+  uint32_t m = 0;
+  Acc128 r = {0, 0, 0, 0};
+  auto flush = [&]() {
+    const uint64_t f = gf_reduce(r);
+    const uint64_t it = cb + lane;
+    if (it >= it_begin && it < it_end && f) atomicXor((unsigned long long*)&fsum[it], (unsigned long long)f);
+    r = Acc128{0, 0, 0, 0};
+  };
+  for (uint32_t t = blockIdx.x * (blockDim.x >> 6) + wv; t < total; t += waves) {
+    if (t >= u_end) {
+      if (u_end != 0) flush();
+      u = find_unit(ubegin, u_end == 0 ? 0u : u + 1, nunits, t);
+      u_begin = ubegin[u];
+      u_end = u + 1 < nunits ? ubegin[u + 1] : total;
+      cMUnit& U = ((cMUnit*)units)[u];
+      e_src = U.e_src;
+      hi = U.hi;
+      lo = U.lo;
+      q = U.q;
+      z = U.z;
+      pp = U.pp;
+      fsum = U.fsum;
+      cb = U.cb;
+      it_begin = U.it_begin;
+      it_end = U.it_end;
+      m = U.m;
+    }
+    const uint32_t e0 = (t - u_begin) * top_edges;
+    const uint32_t e1 = min(m, e0 + top_edges);
+    top_range<KQ, FIRST, false>(e_src, hi, lo, q, z, pp, cb, e0, e1, lane, mk, tab, r);
+  }
+  if (u_end != 0) flush();
+}
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+struct BatchWorkspace {
+  std::mutex mu;
+  DevBuf qs, units, ubegin, per_query, parena, agg, incl, out;
+  uint32_t epoch = 0;
+  std::string key;  // shape of the captured graph
+  hipGraphExec_t exec = nullptr;
+  hipGraph_t graph = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  void drop_graph() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
+    key.clear();
+  }
+  ~BatchWorkspace() { drop_graph(); }
+};
+
+static BatchWorkspace& batch_ws() {
+  static BatchWorkspace* ws = new BatchWorkspace();  // lives until process end
+  return *ws;
+}
+
+// One level launch of the plan.
+struct BLaunch {
+  bool top;         // last-level launch (else prefix level)
+  bool first;       // level 2
+  uint32_t kq;
+  uint32_t unit_off, nunits, total;
+  uint32_t grid;    // blocks, set at enqueue time
+};
+
+struct BatchPlan {
+  std::vector<BQuery> qs;
+  std::vector<uint32_t> qidx;  // query slot -> caller index
+  std::vector<MUnit> units;
+  std::vector<uint32_t> ubegin;
+  std::vector<BLaunch> launches;
+  std::vector<uint32_t> unit_query;   // query slot of each unit
+  std::vector<uint64_t> unit_pbytes;  // offset of a unit's prefix buffers in the arena (bytes)
+  uint64_t per_query_bytes = 0;
+  uint64_t parena_bytes = 0;  // prefix-state arena (largest round)
+  uint64_t records = 1;       // look-back records (largest round)
+  uint32_t scan_launches = 0;
+  uint32_t rounds = 0;
+  Tuning tu;
+  std::string key;
+};
+
+static uint64_t align256(uint64_t b) { return (b + 255) & ~255ull; }
+
+// Bytes one chunk holds while its round runs: two prefix-state arrays and
+// the look-back records of its tiles.
+static uint64_t chunk_bytes(uint64_t m, uint64_t n, uint32_t E) {
+  const uint64_t tiles = (m + E - 1) / E;
+  return 2 * align256((m + n) * kLanes * 8) + 2 * 1024 * tiles;
+}
+
+// Builds the plan: per-query buffers, rounds of chunks within `slot_budget`
+// bytes, and the level launches. Pointers inside qs/units are byte offsets
+// into the per-query arena / prefix arena until resolve_plan() rebases them.
+rs_status batch_plan(const rs_graph* const* graphs, const rs_query* queries, uint32_t nq, const Tuning& tu,
+                     uint64_t slot_budget, rs_result* results, BatchPlan& P) {
+  P = BatchPlan();
+  P.tu = tu;
+  const uint32_t E = tu.edges_per_tile;
+  const uint32_t TE = tu.top_edges_per_tile;
+  std::string key = "E" + std::to_string(E) + "T" + std::to_string(TE) + "W" + std::to_string(tu.waves_per_block) +
+                    "S" + std::to_string(tu.max_slots);
+  struct Chunk {
+    uint32_t query;
+    uint64_t cb;
+  };
+  std::vector<Chunk> chunks;
+  std::vector<const rs_graph*> qgraph;
+  uint64_t pq_off = 0;
+  for (uint32_t i = 0; i < nq; ++i) {
+    QueryPlan qp;
+    results[i] = rs_result{0, 0, RS_OK, 0.0f};
+    rs_status s = plan_query(graphs ? graphs[i] : nullptr, &queries[i], qp);
+    if (s != RS_OK) {
+      results[i].status = s;
+      continue;
+    }
+    const rs_graph* g = graphs[i];
+    const uint64_t m = g->g.m, n = g->g.n;
+    if (m == 0 || qp.k > n || qp.it_end == qp.it_begin) continue;  // F = 0 exactly
+    BQuery Q;
+    memset(&Q, 0, sizeof(Q));
+    Q.e_src = g->g.e_src.as<uint32_t>();
+    Q.e_dst = g->g.e_dst.as<uint32_t>();
+    Q.e_t = g->g.e_t.as<uint32_t>();
+    Q.e_out = g->g.e_out.as<uint32_t>();
+    Q.hi = g->g.hi.as<uint32_t>();
+    Q.in_off = g->g.in_off.as<uint32_t>();
+    Q.colour = g->g.colour.as<uint8_t>();
+    Q.seed = qp.seed;
+    Q.it_begin = qp.it_begin;
+    Q.it_end = qp.it_end;
+    Q.n = (uint32_t)n;
+    Q.m = (uint32_t)m;
+    Q.k = qp.k;
+    Q.kq = qp.kq;
+    Q.delta = qp.delta;
+    Q.motif = qp.motif ? 1 : 0;
+    memcpy(Q.mu, qp.mu, sizeof(Q.mu));
+    memcpy(Q.off, qp.shade_off, sizeof(Q.off));
+    Q.lo = (uint32_t*)(uintptr_t)pq_off;
+    pq_off += align256(4 * m);
+    Q.z = (uint64_t*)(uintptr_t)pq_off;
+    pq_off += align256(8 * n * qp.kq);
+    Q.q = (uint64_t*)(uintptr_t)pq_off;
+    pq_off += align256(8 * m * qp.kq * (qp.k - 1));
+    Q.fsum = (uint64_t*)(uintptr_t)pq_off;
+    pq_off += align256(8 * (1ull << qp.k));
+    const uint32_t qslot = (uint32_t)P.qs.size();
+    P.qs.push_back(Q);
+    P.qidx.push_back(i);
+    qgraph.push_back(g);
+    key += "|" + std::to_string((uintptr_t)g) + ":" + std::to_string(n) + ":" + std::to_string(m) + ":" +
+           std::to_string(qp.k) + ":" + std::to_string(qp.chunk_first) + "-" + std::to_string(qp.chunk_last);
+    for (uint64_t c = qp.chunk_first; c < qp.chunk_last; ++c) chunks.push_back(Chunk{qslot, c * kLanes});
+  }
+  P.per_query_bytes = pq_off;
+  if (chunks.empty()) {
+    P.key = key;
+    return RS_OK;
+  }
+  // longest queries first so that each round's levels are shared by many units
+  std::stable_sort(chunks.begin(), chunks.end(),
+                   [&](const Chunk& a, const Chunk& b) { return P.qs[a.query].k > P.qs[b.query].k; });
+  // rounds: consecutive chunks while their buffers fit the budget
+  std::vector<std::pair<size_t, size_t>> rounds;
+  {
+    size_t r0 = 0;
+    uint64_t bytes = 0;
+    for (size_t c = 0; c < chunks.size(); ++c) {
+      const BQuery& Q = P.qs[chunks[c].query];
+      const uint64_t b = chunk_bytes(Q.m, Q.n, E);
+      const bool full = c > r0 && (bytes + b > slot_budget || (tu.max_slots && c - r0 >= tu.max_slots));
+      if (full) {
+        rounds.push_back({r0, c});
+        r0 = c;
+        bytes = 0;
+      }
+      bytes += b;
+    }
+    rounds.push_back({r0, chunks.size()});
+  }
+  P.rounds = (uint32_t)rounds.size();
+  key += "#R" + std::to_string(rounds.size());
+  // launches
+  for (const auto& rd : rounds) {
+    // per-chunk prefix buffers and record rows within the round
+    std::vector<uint64_t> poff(rd.second - rd.first), row0(rd.second - rd.first);
+    uint64_t pbytes = 0, rows = 0;
+    uint32_t kmax = 0;
+    for (size_t c = rd.first; c < rd.second; ++c) {
+      const BQuery& Q = P.qs[chunks[c].query];
+      poff[c - rd.first] = pbytes;
+      pbytes += 2 * align256(((uint64_t)Q.m + Q.n) * kLanes * 8);
+      row0[c - rd.first] = rows;
+      rows += (Q.m + E - 1) / E;
+      kmax = std::max(kmax, Q.k);
+    }
+    P.parena_bytes = std::max(P.parena_bytes, pbytes);
+    P.records = std::max(P.records, rows);
+    for (uint32_t l = 2; l <= kmax; ++l) {
+      for (uint32_t kq = 4; kq <= 16; kq += 4) {
+        for (int top = 0; top < 2; ++top) {
+          BLaunch L;
+          L.top = top != 0;
+          L.first = l == 2;
+          L.kq = kq;
+          L.unit_off = (uint32_t)P.units.size();
+          L.nunits = 0;
+          L.total = 0;
+          L.grid = 0;
+          for (size_t c = rd.first; c < rd.second; ++c) {
+            const uint32_t qi = chunks[c].query;
+            const BQuery& Q = P.qs[qi];
+            if (Q.kq != kq || (top ? Q.k != l : Q.k <= l)) continue;
+            MUnit U;
+            memset(&U, 0, sizeof(U));
+            U.e_src = Q.e_src;
+            U.e_out = Q.e_out;
+            U.hi = Q.hi;
+            U.lo = Q.lo;  // offset, rebased later
+            U.q = (const uint64_t*)((uintptr_t)Q.q + 8ull * (l - 2) * Q.m * kq);  // byte offset until rebased
+            U.z = Q.z;
+            const uint64_t half = align256(((uint64_t)Q.m + Q.n) * kLanes * 8);
+            U.pp = (const uint64_t*)(uintptr_t)(poff[c - rd.first] + ((l - 1) & 1) * half);
+            U.pc = (uint64_t*)(uintptr_t)(poff[c - rd.first] + (l & 1) * half);
+            U.fsum = Q.fsum;
+            U.cb = chunks[c].cb;
+            U.it_begin = Q.it_begin;
+            U.it_end = Q.it_end;
+            U.row0 = row0[c - rd.first];
+            U.m = Q.m;
+            U.n_items = top ? (Q.m + TE - 1) / TE : (Q.m + E - 1) / E;
+            U.epoch = 0;  // set per call
+            P.ubegin.push_back(L.total);
+            L.total += U.n_items;
+            P.units.push_back(U);
+            P.unit_query.push_back(qi);
+            ++L.nunits;
+          }
+          if (L.nunits) {
+            if (!L.top) ++P.scan_launches;
+            P.launches.push_back(L);
+            key += "/" + std::to_string(L.top) + std::to_string(L.first) + ":" + std::to_string(kq) + ":" +
+                   std::to_string(L.nunits) + ":" + std::to_string(L.total);
+          }
+        }
+      }
+    }
+  }
+  P.key = key;
+  return RS_OK;
+}
+
+// Rebases the plan's offsets onto the allocated arenas, sets record epochs and
+// checks that every unit's ranges lie inside the buffers it addresses.
+static rs_status resolve_plan(BatchPlan& P, BatchWorkspace& W, uint32_t epoch0) {
+  char* pq = W.per_query.as<char>();
+  char* pa = W.parena.as<char>();
+  // per-query tables: byte offsets -> pointers
+  std::vector<uint64_t> lo_off(P.qs.size()), z_off(P.qs.size()), q_off(P.qs.size()), f_off(P.qs.size());
+  for (size_t i = 0; i < P.qs.size(); ++i) {
+    BQuery& Q = P.qs[i];
+    lo_off[i] = (uintptr_t)Q.lo;
+    z_off[i] = (uintptr_t)Q.z;
+    q_off[i] = (uintptr_t)Q.q;
+    f_off[i] = (uintptr_t)Q.fsum;
+    if (f_off[i] + 8 * (1ull << Q.k) > W.per_query.bytes) return RS_EINVAL;
+    Q.lo = (uint32_t*)(pq + lo_off[i]);
+    Q.z = (uint64_t*)(pq + z_off[i]);
+    Q.q = (uint64_t*)(pq + q_off[i]);
+    Q.fsum = (uint64_t*)(pq + f_off[i]);
+  }
+  uint32_t scan_idx = 0;
+  for (const BLaunch& L : P.launches) {
+    const uint32_t epoch = L.top ? 0u : epoch0 + 1 + scan_idx++;
+    for (uint32_t j = 0; j < L.nunits; ++j) {
+      MUnit& U = P.units[L.unit_off + j];
+      const uint32_t qi = P.unit_query[L.unit_off + j];
+      const BQuery& Q = P.qs[qi];
+      const uint64_t half = align256(((uint64_t)Q.m + Q.n) * kLanes * 8);
+      const uint64_t pp_off = (uintptr_t)U.pp, pc_off = (uintptr_t)U.pc;
+      if (pp_off + half > W.parena.bytes || pc_off + half > W.parena.bytes) return RS_EINVAL;
+      if (!L.top && (U.row0 + U.n_items) * 1024 > W.agg.bytes) return RS_EINVAL;
+      const uint64_t q_level = (uintptr_t)U.q;  // offset of this level's rows
+      if (q_level + 8ull * Q.m * Q.kq > q_off[qi] + 8ull * Q.m * Q.kq * (Q.k - 1)) return RS_EINVAL;
+      U.lo = Q.lo;
+      U.z = Q.z;
+      U.q = (const uint64_t*)(pq + q_level);
+      U.pp = (const uint64_t*)(pa + pp_off);
+      U.pc = (uint64_t*)(pa + pc_off);
+      U.fsum = Q.fsum;
+      U.epoch = epoch;
+    }
+  }
+  return RS_OK;
+}
+
+static uint32_t resident_blocks_of(const void* kern, uint32_t threads, size_t lds) {
+  static std::mutex mu;
+  static std::map<std::pair<const void*, uint32_t>, uint32_t> cache;
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = cache.find({kern, threads});
+  if (it != cache.end()) return it->second;
+  int dev = 0, cus = 0, per_cu = 0;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, (int)threads, lds) != hipSuccess || per_cu < 1)
+    per_cu = 1;
+  const uint32_t v = (uint32_t)std::max(cus, 1) * (uint32_t)per_cu;
+  cache[{kern, threads}] = v;
+  return v;
+}
+
+template <int KQ, int E>
+static const void* scan_kernel(bool first) {
+  return first ? (const void*)kb_scan<KQ, E, true> : (const void*)kb_scan<KQ, E, false>;
+}
+
+static const void* pick_scan(uint32_t kq, uint32_t E, bool first) {
+  if (E == 8) {
+    switch (kq) {
+      case 4: return scan_kernel<4, 8>(first);
+      case 8: return scan_kernel<8, 8>(first);
+      case 12: return scan_kernel<12, 8>(first);
+      default: return scan_kernel<16, 8>(first);
+    }
+  }
+  switch (kq) {
+    case 4: return scan_kernel<4, 16>(first);
+    case 8: return scan_kernel<8, 16>(first);
+    case 12: return scan_kernel<12, 16>(first);
+    default: return scan_kernel<16, 16>(first);
+  }
+}
+
+static const void* pick_top(uint32_t kq, bool first) {
+  switch (kq) {
+    case 4: return first ? (const void*)kb_top<4, true> : (const void*)kb_top<4, false>;
+    case 8: return first ? (const void*)kb_top<8, true> : (const void*)kb_top<8, false>;
+    case 12: return first ? (const void*)kb_top<12, true> : (const void*)kb_top<12, false>;
+    default: return first ? (const void*)kb_top<16, true> : (const void*)kb_top<16, false>;
+  }
+}
+
+// Grid of every launch: about as many blocks as are resident, at most one
+// wave per work item.
+static void size_grids(BatchPlan& P) {
+  const uint32_t wpb = P.tu.waves_per_block;
+  const size_t lds = (size_t)wpb * 16 * kLanes * 8;
+  for (BLaunch& L : P.launches) {
+    const void* kern = L.top ? pick_top(L.kq, L.first) : pick_scan(L.kq, P.tu.edges_per_tile, L.first);
+    L.grid = std::max(1u, std::min(resident_blocks_of(kern, 64 * wpb, lds), (L.total + wpb - 1) / wpb));
+    P.key += "g" + std::to_string(L.grid);
+  }
+}
+
+// Enqueues the whole batch on `st` (kernels only, so it can be captured).
+static rs_status batch_enqueue(BatchPlan& P, BatchWorkspace& W, hipStream_t st) {
+  const BQuery* dq = W.qs.as<BQuery>();
+  for (uint32_t qi = 0; qi < P.qs.size(); ++qi) {
+    const BQuery& Q = P.qs[qi];
+    hipLaunchKernelGGL(kb_ztable, dim3((uint32_t)(((uint64_t)Q.n * Q.kq + 255) / 256)), dim3(256), 0, st, dq, qi);
+    hipLaunchKernelGGL(kb_window, dim3((Q.m + 255) / 256), dim3(256), 0, st, dq, qi);
+    switch (Q.kq) {
+      case 4: hipLaunchKernelGGL(kb_qtable<4>, dim3((Q.m + 255) / 256), dim3(256), 0, st, dq, qi); break;
+      case 8: hipLaunchKernelGGL(kb_qtable<8>, dim3((Q.m + 255) / 256), dim3(256), 0, st, dq, qi); break;
+      case 12: hipLaunchKernelGGL(kb_qtable<12>, dim3((Q.m + 255) / 256), dim3(256), 0, st, dq, qi); break;
+      default: hipLaunchKernelGGL(kb_qtable<16>, dim3((Q.m + 255) / 256), dim3(256), 0, st, dq, qi); break;
+    }
+    hipLaunchKernelGGL(kb_clear_fsum, dim3((uint32_t)std::min<uint64_t>(((1ull << Q.k) + 255) / 256, 256)), dim3(256),
+                       0, st, dq, qi);
+  }
+  const uint32_t wpb = P.tu.waves_per_block;
+  const size_t lds = (size_t)wpb * 16 * kLanes * 8;
+  const MUnit* du = W.units.as<MUnit>();
+  const uint32_t* db = W.ubegin.as<uint32_t>();
+  for (BLaunch& L : P.launches) {
+    const void* kern = L.top ? pick_top(L.kq, L.first) : pick_scan(L.kq, P.tu.edges_per_tile, L.first);
+    const MUnit* u = du + L.unit_off;
+    const uint32_t* b = db + L.unit_off;
+    if (L.top) {
+      void* args[] = {(void*)&u, (void*)&b, (void*)&L.nunits, (void*)&L.total, (void*)&P.tu.top_edges_per_tile};
+      RS_HIP(hipLaunchKernel(kern, dim3(L.grid), dim3(64 * wpb), args, lds, st));
+    } else {
+      uint64_t* agg = W.agg.as<uint64_t>();
+      uint64_t* incl = W.incl.as<uint64_t>();
+      void* args[] = {(void*)&u, (void*)&b, (void*)&L.nunits, (void*)&L.total, (void*)&agg, (void*)&incl};
+      RS_HIP(hipLaunchKernel(kern, dim3(L.grid), dim3(64 * wpb), args, lds, st));
+    }
+  }
+  hipLaunchKernelGGL(kb_reduce, dim3((uint32_t)P.qs.size()), dim3(256), 0, st, dq, W.out.as<uint64_t>());
+  RS_HIP(hipGetLastError());
+  return RS_OK;
+}
+
+static uint64_t default_slot_budget() {
+  size_t free_b = 0, total_b = 0;
+  if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return 8ull << 30;
+  return (uint64_t)(free_b / 3);
+}
+
+rs_status run_batch_impl(const rs_graph* const* graphs, const rs_query* queries, uint32_t nq, rs_result* results,
+                         const rs_tuning* tune, hipStream_t st, bool use_graph, uint64_t slot_budget) {
+  if (nq == 0) return RS_OK;
+  if (!queries || !results || !graphs) return RS_EINVAL;
+  BatchWorkspace& W = batch_ws();
+  std::lock_guard<std::mutex> lk(W.mu);
+  // launch shape: explicit knobs, else the graph's autotuned batch shape, else defaults
+  Tuning tu;
+  tu.top_edges_per_tile = 128;
+  if (graphs[0] && graphs[0]->has_batch_tuned) tu = graphs[0]->batch_tuned;
+  if (tune) {
+    if (tune->edges_per_tile) tu.edges_per_tile = tune->edges_per_tile;
+    if (tune->top_edges_per_tile) tu.top_edges_per_tile = tune->top_edges_per_tile;
+    if (tune->waves_per_block) tu.waves_per_block = tune->waves_per_block;
+    if (tune->max_slots) tu.max_slots = tune->max_slots;
+    if (tune->no_graph) use_graph = false;
+  }
+  if (tu.edges_per_tile != 8 && tu.edges_per_tile != 16) tu.edges_per_tile = 16;
+  if (tu.waves_per_block != 1 && tu.waves_per_block != 2 && tu.waves_per_block != 4) tu.waves_per_block = 4;
+  tu.top_edges_per_tile = std::min(std::max(tu.top_edges_per_tile, 1u), 4096u);
+  BatchPlan P;
+  RS_TRY(batch_plan(graphs, queries, nq, tu, slot_budget ? slot_budget : default_slot_budget(), results, P));
+  rs_status first_err = RS_OK;
+  for (uint32_t i = 0; i < nq; ++i)
+    if (results[i].status != RS_OK && first_err == RS_OK) first_err = results[i].status;
+  if (P.qs.empty()) return first_err;
+  // device memory; a reallocation invalidates the captured graph
+  const void* before[8] = {W.qs.p, W.units.p, W.ubegin.p, W.per_query.p, W.parena.p, W.agg.p, W.incl.p, W.out.p};
+  const uint64_t rec_bytes = 1024 * P.records;
+  if (W.per_query.reserve(P.per_query_bytes, st, false) || W.qs.reserve(sizeof(BQuery) * P.qs.size(), st, false) ||
+      W.units.reserve(sizeof(MUnit) * std::max<size_t>(P.units.size(), 1), st, false) ||
+      W.ubegin.reserve(4 * std::max<size_t>(P.ubegin.size(), 1), st, false) ||
+      W.parena.reserve(std::max<uint64_t>(P.parena_bytes, 256), st, false) ||
+      W.out.reserve(8 * P.qs.size(), st, false))
+    return RS_ENOMEM;
+  if (W.agg.bytes < rec_bytes || W.incl.bytes < rec_bytes) {
+    // tagged records start at epoch 0, which no launch uses
+    if (W.agg.reserve(rec_bytes, st, true) || W.incl.reserve(rec_bytes, st, true)) return RS_ENOMEM;
+    W.epoch = 0;
+  }
+  const void* after[8] = {W.qs.p, W.units.p, W.ubegin.p, W.per_query.p, W.parena.p, W.agg.p, W.incl.p, W.out.p};
+  if (memcmp(before, after, sizeof(before)) != 0) W.drop_graph();
+  if ((uint64_t)W.epoch + P.scan_launches + 1 >= (1ull << 30)) {
+    RS_HIP(launch_fill64(W.agg.as<uint64_t>(), 0, W.agg.bytes / 8, st));
+    RS_HIP(launch_fill64(W.incl.as<uint64_t>(), 0, W.incl.bytes / 8, st));
+    W.epoch = 0;
+  }
+  RS_TRY(resolve_plan(P, W, W.epoch));
+  size_grids(P);
+  W.epoch += P.scan_launches + 1;
+  RS_HIP(hipMemcpyAsync(W.qs.p, P.qs.data(), sizeof(BQuery) * P.qs.size(), hipMemcpyHostToDevice, st));
+  if (!P.units.empty()) {
+    RS_HIP(hipMemcpyAsync(W.units.p, P.units.data(), sizeof(MUnit) * P.units.size(), hipMemcpyHostToDevice, st));
+    RS_HIP(hipMemcpyAsync(W.ubegin.p, P.ubegin.data(), 4 * P.ubegin.size(), hipMemcpyHostToDevice, st));
+  }
+  if (!W.ev0) {
+    RS_HIP(hipEventCreate(&W.ev0));
+    RS_HIP(hipEventCreate(&W.ev1));
+  }
+  RS_HIP(hipEventRecord(W.ev0, st));
+  {
+    ProfScope ps(KC_BATCH, st, 0.0);
+    if (use_graph) {
+      if (W.key != P.key || !W.exec) {
+        W.drop_graph();
+        hipStream_t cap = nullptr;
+        RS_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+        hipError_t be = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+        rs_status s = be == hipSuccess ? batch_enqueue(P, W, cap) : RS_EDEVICE;
+        hipGraph_t g = nullptr;
+        hipError_t ce = be == hipSuccess ? hipStreamEndCapture(cap, &g) : be;
+        (void)hipStreamDestroy(cap);
+        if (s != RS_OK) {
+          if (g) (void)hipGraphDestroy(g);
+          return s;
+        }
+        RS_HIP(ce);
+        W.graph = g;
+        RS_HIP(hipGraphInstantiate(&W.exec, g, nullptr, nullptr, 0));
+        W.key = P.key;
+      }
+      RS_HIP(hipGraphLaunch(W.exec, st));
+    } else {
+      RS_TRY(batch_enqueue(P, W, st));
+    }
+  }
+  std::vector<uint64_t> F(P.qs.size());
+  RS_HIP(hipMemcpyAsync(F.data(), W.out.p, 8 * F.size(), hipMemcpyDeviceToHost, st));
+  RS_HIP(hipEventRecord(W.ev1, st));
+  RS_HIP(hipStreamSynchronize(st));
+  if (profiling_on()) profile_flush();
+  float ms = 0;
+  (void)hipEventElapsedTime(&ms, W.ev0, W.ev1);
+  for (size_t j = 0; j < P.qs.size(); ++j) {
+    rs_result& r = results[P.qidx[j]];
+    r.fingerprint = F[j];
+    r.yes = F[j] != 0;
+    r.status = RS_OK;
+  }
+  for (uint32_t i = 0; i < nq; ++i) results[i].device_ms = ms;
+  return first_err;
+}
+
+}  // namespace rs
+
+using namespace rs;
+
+namespace rs {
+rs_status run_plain(rs_graph* g, const QueryPlan& qp, const Tuning& tu, uint64_t* per_it_host, rs_result* r,
+                    hipStream_t st);
+}  // namespace rs
+
+// Times candidate launch shapes on the sample queries. Plain path: edges per
+// tile, waves per block, last-level range and chunks per launch, best total
+// device time per k class. Batched path: edges per tile, waves per block and
+// last-level range for the whole sample batch. Results are cached on the graph.
+rs_status autotune_impl(rs_graph* g, const rs_query* sample, uint32_t ns, rs_tuning* out) {
+  if (!g || !sample || ns == 0) return RS_EINVAL;
+  hipStream_t st = nullptr;
+  RS_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+  std::vector<QueryPlan> plans(ns);
+  for (uint32_t i = 0; i < ns; ++i) {
+    rs_status s = plan_query(g, &sample[i], plans[i]);
+    if (s != RS_OK) {
+      (void)hipStreamDestroy(st);
+      return s;
+    }
+  }
+  // plain path, per k present in the sample
+  std::vector<Tuning> cands;
+  for (uint32_t E : {8u, 16u})
+    for (uint32_t wpb : {2u, 4u})
+      for (uint32_t top : {16u, 64u})
+        for (uint32_t cpl : {1u, 2u}) {
+          Tuning t;
+          t.edges_per_tile = E;
+          t.waves_per_block = wpb;
+          t.top_edges_per_tile = top;
+          t.chunks_per_launch = cpl;
+          cands.push_back(t);
+        }
+  Tuning best_any;
+  for (uint32_t k = 2; k <= RS_MAX_K; ++k) {
+    std::vector<uint32_t> idx;
+    for (uint32_t i = 0; i < ns; ++i)
+      if (plans[i].k == k) idx.push_back(i);
+    if (idx.empty()) continue;
+    double best = 1e30;
+    Tuning bt;
+    for (const Tuning& t : cands) {
+      double tot = 0;
+      for (int rep = 0; rep < 2; ++rep) {
+        double run = 0;
+        for (uint32_t i : idx) {
+          rs_result r;
+          std::lock_guard<std::mutex> lk(g->mu);
+          rs_status s = run_plain(g, plans[i], t, nullptr, &r, st);
+          if (s != RS_OK) {
+            (void)hipStreamDestroy(st);
+            return s;
+          }
+          run += r.device_ms;
+        }
+        tot = rep == 0 ? run : std::min(tot, run);  // first pass warms the workspace
+      }
+      if (tot < best) {
+        best = tot;
+        bt = t;
+      }
+    }
+    g->tuned[k] = bt;
+    g->has_tuned[k] = true;
+    best_any = bt;
+  }
+  // batched path on the whole sample
+  std::vector<const rs_graph*> gl(ns, g);
+  std::vector<rs_result> res(ns);
+  double best = 1e30;
+  Tuning bb;
+  for (uint32_t E : {8u, 16u})
+    for (uint32_t wpb : {2u, 4u})
+      for (uint32_t top : {64u, 256u}) {
+        rs_tuning t{E, top, 0, wpb, 0, 1};
+        double tmin = 1e30;
+        for (int rep = 0; rep < 2; ++rep) {
+          rs_status s = run_batch_impl(gl.data(), sample, ns, res.data(), &t, st, false, 0);
+          if (s != RS_OK) {
+            (void)hipStreamDestroy(st);
+            return s;
+          }
+          if (rep) tmin = std::min(tmin, (double)res[0].device_ms);
+        }
+        if (tmin < best) {
+          best = tmin;
+          bb.edges_per_tile = E;
+          bb.top_edges_per_tile = top;
+          bb.waves_per_block = wpb;
+        }
+      }
+  g->batch_tuned = bb;
+  g->has_batch_tuned = true;
+  (void)hipStreamDestroy(st);
+  if (out) *out = rs_tuning{best_any.edges_per_tile, best_any.top_edges_per_tile, best_any.chunks_per_launch,
+                            best_any.waves_per_block, 0, 0};
+  return RS_OK;
+}
+
+extern "C" rs_status rs_autotune(const rs_graph* g, const rs_query* sample, uint32_t ns, rs_tuning* out) {
+  try {
+    return autotune_impl(const_cast<rs_graph*>(g), sample, ns, out);
+  } catch (...) {
+    return RS_ENOMEM;
+  }
+}
+
+extern "C" rs_status rs_run_batch(const rs_graph* const* graphs, const rs_query* queries, uint32_t nq,
+                                  rs_result* results, const rs_tuning* tune, void* hip_stream) {
+  try {
+    return run_batch_impl(graphs, queries, nq, results, tune, (hipStream_t)hip_stream, true, 0);
+  } catch (...) {
+    return RS_ENOMEM;
+  }
+}

@@ -52,7 +52,7 @@ void DevBuf::release() {
 // ---------------------------------------------------------------------------
 // Kernel timing
 // ---------------------------------------------------------------------------
-static const char* kClassNames[KC_COUNT] = {"level_scan", "level_top", "qtable", "ztable", "window", "persistent"};
+static const char* kClassNames[KC_COUNT] = {"level_scan", "level_top", "qtable", "ztable", "window", "batch"};
 static std::mutex g_prof_mu;
 static std::atomic<bool> g_prof_on{false};
 struct PendingEv {
@@ -146,6 +146,7 @@ Tuning resolve_tuning(const rs_graph* g, uint32_t k, const rs_tuning* t) {
     if (t->top_edges_per_tile) tu.top_edges_per_tile = t->top_edges_per_tile;
     if (t->chunks_per_launch) tu.chunks_per_launch = t->chunks_per_launch;
     if (t->waves_per_block) tu.waves_per_block = t->waves_per_block;
+    if (t->max_slots) tu.max_slots = t->max_slots;
   }
   if (tu.edges_per_tile != 8 && tu.edges_per_tile != 16) tu.edges_per_tile = 16;
   tu.top_edges_per_tile = std::min(std::max(tu.top_edges_per_tile, 1u), 4096u);

@@ -59,6 +59,7 @@ struct Tuning {
   uint32_t top_edges_per_tile = 16;  // last level
   uint32_t chunks_per_launch = 1;
   uint32_t waves_per_block = 4;
+  uint32_t max_slots = 0;  // batched path; 0 = as many as fit
 };
 
 struct QueryPlan {
@@ -139,7 +140,7 @@ struct GraphDev {
 // ---------------------------------------------------------------------------
 // Profiling (rs_engine.hip)
 // ---------------------------------------------------------------------------
-enum KernelClass { KC_SCAN = 0, KC_TOP, KC_QTABLE, KC_ZTABLE, KC_WINDOW, KC_PERSISTENT, KC_COUNT };
+enum KernelClass { KC_SCAN = 0, KC_TOP, KC_QTABLE, KC_ZTABLE, KC_WINDOW, KC_BATCH, KC_COUNT };
 bool profiling_on();
 struct ProfScope {
   // Records events around one launch of class `kc` on `st` when profiling is on.
@@ -168,7 +169,10 @@ struct rs_graph {
     uint32_t flag_tiles = 0, flag_chunks = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
   } ws;
-  // Autotuned launch shapes per k (index k), 0 = not tuned.
+  // Autotuned launch shapes per k (index k) for the plain path, and one for
+  // the batched path.
   rs::Tuning tuned[RS_MAX_K + 1];
   bool has_tuned[RS_MAX_K + 1] = {false};
+  rs::Tuning batch_tuned;
+  bool has_batch_tuned = false;
 };

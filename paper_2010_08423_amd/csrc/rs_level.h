@@ -4,8 +4,10 @@
 // Layout (one query, one 64-iteration chunk):
 //   * Edges are sorted by (dst, t, src); the in-edges of vertex u form the
 //     segment [in_off[u], in_off[u+1]) ordered by time.
-//   * The prefix state P of a level has m + n slots. Slot in_off[u] + u holds 0;
-//     slot e + dst(e) + 1 holds the XOR of the level's values over the edges of
+//   * The prefix state P of a level has m + n slots. Slot in_off[u] + u holds 0
+//     (written by the tile holding u's first in-edge; vertices without in-edges
+//     are never read through it, their windows have hi == lo); slot
+//     e + dst(e) + 1 holds the XOR of the level's values over the edges of
 //     dst(e)'s segment up to and including e. Each slot stores 64 uint64, one
 //     per sieve iteration of the chunk (lane = iteration), 512 contiguous bytes.
 //   * For edge e = (v -> u, t) the restless window of Eq. (poly-enc:1) - the
@@ -312,13 +314,15 @@ __device__ __forceinline__ void scan_tile(const TileCtx& c, uint32_t tile, const
   uint32_t first_len = 0;
   bool started = !cont;
   uint32_t last_slot = 0;
+  uint32_t seg_starts = 0;  // bit i: a segment starts at edge i of the tile
 #pragma unroll
   for (int i = 0; i < E; ++i) {
     pref[i] = 0;
     if ((uint32_t)i < ne) {
-      if (i > 0 && in.slot[i] != last_slot + 1u) {
+      if (i == 0 ? !cont : in.slot[i] != last_slot + 1u) {
         acc = 0;
         started = true;
+        seg_starts |= 1u << i;
       }
       if (!started) first_len = (uint32_t)i + 1u;
       acc ^= edge_value<KQ, E, FIRST>(c, e0 + (uint32_t)i, in.ia[i], in.w[i], mk, tab);
@@ -338,9 +342,14 @@ __device__ __forceinline__ void scan_tile(const TileCtx& c, uint32_t tile, const
     if (next_cont && !started) publish(c.incl, fi, lane, carry ^ acc, rec_tag(c.epoch, kFlagIncl));
   }
 #pragma unroll
-  for (int i = 0; i < E; ++i)
-    if ((uint32_t)i < ne)
+  for (int i = 0; i < E; ++i) {
+    if ((uint32_t)i < ne) {
       p_store<COHERENT>(c.pc + (uint64_t)in.slot[i] * kLanes + lane, pref[i] ^ ((uint32_t)i < first_len ? carry : 0));
+      // the segment's leading slot (just before its first edge's slot) holds 0;
+      // writing it here lets P buffers be reused across graphs without clearing
+      if ((seg_starts >> i) & 1u) p_store<COHERENT>(c.pc + (uint64_t)(in.slot[i] - 1u) * kLanes + lane, 0);
+    }
+  }
 }
 
 // Tiles first, first + stride, ... below n_tiles. (Loading the next tile's

@@ -1,0 +1,122 @@
+"""GPU: the serving loop (rs_server_*) returns, for every query of a stream
+of arrivals, the fingerprint the plain path gives for it alone, while it
+admits queries against an HBM budget, slices long queries across epochs,
+cancels, and is driven from several threads."""
+import sys
+import threading
+import time
+
+import numpy as np
+import pytest
+
+from paper_2010_08423_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+R = None
+
+
+def setup_module(module):
+    global R
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2010_08423_amd as lib
+
+    R = lib
+    R.library()
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def mixed_queries(n_q, n_colours, seed, k_range=(2, 9), delta_range=(0, 6)):
+    r = np.random.default_rng(seed)
+    out = []
+    for i in range(n_q):
+        k = int(r.integers(k_range[0], k_range[1] + 1))
+        d = int(r.integers(delta_range[0], delta_range[1] + 1))
+        motif = inputs.random_motif(k, n_colours, r) if i % 2 else None
+        q = inputs.Query(k=k, delta=d, seed=int(r.integers(0, 2**63)), motif=motif)
+        if i % 5 == 3:
+            total = 1 << k
+            a = int(r.integers(0, total))
+            b = int(r.integers(a, total + 1))
+            q.it_begin, q.it_end = a, b
+        out.append(q)
+    return out
+
+
+def plain(gd, q):
+    return R.run(gd, q.k, q.delta, q.seed, motif=q.motif, it_begin=q.it_begin, it_end=q.it_end).fingerprint
+
+
+def graphs():
+    g1 = inputs.add_colours(inputs.uniform_graph(300, 4000, 40, seed=31), 4, seed=31)
+    g2 = inputs.add_colours(inputs.chung_lu_graph(500, 9000, 2.3, 60, seed=32), 4, seed=32)
+    g3 = inputs.tiny_graph(33, n_max=8, m_max=30, n_colours=4)
+    return [g1, g2, g3]
+
+
+def test_server_alone_vs_mix():
+    gs = graphs()
+    gds = [R.Graph.from_inputs(g) for g in gs]
+    qs = mixed_queries(30, 4, seed=17, k_range=(2, 10))
+    which = [i % 3 for i in range(len(qs))]
+    alone = [plain(gds[w], q) for q, w in zip(qs, which)]
+    say("[server] 30 arrivals over 3 graphs")
+    srv = R.Server(hbm_budget=8 << 30, epoch_edge_updates=2_000_000)
+    ids = [srv.add_graph(gd) for gd in gds]
+    tickets = []
+    for q, w in zip(qs, which):
+        tickets.append(srv.submit(ids[w], q))
+        time.sleep(0.001)  # arrivals while earlier work is on the device
+    got = [srv.poll(t, wait_ms=60000) for t in tickets]
+    assert all(r is not None and r.status == R.RS_OK for r in got)
+    assert [r.fingerprint for r in got] == alone
+    st = srv.stats()
+    assert st["completed"] == len(qs) and st["epochs"] >= 1
+    assert st["p99_ms"] >= st["p50_ms"] > 0
+    srv.close()
+
+
+def test_server_budget_deferral_cancel_and_threads():
+    g = graphs()[1]
+    gd = R.Graph.from_inputs(g)
+    qs = mixed_queries(16, 4, seed=19, k_range=(6, 9))
+    alone = [plain(gd, q) for q in qs]
+    fp = max(R.footprint(gd, q.k, q.delta) for q in qs)
+    # room for about two queries at a time: the rest must wait
+    say("[server] budget for about two queries, 4 submitting threads")
+    srv = R.Server(hbm_budget=int(fp * 2.2), max_inflight=64, epoch_edge_updates=1_000_000)
+    gid = srv.add_graph(gd)
+    with pytest.raises(R.RSError):
+        srv.submit(gid, inputs.Query(k=17, delta=1, seed=1))  # invalid k
+    tickets = [None] * len(qs)
+
+    def sub(lo, hi):
+        for i in range(lo, hi):
+            tickets[i] = srv.submit(gid, qs[i])
+
+    th = [threading.Thread(target=sub, args=(a, a + 4)) for a in range(0, 16, 4)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    extra = srv.submit(gid, qs[0])
+    srv.cancel(extra)
+    r_extra = srv.poll(extra, wait_ms=60000)
+    assert r_extra.status in (R.RS_ECANCELED, R.RS_OK)
+    got = [srv.poll(t, wait_ms=120000) for t in tickets]
+    assert [r.fingerprint for r in got] == alone
+    st = srv.stats()
+    assert st["deferred"] > 0 and st["completed"] >= len(qs)
+    small = R.Server(hbm_budget=1024)
+    gid2 = small.add_graph(gd)
+    with pytest.raises(R.RSError):
+        small.submit(gid2, qs[0])  # can never fit
+    small.close()
+    srv.close()
