@@ -10,7 +10,8 @@ performs 2^k (k-1) m of them.
 
 Prints one JSON line. Extra modes (not the driver's default):
   --mode batch   64 mixed queries on the same graph: one rs_run_batch vs 64 rs_run
-  --mode serve   the continuous-batching server on resident graphs
+  --mode serve   the continuous-batching server on four resident graphs vs
+                 first-come first-served plain calls over the same arrivals
 """
 from __future__ import annotations
 
@@ -76,6 +77,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--mode", default="plain", choices=["plain", "batch", "serve"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    # serve mode: offered load, arrival window, wall-clock cap, server budget
+    ap.add_argument("--rate", type=float, default=200.0)
+    ap.add_argument("--window", type=float, default=5.0)
+    ap.add_argument("--cap", type=float, default=40.0)
+    ap.add_argument("--budget-gb", type=float, default=96.0)
+    ap.add_argument("--epoch-updates", type=float, default=4e9)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; the sieve shards over iteration "

@@ -1,0 +1,210 @@
+"""The batched and served benchmark modes of bench.py.
+
+batch: 64 queries on the 1,000,000-edge Chung-Lu graph (k uniform in 4..12,
+       delta uniform in 2..50, half path and half motif over 8 colours, seeds
+       100..163), launch shape chosen by the autotuner on a sample of the mix.
+       A step is one rs_run_batch of all 64; the comparison is the same 64
+       queries as 64 plain rs_run calls one after another. Fingerprints must
+       agree exactly.
+serve: four resident graphs (m = 1e4, 1e5, 1e6, 1e7; uniform and Chung-Lu),
+       open-loop Poisson arrivals (k uniform in 4..12, delta in 1..100, 30 %
+       motif queries over 8 colours) submitted at their arrival times to the
+       continuous-batching server; the comparison serves the same arrivals
+       first-come first-served with plain rs_run calls. Both runs stop at the
+       same wall-clock cap; what has not completed by then is counted, not
+       timed.
+"""
+from __future__ import annotations
+
+import threading
+import time
+
+import numpy as np
+
+import paper_2010_08423_amd as R
+from paper_2010_08423_amd import inputs
+
+
+def _log(*a):
+    import sys
+
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _updates(m, q):
+    span = (q.it_end - q.it_begin) if (q.it_begin or q.it_end) else (1 << q.k)
+    return span * (q.k - 1) * m
+
+
+def run_batch_mode(args):
+    import torch
+
+    _log("generating graph")
+    g, _ = inputs.config_path_scale()
+    gd = R.Graph.from_inputs(g)
+    m = gd.info()["m"]
+    qs = inputs.batch_mix()
+    upd = sum(_updates(m, q) for q in qs)
+    # autotune on the smaller-k half of the mix (bounded tuning time)
+    sample = sorted(qs, key=lambda q: q.k)[:6]
+    _log("autotuning on", [(q.k, q.delta) for q in sample])
+    t0 = time.perf_counter()
+    tuned = R.autotune(gd, sample)
+    tune_s = time.perf_counter() - t0
+    # plain reference: one query at a time
+    _log("plain: 64 queries one at a time")
+    for q in qs[:2]:
+        R.run(gd, q.k, q.delta, q.seed, motif=q.motif)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plain = [R.run(gd, q.k, q.delta, q.seed, motif=q.motif).fingerprint for q in qs]
+    torch.cuda.synchronize()
+    plain_s = time.perf_counter() - t0
+    _log(f"plain {plain_s:.2f} s")
+    # batched
+    graphs = [gd] * len(qs)
+    for _ in range(args.warmup):
+        res, st = R.run_batch(graphs, qs)
+    R.profile_enable(True)
+    R.profile_reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        res, st = R.run_batch(graphs, qs)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    R.profile_enable(False)
+    if st != R.RS_OK:
+        raise SystemExit(f"rs_run_batch failed: {st}")
+    got = [r.fingerprint for r in res]
+    if got != plain:
+        bad = [i for i in range(len(qs)) if got[i] != plain[i]]
+        raise SystemExit(f"batched fingerprints differ from plain for queries {bad}")
+    return {
+        "metric": "queries/s (batched vs plain, equal fingerprints)",
+        "value": len(qs) / dt,
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": "64-query batch on Chung-Lu(2.5) n=100000 m=1000000 t in [1,1000]: k in 4..12, "
+                               "delta in 2..50, half motif over 8 colours, seeds 100..163",
+                   "edge_updates_per_step": upd,
+                   "tuning": {"edges_per_tile": tuned.edges_per_tile, "waves_per_block": tuned.waves_per_block,
+                              "top_edges_per_tile": tuned.top_edges_per_tile},
+                   "autotune_s": tune_s},
+        "batched": {"queries_per_s": len(qs) / dt, "edge_updates_per_s": upd / dt, "s_per_batch": dt},
+        "plain": {"queries_per_s": len(qs) / plain_s, "edge_updates_per_s": upd / plain_s, "s_total": plain_s},
+        "speedup_vs_plain": plain_s / dt,
+        "fingerprints_equal": True,
+    }
+
+
+def _percentiles(lat):
+    if not lat:
+        return None, None
+    a = np.sort(np.asarray(lat))
+    return float(np.percentile(a, 50)), float(np.percentile(a, 99))
+
+
+def run_serve_mode(args):
+    import torch
+
+    rate, window, cap = args.rate, args.window, args.cap
+    _log("generating served graphs")
+    gs = inputs.served_graphs()
+    gds = [R.Graph.from_inputs(g) for g in gs]
+    ms = [gd.info()["m"] for gd in gds]
+    stream = inputs.served_stream(rate, window, len(gs))
+    _log(f"{len(stream)} arrivals over {window} s at {rate}/s")
+
+    # served
+    srv = R.Server(hbm_budget=int(args.budget_gb * (1 << 30)), epoch_edge_updates=int(args.epoch_updates))
+    ids = [srv.add_graph(gd) for gd in gds]
+    tickets = [None] * len(stream)
+    t_sub = [0.0] * len(stream)
+    start = time.perf_counter()
+
+    def submitter():
+        for i, (ta, gi, q) in enumerate(stream):
+            d = start + ta - time.perf_counter()
+            if d > 0:
+                time.sleep(d)
+            t_sub[i] = time.perf_counter()
+            tickets[i] = srv.submit(ids[gi], q)
+
+    th = threading.Thread(target=submitter)
+    th.start()
+    th.join()
+    lat, fps, done = [], {}, 0
+    for i, tk in enumerate(tickets):
+        left_ms = int(max(0.0, start + cap - time.perf_counter()) * 1e3)
+        r = srv.poll(tk, wait_ms=left_ms) if left_ms > 0 else srv.poll(tk, wait_ms=0)
+        if r is not None and r.status == R.RS_OK:
+            fps[i] = r.fingerprint
+    end_served = time.perf_counter()
+    st = srv.stats()
+    for i, tk in enumerate(tickets):
+        if i not in fps:
+            srv.cancel(tk)
+    srv.close()
+    served_elapsed = end_served - start
+    p50, p99 = st["p50_ms"], st["p99_ms"]
+    served_done = len(fps)
+    done_updates = sum(_updates(ms[stream[i][1]], stream[i][2]) for i in fps)
+
+    # plain first-come first-served over the same arrivals, same cap
+    _log("plain FCFS over the same arrivals")
+    torch.cuda.synchronize()
+    start = time.perf_counter()
+    plain_lat, plain_fp = [], {}
+    for i, (ta, gi, q) in enumerate(stream):
+        now = time.perf_counter()
+        if now - start >= cap:
+            break
+        if start + ta > now:
+            time.sleep(start + ta - now)
+        plain_fp[i] = R.run(gds[gi], q.k, q.delta, q.seed, motif=q.motif).fingerprint
+        plain_lat.append((time.perf_counter() - (start + ta)) * 1e3)
+    plain_elapsed = time.perf_counter() - start
+    pp50, pp99 = _percentiles(plain_lat)
+    common = [i for i in fps if i in plain_fp]
+    mismatch = [i for i in common if fps[i] != plain_fp[i]]
+    if mismatch:
+        raise SystemExit(f"served fingerprints differ from plain for arrivals {mismatch[:10]}")
+    return {
+        "metric": "queries/s + p50/p99 latency (served vs plain FCFS, equal fingerprints)",
+        "value": served_done / served_elapsed,
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": 0,
+        "ms_per_step": served_elapsed * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": f"served stream: Poisson {rate}/s for {window} s over 4 resident graphs "
+                               f"(m = {ms}), k in 4..12, delta in 1..100, 30% motif; cap {cap} s",
+                   "arrivals": len(stream), "hbm_budget_gb": args.budget_gb,
+                   "epoch_edge_updates": args.epoch_updates},
+        "served": {"completed": served_done, "queries_per_s": served_done / served_elapsed,
+                   "edge_updates_per_s": done_updates / served_elapsed, "p50_ms": p50, "p99_ms": p99,
+                   "epochs": st["epochs"], "deferred": st["deferred"], "elapsed_s": served_elapsed},
+        "plain": {"completed": len(plain_fp), "queries_per_s": len(plain_fp) / plain_elapsed,
+                  "p50_ms": pp50, "p99_ms": pp99, "elapsed_s": plain_elapsed},
+        "fingerprints_equal_on_common": len(common),
+    }
+
+
+def run(args):
+    if args.mode == "batch":
+        return run_batch_mode(args)
+    return run_serve_mode(args)

@@ -198,7 +198,7 @@ __global__ __launch_bounds__(256) void kb_scan(const MUnit* __restrict__ units, 
                                                uint64_t* __restrict__ incl) {
   extern __shared__ uint64_t dyn_lds[];  // [waves][16][64]; starts at LDS address 0
   const uint32_t lane = threadIdx.x & 63u;
-  const uint32_t wv = threadIdx.x >> 6;
+  const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform for the compiler
   uint64_t* tab = dyn_lds + wv * 16 * kLanes + lane;
   tab[0] = 0;
   uint32_t mk[6];
@@ -244,7 +244,7 @@ __global__ __launch_bounds__(256) void kb_top(const MUnit* __restrict__ units, c
                                               uint32_t nunits, uint32_t total, uint32_t top_edges) {
   extern __shared__ uint64_t dyn_lds[];  // [waves][16][64]; starts at LDS address 0
   const uint32_t lane = threadIdx.x & 63u;
-  const uint32_t wv = threadIdx.x >> 6;
+  const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform for the compiler
   uint64_t* tab = dyn_lds + wv * 16 * kLanes + lane;
   tab[0] = 0;
   uint32_t mk[6];

@@ -27,7 +27,7 @@ __global__ __launch_bounds__(256) void k_scan(
     uint64_t* __restrict__ agg, uint64_t* __restrict__ incl) {
   extern __shared__ uint64_t dyn_lds[];  // [waves][16][64]; starts at LDS address 0
   const uint32_t lane = threadIdx.x & 63u;
-  const uint32_t wv = threadIdx.x >> 6;
+  const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform for the compiler
   uint64_t* tab = dyn_lds + wv * 16 * kLanes + lane;
   tab[0] = 0;
 
@@ -67,7 +67,7 @@ __global__ __launch_bounds__(256) void k_top(
     uint64_t chunk_base, uint32_t m, uint32_t edges_per_wave, uint64_t* __restrict__ partial) {
   extern __shared__ uint64_t dyn_lds[];  // [waves][16][64]; starts at LDS address 0
   const uint32_t lane = threadIdx.x & 63u;
-  const uint32_t wv = threadIdx.x >> 6;
+  const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform for the compiler
   const uint32_t nw = blockDim.x >> 6;
   uint64_t* tab = dyn_lds + wv * 16 * kLanes + lane;
   tab[0] = 0;

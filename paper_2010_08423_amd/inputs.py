@@ -197,6 +197,21 @@ def batch_mix(n_queries=64, n_colours=8, seed=4, k_range=(4, 12), delta_range=(2
     return out
 
 
+def served_graphs(sizes=(10_000, 100_000, 1_000_000, 10_000_000), n_colours=8, seed=10):
+    """Resident graphs of the served stream: alternately uniform and Chung-Lu
+    (exponent 2.5), m edges, n = m/10 vertices, timestamps in [1, m/100],
+    n_colours vertex colours."""
+    out = []
+    for i, m in enumerate(sizes):
+        n, tau = max(m // 10, 2), max(m // 100, 1)
+        if i % 2 == 0:
+            g = uniform_graph(n, m, tau, seed=seed + i, name=f"uniform n={n} m={m} tau={tau}")
+        else:
+            g = chung_lu_graph(n, m, 2.5, tau, seed=seed + i, name=f"chung-lu(2.5) n={n} m={m} tau={tau}")
+        out.append(add_colours(g, n_colours, seed=seed + i))
+    return out
+
+
 def served_stream(rate_per_s, duration_s, n_graphs, seed=5, k_range=(4, 12), delta_range=(1, 100),
                   motif_frac=0.3, n_colours=8):
     """Open-loop Poisson arrivals: list of (arrival_s, graph_index, Query)."""
