@@ -12,6 +12,7 @@ Prints one JSON line. Extra modes (not the driver's default):
   --mode batch   64 mixed queries on the same graph: one rs_run_batch vs 64 rs_run
   --mode serve   the continuous-batching server on four resident graphs vs
                  first-come first-served plain calls over the same arrivals
+  --mode copy    a plain 1 GiB device copy, the reference for HBM byte counters
 """
 from __future__ import annotations
 
@@ -75,7 +76,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--mode", default="plain", choices=["plain", "batch", "serve"])
+    ap.add_argument("--mode", default="plain", choices=["plain", "batch", "serve", "copy"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     # serve mode: offered load, arrival window, wall-clock cap, server budget
     ap.add_argument("--rate", type=float, default=200.0)
@@ -98,6 +99,17 @@ def main():
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
     torch.cuda.set_device(0)
+    if args.mode == "copy":
+        # calibration for HBM byte counters: a plain device copy of known size
+        n = 1 << 30
+        x = torch.ones(n, dtype=torch.uint8, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(args.steps):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"mode": "copy", "bytes_read_per_copy": n, "bytes_written_per_copy": n,
+                          "copies": args.steps}), flush=True)
+        return
     if args.mode != "plain":
         from paper_2010_08423_amd import bench_modes
 
@@ -132,7 +144,7 @@ def main():
     avg_scan_ms = ms_scan / max(n_scan, 1)
     achieved = bytes_scan / max(n_scan, 1) / (avg_scan_ms * 1e-3) / 1e9
     classes = {}
-    for c in ("level_scan", "level_top", "qtable", "ztable", "window"):
+    for c in ("level_scan", "level_first", "level_top", "qtable", "ztable", "window"):
         n, tot, b = R.profile_get(c)
         classes[c] = {"launches": n, "avg_ms": tot / max(n, 1), "GBps": b / max(tot, 1e-9) / 1e6}
     out = {
@@ -154,7 +166,7 @@ def main():
                    "edge_updates_per_query": upd, "fingerprint": f"{r.fingerprint:#018x}"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_scan (prefix levels 3..k-1 and level 2)",
+                     "kernel": "k_scan, prefix levels 3..k-1 (1536 B per edge and chunk + 12 + 8kq B per edge)",
                      "avg_launch_ms": avg_scan_ms, "launches": n_scan},
         "kernels": classes,
     }

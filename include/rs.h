@@ -200,8 +200,13 @@ rs_status rs_autotune(const rs_graph* g, const rs_query* sample, uint32_t ns, rs
 /* ------------------------------------------------------------------------
  * Kernel timing (hipEvents recorded around the launches of each kernel
  * class on the launch stream while enabled). Classes: "level_scan" (prefix
- * levels 2..k-1), "level_top" (level k), "qtable", "ztable", "window" (plain
- * path), "batch" (one whole rs_run_batch launch sequence).
+ * levels 3..k-1), "level_first" (level 2), "level_top" (level k), "qtable",
+ * "ztable", "window" (plain path), "batch" (one whole rs_run_batch launch
+ * sequence). algorithmic_bytes sums, per launch, the HBM bytes the level
+ * needs at minimum: per edge and chunk 1024 bytes of window gathers (levels
+ * >= 3) and 512 bytes of prefix store (prefix levels); per edge once per
+ * launch 12 bytes of indices and 8*kq bytes of product row (plus 8*kq of
+ * substitution row at level 2).
  * ---------------------------------------------------------------------- */
 rs_status rs_profile_enable(int on);
 rs_status rs_profile_reset(void);

@@ -401,7 +401,7 @@ rs_status batch_plan(const rs_graph* const* graphs, const rs_query* queries, uin
     memcpy(Q.mu, qp.mu, sizeof(Q.mu));
     memcpy(Q.off, qp.shade_off, sizeof(Q.off));
     Q.lo = (uint32_t*)(uintptr_t)pq_off;
-    pq_off += align256(4 * m);
+    pq_off += align256(4 * (m + kEdgePad));
     Q.z = (uint64_t*)(uintptr_t)pq_off;
     pq_off += align256(8 * n * qp.kq);
     Q.q = (uint64_t*)(uintptr_t)pq_off;

@@ -52,7 +52,7 @@ void DevBuf::release() {
 // ---------------------------------------------------------------------------
 // Kernel timing
 // ---------------------------------------------------------------------------
-static const char* kClassNames[KC_COUNT] = {"level_scan", "level_top", "qtable", "ztable", "window", "batch"};
+static const char* kClassNames[KC_COUNT] = {"level_scan", "level_first", "level_top", "qtable", "ztable", "window", "batch"};
 static std::mutex g_prof_mu;
 static std::atomic<bool> g_prof_on{false};
 struct PendingEv {
@@ -171,13 +171,20 @@ uint64_t plain_footprint(const rs_graph* g, const QueryPlan& qp, const Tuning& t
 // Algorithmic HBM bytes of one prefix-level launch: per edge and chunk two
 // 512-byte window gathers (one z row at level 2) and one 512-byte prefix
 // store, plus the edge's indices and q row.
+// Algorithmic HBM bytes of one level launch over `chunks` 64-iteration chunks:
+// per edge and chunk the two 512-byte prefix-state rows of its window
+// (levels >= 3) and its 512-byte prefix store (prefix levels); per edge once
+// per launch its indices (12 bytes) and its kq-entry product row, and at level
+// 2 its source's kq-entry substitution row.
 double scan_bytes(uint64_t m, uint32_t kq, uint64_t chunks, bool first) {
-  const double per = (first ? 8.0 * kq : 1024.0) + 512.0 + 12.0 + 8.0 * kq;
-  return per * (double)m * (double)chunks;
+  const double per_chunk = (first ? 0.0 : 1024.0) + 512.0;
+  const double per_edge = 12.0 + 8.0 * kq + (first ? 8.0 * kq : 0.0);
+  return (per_chunk * (double)chunks + per_edge) * (double)m;
 }
 double top_bytes(uint64_t m, uint32_t kq, uint64_t chunks, bool first) {
-  const double per = (first ? 8.0 * kq : 1024.0) + 8.0 + 8.0 * kq;
-  return per * (double)m * (double)chunks;
+  const double per_chunk = first ? 0.0 : 1024.0;
+  const double per_edge = 12.0 + 8.0 * kq + (first ? 8.0 * kq : 0.0);
+  return (per_chunk * (double)chunks + per_edge) * (double)m;
 }
 
 // ---------------------------------------------------------------------------
@@ -215,7 +222,7 @@ rs_status run_plain(rs_graph* g, const QueryPlan& qp, const Tuning& tu, uint64_t
     // Rows per chunk of the last level's partial sums; the single-chunk launch
     // bounds every group: gc * blocks(gc) <= cpl * blocks(1).
     const uint32_t tblocks = top_blocks(ta, k == 2, kq, 1, tu);
-    if (ws.lo.reserve(4 * m, st, false) || ws.z.reserve(8 * n * kq, st, false) ||
+    if (ws.lo.reserve(4 * (m + kEdgePad), st, false) || ws.z.reserve(8 * n * kq, st, false) ||
         ws.q.reserve(8 * m * kq * (k - 1), st, false) || ws.p0.reserve(8 * p_elems * cpl, st, true) ||
         ws.p1.reserve(8 * p_elems * cpl, st, true) ||
         ws.partial.reserve(8 * 64 * cpl * (uint64_t)tblocks, st, false) ||
@@ -272,7 +279,7 @@ rs_status run_plain(rs_graph* g, const QueryPlan& qp, const Tuning& tu, uint64_t
           a.epoch = ws.epoch;
           a.agg = ws.agg.as<uint64_t>();
           a.incl = ws.incl.as<uint64_t>();
-          ProfScope ps(KC_SCAN, st, scan_bytes(m, kq, gc, first));
+          ProfScope ps(first ? KC_FIRST : KC_SCAN, st, scan_bytes(m, kq, gc, first));
           RS_HIP(launch_scan(a, first, kq, gc, tu, st));
           std::swap(prev, cur);
         } else {

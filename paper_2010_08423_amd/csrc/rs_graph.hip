@@ -218,7 +218,7 @@ rs_status graph_build(uint32_t n, uint64_t m, const uint32_t* src, const uint32_
     RS_HIP(hipMemcpyAsync(&last_keep, keep.as<uint32_t>() + (m - 1), 4, hipMemcpyDeviceToHost, st));
     RS_HIP(hipStreamSynchronize(st));
     mk = (uint64_t)last_pos + last_keep;
-    const size_t kb = (size_t)std::max<uint64_t>(mk, 1);
+    const size_t kb = (size_t)std::max<uint64_t>(mk, 1) + kEdgePad;
     if (G.e_src.reserve(kb * 4, st, false) || G.e_dst.reserve(kb * 4, st, false) ||
         G.e_t.reserve(kb * 4, st, false) || G.e_out.reserve(kb * 4, st, false) ||
         G.hi.reserve(kb * 4, st, false)) {

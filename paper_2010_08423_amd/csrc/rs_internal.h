@@ -51,6 +51,11 @@ struct DevBuf {
 // ---------------------------------------------------------------------------
 // Kernel launch shapes and per-query plan
 // ---------------------------------------------------------------------------
+// The per-edge index arrays (e_src, e_dst, e_t, e_out, hi, lo) hold this many
+// readable entries past m, so a level kernel can fetch a whole tile's indices
+// in one scalar load; entries past m are never used.
+constexpr uint32_t kEdgePad = 64;
+
 constexpr uint32_t kFlagAgg = 1;   // record: XOR of the tile's open segment part
 constexpr uint32_t kFlagIncl = 2;  // record: full prefix of that segment
 
@@ -140,7 +145,7 @@ struct GraphDev {
 // ---------------------------------------------------------------------------
 // Profiling (rs_engine.hip)
 // ---------------------------------------------------------------------------
-enum KernelClass { KC_SCAN = 0, KC_TOP, KC_QTABLE, KC_ZTABLE, KC_WINDOW, KC_BATCH, KC_COUNT };
+enum KernelClass { KC_SCAN = 0, KC_FIRST, KC_TOP, KC_QTABLE, KC_ZTABLE, KC_WINDOW, KC_BATCH, KC_COUNT };
 bool profiling_on();
 struct ProfScope {
   // Records events around one launch of class `kc` on `st` when profiling is on.

@@ -20,7 +20,9 @@
 // XOR_{j in L} q_j(e) with q_j(e) = z_{u,j} * y_{e,l-1} precomputed per edge and
 // level; within a wavefront the edge is uniform, so the q row is one scalar
 // load and each lane forms its own subset XOR (6 lane bits + chunk bits).
-// One GF(2^64) product remains per edge-update.
+// One GF(2^64) product remains per edge-update, and none where the window is
+// empty (hi == lo): at levels >= 3 such an edge contributes exactly zero, so
+// the wave skips its gathers and product on a uniform branch.
 //
 // Prefix levels keep a running XOR per lane along a tile of E consecutive
 // edges; a segment that crosses tiles receives its carry through a decoupled
@@ -68,10 +70,14 @@ __device__ __forceinline__ void order_acquire() {
 
 // P-state accesses: plain (kernel boundaries order levels) or device-coherent
 // (levels ordered inside one persistent kernel).
+// Plain P loads go through the global address space explicitly: a generic
+// (flat) load would also count against the LDS wait counter and make every
+// table lookup wait for the gathers.
+typedef __attribute__((address_space(1))) const uint64_t gu64;
 template <bool COHERENT>
 __device__ __forceinline__ uint64_t p_load(const uint64_t* p) {
   if (COHERENT) return ld_dev64(p);
-  return *p;
+  return *(gu64*)p;
 }
 template <bool COHERENT>
 __device__ __forceinline__ void p_store(uint64_t* p, uint64_t v) {
@@ -144,33 +150,50 @@ struct TileCtx {
   uint64_t* incl;      // [tiles][64][2] records: inclusive prefix of that segment
 };
 
-// Loads the tile's indices (scalar) and issues all of its window gathers at
-// once. Slots past the tile end read edge e0 so every load stays in bounds.
+// N consecutive entries of an index array in one scalar load (the arrays are
+// padded past m, so the load stays in bounds for the last tile).
+template <int N>
+struct IdxN {
+  uint32_t v[N];
+};
+template <int N>
+__device__ __forceinline__ IdxN<N> load_idx(const uint32_t* p) {
+  cu32* q = as_const(p);
+  IdxN<N> r;
+#pragma unroll
+  for (int i = 0; i < N; ++i) r.v[i] = q[i];
+  return r;
+}
+
+// Row gathered by empty windows (and by slots past the tile end): all zero,
+// so both gathers of such an edge hit the same cached line and XOR to zero.
+static __device__ const uint64_t kZeroRow[kLanes] = {0};
+
+// Loads the tile's indices (three scalar loads) and issues all of its window
+// gathers at once, without branches: an edge whose window is empty (hi == lo,
+// its sum is zero) or that lies past the tile end gathers the zero row.
 template <int KQ, int E, bool FIRST, bool COHERENT>
 __device__ __forceinline__ void tile_inputs(const TileCtx& c, uint32_t e0, uint32_t ne, uint32_t lane,
                                             uint32_t (&slot)[E], uint32_t (&ia)[E], uint64_t (&w)[E]) {
-  cu32* e_out = as_const(c.e_out);
-  cu32* hi_idx = as_const(c.hi);
-  cu32* lo_idx = as_const(c.lo);
-  cu32* e_src = as_const(c.e_src);
-  uint32_t ib[E];
+  const IdxN<E> so = load_idx<E>(c.e_out + e0);
 #pragma unroll
-  for (int i = 0; i < E; ++i) {
-    const uint32_t e = (uint32_t)i < ne ? e0 + (uint32_t)i : e0;
-    slot[i] = e_out[e];
-    if (FIRST) {
-      ia[i] = e_src[e];
-      ib[i] = 0;
-    } else {
-      ia[i] = hi_idx[e];
-      ib[i] = lo_idx[e];
+  for (int i = 0; i < E; ++i) slot[i] = so.v[i];
+  if (FIRST) {
+    const IdxN<E> sr = load_idx<E>(c.e_src + e0);
+#pragma unroll
+    for (int i = 0; i < E; ++i) ia[i] = sr.v[i];
+  } else {
+    const IdxN<E> h = load_idx<E>(c.hi + e0);
+    const IdxN<E> l = load_idx<E>(c.lo + e0);
+    const uint64_t* zero = kZeroRow + lane;
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      const bool live = (uint32_t)i < ne && h.v[i] != l.v[i];
+      const uint64_t* pa = live ? c.pp + (uint64_t)h.v[i] * kLanes + lane : zero;
+      const uint64_t* pb = live ? c.pp + (uint64_t)l.v[i] * kLanes + lane : zero;
+      w[i] = p_load<COHERENT>(pa) ^ p_load<COHERENT>(pb);
+      ia[i] = live;
     }
-  }
-  if (!FIRST) {
-#pragma unroll
-    for (int i = 0; i < E; ++i)
-      w[i] = p_load<COHERENT>(c.pp + (uint64_t)ia[i] * kLanes + lane) ^
-             p_load<COHERENT>(c.pp + (uint64_t)ib[i] * kLanes + lane);
   }
 }
 
@@ -205,6 +228,7 @@ __device__ uint64_t tile_open_part(const TileCtx& c, uint32_t j, uint32_t lane, 
       acc = 0;
       st = true;
     }
+    if (!FIRST && hi_idx[e] == lo_idx[e]) continue;  // empty window: contributes zero
     const uint64_t w = FIRST ? 0
                              : p_load<COHERENT>(c.pp + (uint64_t)hi_idx[e] * kLanes + lane) ^
                                    p_load<COHERENT>(c.pp + (uint64_t)lo_idx[e] * kLanes + lane);
@@ -285,7 +309,9 @@ __device__ uint64_t look_back(const TileCtx& c, uint32_t tile, uint32_t lane, co
   return carry;
 }
 
-// Inputs of one tile: indices and window sums, loaded ahead of its compute.
+// Inputs of one tile, loaded ahead of its compute: per edge its P slot, at
+// level 2 its source vertex (ia) and at levels >= 3 its window sum (w) and
+// whether that window is non-empty (ia).
 template <int E>
 struct TileIn {
   uint32_t slot[E], ia[E];
@@ -325,7 +351,8 @@ __device__ __forceinline__ void scan_tile(const TileCtx& c, uint32_t tile, const
         seg_starts |= 1u << i;
       }
       if (!started) first_len = (uint32_t)i + 1u;
-      acc ^= edge_value<KQ, E, FIRST>(c, e0 + (uint32_t)i, in.ia[i], in.w[i], mk, tab);
+      // levels >= 3: an edge with an empty window contributes exactly zero
+      if (FIRST || in.ia[i]) acc ^= edge_value<KQ, E, FIRST>(c, e0 + (uint32_t)i, in.ia[i], in.w[i], mk, tab);
       pref[i] = acc;
       last_slot = in.slot[i];
     }
@@ -366,45 +393,55 @@ __device__ __forceinline__ void scan_tiles(const TileCtx& c, uint32_t first, uin
 }
 
 // Last level k over edges [e0, e1): unreduced per-lane sum of c_k(e) into r.
+// Edges go in batches of 8: one scalar load per index array and batch, the
+// next batch's gathers in flight during this batch's products; empty windows
+// gather the zero row and skip their product.
 template <int KQ, bool FIRST, bool COHERENT>
 __device__ __forceinline__ void top_range(const uint32_t* e_src_p, const uint32_t* hi_p,
                                           const uint32_t* lo_p, const uint64_t* q_p,
                                           const uint64_t* z_p, const uint64_t* pp, uint64_t cb,
                                           uint32_t e0, uint32_t e1, uint32_t lane,
                                           const uint32_t (&mk)[6], uint64_t* tab, Acc128& r) {
-  cu32* e_src = as_const(e_src_p);
-  cu32* hi_idx = as_const(hi_p);
-  cu32* lo_idx = as_const(lo_p);
   cu64* q = as_const(q_p);
   cu64* z = as_const(z_p);
   const uint32_t base = lds_addr(tab);
-  constexpr int B = 8;  // edges per batch; the next batch's gathers fly during this one
+  constexpr int B = 8;
+  const uint64_t* zero = kZeroRow + lane;
   uint64_t w[B], wn[B];
-  auto gather = [&](uint32_t eb, uint64_t(&dst)[B]) {
-    if (!FIRST) {
+  IdxN<B> a, an;  // per batch: sources (level 2) or window-is-live flags
+  auto gather = [&](uint32_t eb, uint64_t(&dst)[B], IdxN<B>& aux) {
+    if (FIRST) {
+      aux = load_idx<B>(e_src_p + eb);
+    } else {
+      const IdxN<B> h = load_idx<B>(hi_p + eb);
+      const IdxN<B> l = load_idx<B>(lo_p + eb);
 #pragma unroll
       for (int i = 0; i < B; ++i) {
-        const uint32_t e = eb + (uint32_t)i < e1 ? eb + (uint32_t)i : eb;
-        dst[i] = p_load<COHERENT>(pp + (uint64_t)hi_idx[e] * kLanes + lane) ^
-                 p_load<COHERENT>(pp + (uint64_t)lo_idx[e] * kLanes + lane);
+        const bool live = eb + (uint32_t)i < e1 && h.v[i] != l.v[i];
+        const uint64_t* pa = live ? pp + (uint64_t)h.v[i] * kLanes + lane : zero;
+        const uint64_t* pb = live ? pp + (uint64_t)l.v[i] * kLanes + lane : zero;
+        dst[i] = p_load<COHERENT>(pa) ^ p_load<COHERENT>(pb);
+        aux.v[i] = live;
       }
     }
   };
-  if (e0 < e1) gather(e0, w);
+  if (e0 < e1) gather(e0, w, a);
   for (uint32_t eb = e0; eb < e1; eb += B) {
-    if (eb + B < e1) gather(eb + B, wn);
+    if (eb + B < e1) gather(eb + B, wn, an);
 #pragma unroll
     for (int i = 0; i < B; ++i) {
       const uint32_t e = eb + (uint32_t)i;
-      if (e < e1) {
+      // levels >= 3: an empty window (hi == lo) contributes exactly zero
+      if (e < e1 && (FIRST || a.v[i])) {
         const uint64_t aL = subset_xor<KQ>(q + (uint64_t)e * KQ, cb, mk);
-        const uint64_t wv = FIRST ? subset_xor<KQ>(z + (uint64_t)e_src[e] * KQ, cb, mk) : w[i];
+        const uint64_t wv = FIRST ? subset_xor<KQ>(z + (uint64_t)a.v[i] * KQ, cb, mk) : w[i];
         gf_table(tab, wv);
         gf_comb_acc(base, aL, r);
       }
     }
 #pragma unroll
     for (int i = 0; i < B; ++i) w[i] = wn[i];
+    a = an;
   }
 }
 
