@@ -230,7 +230,7 @@ __global__ __launch_bounds__(256) void kb_scan(const MUnit* __restrict__ units, 
       c.row0 = U.row0;
     }
     const uint32_t tile = t - u_begin;
-    TileIn<E> in;
+    TileIn<KQ, E> in;
     load_tile<KQ, E, FIRST, false>(c, tile, lane, in);
     scan_tile<KQ, E, FIRST, false>(c, tile, in, lane, mk, tab);
   }
@@ -405,7 +405,7 @@ rs_status batch_plan(const rs_graph* const* graphs, const rs_query* queries, uin
     Q.z = (uint64_t*)(uintptr_t)pq_off;
     pq_off += align256(8 * n * qp.kq);
     Q.q = (uint64_t*)(uintptr_t)pq_off;
-    pq_off += align256(8 * m * qp.kq * (qp.k - 1));
+    pq_off += align256(8 * (m * (qp.k - 1) + kEdgePad) * qp.kq);
     Q.fsum = (uint64_t*)(uintptr_t)pq_off;
     pq_off += align256(8 * (1ull << qp.k));
     const uint32_t qslot = (uint32_t)P.qs.size();
@@ -546,6 +546,7 @@ static rs_status resolve_plan(BatchPlan& P, BatchWorkspace& W, uint32_t epoch0) 
       if (!L.top && (U.row0 + U.n_items) * 1024 > W.agg.bytes) return RS_EINVAL;
       const uint64_t q_level = (uintptr_t)U.q;  // offset of this level's rows
       if (q_level + 8ull * Q.m * Q.kq > q_off[qi] + 8ull * Q.m * Q.kq * (Q.k - 1)) return RS_EINVAL;
+      if (q_off[qi] + 8ull * ((uint64_t)Q.m * (Q.k - 1) + kEdgePad) * Q.kq > W.per_query.bytes) return RS_EINVAL;
       U.lo = Q.lo;
       U.z = Q.z;
       U.q = (const uint64_t*)(pq + q_level);

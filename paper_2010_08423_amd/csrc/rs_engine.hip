@@ -223,7 +223,7 @@ rs_status run_plain(rs_graph* g, const QueryPlan& qp, const Tuning& tu, uint64_t
     // bounds every group: gc * blocks(gc) <= cpl * blocks(1).
     const uint32_t tblocks = top_blocks(ta, k == 2, kq, 1, tu);
     if (ws.lo.reserve(4 * (m + kEdgePad), st, false) || ws.z.reserve(8 * n * kq, st, false) ||
-        ws.q.reserve(8 * m * kq * (k - 1), st, false) || ws.p0.reserve(8 * p_elems * cpl, st, true) ||
+        ws.q.reserve(8 * (m * (k - 1) + kEdgePad) * kq, st, false) || ws.p0.reserve(8 * p_elems * cpl, st, true) ||
         ws.p1.reserve(8 * p_elems * cpl, st, true) ||
         ws.partial.reserve(8 * 64 * cpl * (uint64_t)tblocks, st, false) ||
         ws.fsum.reserve(8 * (1ull << k), st, false) || ws.out.reserve(64, st, false))

@@ -52,8 +52,9 @@ struct DevBuf {
 // Kernel launch shapes and per-query plan
 // ---------------------------------------------------------------------------
 // The per-edge index arrays (e_src, e_dst, e_t, e_out, hi, lo) hold this many
-// readable entries past m, so a level kernel can fetch a whole tile's indices
-// in one scalar load; entries past m are never used.
+// readable entries past m, and the product table this many rows past its last
+// level, so a level kernel can fetch a whole tile's indices and rows in one
+// load; entries past m are never used.
 constexpr uint32_t kEdgePad = 64;
 
 constexpr uint32_t kFlagAgg = 1;   // record: XOR of the tile's open segment part

@@ -169,6 +169,74 @@ __device__ __forceinline__ IdxN<N> load_idx(const uint32_t* p) {
 // so both gathers of such an edge hit the same cached line and XOR to zero.
 static __device__ const uint64_t kZeroRow[kLanes] = {0};
 
+// The product rows (and, at level 2, the substitution rows) of a group of N
+// consecutive edges, spread over the wave: lane l holds entries l*P .. l*P+P-1
+// of the N x KQ block (P = N*KQ/64 rounded up; P divides KQ, so one lane's
+// entries belong to one edge). They arrive by vector loads issued with the
+// window gathers, so their latency overlaps; an entry is broadcast to a scalar
+// register right before its use. (Scalar loads would share the wait counter
+// of the LDS table accesses and be waited for at the first table read.)
+template <int KQ, int N>
+struct RowBlock {
+  static constexpr int P = (N * KQ + 63) / 64;
+  uint64_t v[P];
+};
+
+// Product rows of edges e0 .. e0+N-1: contiguous at q + e0*KQ.
+template <int KQ, int N>
+__device__ __forceinline__ void load_qrows(RowBlock<KQ, N>& rb, const uint64_t* q, uint32_t e0, uint32_t lane) {
+  constexpr int P = RowBlock<KQ, N>::P;
+  const uint32_t g = lane * P;
+#pragma unroll
+  for (int p = 0; p < P; ++p) rb.v[p] = 0;
+  if (N * KQ >= 64 || g < N * KQ) {
+#pragma unroll
+    for (int p = 0; p < P; ++p) rb.v[p] = *(gu64*)(q + (uint64_t)e0 * KQ + g + p);
+  }
+}
+
+// Substitution rows of the sources of edges e0 .. e0+N-1 (rows of edges at or
+// past ne are not loaded).
+template <int KQ, int N>
+__device__ __forceinline__ void load_zrows(RowBlock<KQ, N>& rb, const uint64_t* z, const uint32_t* e_src,
+                                           uint32_t e0, uint32_t ne, uint32_t lane) {
+  constexpr int P = RowBlock<KQ, N>::P;
+  const uint32_t g = lane * P, i = g / KQ, j = g % KQ;
+#pragma unroll
+  for (int p = 0; p < P; ++p) rb.v[p] = 0;
+  if ((N * KQ >= 64 || g < N * KQ) && i < ne) {
+    const uint32_t src = *(__attribute__((address_space(1))) const uint32_t*)(e_src + e0 + i);
+#pragma unroll
+    for (int p = 0; p < P; ++p) rb.v[p] = *(gu64*)(z + (uint64_t)src * KQ + j + p);
+  }
+}
+
+// Entry j of edge i's row, wave-uniform.
+template <int KQ, int N>
+__device__ __forceinline__ uint64_t row_entry(const RowBlock<KQ, N>& rb, int i, int j) {
+  constexpr int P = RowBlock<KQ, N>::P;
+  const int g = i * KQ + j;
+  const uint64_t v = rb.v[g % P];
+  return mk64(__builtin_amdgcn_readlane(lo32(v), g / P), __builtin_amdgcn_readlane(hi32(v), g / P));
+}
+
+// Per-lane subset XOR of edge i's row (see subset_xor).
+template <int KQ, int N>
+__device__ __forceinline__ uint64_t subset_xor(const RowBlock<KQ, N>& rb, int i, uint64_t cb,
+                                               const uint32_t (&mk)[6]) {
+  uint64_t h = 0;
+#pragma unroll
+  for (int j = 6; j < KQ; ++j) h ^= row_entry<KQ, N>(rb, i, j) & (0ull - ((cb >> j) & 1ull));
+  uint32_t lo = lo32(h), hi = hi32(h);
+#pragma unroll
+  for (int b = 0; b < 6 && b < KQ; ++b) {
+    const uint64_t v = row_entry<KQ, N>(rb, i, b);
+    lo = and_xor(lo32(v), mk[b], lo);
+    hi = and_xor(hi32(v), mk[b], hi);
+  }
+  return mk64(lo, hi);
+}
+
 // Loads the tile's indices (three scalar loads) and issues all of its window
 // gathers at once, without branches: an edge whose window is empty (hi == lo,
 // its sum is zero) or that lies past the tile end gathers the zero row.
@@ -312,22 +380,25 @@ __device__ uint64_t look_back(const TileCtx& c, uint32_t tile, uint32_t lane, co
 // Inputs of one tile, loaded ahead of its compute: per edge its P slot, at
 // level 2 its source vertex (ia) and at levels >= 3 its window sum (w) and
 // whether that window is non-empty (ia).
-template <int E>
+template <int KQ, int E>
 struct TileIn {
   uint32_t slot[E], ia[E];
   uint64_t w[E];
+  RowBlock<KQ, E> qr, zr;  // product rows; substitution rows (level 2)
 };
 
 template <int KQ, int E, bool FIRST, bool COHERENT>
-__device__ __forceinline__ void load_tile(const TileCtx& c, uint32_t tile, uint32_t lane, TileIn<E>& in) {
+__device__ __forceinline__ void load_tile(const TileCtx& c, uint32_t tile, uint32_t lane, TileIn<KQ, E>& in) {
   const uint32_t e0 = tile * (uint32_t)E;
   const uint32_t ne = min((uint32_t)E, c.m - e0);
+  load_qrows<KQ, E>(in.qr, c.q, e0, lane);
+  if (FIRST) load_zrows<KQ, E>(in.zr, c.z, c.e_src, e0, ne, lane);
   tile_inputs<KQ, E, FIRST, COHERENT>(c, e0, ne, lane, in.slot, in.ia, in.w);
 }
 
 // One tile of E edges of a prefix level (2..k-1), inputs already loaded.
 template <int KQ, int E, bool FIRST, bool COHERENT>
-__device__ __forceinline__ void scan_tile(const TileCtx& c, uint32_t tile, const TileIn<E>& in,
+__device__ __forceinline__ void scan_tile(const TileCtx& c, uint32_t tile, const TileIn<KQ, E>& in,
                                           uint32_t lane, const uint32_t (&mk)[6], uint64_t* tab) {
   cu32* e_out = as_const(c.e_out);
   const uint32_t m = c.m;
@@ -341,6 +412,9 @@ __device__ __forceinline__ void scan_tile(const TileCtx& c, uint32_t tile, const
   bool started = !cont;
   uint32_t last_slot = 0;
   uint32_t seg_starts = 0;  // bit i: a segment starts at edge i of the tile
+  // an edge needs a product at level 2, or at levels >= 3 when its window is
+  // non-empty (an empty window contributes exactly zero)
+  auto needs = [&](int i) { return (uint32_t)i < ne && (FIRST || in.ia[i] != 0); };
 #pragma unroll
   for (int i = 0; i < E; ++i) {
     pref[i] = 0;
@@ -351,8 +425,11 @@ __device__ __forceinline__ void scan_tile(const TileCtx& c, uint32_t tile, const
         seg_starts |= 1u << i;
       }
       if (!started) first_len = (uint32_t)i + 1u;
-      // levels >= 3: an edge with an empty window contributes exactly zero
-      if (FIRST || in.ia[i]) acc ^= edge_value<KQ, E, FIRST>(c, e0 + (uint32_t)i, in.ia[i], in.w[i], mk, tab);
+      if (needs(i)) {
+        const uint64_t aL = subset_xor<KQ, E>(in.qr, i, c.cb, mk);
+        const uint64_t wv = FIRST ? subset_xor<KQ, E>(in.zr, i, c.cb, mk) : in.w[i];
+        acc ^= gf_mul(tab, aL, wv);
+      }
       pref[i] = acc;
       last_slot = in.slot[i];
     }
@@ -386,62 +463,64 @@ template <int KQ, int E, bool FIRST, bool COHERENT>
 __device__ __forceinline__ void scan_tiles(const TileCtx& c, uint32_t first, uint32_t stride, uint32_t lane,
                                            const uint32_t (&mk)[6], uint64_t* tab) {
   for (uint32_t tile = first; tile < c.n_tiles; tile += stride) {
-    TileIn<E> in;
+    TileIn<KQ, E> in;
     load_tile<KQ, E, FIRST, COHERENT>(c, tile, lane, in);
     scan_tile<KQ, E, FIRST, COHERENT>(c, tile, in, lane, mk, tab);
   }
 }
 
 // Last level k over edges [e0, e1): unreduced per-lane sum of c_k(e) into r.
-// Edges go in batches of 8: one scalar load per index array and batch, the
-// next batch's gathers in flight during this batch's products; empty windows
-// gather the zero row and skip their product.
+// Edges go in batches of 8: one scalar load per index array and batch, and
+// the next batch's gathers and rows in flight during this batch's products;
+// empty windows gather the zero row and skip their product.
 template <int KQ, bool FIRST, bool COHERENT>
 __device__ __forceinline__ void top_range(const uint32_t* e_src_p, const uint32_t* hi_p,
                                           const uint32_t* lo_p, const uint64_t* q_p,
                                           const uint64_t* z_p, const uint64_t* pp, uint64_t cb,
                                           uint32_t e0, uint32_t e1, uint32_t lane,
                                           const uint32_t (&mk)[6], uint64_t* tab, Acc128& r) {
-  cu64* q = as_const(q_p);
-  cu64* z = as_const(z_p);
   const uint32_t base = lds_addr(tab);
   constexpr int B = 8;
   const uint64_t* zero = kZeroRow + lane;
-  uint64_t w[B], wn[B];
-  IdxN<B> a, an;  // per batch: sources (level 2) or window-is-live flags
-  auto gather = [&](uint32_t eb, uint64_t(&dst)[B], IdxN<B>& aux) {
+  struct Batch {
+    uint64_t w[B];
+    IdxN<B> live;
+    RowBlock<KQ, B> qr, zr;
+  };
+  Batch cur, nxt;
+  auto gather = [&](uint32_t eb, Batch& b) {
+    load_qrows<KQ, B>(b.qr, q_p, eb, lane);
     if (FIRST) {
-      aux = load_idx<B>(e_src_p + eb);
+      load_zrows<KQ, B>(b.zr, z_p, e_src_p, eb, e1 - eb, lane);
+#pragma unroll
+      for (int i = 0; i < B; ++i) b.live.v[i] = eb + (uint32_t)i < e1;
     } else {
       const IdxN<B> h = load_idx<B>(hi_p + eb);
       const IdxN<B> l = load_idx<B>(lo_p + eb);
 #pragma unroll
       for (int i = 0; i < B; ++i) {
+        // levels >= 3: an empty window (hi == lo) contributes exactly zero
         const bool live = eb + (uint32_t)i < e1 && h.v[i] != l.v[i];
         const uint64_t* pa = live ? pp + (uint64_t)h.v[i] * kLanes + lane : zero;
         const uint64_t* pb = live ? pp + (uint64_t)l.v[i] * kLanes + lane : zero;
-        dst[i] = p_load<COHERENT>(pa) ^ p_load<COHERENT>(pb);
-        aux.v[i] = live;
+        b.w[i] = p_load<COHERENT>(pa) ^ p_load<COHERENT>(pb);
+        b.live.v[i] = live;
       }
     }
   };
-  if (e0 < e1) gather(e0, w, a);
+  if (e0 < e1) gather(e0, cur);
   for (uint32_t eb = e0; eb < e1; eb += B) {
-    if (eb + B < e1) gather(eb + B, wn, an);
+    if (eb + B < e1) gather(eb + B, nxt);
 #pragma unroll
     for (int i = 0; i < B; ++i) {
-      const uint32_t e = eb + (uint32_t)i;
-      // levels >= 3: an empty window (hi == lo) contributes exactly zero
-      if (e < e1 && (FIRST || a.v[i])) {
-        const uint64_t aL = subset_xor<KQ>(q + (uint64_t)e * KQ, cb, mk);
-        const uint64_t wv = FIRST ? subset_xor<KQ>(z + (uint64_t)a.v[i] * KQ, cb, mk) : w[i];
+      if (cur.live.v[i]) {
+        const uint64_t aL = subset_xor<KQ, B>(cur.qr, i, cb, mk);
+        const uint64_t wv = FIRST ? subset_xor<KQ, B>(cur.zr, i, cb, mk) : cur.w[i];
         gf_table(tab, wv);
         gf_comb_acc(base, aL, r);
       }
     }
-#pragma unroll
-    for (int i = 0; i < B; ++i) w[i] = wn[i];
-    a = an;
+    cur = nxt;
   }
 }
 
