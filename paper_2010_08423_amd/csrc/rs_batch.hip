@@ -49,6 +49,8 @@ struct BQuery {
   uint64_t* z;
   uint64_t* q;
   uint64_t* fsum;
+  uint8_t* need;  // store flags
+  uint8_t* ref;   // slot marks (scratch shared by the queries of a batch)
   uint64_t seed, it_begin, it_end;
   uint32_t n, m, k, kq, delta, motif;
   uint8_t mu[RS_MAX_COLOURS];
@@ -69,12 +71,13 @@ struct MUnit {
   uint64_t cb;         // first iteration of the chunk
   uint64_t it_begin, it_end;
   uint64_t row0;       // first look-back record row
+  const uint8_t* need; // store flags of the query
   uint32_t m;
   uint32_t n_items;    // edge tiles or edge ranges
   uint32_t epoch;      // record tag epoch of this launch
   uint32_t pad;
 };
-static_assert(sizeof(MUnit) == 120, "MUnit layout");
+static_assert(sizeof(MUnit) == 128, "MUnit layout");
 // Units are read through the constant address space: scalar loads into SGPRs.
 typedef __attribute__((address_space(4))) const MUnit cMUnit;
 
@@ -149,6 +152,25 @@ __global__ __launch_bounds__(256) void kb_qtable(const BQuery* __restrict__ qs, 
       out[j] = gf_reduce(r);
     }
   }
+}
+
+// Store flags of query qi (see mark_need); ref is zeroed by kb_clear_ref.
+__global__ void kb_clear_ref(const BQuery* __restrict__ qs, uint32_t qi) {
+  const BQuery& Q = qs[qi];
+  const uint64_t words = ((uint64_t)Q.m + Q.n + 3) / 4;
+  uint32_t* r = (uint32_t*)Q.ref;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words; i += (uint64_t)gridDim.x * blockDim.x)
+    r[i] = 0;
+}
+__global__ __launch_bounds__(256) void kb_mark_ref(const BQuery* __restrict__ qs, uint32_t qi) {
+  const BQuery& Q = qs[qi];
+  const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < Q.m) mark_ref(Q.hi, Q.lo, e, Q.ref);
+}
+__global__ __launch_bounds__(256) void kb_mark_need(const BQuery* __restrict__ qs, uint32_t qi) {
+  const BQuery& Q = qs[qi];
+  const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < Q.m) mark_need(Q.e_out, Q.ref, e, Q.need);
 }
 
 __global__ void kb_clear_fsum(const BQuery* __restrict__ qs, uint32_t qi) {
@@ -228,6 +250,7 @@ __global__ __launch_bounds__(256) void kb_scan(const MUnit* __restrict__ units, 
       c.n_tiles = U.n_items;
       c.epoch = U.epoch;
       c.row0 = U.row0;
+      c.need = U.need;
     }
     const uint32_t tile = t - u_begin;
     TileIn<KQ, E> in;
@@ -295,7 +318,7 @@ __global__ __launch_bounds__(256) void kb_top(const MUnit* __restrict__ units, c
 // ---------------------------------------------------------------------------
 struct BatchWorkspace {
   std::mutex mu;
-  DevBuf qs, units, ubegin, per_query, parena, agg, incl, out;
+  DevBuf qs, units, ubegin, per_query, parena, agg, incl, out, ref;
   uint32_t epoch = 0;
   std::string key;  // shape of the captured graph
   hipGraphExec_t exec = nullptr;
@@ -334,6 +357,7 @@ struct BatchPlan {
   std::vector<uint32_t> unit_query;   // query slot of each unit
   std::vector<uint64_t> unit_pbytes;  // offset of a unit's prefix buffers in the arena (bytes)
   uint64_t per_query_bytes = 0;
+  uint64_t ref_bytes = 4;     // slot-mark scratch (largest m + n)
   uint64_t parena_bytes = 0;  // prefix-state arena (largest round)
   uint64_t records = 1;       // look-back records (largest round)
   uint32_t scan_launches = 0;
@@ -408,6 +432,9 @@ rs_status batch_plan(const rs_graph* const* graphs, const rs_query* queries, uin
     pq_off += align256(8 * (m * (qp.k - 1) + kEdgePad) * qp.kq);
     Q.fsum = (uint64_t*)(uintptr_t)pq_off;
     pq_off += align256(8 * (1ull << qp.k));
+    Q.need = (uint8_t*)(uintptr_t)pq_off;
+    pq_off += align256(m + kEdgePad);
+    P.ref_bytes = std::max<uint64_t>(P.ref_bytes, (m + n + 3) & ~3ull);
     const uint32_t qslot = (uint32_t)P.qs.size();
     P.qs.push_back(Q);
     P.qidx.push_back(i);
@@ -491,6 +518,7 @@ rs_status batch_plan(const rs_graph* const* graphs, const rs_query* queries, uin
             U.it_begin = Q.it_begin;
             U.it_end = Q.it_end;
             U.row0 = row0[c - rd.first];
+            U.need = Q.need;  // offset, rebased later
             U.m = Q.m;
             U.n_items = top ? (Q.m + TE - 1) / TE : (Q.m + E - 1) / E;
             U.epoch = 0;  // set per call
@@ -527,11 +555,16 @@ static rs_status resolve_plan(BatchPlan& P, BatchWorkspace& W, uint32_t epoch0) 
     z_off[i] = (uintptr_t)Q.z;
     q_off[i] = (uintptr_t)Q.q;
     f_off[i] = (uintptr_t)Q.fsum;
+    const uint64_t need_off = (uintptr_t)Q.need;
     if (f_off[i] + 8 * (1ull << Q.k) > W.per_query.bytes) return RS_EINVAL;
+    if (need_off + Q.m + kEdgePad > W.per_query.bytes) return RS_EINVAL;
+    if ((uint64_t)Q.m + Q.n > W.ref.bytes) return RS_EINVAL;
     Q.lo = (uint32_t*)(pq + lo_off[i]);
     Q.z = (uint64_t*)(pq + z_off[i]);
     Q.q = (uint64_t*)(pq + q_off[i]);
     Q.fsum = (uint64_t*)(pq + f_off[i]);
+    Q.need = (uint8_t*)(pq + need_off);
+    Q.ref = W.ref.as<uint8_t>();
   }
   uint32_t scan_idx = 0;
   for (const BLaunch& L : P.launches) {
@@ -548,6 +581,7 @@ static rs_status resolve_plan(BatchPlan& P, BatchWorkspace& W, uint32_t epoch0) 
       if (q_level + 8ull * Q.m * Q.kq > q_off[qi] + 8ull * Q.m * Q.kq * (Q.k - 1)) return RS_EINVAL;
       if (q_off[qi] + 8ull * ((uint64_t)Q.m * (Q.k - 1) + kEdgePad) * Q.kq > W.per_query.bytes) return RS_EINVAL;
       U.lo = Q.lo;
+      U.need = Q.need;
       U.z = Q.z;
       U.q = (const uint64_t*)(pq + q_level);
       U.pp = (const uint64_t*)(pa + pp_off);
@@ -625,6 +659,10 @@ static rs_status batch_enqueue(BatchPlan& P, BatchWorkspace& W, hipStream_t st) 
     const BQuery& Q = P.qs[qi];
     hipLaunchKernelGGL(kb_ztable, dim3((uint32_t)(((uint64_t)Q.n * Q.kq + 255) / 256)), dim3(256), 0, st, dq, qi);
     hipLaunchKernelGGL(kb_window, dim3((Q.m + 255) / 256), dim3(256), 0, st, dq, qi);
+    hipLaunchKernelGGL(kb_clear_ref, dim3((uint32_t)std::min<uint64_t>(((uint64_t)Q.m + Q.n + 1023) / 1024, 1024)),
+                       dim3(256), 0, st, dq, qi);
+    hipLaunchKernelGGL(kb_mark_ref, dim3((Q.m + 255) / 256), dim3(256), 0, st, dq, qi);
+    hipLaunchKernelGGL(kb_mark_need, dim3((Q.m + 255) / 256), dim3(256), 0, st, dq, qi);
     switch (Q.kq) {
       case 4: hipLaunchKernelGGL(kb_qtable<4>, dim3((Q.m + 255) / 256), dim3(256), 0, st, dq, qi); break;
       case 8: hipLaunchKernelGGL(kb_qtable<8>, dim3((Q.m + 255) / 256), dim3(256), 0, st, dq, qi); break;
@@ -690,20 +728,22 @@ rs_status run_batch_impl(const rs_graph* const* graphs, const rs_query* queries,
     if (results[i].status != RS_OK && first_err == RS_OK) first_err = results[i].status;
   if (P.qs.empty()) return first_err;
   // device memory; a reallocation invalidates the captured graph
-  const void* before[8] = {W.qs.p, W.units.p, W.ubegin.p, W.per_query.p, W.parena.p, W.agg.p, W.incl.p, W.out.p};
+  const void* before[9] = {W.qs.p,   W.units.p, W.ubegin.p, W.per_query.p, W.parena.p,
+                           W.agg.p,  W.incl.p,  W.out.p,    W.ref.p};
   const uint64_t rec_bytes = 1024 * P.records;
   if (W.per_query.reserve(P.per_query_bytes, st, false) || W.qs.reserve(sizeof(BQuery) * P.qs.size(), st, false) ||
       W.units.reserve(sizeof(MUnit) * std::max<size_t>(P.units.size(), 1), st, false) ||
       W.ubegin.reserve(4 * std::max<size_t>(P.ubegin.size(), 1), st, false) ||
       W.parena.reserve(std::max<uint64_t>(P.parena_bytes, 256), st, false) ||
-      W.out.reserve(8 * P.qs.size(), st, false))
+      W.out.reserve(8 * P.qs.size(), st, false) || W.ref.reserve(P.ref_bytes, st, false))
     return RS_ENOMEM;
   if (W.agg.bytes < rec_bytes || W.incl.bytes < rec_bytes) {
     // tagged records start at epoch 0, which no launch uses
     if (W.agg.reserve(rec_bytes, st, true) || W.incl.reserve(rec_bytes, st, true)) return RS_ENOMEM;
     W.epoch = 0;
   }
-  const void* after[8] = {W.qs.p, W.units.p, W.ubegin.p, W.per_query.p, W.parena.p, W.agg.p, W.incl.p, W.out.p};
+  const void* after[9] = {W.qs.p,   W.units.p, W.ubegin.p, W.per_query.p, W.parena.p,
+                          W.agg.p,  W.incl.p,  W.out.p,    W.ref.p};
   if (memcmp(before, after, sizeof(before)) != 0) W.drop_graph();
   if ((uint64_t)W.epoch + P.scan_launches + 1 >= (1ull << 30)) {
     RS_HIP(launch_fill64(W.agg.as<uint64_t>(), 0, W.agg.bytes / 8, st));

@@ -96,6 +96,7 @@ struct ScanArgs {
   uint32_t epoch;
   uint64_t* agg;           // [chunks][n_tiles][64][2] tagged records
   uint64_t* incl;          // [chunks][n_tiles][64][2]
+  const uint8_t* need;     // [m] store flags
 };
 
 // Arguments of the last level k.
@@ -123,6 +124,9 @@ hipError_t launch_ztable(uint64_t* z, uint32_t n, const QueryPlan& qp, const uin
                          hipStream_t st);
 hipError_t launch_window(const uint32_t* e_src, const uint32_t* e_t, const uint32_t* in_off,
                          uint32_t* lo, uint32_t m, uint32_t delta, hipStream_t st);
+// Store flags: ref[m+n] is scratch, need[m] the per-edge flags.
+hipError_t launch_need(const uint32_t* e_out, const uint32_t* hi, const uint32_t* lo, uint32_t m, uint32_t n,
+                       uint8_t* ref, uint8_t* need, hipStream_t st);
 hipError_t launch_qtable(const uint32_t* e_src, const uint32_t* e_dst, const uint32_t* e_t,
                          const uint64_t* z, uint64_t* q, uint32_t m, const QueryPlan& qp,
                          hipStream_t st);
@@ -169,7 +173,7 @@ struct rs_graph {
   // Query workspace cached on the graph; guarded by mu.
   std::mutex mu;
   struct Workspace {
-    rs::DevBuf lo, z, q, p0, p1, partial, agg, incl, fsum, out;
+    rs::DevBuf lo, z, q, p0, p1, partial, agg, incl, fsum, out, ref, need;
     uint32_t epoch = 0;
     uint64_t p_elems_per_chunk = 0;
     uint32_t flag_tiles = 0, flag_chunks = 0;

@@ -24,7 +24,7 @@ __global__ __launch_bounds__(256) void k_scan(
     const uint64_t* __restrict__ q, const uint64_t* __restrict__ z,
     const uint64_t* __restrict__ p_prev, uint64_t* __restrict__ p_cur, uint64_t p_stride,
     uint64_t chunk_base, uint32_t m, uint32_t n_tiles, uint32_t epoch,
-    uint64_t* __restrict__ agg, uint64_t* __restrict__ incl) {
+    uint64_t* __restrict__ agg, uint64_t* __restrict__ incl, const uint8_t* __restrict__ need) {
   extern __shared__ uint64_t dyn_lds[];  // [waves][16][64]; starts at LDS address 0
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform for the compiler
@@ -50,6 +50,7 @@ __global__ __launch_bounds__(256) void k_scan(
   c.row0 = (uint64_t)chunk * n_tiles;
   c.agg = agg;
   c.incl = incl;
+  c.need = need;
   const uint32_t waves = gridDim.x * (blockDim.x >> 6);
   scan_tiles<KQ, E, FIRST, false>(c, blockIdx.x * (blockDim.x >> 6) + wv, waves, lane, mk, tab);
 }
@@ -181,6 +182,19 @@ __global__ __launch_bounds__(256) void k_window(const uint32_t* __restrict__ e_s
   lo[e] = a + v;
 }
 
+__global__ __launch_bounds__(256) void k_mark_ref(const uint32_t* __restrict__ hi, const uint32_t* __restrict__ lo,
+                                                  uint32_t m, uint8_t* __restrict__ ref) {
+  const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < m) mark_ref(hi, lo, e, ref);
+}
+
+__global__ __launch_bounds__(256) void k_mark_need(const uint32_t* __restrict__ e_out,
+                                                   const uint8_t* __restrict__ ref, uint32_t m,
+                                                   uint8_t* __restrict__ need) {
+  const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < m) mark_need(e_out, ref, e, need);
+}
+
 // q[l-2][e][j] = z_{dst(e),j} * y_{e,l-1} for l = 2..k.
 template <int KQ>
 __global__ __launch_bounds__(256) void k_qtable(const uint32_t* __restrict__ e_src,
@@ -277,6 +291,16 @@ hipError_t launch_ztable(uint64_t* z, uint32_t n, const QueryPlan& qp, const uin
   return hipGetLastError();
 }
 
+hipError_t launch_need(const uint32_t* e_out, const uint32_t* hi, const uint32_t* lo, uint32_t m, uint32_t n,
+                       uint8_t* ref, uint8_t* need, hipStream_t st) {
+  if (!m) return hipSuccess;
+  hipError_t e = launch_fill32((uint32_t*)ref, 0, ((uint64_t)m + n + 3) / 4, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_mark_ref, dim3(div_up(m, 256)), dim3(256), 0, st, hi, lo, m, ref);
+  hipLaunchKernelGGL(k_mark_need, dim3(div_up(m, 256)), dim3(256), 0, st, e_out, ref, m, need);
+  return hipGetLastError();
+}
+
 hipError_t launch_window(const uint32_t* e_src, const uint32_t* e_t, const uint32_t* in_off,
                          uint32_t* lo, uint32_t m, uint32_t delta, hipStream_t st) {
   if (!m) return hipSuccess;
@@ -306,7 +330,7 @@ static void scan_one(const ScanArgs& a, uint32_t chunks, uint32_t wpb, hipStream
   dim3 g(std::min(div_up(a.n_tiles, wpb), fit), chunks), b(64 * wpb);
   hipLaunchKernelGGL((k_scan<KQ, E, FIRST>), g, b, lds, st, a.e_src, a.e_out, a.hi, a.lo, a.q, a.z,
                      a.p_prev, a.p_cur, a.p_stride, a.chunk_base, a.m, a.n_tiles, a.epoch, a.agg,
-                     a.incl);
+                     a.incl, a.need);
 }
 
 template <int KQ>

@@ -148,6 +148,7 @@ struct TileCtx {
   uint64_t row0;       // record row of this (chunk, level)
   uint64_t* agg;       // [tiles][64][2] records: XOR of the tile's open segment part
   uint64_t* incl;      // [tiles][64][2] records: inclusive prefix of that segment
+  const uint8_t* need; // per edge: which of its P slots some window reads (see mark_need)
 };
 
 // N consecutive entries of an index array in one scalar load (the arrays are
@@ -385,12 +386,14 @@ struct TileIn {
   uint32_t slot[E], ia[E];
   uint64_t w[E];
   RowBlock<KQ, E> qr, zr;  // product rows; substitution rows (level 2)
+  IdxN<E / 4> need;        // store flags, four edges per word
 };
 
 template <int KQ, int E, bool FIRST, bool COHERENT>
 __device__ __forceinline__ void load_tile(const TileCtx& c, uint32_t tile, uint32_t lane, TileIn<KQ, E>& in) {
   const uint32_t e0 = tile * (uint32_t)E;
   const uint32_t ne = min((uint32_t)E, c.m - e0);
+  in.need = load_idx<E / 4>((const uint32_t*)(c.need + e0));
   load_qrows<KQ, E>(in.qr, c.q, e0, lane);
   if (FIRST) load_zrows<KQ, E>(in.zr, c.z, c.e_src, e0, ne, lane);
   tile_inputs<KQ, E, FIRST, COHERENT>(c, e0, ne, lane, in.slot, in.ia, in.w);
@@ -445,13 +448,17 @@ __device__ __forceinline__ void scan_tile(const TileCtx& c, uint32_t tile, const
     carry = look_back<KQ, E, FIRST, COHERENT>(c, tile, lane, mk, tab);
     if (next_cont && !started) publish(c.incl, fi, lane, carry ^ acc, rec_tag(c.epoch, kFlagIncl));
   }
+  // Only slots that some non-empty window reads are stored (the others are
+  // never read: empty windows gather the zero row).
 #pragma unroll
   for (int i = 0; i < E; ++i) {
+    const uint32_t nf = (in.need.v[i / 4] >> (8 * (i % 4))) & 3u;
     if ((uint32_t)i < ne) {
-      p_store<COHERENT>(c.pc + (uint64_t)in.slot[i] * kLanes + lane, pref[i] ^ ((uint32_t)i < first_len ? carry : 0));
+      if (nf & 1u)
+        p_store<COHERENT>(c.pc + (uint64_t)in.slot[i] * kLanes + lane, pref[i] ^ ((uint32_t)i < first_len ? carry : 0));
       // the segment's leading slot (just before its first edge's slot) holds 0;
       // writing it here lets P buffers be reused across graphs without clearing
-      if ((seg_starts >> i) & 1u) p_store<COHERENT>(c.pc + (uint64_t)(in.slot[i] - 1u) * kLanes + lane, 0);
+      if (((seg_starts >> i) & 1u) && (nf & 2u)) p_store<COHERENT>(c.pc + (uint64_t)(in.slot[i] - 1u) * kLanes + lane, 0);
     }
   }
 }
@@ -522,6 +529,24 @@ __device__ __forceinline__ void top_range(const uint32_t* e_src_p, const uint32_
     }
     cur = nxt;
   }
+}
+
+// Store flags of a query (they depend on the graph and delta only). First
+// every slot that a non-empty window reads is marked (ref, one byte per slot,
+// zeroed beforehand); then need[e] bit 0 says whether e's own slot is read
+// and bit 1 whether the leading slot of the segment e starts is read.
+__device__ __forceinline__ void mark_ref(const uint32_t* hi, const uint32_t* lo, uint64_t e, uint8_t* ref) {
+  const uint32_t h = hi[e], l = lo[e];
+  if (h != l) {
+    ref[h] = 1;
+    ref[l] = 1;
+  }
+}
+__device__ __forceinline__ void mark_need(const uint32_t* e_out, const uint8_t* ref, uint64_t e, uint8_t* need) {
+  const uint32_t slot = e_out[e];
+  uint32_t f = ref[slot];
+  if (e == 0 || e_out[e - 1] + 1u != slot) f |= (uint32_t)ref[slot - 1] << 1;
+  need[e] = (uint8_t)f;
 }
 
 }  // namespace rs
