@@ -159,7 +159,7 @@ typedef struct {
 
 /* HBM bytes rs_run needs for this query on this graph beyond the graph
  * itself: window indices 4m, substitution table 8nk, per-level products
- * 8m*kq*(k-1) (kq = k rounded up to a multiple of 4), store flags 2m+n, two
+ * 8m*kq*(k-1) (kq = k rounded up to a multiple of 4), store flags 2m+5n, two
  * prefix-state buffers 2*8*(m+n)*64 per concurrent chunk, look-back state
  * and 8*2^k of per-iteration sums. */
 rs_status rs_query_footprint(const rs_graph* g, const rs_query* q, uint64_t* bytes);

@@ -49,8 +49,9 @@ struct BQuery {
   uint64_t* z;
   uint64_t* q;
   uint64_t* fsum;
-  uint8_t* need;  // store flags
-  uint8_t* ref;   // slot marks (scratch shared by the queries of a batch)
+  uint8_t* need;     // store and product flags
+  uint8_t* ref;      // slot marks (scratch shared by the queries of a batch)
+  uint32_t* lastref; // last read slot per vertex (scratch, shared)
   uint64_t seed, it_begin, it_end;
   uint32_t n, m, k, kq, delta, motif;
   uint8_t mu[RS_MAX_COLOURS];
@@ -167,10 +168,15 @@ __global__ __launch_bounds__(256) void kb_mark_ref(const BQuery* __restrict__ qs
   const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e < Q.m) mark_ref(Q.hi, Q.lo, e, Q.ref);
 }
+__global__ __launch_bounds__(256) void kb_mark_last(const BQuery* __restrict__ qs, uint32_t qi) {
+  const BQuery& Q = qs[qi];
+  const uint32_t u = blockIdx.x * blockDim.x + threadIdx.x;
+  if (u < Q.n) mark_last(Q.in_off, Q.ref, u, Q.lastref);
+}
 __global__ __launch_bounds__(256) void kb_mark_need(const BQuery* __restrict__ qs, uint32_t qi) {
   const BQuery& Q = qs[qi];
   const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < Q.m) mark_need(Q.e_out, Q.ref, e, Q.need);
+  if (e < Q.m) mark_need(Q.e_out, Q.e_dst, Q.ref, Q.lastref, e, Q.need);
 }
 
 __global__ void kb_clear_fsum(const BQuery* __restrict__ qs, uint32_t qi) {
@@ -318,7 +324,7 @@ __global__ __launch_bounds__(256) void kb_top(const MUnit* __restrict__ units, c
 // ---------------------------------------------------------------------------
 struct BatchWorkspace {
   std::mutex mu;
-  DevBuf qs, units, ubegin, per_query, parena, agg, incl, out, ref;
+  DevBuf qs, units, ubegin, per_query, parena, agg, incl, out, ref, lastref;
   uint32_t epoch = 0;
   std::string key;  // shape of the captured graph
   hipGraphExec_t exec = nullptr;
@@ -358,6 +364,7 @@ struct BatchPlan {
   std::vector<uint64_t> unit_pbytes;  // offset of a unit's prefix buffers in the arena (bytes)
   uint64_t per_query_bytes = 0;
   uint64_t ref_bytes = 4;     // slot-mark scratch (largest m + n)
+  uint64_t n_max = 1;         // largest vertex count (per-vertex scratch)
   uint64_t parena_bytes = 0;  // prefix-state arena (largest round)
   uint64_t records = 1;       // look-back records (largest round)
   uint32_t scan_launches = 0;
@@ -435,6 +442,7 @@ rs_status batch_plan(const rs_graph* const* graphs, const rs_query* queries, uin
     Q.need = (uint8_t*)(uintptr_t)pq_off;
     pq_off += align256(m + kEdgePad);
     P.ref_bytes = std::max<uint64_t>(P.ref_bytes, (m + n + 3) & ~3ull);
+    P.n_max = std::max<uint64_t>(P.n_max, n);
     const uint32_t qslot = (uint32_t)P.qs.size();
     P.qs.push_back(Q);
     P.qidx.push_back(i);
@@ -558,13 +566,14 @@ static rs_status resolve_plan(BatchPlan& P, BatchWorkspace& W, uint32_t epoch0) 
     const uint64_t need_off = (uintptr_t)Q.need;
     if (f_off[i] + 8 * (1ull << Q.k) > W.per_query.bytes) return RS_EINVAL;
     if (need_off + Q.m + kEdgePad > W.per_query.bytes) return RS_EINVAL;
-    if ((uint64_t)Q.m + Q.n > W.ref.bytes) return RS_EINVAL;
+    if ((uint64_t)Q.m + Q.n > W.ref.bytes || 4ull * Q.n > W.lastref.bytes) return RS_EINVAL;
     Q.lo = (uint32_t*)(pq + lo_off[i]);
     Q.z = (uint64_t*)(pq + z_off[i]);
     Q.q = (uint64_t*)(pq + q_off[i]);
     Q.fsum = (uint64_t*)(pq + f_off[i]);
     Q.need = (uint8_t*)(pq + need_off);
     Q.ref = W.ref.as<uint8_t>();
+    Q.lastref = W.lastref.as<uint32_t>();
   }
   uint32_t scan_idx = 0;
   for (const BLaunch& L : P.launches) {
@@ -662,6 +671,7 @@ static rs_status batch_enqueue(BatchPlan& P, BatchWorkspace& W, hipStream_t st) 
     hipLaunchKernelGGL(kb_clear_ref, dim3((uint32_t)std::min<uint64_t>(((uint64_t)Q.m + Q.n + 1023) / 1024, 1024)),
                        dim3(256), 0, st, dq, qi);
     hipLaunchKernelGGL(kb_mark_ref, dim3((Q.m + 255) / 256), dim3(256), 0, st, dq, qi);
+    hipLaunchKernelGGL(kb_mark_last, dim3((Q.n + 255) / 256), dim3(256), 0, st, dq, qi);
     hipLaunchKernelGGL(kb_mark_need, dim3((Q.m + 255) / 256), dim3(256), 0, st, dq, qi);
     switch (Q.kq) {
       case 4: hipLaunchKernelGGL(kb_qtable<4>, dim3((Q.m + 255) / 256), dim3(256), 0, st, dq, qi); break;
@@ -728,22 +738,23 @@ rs_status run_batch_impl(const rs_graph* const* graphs, const rs_query* queries,
     if (results[i].status != RS_OK && first_err == RS_OK) first_err = results[i].status;
   if (P.qs.empty()) return first_err;
   // device memory; a reallocation invalidates the captured graph
-  const void* before[9] = {W.qs.p,   W.units.p, W.ubegin.p, W.per_query.p, W.parena.p,
-                           W.agg.p,  W.incl.p,  W.out.p,    W.ref.p};
+  const void* before[10] = {W.qs.p,  W.units.p, W.ubegin.p, W.per_query.p, W.parena.p,
+                            W.agg.p, W.incl.p,  W.out.p,    W.ref.p,       W.lastref.p};
   const uint64_t rec_bytes = 1024 * P.records;
   if (W.per_query.reserve(P.per_query_bytes, st, false) || W.qs.reserve(sizeof(BQuery) * P.qs.size(), st, false) ||
       W.units.reserve(sizeof(MUnit) * std::max<size_t>(P.units.size(), 1), st, false) ||
       W.ubegin.reserve(4 * std::max<size_t>(P.ubegin.size(), 1), st, false) ||
       W.parena.reserve(std::max<uint64_t>(P.parena_bytes, 256), st, false) ||
-      W.out.reserve(8 * P.qs.size(), st, false) || W.ref.reserve(P.ref_bytes, st, false))
+      W.out.reserve(8 * P.qs.size(), st, false) || W.ref.reserve(P.ref_bytes, st, false) ||
+      W.lastref.reserve(4 * P.n_max, st, false))
     return RS_ENOMEM;
   if (W.agg.bytes < rec_bytes || W.incl.bytes < rec_bytes) {
     // tagged records start at epoch 0, which no launch uses
     if (W.agg.reserve(rec_bytes, st, true) || W.incl.reserve(rec_bytes, st, true)) return RS_ENOMEM;
     W.epoch = 0;
   }
-  const void* after[9] = {W.qs.p,   W.units.p, W.ubegin.p, W.per_query.p, W.parena.p,
-                          W.agg.p,  W.incl.p,  W.out.p,    W.ref.p};
+  const void* after[10] = {W.qs.p,  W.units.p, W.ubegin.p, W.per_query.p, W.parena.p,
+                           W.agg.p, W.incl.p,  W.out.p,    W.ref.p,       W.lastref.p};
   if (memcmp(before, after, sizeof(before)) != 0) W.drop_graph();
   if ((uint64_t)W.epoch + P.scan_launches + 1 >= (1ull << 30)) {
     RS_HIP(launch_fill64(W.agg.as<uint64_t>(), 0, W.agg.bytes / 8, st));

@@ -161,7 +161,7 @@ uint64_t plain_footprint(const rs_graph* g, const QueryPlan& qp, const Tuning& t
   const uint64_t m = g->g.m, n = g->g.n;
   const uint64_t cpl = std::min<uint64_t>(tu.chunks_per_launch, std::max<uint64_t>(chunks_of(qp), 1));
   const uint64_t tiles = (m + tu.edges_per_tile - 1) / tu.edges_per_tile;
-  uint64_t b = 4 * m + 8 * n * qp.kq + 8 * m * qp.kq * (qp.k - 1) + (2 * m + n);
+  uint64_t b = 4 * m + 8 * n * qp.kq + 8 * m * qp.kq * (qp.k - 1) + (2 * m + 5 * n);
   b += 2 * 8 * (m + n) * 64 * cpl;
   b += cpl * tiles * 2 * 1024 + cpl * 512 * 4096;
   b += 8 * (1ull << qp.k) + 64;
@@ -227,7 +227,8 @@ rs_status run_plain(rs_graph* g, const QueryPlan& qp, const Tuning& tu, uint64_t
         ws.p1.reserve(8 * p_elems * cpl, st, true) ||
         ws.partial.reserve(8 * 64 * cpl * (uint64_t)tblocks, st, false) ||
         ws.fsum.reserve(8 * (1ull << k), st, false) || ws.out.reserve(64, st, false) ||
-        ws.ref.reserve(((m + n + 3) & ~3ull), st, false) || ws.need.reserve(m + kEdgePad, st, false))
+        ws.ref.reserve(((m + n + 3) & ~3ull), st, false) || ws.need.reserve(m + kEdgePad, st, false) ||
+        ws.lastref.reserve(4 * n, st, false))
       return RS_ENOMEM;
     if (ws.agg.bytes < 1024 * cpl * tiles || ws.incl.bytes < 1024 * cpl * tiles) {
       // tagged records start at epoch 0, which no launch uses
@@ -243,8 +244,9 @@ rs_status run_plain(rs_graph* g, const QueryPlan& qp, const Tuning& tu, uint64_t
       ProfScope ps(KC_WINDOW, st, 16.0 * m);
       RS_HIP(launch_window(G.e_src.as<uint32_t>(), G.e_t.as<uint32_t>(), G.in_off.as<uint32_t>(),
                            ws.lo.as<uint32_t>(), (uint32_t)m, qp.delta, st));
-      RS_HIP(launch_need(G.e_out.as<uint32_t>(), G.hi.as<uint32_t>(), ws.lo.as<uint32_t>(), (uint32_t)m,
-                         (uint32_t)n, ws.ref.as<uint8_t>(), ws.need.as<uint8_t>(), st));
+      RS_HIP(launch_need(G.in_off.as<uint32_t>(), G.e_dst.as<uint32_t>(), G.e_out.as<uint32_t>(),
+                         G.hi.as<uint32_t>(), ws.lo.as<uint32_t>(), (uint32_t)m, (uint32_t)n, ws.ref.as<uint8_t>(),
+                         ws.lastref.as<uint32_t>(), ws.need.as<uint8_t>(), st));
     }
     {
       ProfScope ps(KC_QTABLE, st, (double)m * (12.0 + 8.0 * kq * (k - 1)));

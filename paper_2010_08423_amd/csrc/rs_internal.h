@@ -62,8 +62,8 @@ constexpr uint32_t kFlagIncl = 2;  // record: full prefix of that segment
 
 struct Tuning {
   uint32_t edges_per_tile = 16;      // scan levels: 8 or 16
-  uint32_t top_edges_per_tile = 16;  // last level
-  uint32_t chunks_per_launch = 1;
+  uint32_t top_edges_per_tile = 8;   // last level
+  uint32_t chunks_per_launch = 4;
   uint32_t waves_per_block = 4;
   uint32_t max_slots = 0;  // batched path; 0 = as many as fit
 };
@@ -124,9 +124,11 @@ hipError_t launch_ztable(uint64_t* z, uint32_t n, const QueryPlan& qp, const uin
                          hipStream_t st);
 hipError_t launch_window(const uint32_t* e_src, const uint32_t* e_t, const uint32_t* in_off,
                          uint32_t* lo, uint32_t m, uint32_t delta, hipStream_t st);
-// Store flags: ref[m+n] is scratch, need[m] the per-edge flags.
-hipError_t launch_need(const uint32_t* e_out, const uint32_t* hi, const uint32_t* lo, uint32_t m, uint32_t n,
-                       uint8_t* ref, uint8_t* need, hipStream_t st);
+// Store and product flags: ref[m+n] and lastref[n] are scratch, need[m] the
+// per-edge flags.
+hipError_t launch_need(const uint32_t* in_off, const uint32_t* e_dst, const uint32_t* e_out, const uint32_t* hi,
+                       const uint32_t* lo, uint32_t m, uint32_t n, uint8_t* ref, uint32_t* lastref, uint8_t* need,
+                       hipStream_t st);
 hipError_t launch_qtable(const uint32_t* e_src, const uint32_t* e_dst, const uint32_t* e_t,
                          const uint64_t* z, uint64_t* q, uint32_t m, const QueryPlan& qp,
                          hipStream_t st);
@@ -173,7 +175,7 @@ struct rs_graph {
   // Query workspace cached on the graph; guarded by mu.
   std::mutex mu;
   struct Workspace {
-    rs::DevBuf lo, z, q, p0, p1, partial, agg, incl, fsum, out, ref, need;
+    rs::DevBuf lo, z, q, p0, p1, partial, agg, incl, fsum, out, ref, need, lastref;
     uint32_t epoch = 0;
     uint64_t p_elems_per_chunk = 0;
     uint32_t flag_tiles = 0, flag_chunks = 0;

@@ -188,11 +188,20 @@ __global__ __launch_bounds__(256) void k_mark_ref(const uint32_t* __restrict__ h
   if (e < m) mark_ref(hi, lo, e, ref);
 }
 
+__global__ __launch_bounds__(256) void k_mark_last(const uint32_t* __restrict__ in_off,
+                                                   const uint8_t* __restrict__ ref, uint32_t n,
+                                                   uint32_t* __restrict__ lastref) {
+  const uint32_t u = blockIdx.x * blockDim.x + threadIdx.x;
+  if (u < n) mark_last(in_off, ref, u, lastref);
+}
+
 __global__ __launch_bounds__(256) void k_mark_need(const uint32_t* __restrict__ e_out,
-                                                   const uint8_t* __restrict__ ref, uint32_t m,
+                                                   const uint32_t* __restrict__ e_dst,
+                                                   const uint8_t* __restrict__ ref,
+                                                   const uint32_t* __restrict__ lastref, uint32_t m,
                                                    uint8_t* __restrict__ need) {
   const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < m) mark_need(e_out, ref, e, need);
+  if (e < m) mark_need(e_out, e_dst, ref, lastref, e, need);
 }
 
 // q[l-2][e][j] = z_{dst(e),j} * y_{e,l-1} for l = 2..k.
@@ -291,13 +300,15 @@ hipError_t launch_ztable(uint64_t* z, uint32_t n, const QueryPlan& qp, const uin
   return hipGetLastError();
 }
 
-hipError_t launch_need(const uint32_t* e_out, const uint32_t* hi, const uint32_t* lo, uint32_t m, uint32_t n,
-                       uint8_t* ref, uint8_t* need, hipStream_t st) {
+hipError_t launch_need(const uint32_t* in_off, const uint32_t* e_dst, const uint32_t* e_out, const uint32_t* hi,
+                       const uint32_t* lo, uint32_t m, uint32_t n, uint8_t* ref, uint32_t* lastref, uint8_t* need,
+                       hipStream_t st) {
   if (!m) return hipSuccess;
   hipError_t e = launch_fill32((uint32_t*)ref, 0, ((uint64_t)m + n + 3) / 4, st);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_mark_ref, dim3(div_up(m, 256)), dim3(256), 0, st, hi, lo, m, ref);
-  hipLaunchKernelGGL(k_mark_need, dim3(div_up(m, 256)), dim3(256), 0, st, e_out, ref, m, need);
+  hipLaunchKernelGGL(k_mark_last, dim3(div_up(n, 256)), dim3(256), 0, st, in_off, ref, n, lastref);
+  hipLaunchKernelGGL(k_mark_need, dim3(div_up(m, 256)), dim3(256), 0, st, e_out, e_dst, ref, lastref, m, need);
   return hipGetLastError();
 }
 

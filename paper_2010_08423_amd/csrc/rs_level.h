@@ -243,7 +243,8 @@ __device__ __forceinline__ uint64_t subset_xor(const RowBlock<KQ, N>& rb, int i,
 // its sum is zero) or that lies past the tile end gathers the zero row.
 template <int KQ, int E, bool FIRST, bool COHERENT>
 __device__ __forceinline__ void tile_inputs(const TileCtx& c, uint32_t e0, uint32_t ne, uint32_t lane,
-                                            uint32_t (&slot)[E], uint32_t (&ia)[E], uint64_t (&w)[E]) {
+                                            const IdxN<E / 4>& need, uint32_t (&slot)[E], uint32_t (&ia)[E],
+                                            uint64_t (&w)[E]) {
   const IdxN<E> so = load_idx<E>(c.e_out + e0);
 #pragma unroll
   for (int i = 0; i < E; ++i) slot[i] = so.v[i];
@@ -257,7 +258,8 @@ __device__ __forceinline__ void tile_inputs(const TileCtx& c, uint32_t e0, uint3
     const uint64_t* zero = kZeroRow + lane;
 #pragma unroll
     for (int i = 0; i < E; ++i) {
-      const bool live = (uint32_t)i < ne && h.v[i] != l.v[i];
+      // gather only where the product is needed (bit 2) and the window is non-empty
+      const bool live = (uint32_t)i < ne && h.v[i] != l.v[i] && ((need.v[i / 4] >> (8 * (i % 4) + 2)) & 1u);
       const uint64_t* pa = live ? c.pp + (uint64_t)h.v[i] * kLanes + lane : zero;
       const uint64_t* pb = live ? c.pp + (uint64_t)l.v[i] * kLanes + lane : zero;
       w[i] = p_load<COHERENT>(pa) ^ p_load<COHERENT>(pb);
@@ -298,6 +300,7 @@ __device__ uint64_t tile_open_part(const TileCtx& c, uint32_t j, uint32_t lane, 
       st = true;
     }
     if (!FIRST && hi_idx[e] == lo_idx[e]) continue;  // empty window: contributes zero
+    if (!(c.need[e] & 4u)) continue;                  // reaches no read slot
     const uint64_t w = FIRST ? 0
                              : p_load<COHERENT>(c.pp + (uint64_t)hi_idx[e] * kLanes + lane) ^
                                    p_load<COHERENT>(c.pp + (uint64_t)lo_idx[e] * kLanes + lane);
@@ -396,7 +399,7 @@ __device__ __forceinline__ void load_tile(const TileCtx& c, uint32_t tile, uint3
   in.need = load_idx<E / 4>((const uint32_t*)(c.need + e0));
   load_qrows<KQ, E>(in.qr, c.q, e0, lane);
   if (FIRST) load_zrows<KQ, E>(in.zr, c.z, c.e_src, e0, ne, lane);
-  tile_inputs<KQ, E, FIRST, COHERENT>(c, e0, ne, lane, in.slot, in.ia, in.w);
+  tile_inputs<KQ, E, FIRST, COHERENT>(c, e0, ne, lane, in.need, in.slot, in.ia, in.w);
 }
 
 // One tile of E edges of a prefix level (2..k-1), inputs already loaded.
@@ -415,9 +418,11 @@ __device__ __forceinline__ void scan_tile(const TileCtx& c, uint32_t tile, const
   bool started = !cont;
   uint32_t last_slot = 0;
   uint32_t seg_starts = 0;  // bit i: a segment starts at edge i of the tile
-  // an edge needs a product at level 2, or at levels >= 3 when its window is
-  // non-empty (an empty window contributes exactly zero)
-  auto needs = [&](int i) { return (uint32_t)i < ne && (FIRST || in.ia[i] != 0); };
+  // an edge needs a product when it reaches a read slot (need bit 2) and, at
+  // levels >= 3, its window is non-empty (an empty window contributes zero)
+  auto needs = [&](int i) {
+    return (uint32_t)i < ne && (FIRST ? ((in.need.v[i / 4] >> (8 * (i % 4) + 2)) & 1u) != 0 : in.ia[i] != 0);
+  };
 #pragma unroll
   for (int i = 0; i < E; ++i) {
     pref[i] = 0;
@@ -531,10 +536,17 @@ __device__ __forceinline__ void top_range(const uint32_t* e_src_p, const uint32_
   }
 }
 
-// Store flags of a query (they depend on the graph and delta only). First
-// every slot that a non-empty window reads is marked (ref, one byte per slot,
-// zeroed beforehand); then need[e] bit 0 says whether e's own slot is read
-// and bit 1 whether the leading slot of the segment e starts is read.
+// Store and product flags of a query (they depend on the graph and delta
+// only). First every slot that a non-empty window reads is marked (ref, one
+// byte per slot, zeroed beforehand); then, per vertex, the last marked slot
+// of its segment is found by a backward scan (lastref, 0 if none; edge slots
+// are >= 1). Then need[e] says
+//   bit 0: e's own slot is read;
+//   bit 1: the leading slot of the segment e starts is read;
+//   bit 2: some slot at or after e's in its segment is read, i.e. e's product
+//          at a prefix level reaches a value that is read.
+// A prefix level skips the product of an edge without bit 2 (it only reaches
+// slots nothing reads) and stores only slots with bit 0 / bit 1.
 __device__ __forceinline__ void mark_ref(const uint32_t* hi, const uint32_t* lo, uint64_t e, uint8_t* ref) {
   const uint32_t h = hi[e], l = lo[e];
   if (h != l) {
@@ -542,10 +554,19 @@ __device__ __forceinline__ void mark_ref(const uint32_t* hi, const uint32_t* lo,
     ref[l] = 1;
   }
 }
-__device__ __forceinline__ void mark_need(const uint32_t* e_out, const uint8_t* ref, uint64_t e, uint8_t* need) {
+// Vertex u's slots are in_off[u] + u (leading) .. in_off[u+1] + u.
+__device__ __forceinline__ void mark_last(const uint32_t* in_off, const uint8_t* ref, uint32_t u, uint32_t* lastref) {
+  const uint32_t a = in_off[u] + u;
+  uint32_t s = in_off[u + 1] + u;
+  while (s > a && !ref[s]) --s;
+  lastref[u] = ref[s] ? s : 0u;
+}
+__device__ __forceinline__ void mark_need(const uint32_t* e_out, const uint32_t* e_dst, const uint8_t* ref,
+                                          const uint32_t* lastref, uint64_t e, uint8_t* need) {
   const uint32_t slot = e_out[e];
   uint32_t f = ref[slot];
   if (e == 0 || e_out[e - 1] + 1u != slot) f |= (uint32_t)ref[slot - 1] << 1;
+  if (slot <= lastref[e_dst[e]]) f |= 4u;
   need[e] = (uint8_t)f;
 }
 

@@ -77,7 +77,7 @@ namespace rs {
 
 static uint64_t footprint_of(const rs_graph* g, const QueryPlan& qp) {
   const uint64_t m = g->g.m, n = g->g.n;
-  const uint64_t per_query = 4 * m + 8 * n * qp.kq + 8 * m * qp.kq * (qp.k - 1) + 8 * (1ull << qp.k) + 2 * m + n;
+  const uint64_t per_query = 4 * m + 8 * n * qp.kq + 8 * m * qp.kq * (qp.k - 1) + 8 * (1ull << qp.k) + 2 * m + 5 * n;
   const uint64_t slot = 2ull * (m + n) * 64 * 8 + 2ull * ((m + 15) / 16) * 1024;  // one chunk's buffers
   return per_query + slot;
 }
