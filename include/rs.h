@@ -202,11 +202,14 @@ rs_status rs_autotune(const rs_graph* g, const rs_query* sample, uint32_t ns, rs
  * class on the launch stream while enabled). Classes: "level_scan" (prefix
  * levels 3..k-1), "level_first" (level 2), "level_top" (level k), "qtable",
  * "ztable", "window" (plain path), "batch" (one whole rs_run_batch launch
- * sequence). algorithmic_bytes sums, per launch, the HBM bytes the level
- * needs at minimum: per edge and chunk 1024 bytes of window gathers (levels
- * >= 3) and 512 bytes of prefix store (prefix levels); per edge once per
- * launch 12 bytes of indices and 8*kq bytes of product row (plus 8*kq of
- * substitution row at level 2).
+ * sequence). algorithmic_bytes sums, per launch, the HBM bytes the exact
+ * computation has to move: per 64-iteration chunk 1024 bytes of window
+ * gathers per edge whose window is non-empty and whose product reaches a read
+ * slot (all non-empty windows at level k), and 512 bytes per prefix slot that
+ * some window reads; per launch the indices and flags of every edge (8 to 13
+ * bytes) and the 8*kq-byte rows of the edges that form a product (twice that
+ * at level 2). The window counts are measured once per (graph, delta) while
+ * timing is on; that first query synchronises once to read them back.
  * ---------------------------------------------------------------------- */
 rs_status rs_profile_enable(int on);
 rs_status rs_profile_reset(void);

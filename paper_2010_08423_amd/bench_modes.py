@@ -118,7 +118,9 @@ def run_serve_mode(args):
 
     rate, window, cap = args.rate, args.window, args.cap
     _log("generating served graphs")
-    gs = inputs.served_graphs()
+    # the 10^7-edge member of the served set is left out: a 10^7-edge plain
+    # query went silent on its first GPU run and is not run until that is explained
+    gs = inputs.served_graphs(sizes=tuple(int(x) for x in args.sizes.split(",")))
     gds = [R.Graph.from_inputs(g) for g in gs]
     ms = [gd.info()["m"] for gd in gds]
     stream = inputs.served_stream(rate, window, len(gs))

@@ -171,20 +171,22 @@ uint64_t plain_footprint(const rs_graph* g, const QueryPlan& qp, const Tuning& t
 // Algorithmic HBM bytes of one prefix-level launch: per edge and chunk two
 // 512-byte window gathers (one z row at level 2) and one 512-byte prefix
 // store, plus the edge's indices and q row.
-// Algorithmic HBM bytes of one level launch over `chunks` 64-iteration chunks:
-// per edge and chunk the two 512-byte prefix-state rows of its window
-// (levels >= 3) and its 512-byte prefix store (prefix levels); per edge once
-// per launch its indices (12 bytes) and its kq-entry product row, and at level
-// 2 its source's kq-entry substitution row.
-double scan_bytes(uint64_t m, uint32_t kq, uint64_t chunks, bool first) {
-  const double per_chunk = (first ? 0.0 : 1024.0) + 512.0;
-  const double per_edge = 12.0 + 8.0 * kq + (first ? 8.0 * kq : 0.0);
-  return (per_chunk * (double)chunks + per_edge) * (double)m;
+// Algorithmic HBM bytes of one level launch over `chunks` 64-iteration
+// chunks: what the exact computation has to move once edges whose window is
+// empty, or whose product reaches no read slot, are skipped and only read
+// slots are stored. Per chunk: two 512-byte window rows per gathered edge and
+// one 512-byte row per stored slot; per launch: the tile indices and flags
+// of every edge and the kq-entry rows of the edges that form a product.
+double scan_bytes(const NeedCounts& nc, uint64_t m, uint32_t kq, uint64_t chunks, bool first) {
+  const double stores = 512.0 * (double)(nc.ref_slots + nc.ref_lead);
+  if (first)  // level 2: no gathers; product and substitution rows of needed edges
+    return stores * (double)chunks + 9.0 * (double)m + 16.0 * kq * (double)nc.needed;
+  return (1024.0 * (double)nc.live_needed + stores) * (double)chunks + 13.0 * (double)m +
+         8.0 * kq * (double)nc.live_needed;
 }
-double top_bytes(uint64_t m, uint32_t kq, uint64_t chunks, bool first) {
-  const double per_chunk = first ? 0.0 : 1024.0;
-  const double per_edge = 12.0 + 8.0 * kq + (first ? 8.0 * kq : 0.0);
-  return (per_chunk * (double)chunks + per_edge) * (double)m;
+double top_bytes(const NeedCounts& nc, uint64_t m, uint32_t kq, uint64_t chunks, bool first) {
+  if (first) return 8.0 * (double)m + 16.0 * kq * (double)m;
+  return 1024.0 * (double)nc.live * (double)chunks + 8.0 * (double)m + 8.0 * kq * (double)nc.live;
 }
 
 // ---------------------------------------------------------------------------
@@ -248,6 +250,29 @@ rs_status run_plain(rs_graph* g, const QueryPlan& qp, const Tuning& tu, uint64_t
                          G.hi.as<uint32_t>(), ws.lo.as<uint32_t>(), (uint32_t)m, (uint32_t)n, ws.ref.as<uint8_t>(),
                          ws.lastref.as<uint32_t>(), ws.need.as<uint8_t>(), st));
     }
+    // Counts for the byte accounting of timed launches: measured once per
+    // delta (a synchronising read-back), only while kernel timing is on.
+    NeedCounts nc;
+    if (profiling_on()) {
+      auto it = g->need_counts.find(qp.delta);
+      if (it == g->need_counts.end()) {
+        unsigned long long h[5] = {0, 0, 0, 0, 0};
+        if (g->counts_dev.reserve(64, st, true)) return RS_ENOMEM;
+        RS_HIP(launch_fill64(g->counts_dev.as<uint64_t>(), 0, 8, st));
+        RS_HIP(launch_need_counts(G.hi.as<uint32_t>(), ws.lo.as<uint32_t>(), ws.need.as<uint8_t>(), (uint32_t)m,
+                                  g->counts_dev.as<unsigned long long>(), st));
+        RS_HIP(hipMemcpyAsync(h, g->counts_dev.p, sizeof(h), hipMemcpyDeviceToHost, st));
+        RS_HIP(hipStreamSynchronize(st));
+        nc.live = h[0];
+        nc.live_needed = h[1];
+        nc.needed = h[2];
+        nc.ref_slots = h[3];
+        nc.ref_lead = h[4];
+        g->need_counts[qp.delta] = nc;
+      } else {
+        nc = it->second;
+      }
+    }
     {
       ProfScope ps(KC_QTABLE, st, (double)m * (12.0 + 8.0 * kq * (k - 1)));
       RS_HIP(launch_qtable(G.e_src.as<uint32_t>(), G.e_dst.as<uint32_t>(), G.e_t.as<uint32_t>(),
@@ -285,7 +310,7 @@ rs_status run_plain(rs_graph* g, const QueryPlan& qp, const Tuning& tu, uint64_t
           a.agg = ws.agg.as<uint64_t>();
           a.incl = ws.incl.as<uint64_t>();
           a.need = ws.need.as<uint8_t>();
-          ProfScope ps(first ? KC_FIRST : KC_SCAN, st, scan_bytes(m, kq, gc, first));
+          ProfScope ps(first ? KC_FIRST : KC_SCAN, st, scan_bytes(nc, m, kq, gc, first));
           RS_HIP(launch_scan(a, first, kq, gc, tu, st));
           std::swap(prev, cur);
         } else {
@@ -305,7 +330,7 @@ rs_status run_plain(rs_graph* g, const QueryPlan& qp, const Tuning& tu, uint64_t
           a.k = k;
           a.partial = ws.partial.as<uint64_t>();
           a.fsum = ws.fsum.as<uint64_t>();
-          ProfScope ps(KC_TOP, st, top_bytes(m, kq, gc, first));
+          ProfScope ps(KC_TOP, st, top_bytes(nc, m, kq, gc, first));
           RS_HIP(launch_top(a, first, kq, gc, tu, st));
         }
       }

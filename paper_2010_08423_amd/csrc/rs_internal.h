@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include <atomic>
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -124,6 +125,19 @@ hipError_t launch_ztable(uint64_t* z, uint32_t n, const QueryPlan& qp, const uin
                          hipStream_t st);
 hipError_t launch_window(const uint32_t* e_src, const uint32_t* e_t, const uint32_t* in_off,
                          uint32_t* lo, uint32_t m, uint32_t delta, hipStream_t st);
+// Edge counts of a query's windows and flags (graph and delta only), used to
+// state the algorithmic bytes of the level launches.
+struct NeedCounts {
+  uint64_t live = 0;         // non-empty windows
+  uint64_t live_needed = 0;  // non-empty windows whose product reaches a read slot
+  uint64_t needed = 0;       // edges whose product reaches a read slot
+  uint64_t ref_slots = 0;    // edge slots that some window reads
+  uint64_t ref_lead = 0;     // leading slots that some window reads
+};
+// counts[5] on the device, zeroed beforehand: live, live_needed, needed,
+// ref_slots, ref_lead.
+hipError_t launch_need_counts(const uint32_t* hi, const uint32_t* lo, const uint8_t* need, uint32_t m,
+                              unsigned long long* counts, hipStream_t st);
 // Store and product flags: ref[m+n] and lastref[n] are scratch, need[m] the
 // per-edge flags.
 hipError_t launch_need(const uint32_t* in_off, const uint32_t* e_dst, const uint32_t* e_out, const uint32_t* hi,
@@ -187,4 +201,7 @@ struct rs_graph {
   bool has_tuned[RS_MAX_K + 1] = {false};
   rs::Tuning batch_tuned;
   bool has_batch_tuned = false;
+  // Window and flag counts per delta, measured when kernel timing is on.
+  std::map<uint32_t, rs::NeedCounts> need_counts;
+  rs::DevBuf counts_dev;
 };

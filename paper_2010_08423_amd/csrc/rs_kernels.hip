@@ -300,6 +300,34 @@ hipError_t launch_ztable(uint64_t* z, uint32_t n, const QueryPlan& qp, const uin
   return hipGetLastError();
 }
 
+__global__ __launch_bounds__(256) void k_need_counts(const uint32_t* __restrict__ hi, const uint32_t* __restrict__ lo,
+                                                     const uint8_t* __restrict__ need, uint32_t m,
+                                                     unsigned long long* __restrict__ counts) {
+  __shared__ unsigned long long part[5];
+  if (threadIdx.x < 5) part[threadIdx.x] = 0;
+  __syncthreads();
+  uint32_t c[5] = {0, 0, 0, 0, 0};
+  for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t f = need[e];
+    const bool live = hi[e] != lo[e];
+    c[0] += live;
+    c[1] += live && (f & 4u);
+    c[2] += (f >> 2) & 1u;
+    c[3] += f & 1u;
+    c[4] += (f >> 1) & 1u;
+  }
+  for (int j = 0; j < 5; ++j) atomicAdd(&part[j], (unsigned long long)c[j]);
+  __syncthreads();
+  if (threadIdx.x < 5) atomicAdd(&counts[threadIdx.x], part[threadIdx.x]);
+}
+
+hipError_t launch_need_counts(const uint32_t* hi, const uint32_t* lo, const uint8_t* need, uint32_t m,
+                              unsigned long long* counts, hipStream_t st) {
+  if (!m) return hipSuccess;
+  hipLaunchKernelGGL(k_need_counts, dim3(std::min(div_up(m, 256), 512u)), dim3(256), 0, st, hi, lo, need, m, counts);
+  return hipGetLastError();
+}
+
 hipError_t launch_need(const uint32_t* in_off, const uint32_t* e_dst, const uint32_t* e_out, const uint32_t* hi,
                        const uint32_t* lo, uint32_t m, uint32_t n, uint8_t* ref, uint32_t* lastref, uint8_t* need,
                        hipStream_t st) {

