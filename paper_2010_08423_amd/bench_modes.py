@@ -6,7 +6,8 @@ batch: 64 queries on the 1,000,000-edge Chung-Lu graph (k uniform in 4..12,
        A step is one rs_run_batch of all 64; the comparison is the same 64
        queries as 64 plain rs_run calls one after another. Fingerprints must
        agree exactly.
-serve: four resident graphs (m = 1e4, 1e5, 1e6, 1e7; uniform and Chung-Lu),
+serve: resident graphs (by default m = 1e4, 1e5, 1e6 of the 1e4..1e7 served
+       set, alternately uniform and Chung-Lu),
        open-loop Poisson arrivals (k uniform in 4..12, delta in 1..100, 30 %
        motif queries over 8 colours) submitted at their arrival times to the
        continuous-batching server; the comparison serves the same arrivals
