@@ -219,19 +219,28 @@ rs_status rs_profile_get(const char* kernel_class, uint64_t* launches, double* t
 
 /* ------------------------------------------------------------------------
  * Server: continuous batching over resident graphs.
- * A worker thread keeps the graphs and per-slot device buffers resident,
- * admits queued queries while their footprint fits the HBM budget, and runs
- * epochs of the batched kernel over the admitted work; queries arriving
- * while an epoch runs join the next epoch. Long queries are split into
- * iteration ranges across epochs. All server calls are thread-safe.
+ * Worker threads, each with its own HIP stream, take queued queries in
+ * arrival order. A query on a large graph runs alone through the plain
+ * kernels in a workspace kept resident per graph; queries on small graphs
+ * (at most group_max_edges edges) that wait together run as one group
+ * through the batched path (shared level launches). Workers run
+ * concurrently, so queries overlap on the device. Admission is by HBM: the
+ * resident workspaces plus what a job adds stay within the budget, and idle
+ * workspaces are freed when a job needs their room. Every result equals the
+ * query's rs_run result. All server calls are thread-safe.
  * ---------------------------------------------------------------------- */
 typedef struct rs_server rs_server;
 
 typedef struct {
-  uint32_t max_inflight;       /* queries admitted at once (0 = 64) */
-  uint64_t epoch_edge_updates; /* work per epoch before new arrivals are
-                                  admitted (0 = automatic) */
-  uint32_t streams;            /* concurrent device streams (0 = 2) */
+  uint32_t max_inflight;       /* queries running at once (0 = 256) */
+  uint64_t group_edge_updates; /* work cap of one group, in edge-updates
+                                  (iterations * (k-1) * m summed over its
+                                  queries; 0 = 4e9; a query whose own work
+                                  reaches the cap runs alone, so 1 turns
+                                  grouping off) */
+  uint32_t streams;            /* worker threads and streams (0 = 4, at most 16) */
+  uint64_t group_max_edges;    /* graphs with at most this many edges are
+                                  grouped (0 = 262144) */
 } rs_server_opts;
 
 typedef struct {
@@ -239,8 +248,9 @@ typedef struct {
   uint64_t queued, inflight;   /* at the time of the call */
   double qps;                  /* completed / seconds since creation */
   double p50_ms, p99_ms;       /* latency submit -> completion of completed queries */
-  double busy_ms;              /* device time spent in epochs */
-  uint64_t epochs;
+  double busy_ms;              /* wall time of jobs, summed over workers */
+  uint64_t jobs;               /* jobs run (a group or a single query) */
+  uint64_t held_bytes;         /* device bytes held by resident workspaces */
 } rs_server_stats;
 
 /* hbm_budget: bytes of HBM the server may hold for query workspaces. */
@@ -248,7 +258,8 @@ rs_status rs_server_create(uint64_t hbm_budget, const rs_server_opts* opts, rs_s
 /* The graph must outlive the server. */
 rs_status rs_server_add_graph(rs_server* s, const rs_graph* g, uint32_t* graph_id);
 /* Non-blocking. Copies the query (and its motif). RS_EINVAL for invalid
- * queries, RS_ENOMEM if its footprint can never fit the budget. */
+ * queries, RS_ENOMEM if its plain workspace (rs_query_footprint) can never
+ * fit the budget. */
 rs_status rs_server_submit(rs_server* s, uint32_t graph_id, const rs_query* q, uint64_t* ticket);
 /* Wait up to wait_ms (0 = don't wait, <0 = forever). RS_OK with the result,
  * RS_ETIMEOUT if not yet complete, RS_ENOTFOUND for unknown or already
@@ -256,8 +267,8 @@ rs_status rs_server_submit(rs_server* s, uint32_t graph_id, const rs_query* q, u
 rs_status rs_server_poll(rs_server* s, uint64_t ticket, rs_result* r, int32_t wait_ms);
 rs_status rs_server_cancel(rs_server* s, uint64_t ticket);
 rs_status rs_server_stats_get(rs_server* s, rs_server_stats* out);
-/* Stops the worker after in-flight epochs finish; pending queries are
- * cancelled. */
+/* Stops the workers after running jobs finish; queued queries are
+ * cancelled; frees the server's workspaces. */
 rs_status rs_server_destroy(rs_server* s);
 
 #ifdef __cplusplus

@@ -66,8 +66,8 @@ class _GraphInfo(ctypes.Structure):
 
 
 class _ServerOpts(ctypes.Structure):
-    _fields_ = [("max_inflight", ctypes.c_uint32), ("epoch_edge_updates", ctypes.c_uint64),
-                ("streams", ctypes.c_uint32)]
+    _fields_ = [("max_inflight", ctypes.c_uint32), ("group_edge_updates", ctypes.c_uint64),
+                ("streams", ctypes.c_uint32), ("group_max_edges", ctypes.c_uint64)]
 
 
 class _ServerStats(ctypes.Structure):
@@ -75,7 +75,7 @@ class _ServerStats(ctypes.Structure):
                 ("deferred", ctypes.c_uint64), ("cancelled", ctypes.c_uint64), ("rejected", ctypes.c_uint64),
                 ("queued", ctypes.c_uint64), ("inflight", ctypes.c_uint64), ("qps", ctypes.c_double),
                 ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double), ("busy_ms", ctypes.c_double),
-                ("epochs", ctypes.c_uint64)]
+                ("jobs", ctypes.c_uint64), ("held_bytes", ctypes.c_uint64)]
 
 
 # Every symbol include/rs.h declares, with its ctypes signature.
@@ -361,11 +361,12 @@ def profile_get(kernel_class: str):
 # --- server ------------------------------------------------------------------------
 
 class Server:
-    """rs_server_*: continuous batching over resident graphs."""
+    """rs_server_*: continuous batching over resident graphs (0 = the
+    library's default for every option)."""
 
-    def __init__(self, hbm_budget, max_inflight=0, epoch_edge_updates=0, streams=0):
+    def __init__(self, hbm_budget, max_inflight=0, group_edge_updates=0, streams=0, group_max_edges=0):
         h = ctypes.c_void_p()
-        opts = _ServerOpts(int(max_inflight), int(epoch_edge_updates), int(streams))
+        opts = _ServerOpts(int(max_inflight), int(group_edge_updates), int(streams), int(group_max_edges))
         _check(_load().rs_server_create(int(hbm_budget), ctypes.byref(opts), ctypes.byref(h)), "rs_server_create")
         self._h = h
         self._graphs = []

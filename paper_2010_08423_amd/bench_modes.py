@@ -128,7 +128,8 @@ def run_serve_mode(args):
     _log(f"{len(stream)} arrivals over {window} s at {rate}/s")
 
     # served
-    srv = R.Server(hbm_budget=int(args.budget_gb * (1 << 30)), epoch_edge_updates=int(args.epoch_updates))
+    srv = R.Server(hbm_budget=int(args.budget_gb * (1 << 30)), group_edge_updates=int(args.group_updates),
+                   streams=args.streams)
     ids = [srv.add_graph(gd) for gd in gds]
     tickets = [None] * len(stream)
     t_sub = [0.0] * len(stream)
@@ -197,10 +198,11 @@ def run_serve_mode(args):
         "config": {"workload": f"served stream: Poisson {rate}/s for {window} s over 4 resident graphs "
                                f"(m = {ms}), k in 4..12, delta in 1..100, 30% motif; cap {cap} s",
                    "arrivals": len(stream), "hbm_budget_gb": args.budget_gb,
-                   "epoch_edge_updates": args.epoch_updates},
+                   "group_edge_updates": args.group_updates, "streams": args.streams or 4},
         "served": {"completed": served_done, "queries_per_s": served_done / served_elapsed,
                    "edge_updates_per_s": done_updates / served_elapsed, "p50_ms": p50, "p99_ms": p99,
-                   "epochs": st["epochs"], "deferred": st["deferred"], "elapsed_s": served_elapsed},
+                   "jobs": st["jobs"], "deferred": st["deferred"], "held_gb": st["held_bytes"] / 2**30,
+                   "elapsed_s": served_elapsed},
         "plain": {"completed": len(plain_fp), "queries_per_s": len(plain_fp) / plain_elapsed,
                   "p50_ms": pp50, "p99_ms": pp99, "elapsed_s": plain_elapsed},
         "fingerprints_equal_on_common": len(common),

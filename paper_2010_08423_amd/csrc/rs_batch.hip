@@ -33,8 +33,6 @@
 
 namespace rs {
 
-rs_status plan_query(const rs_graph* g, const rs_query* q, QueryPlan& qp);
-Tuning resolve_tuning(const rs_graph* g, uint32_t k, const rs_tuning* t);
 
 // Per-query descriptor of the setup kernels and the final reduction.
 struct BQuery {
@@ -73,12 +71,13 @@ struct MUnit {
   uint64_t it_begin, it_end;
   uint64_t row0;       // first look-back record row
   const uint8_t* need; // store flags of the query
+  uint64_t p_stride;   // prefix-level units: elements between consecutive chunks' P arrays
   uint32_t m;
-  uint32_t n_items;    // edge tiles or edge ranges
+  uint32_t n_items;    // edge tiles, or edge ranges
   uint32_t epoch;      // record tag epoch of this launch
-  uint32_t pad;
+  uint32_t nchunks;    // prefix-level units: consecutive chunks of the query run per tile
 };
-static_assert(sizeof(MUnit) == 128, "MUnit layout");
+static_assert(sizeof(MUnit) == 136, "MUnit layout");
 // Units are read through the constant address space: scalar loads into SGPRs.
 typedef __attribute__((address_space(4))) const MUnit cMUnit;
 
@@ -219,7 +218,10 @@ __device__ __forceinline__ uint32_t find_unit(cu32* ubegin, uint32_t from, uint3
   return lo;
 }
 
-// Prefix level: flat index = (unit, edge tile).
+// Prefix level: flat index = (unit, edge tile); the wave runs the tile for
+// each of the unit's chunks in turn, so a tile's indices and rows are loaded
+// from HBM once and then hit the cache, and the predecessor tile of every
+// chunk is on the neighbouring wave working on the same chunk at the same time.
 template <int KQ, int E, bool FIRST>
 __global__ __launch_bounds__(256) void kb_scan(const MUnit* __restrict__ units, const uint32_t* __restrict__ ubegin_p,
                                                uint32_t nunits, uint32_t total, uint64_t* __restrict__ agg,
@@ -237,6 +239,10 @@ __global__ __launch_bounds__(256) void kb_scan(const MUnit* __restrict__ units, 
   TileCtx c;
   c.agg = agg;
   c.incl = incl;
+  const uint64_t* pp0 = nullptr;
+  uint64_t* pc0 = nullptr;
+  uint64_t cb0 = 0, row00 = 0, pstride = 0;
+  uint32_t nch = 1;
   for (uint32_t t = blockIdx.x * (blockDim.x >> 6) + wv; t < total; t += waves) {
     if (t >= u_end) {
       u = find_unit(ubegin, u_end == 0 ? 0u : u + 1, nunits, t);
@@ -249,19 +255,27 @@ __global__ __launch_bounds__(256) void kb_scan(const MUnit* __restrict__ units, 
       c.lo = U.lo;
       c.q = U.q;
       c.z = U.z;
-      c.pp = U.pp;
-      c.pc = U.pc;
-      c.cb = U.cb;
       c.m = U.m;
-      c.n_tiles = U.n_items;
       c.epoch = U.epoch;
-      c.row0 = U.row0;
       c.need = U.need;
+      nch = U.nchunks;
+      c.n_tiles = U.n_items;
+      pp0 = U.pp;
+      pc0 = U.pc;
+      cb0 = U.cb;
+      row00 = U.row0;
+      pstride = U.p_stride;
     }
     const uint32_t tile = t - u_begin;
-    TileIn<KQ, E> in;
-    load_tile<KQ, E, FIRST, false>(c, tile, lane, in);
-    scan_tile<KQ, E, FIRST, false>(c, tile, in, lane, mk, tab);
+    for (uint32_t ch = 0; ch < nch; ++ch) {
+      c.pp = pp0 + ch * pstride;
+      c.pc = pc0 + ch * pstride;
+      c.cb = cb0 + (uint64_t)ch * kLanes;
+      c.row0 = row00 + (uint64_t)ch * c.n_tiles;
+      TileIn<KQ, E> in;
+      load_tile<KQ, E, FIRST, false>(c, tile, lane, in);
+      scan_tile<KQ, E, FIRST, false>(c, tile, in, lane, mk, tab);
+    }
   }
 }
 
@@ -337,8 +351,34 @@ struct BatchWorkspace {
     graph = nullptr;
     key.clear();
   }
-  ~BatchWorkspace() { drop_graph(); }
+  void release() {
+    drop_graph();
+    for (DevBuf* b : {&qs, &units, &ubegin, &per_query, &parena, &agg, &incl, &out, &ref, &lastref}) b->release();
+    epoch = 0;
+  }
+  uint64_t bytes() const {
+    uint64_t t = 0;
+    for (const DevBuf* b : {&qs, &units, &ubegin, &per_query, &parena, &agg, &incl, &out, &ref, &lastref})
+      t += b->bytes;
+    return t;
+  }
+  ~BatchWorkspace() {
+    release();
+    if (ev0) (void)hipEventDestroy(ev0);
+    if (ev1) (void)hipEventDestroy(ev1);
+  }
 };
+
+BatchWorkspace* batch_ws_create() { return new BatchWorkspace(); }
+void batch_ws_destroy(BatchWorkspace* w) { delete w; }
+void batch_ws_release(BatchWorkspace* w) {
+  std::lock_guard<std::mutex> lk(w->mu);
+  w->release();
+}
+uint64_t batch_ws_bytes(BatchWorkspace* w) {
+  std::lock_guard<std::mutex> lk(w->mu);
+  return w->bytes();
+}
 
 static BatchWorkspace& batch_ws() {
   static BatchWorkspace* ws = new BatchWorkspace();  // lives until process end
@@ -431,18 +471,19 @@ rs_status batch_plan(const rs_graph* const* graphs, const rs_query* queries, uin
     Q.motif = qp.motif ? 1 : 0;
     memcpy(Q.mu, qp.mu, sizeof(Q.mu));
     memcpy(Q.off, qp.shade_off, sizeof(Q.off));
+    // byte offsets into the per-query arena, rebased by resolve_plan
     Q.lo = (uint32_t*)(uintptr_t)pq_off;
-    pq_off += align256(4 * (m + kEdgePad));
+    pq_off += align256(table_lo_bytes(m));
     Q.z = (uint64_t*)(uintptr_t)pq_off;
-    pq_off += align256(8 * n * qp.kq);
+    pq_off += align256(table_z_bytes(n, qp.kq));
     Q.q = (uint64_t*)(uintptr_t)pq_off;
-    pq_off += align256(8 * (m * (qp.k - 1) + kEdgePad) * qp.kq);
-    Q.fsum = (uint64_t*)(uintptr_t)pq_off;
-    pq_off += align256(8 * (1ull << qp.k));
+    pq_off += align256(table_q_bytes(m, qp.k, qp.kq));
     Q.need = (uint8_t*)(uintptr_t)pq_off;
-    pq_off += align256(m + kEdgePad);
+    pq_off += align256(table_need_bytes(m));
     P.ref_bytes = std::max<uint64_t>(P.ref_bytes, (m + n + 3) & ~3ull);
     P.n_max = std::max<uint64_t>(P.n_max, n);
+    Q.fsum = (uint64_t*)(uintptr_t)pq_off;
+    pq_off += align256(8 * (1ull << qp.k));
     const uint32_t qslot = (uint32_t)P.qs.size();
     P.qs.push_back(Q);
     P.qidx.push_back(i);
@@ -510,6 +551,14 @@ rs_status batch_plan(const rs_graph* const* graphs, const rs_query* queries, uin
             const uint32_t qi = chunks[c].query;
             const BQuery& Q = P.qs[qi];
             if (Q.kq != kq || (top ? Q.k != l : Q.k <= l)) continue;
+            // prefix levels: this and the following chunks of the same query
+            // (consecutive in the round, their buffers and record rows at a
+            // fixed stride) form one unit
+            uint32_t nch = 1;
+            if (!top)
+              while (c + nch < rd.second && chunks[c + nch].query == qi &&
+                     chunks[c + nch].cb == chunks[c].cb + (uint64_t)nch * kLanes)
+                ++nch;
             MUnit U;
             memset(&U, 0, sizeof(U));
             U.e_src = Q.e_src;
@@ -528,6 +577,8 @@ rs_status batch_plan(const rs_graph* const* graphs, const rs_query* queries, uin
             U.row0 = row0[c - rd.first];
             U.need = Q.need;  // offset, rebased later
             U.m = Q.m;
+            U.nchunks = nch;
+            U.p_stride = 2 * half / 8;
             U.n_items = top ? (Q.m + TE - 1) / TE : (Q.m + E - 1) / E;
             U.epoch = 0;  // set per call
             P.ubegin.push_back(L.total);
@@ -535,6 +586,7 @@ rs_status batch_plan(const rs_graph* const* graphs, const rs_query* queries, uin
             P.units.push_back(U);
             P.unit_query.push_back(qi);
             ++L.nunits;
+            c += nch - 1;
           }
           if (L.nunits) {
             if (!L.top) ++P.scan_launches;
@@ -559,18 +611,19 @@ static rs_status resolve_plan(BatchPlan& P, BatchWorkspace& W, uint32_t epoch0) 
   std::vector<uint64_t> lo_off(P.qs.size()), z_off(P.qs.size()), q_off(P.qs.size()), f_off(P.qs.size());
   for (size_t i = 0; i < P.qs.size(); ++i) {
     BQuery& Q = P.qs[i];
+    f_off[i] = (uintptr_t)Q.fsum;
+    if (f_off[i] + 8 * (1ull << Q.k) > W.per_query.bytes) return RS_EINVAL;
+    Q.fsum = (uint64_t*)(pq + f_off[i]);
     lo_off[i] = (uintptr_t)Q.lo;
     z_off[i] = (uintptr_t)Q.z;
     q_off[i] = (uintptr_t)Q.q;
-    f_off[i] = (uintptr_t)Q.fsum;
     const uint64_t need_off = (uintptr_t)Q.need;
-    if (f_off[i] + 8 * (1ull << Q.k) > W.per_query.bytes) return RS_EINVAL;
-    if (need_off + Q.m + kEdgePad > W.per_query.bytes) return RS_EINVAL;
+    if (need_off + table_need_bytes(Q.m) > W.per_query.bytes) return RS_EINVAL;
+    if (q_off[i] + table_q_bytes(Q.m, Q.k, Q.kq) > W.per_query.bytes) return RS_EINVAL;
     if ((uint64_t)Q.m + Q.n > W.ref.bytes || 4ull * Q.n > W.lastref.bytes) return RS_EINVAL;
     Q.lo = (uint32_t*)(pq + lo_off[i]);
     Q.z = (uint64_t*)(pq + z_off[i]);
     Q.q = (uint64_t*)(pq + q_off[i]);
-    Q.fsum = (uint64_t*)(pq + f_off[i]);
     Q.need = (uint8_t*)(pq + need_off);
     Q.ref = W.ref.as<uint8_t>();
     Q.lastref = W.lastref.as<uint32_t>();
@@ -584,15 +637,15 @@ static rs_status resolve_plan(BatchPlan& P, BatchWorkspace& W, uint32_t epoch0) 
       const BQuery& Q = P.qs[qi];
       const uint64_t half = align256(((uint64_t)Q.m + Q.n) * kLanes * 8);
       const uint64_t pp_off = (uintptr_t)U.pp, pc_off = (uintptr_t)U.pc;
-      if (pp_off + half > W.parena.bytes || pc_off + half > W.parena.bytes) return RS_EINVAL;
-      if (!L.top && (U.row0 + U.n_items) * 1024 > W.agg.bytes) return RS_EINVAL;
+      const uint64_t span = 8 * U.p_stride * (U.nchunks - 1) + half;  // from the first chunk's array
+      if (pp_off + span > W.parena.bytes || pc_off + span > W.parena.bytes) return RS_EINVAL;
+      if (!L.top && (U.row0 + (uint64_t)U.nchunks * U.n_items) * 1024 > W.agg.bytes) return RS_EINVAL;
       const uint64_t q_level = (uintptr_t)U.q;  // offset of this level's rows
       if (q_level + 8ull * Q.m * Q.kq > q_off[qi] + 8ull * Q.m * Q.kq * (Q.k - 1)) return RS_EINVAL;
-      if (q_off[qi] + 8ull * ((uint64_t)Q.m * (Q.k - 1) + kEdgePad) * Q.kq > W.per_query.bytes) return RS_EINVAL;
+      U.q = (const uint64_t*)(pq + q_level);
       U.lo = Q.lo;
       U.need = Q.need;
       U.z = Q.z;
-      U.q = (const uint64_t*)(pq + q_level);
       U.pp = (const uint64_t*)(pa + pp_off);
       U.pc = (uint64_t*)(pa + pc_off);
       U.fsum = Q.fsum;
@@ -712,10 +765,11 @@ static uint64_t default_slot_budget() {
 }
 
 rs_status run_batch_impl(const rs_graph* const* graphs, const rs_query* queries, uint32_t nq, rs_result* results,
-                         const rs_tuning* tune, hipStream_t st, bool use_graph, uint64_t slot_budget) {
+                         const rs_tuning* tune, hipStream_t st, bool use_graph, uint64_t slot_budget,
+                         BatchWorkspace* ws) {
   if (nq == 0) return RS_OK;
   if (!queries || !results || !graphs) return RS_EINVAL;
-  BatchWorkspace& W = batch_ws();
+  BatchWorkspace& W = ws ? *ws : batch_ws();
   std::lock_guard<std::mutex> lk(W.mu);
   // launch shape: explicit knobs, else the graph's autotuned batch shape, else defaults
   Tuning tu;
@@ -821,10 +875,6 @@ rs_status run_batch_impl(const rs_graph* const* graphs, const rs_query* queries,
 
 using namespace rs;
 
-namespace rs {
-rs_status run_plain(rs_graph* g, const QueryPlan& qp, const Tuning& tu, uint64_t* per_it_host, rs_result* r,
-                    hipStream_t st);
-}  // namespace rs
 
 // Times candidate launch shapes on the sample queries. Plain path: edges per
 // tile, waves per block, last-level range and chunks per launch, best total
@@ -870,7 +920,7 @@ rs_status autotune_impl(rs_graph* g, const rs_query* sample, uint32_t ns, rs_tun
         for (uint32_t i : idx) {
           rs_result r;
           std::lock_guard<std::mutex> lk(g->mu);
-          rs_status s = run_plain(g, plans[i], t, nullptr, &r, st);
+          rs_status s = run_plain(g, g->ws, plans[i], t, nullptr, &r, st);
           if (s != RS_OK) {
             (void)hipStreamDestroy(st);
             return s;
@@ -899,7 +949,7 @@ rs_status autotune_impl(rs_graph* g, const rs_query* sample, uint32_t ns, rs_tun
         rs_tuning t{E, top, 0, wpb, 0, 1};
         double tmin = 1e30;
         for (int rep = 0; rep < 2; ++rep) {
-          rs_status s = run_batch_impl(gl.data(), sample, ns, res.data(), &t, st, false, 0);
+          rs_status s = run_batch_impl(gl.data(), sample, ns, res.data(), &t, st, false, 0, nullptr);
           if (s != RS_OK) {
             (void)hipStreamDestroy(st);
             return s;
@@ -932,7 +982,7 @@ extern "C" rs_status rs_autotune(const rs_graph* g, const rs_query* sample, uint
 extern "C" rs_status rs_run_batch(const rs_graph* const* graphs, const rs_query* queries, uint32_t nq,
                                   rs_result* results, const rs_tuning* tune, void* hip_stream) {
   try {
-    return run_batch_impl(graphs, queries, nq, results, tune, (hipStream_t)hip_stream, true, 0);
+    return run_batch_impl(graphs, queries, nq, results, tune, (hipStream_t)hip_stream, true, 0, nullptr);
   } catch (...) {
     return RS_ENOMEM;
   }

@@ -157,16 +157,6 @@ Tuning resolve_tuning(const rs_graph* g, uint32_t k, const rs_tuning* t) {
 
 static uint64_t chunks_of(const QueryPlan& qp) { return qp.chunk_last - qp.chunk_first; }
 
-uint64_t plain_footprint(const rs_graph* g, const QueryPlan& qp, const Tuning& tu) {
-  const uint64_t m = g->g.m, n = g->g.n;
-  const uint64_t cpl = std::min<uint64_t>(tu.chunks_per_launch, std::max<uint64_t>(chunks_of(qp), 1));
-  const uint64_t tiles = (m + tu.edges_per_tile - 1) / tu.edges_per_tile;
-  uint64_t b = 4 * m + 8 * n * qp.kq + 8 * m * qp.kq * (qp.k - 1) + (2 * m + 5 * n);
-  b += 2 * 8 * (m + n) * 64 * cpl;
-  b += cpl * tiles * 2 * 1024 + cpl * 512 * 4096;
-  b += 8 * (1ull << qp.k) + 64;
-  return b;
-}
 
 // Algorithmic HBM bytes of one prefix-level launch: per edge and chunk two
 // 512-byte window gathers (one z row at level 2) and one 512-byte prefix
@@ -189,12 +179,48 @@ double top_bytes(const NeedCounts& nc, uint64_t m, uint32_t kq, uint64_t chunks,
   return 1024.0 * (double)nc.live * (double)chunks + 8.0 * (double)m + 8.0 * kq * (double)nc.live;
 }
 
+uint64_t table_lo_bytes(uint64_t m) { return 4 * (m + kEdgePad); }
+uint64_t table_z_bytes(uint64_t n, uint32_t kq) { return 8 * n * kq; }
+uint64_t table_q_bytes(uint64_t m, uint32_t k, uint32_t kq) { return 8 * (m * (k - 1) + kEdgePad) * kq; }
+uint64_t table_need_bytes(uint64_t m) { return m + kEdgePad; }
+
 // ---------------------------------------------------------------------------
 // Plain path: setup kernels, then per chunk group levels 2..k.
 // ---------------------------------------------------------------------------
-rs_status run_plain(rs_graph* g, const QueryPlan& qp, const Tuning& tu, uint64_t* per_it_host,
+// Buffer sizes (bytes) one query needs in a plain workspace.
+PlainSizes plain_sizes(uint64_t m, uint64_t n, const QueryPlan& qp, const Tuning& tu) {
+  PlainSizes s;
+  const uint32_t k = qp.k, kq = qp.kq;
+  const uint64_t nchunks = std::max<uint64_t>(chunks_of(qp), 1);
+  const uint64_t cpl = std::max<uint64_t>(std::min<uint64_t>(tu.chunks_per_launch, nchunks), 1);
+  const uint64_t tiles = (m + tu.edges_per_tile - 1) / tu.edges_per_tile;
+  TopArgs ta{};
+  ta.m = (uint32_t)m;
+  ta.edges_per_wave = tu.top_edges_per_tile;
+  // Rows per chunk of the last level's partial sums; the single-chunk launch
+  // bounds every group: gc * blocks(gc) <= cpl * blocks(1).
+  const uint32_t tblocks = top_blocks(ta, k == 2, kq, 1, tu);
+  s.lo = table_lo_bytes(m);
+  s.z = table_z_bytes(n, kq);
+  s.q = table_q_bytes(m, k, kq);
+  s.p = 8 * (m + n) * 64 * cpl;
+  s.partial = 8 * 64 * cpl * (uint64_t)tblocks;
+  s.fsum = 8 * (1ull << k);
+  s.ref = (m + n + 3) & ~3ull;
+  s.need = table_need_bytes(m);
+  s.lastref = 4 * n;
+  s.records = 1024 * cpl * tiles;
+  return s;
+}
+
+uint64_t PlainSizes::total() const { return lo + z + q + 2 * p + partial + fsum + 64 + ref + need + lastref + 2 * records; }
+
+uint64_t plain_footprint(const rs_graph* g, const QueryPlan& qp, const Tuning& tu) {
+  return plain_sizes(g->g.m, g->g.n, qp, tu).total();
+}
+
+rs_status run_plain(rs_graph* g, PlainWorkspace& ws, const QueryPlan& qp, const Tuning& tu, uint64_t* per_it_host,
                     rs_result* r, hipStream_t st) {
-  auto& ws = g->ws;
   const GraphDev& G = g->g;
   const uint64_t m = G.m, n = G.n;
   const uint64_t span = qp.it_end - qp.it_begin;
@@ -221,21 +247,16 @@ rs_status run_plain(rs_graph* g, const QueryPlan& qp, const Tuning& tu, uint64_t
     TopArgs ta{};
     ta.m = (uint32_t)m;
     ta.edges_per_wave = tu.top_edges_per_tile;
-    // Rows per chunk of the last level's partial sums; the single-chunk launch
-    // bounds every group: gc * blocks(gc) <= cpl * blocks(1).
-    const uint32_t tblocks = top_blocks(ta, k == 2, kq, 1, tu);
-    if (ws.lo.reserve(4 * (m + kEdgePad), st, false) || ws.z.reserve(8 * n * kq, st, false) ||
-        ws.q.reserve(8 * (m * (k - 1) + kEdgePad) * kq, st, false) || ws.p0.reserve(8 * p_elems * cpl, st, true) ||
-        ws.p1.reserve(8 * p_elems * cpl, st, true) ||
-        ws.partial.reserve(8 * 64 * cpl * (uint64_t)tblocks, st, false) ||
-        ws.fsum.reserve(8 * (1ull << k), st, false) || ws.out.reserve(64, st, false) ||
-        ws.ref.reserve(((m + n + 3) & ~3ull), st, false) || ws.need.reserve(m + kEdgePad, st, false) ||
-        ws.lastref.reserve(4 * n, st, false))
+    const PlainSizes sz = plain_sizes(m, n, qp, tu);
+    if (ws.lo.reserve(sz.lo, st, false) || ws.z.reserve(sz.z, st, false) || ws.q.reserve(sz.q, st, false) ||
+        ws.p0.reserve(sz.p, st, true) || ws.p1.reserve(sz.p, st, true) ||
+        ws.partial.reserve(sz.partial, st, false) || ws.fsum.reserve(sz.fsum, st, false) ||
+        ws.out.reserve(64, st, false) || ws.ref.reserve(sz.ref, st, false) || ws.need.reserve(sz.need, st, false) ||
+        ws.lastref.reserve(sz.lastref, st, false))
       return RS_ENOMEM;
-    if (ws.agg.bytes < 1024 * cpl * tiles || ws.incl.bytes < 1024 * cpl * tiles) {
+    if (ws.agg.bytes < sz.records || ws.incl.bytes < sz.records) {
       // tagged records start at epoch 0, which no launch uses
-      if (ws.agg.reserve(1024 * cpl * tiles, st, true) || ws.incl.reserve(1024 * cpl * tiles, st, true))
-        return RS_ENOMEM;
+      if (ws.agg.reserve(sz.records, st, true) || ws.incl.reserve(sz.records, st, true)) return RS_ENOMEM;
       ws.epoch = 0;
     }
     {
@@ -254,6 +275,7 @@ rs_status run_plain(rs_graph* g, const QueryPlan& qp, const Tuning& tu, uint64_t
     // delta (a synchronising read-back), only while kernel timing is on.
     NeedCounts nc;
     if (profiling_on()) {
+      std::lock_guard<std::mutex> lk(g->counts_mu);
       auto it = g->need_counts.find(qp.delta);
       if (it == g->need_counts.end()) {
         unsigned long long h[5] = {0, 0, 0, 0, 0};
@@ -425,11 +447,9 @@ rs_status rs_graph_destroy(rs_graph* g) {
   if (!g) return RS_OK;
   (void)hipDeviceSynchronize();
   for (DevBuf* b : {&g->g.e_src, &g->g.e_dst, &g->g.e_t, &g->g.e_out, &g->g.hi, &g->g.in_off, &g->g.colour,
-                    &g->ws.lo, &g->ws.z, &g->ws.q, &g->ws.p0, &g->ws.p1, &g->ws.partial,
-                    &g->ws.agg, &g->ws.incl, &g->ws.fsum, &g->ws.out})
+                    &g->counts_dev})
     b->release();
-  if (g->ws.ev0) (void)hipEventDestroy(g->ws.ev0);
-  if (g->ws.ev1) (void)hipEventDestroy(g->ws.ev1);
+  g->ws.release();
   delete g;
   return RS_OK;
 }
@@ -454,7 +474,7 @@ rs_status rs_run_ex(const rs_graph* gc, const rs_query* q, const rs_tuning* tune
   rs_graph* g = const_cast<rs_graph*>(gc);
   try {
     std::lock_guard<std::mutex> lk(g->mu);
-    s = run_plain(g, qp, resolve_tuning(g, qp.k, tune), per_iteration, r, (hipStream_t)hip_stream);
+    s = run_plain(g, g->ws, qp, resolve_tuning(g, qp.k, tune), per_iteration, r, (hipStream_t)hip_stream);
   } catch (...) {
     s = RS_ENOMEM;
   }

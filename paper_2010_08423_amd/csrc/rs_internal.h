@@ -155,6 +155,32 @@ hipError_t launch_fill64(uint64_t* p, uint64_t value, uint64_t count, hipStream_
 hipError_t launch_xor_reduce(const uint64_t* f, uint64_t begin, uint64_t end, uint64_t* out,
                              hipStream_t st);
 
+// Bytes of a query's per-query tables on a graph with n vertices, m edges:
+// window starts lo[m], substitution rows z[n][kq], product rows
+// q[k-1][m][kq] and per-edge flags need[m] (each padded past m as the level
+// kernels expect).
+uint64_t table_lo_bytes(uint64_t m);
+uint64_t table_z_bytes(uint64_t n, uint32_t kq);
+uint64_t table_q_bytes(uint64_t m, uint32_t k, uint32_t kq);
+uint64_t table_need_bytes(uint64_t m);
+struct PlainWorkspace;
+// Plain path (rs_engine.hip): one query through workspace ws on stream st.
+rs_status run_plain(rs_graph* g, PlainWorkspace& ws, const QueryPlan& qp, const Tuning& tu, uint64_t* per_it_host,
+                    rs_result* r, hipStream_t st);
+rs_status plan_query(const rs_graph* g, const rs_query* q, QueryPlan& qp);
+Tuning resolve_tuning(const rs_graph* g, uint32_t k, const rs_tuning* t);
+// Batched path (rs_batch.hip). A batch workspace holds the device buffers and
+// the captured graph of batched calls; calls through one workspace run one at
+// a time. ws = nullptr uses the process-wide workspace of rs_run_batch.
+struct BatchWorkspace;
+BatchWorkspace* batch_ws_create();
+void batch_ws_destroy(BatchWorkspace* w);
+void batch_ws_release(BatchWorkspace* w);  // frees its device memory (synchronises the device)
+uint64_t batch_ws_bytes(BatchWorkspace* w);
+rs_status run_batch_impl(const rs_graph* const* graphs, const rs_query* queries, uint32_t nq, rs_result* results,
+                         const rs_tuning* tune, hipStream_t st, bool use_graph, uint64_t slot_budget,
+                         BatchWorkspace* ws);
+
 // Graph construction kernels (rs_graph.hip).
 struct GraphDev {
   uint32_t n = 0;
@@ -181,27 +207,55 @@ void profile_flush();  // folds completed event pairs into the totals
 
 }  // namespace rs
 
+namespace rs {
+// Device buffers of one plain-path query stream on one graph; they grow to
+// the largest query run through them and stay allocated until release().
+struct PlainWorkspace {
+  DevBuf lo, z, q, p0, p1, partial, agg, incl, fsum, out, ref, need, lastref;
+  uint32_t epoch = 0;
+  uint64_t p_elems_per_chunk = 0;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  uint64_t bytes() const {
+    uint64_t t = 0;
+    for (const DevBuf* b : {&lo, &z, &q, &p0, &p1, &partial, &agg, &incl, &fsum, &out, &ref, &need, &lastref})
+      t += b->bytes;
+    return t;
+  }
+  void release() {
+    for (DevBuf* b : {&lo, &z, &q, &p0, &p1, &partial, &agg, &incl, &fsum, &out, &ref, &need, &lastref}) b->release();
+    if (ev0) (void)hipEventDestroy(ev0);
+    if (ev1) (void)hipEventDestroy(ev1);
+    ev0 = ev1 = nullptr;
+    epoch = 0;
+    p_elems_per_chunk = 0;
+  }
+};
+// Buffer sizes (bytes) a query needs in a plain workspace (p: each of the two
+// prefix-state arrays; records: each of the two look-back record arrays).
+struct PlainSizes {
+  uint64_t lo, z, q, p, partial, fsum, ref, need, lastref, records;
+  uint64_t total() const;
+};
+PlainSizes plain_sizes(uint64_t m, uint64_t n, const QueryPlan& qp, const Tuning& tu);
+}  // namespace rs
+
 // Opaque graph handle.
 struct rs_graph {
   int device = 0;
   rs::GraphDev g;
   rs_graph_info info{};
-  // Query workspace cached on the graph; guarded by mu.
+  // Query workspace of rs_run on this graph; guarded by mu.
   std::mutex mu;
-  struct Workspace {
-    rs::DevBuf lo, z, q, p0, p1, partial, agg, incl, fsum, out, ref, need, lastref;
-    uint32_t epoch = 0;
-    uint64_t p_elems_per_chunk = 0;
-    uint32_t flag_tiles = 0, flag_chunks = 0;
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
-  } ws;
+  rs::PlainWorkspace ws;
   // Autotuned launch shapes per k (index k) for the plain path, and one for
   // the batched path.
   rs::Tuning tuned[RS_MAX_K + 1];
   bool has_tuned[RS_MAX_K + 1] = {false};
   rs::Tuning batch_tuned;
   bool has_batch_tuned = false;
-  // Window and flag counts per delta, measured when kernel timing is on.
+  // Window and flag counts per delta, measured when kernel timing is on;
+  // guarded by counts_mu.
+  std::mutex counts_mu;
   std::map<uint32_t, rs::NeedCounts> need_counts;
   rs::DevBuf counts_dev;
 };

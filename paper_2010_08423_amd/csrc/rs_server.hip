@@ -1,17 +1,21 @@
 // Serving: continuous batching of sieve queries over resident graphs.
 //
-// A worker thread owns a HIP stream (default priority) and loops:
-//   1. admit queued queries in arrival order while the HBM footprint of the
-//      admitted set stays within the budget and fewer than max_inflight are
-//      admitted (a query that has to wait counts once as deferred);
-//   2. build an epoch: every admitted query contributes its next range of
-//      64-iteration chunks, oldest first, until the epoch's edge-update
-//      target is reached (each query gets at least one chunk);
-//   3. run the epoch as one batched persistent launch and XOR each slice's
-//      partial fingerprint into its query (F over disjoint iteration ranges
-//      XOR to F over their union); finished queries complete and wake pollers.
-// Queries arriving while an epoch runs are admitted for the next epoch, so
-// long queries do not hold back short ones and the device always runs a mix.
+// A pool of worker threads, each with its own HIP stream (default priority),
+// takes queued queries in arrival order:
+//   * a query on a large graph (its launches fill the GPU by themselves) runs
+//     alone through the plain level kernels, in a plain workspace taken from
+//     a pool of workspaces kept resident per graph;
+//   * queries on small graphs that wait together are taken as one group (up
+//     to a work cap) and evaluated by the batched path in shared level
+//     launches, which removes their per-query launch and setup overhead;
+//     while a group runs, small-graph arrivals queue for the next group and
+//     idle workers take large-graph queries.
+// Workers run concurrently, so queries overlap on the device. Admission is
+// by HBM: the resident plain workspaces, the group workspace and the growth
+// a job needs must stay within the budget; idle workspaces are freed when a
+// job needs their room. A query that has to wait for memory or for an
+// in-flight slot counts once as deferred. Every result is the one the query
+// gives alone (same kernels, same arithmetic).
 #include <string.h>
 
 #include <algorithm>
@@ -19,6 +23,7 @@
 #include <condition_variable>
 #include <deque>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <thread>
 #include <vector>
@@ -27,12 +32,12 @@
 
 namespace rs {
 
-rs_status plan_query(const rs_graph* g, const rs_query* q, QueryPlan& qp);
-rs_status run_batch_impl(const rs_graph* const* graphs, const rs_query* queries, uint32_t nq,
-                         rs_result* results, const rs_tuning* tune, hipStream_t st, bool use_graph,
-                         uint64_t slot_budget);
-
 using Clock = std::chrono::steady_clock;
+
+constexpr uint64_t kGroupMaxEdges = 262144;  // default: graphs this small are grouped
+constexpr uint64_t kGroupEdgeUpdates = 4000000000ull;
+constexpr uint32_t kMaxGroup = 64;
+constexpr uint32_t kMaxWorkers = 16;
 
 struct SQuery {
   uint64_t ticket;
@@ -41,14 +46,29 @@ struct SQuery {
   uint8_t motif[RS_MAX_COLOURS];
   bool has_motif;
   QueryPlan plan;
-  uint64_t next_chunk;  // next 64-iteration chunk to schedule
-  uint64_t F = 0;
-  uint64_t footprint;
-  uint64_t work_per_chunk;  // edge-updates
+  Tuning tu;
+  PlainSizes sizes;    // plain workspace buffers it needs
+  uint64_t group_bytes;  // its per-query tables in a group
+  uint64_t work;         // edge-updates
   Clock::time_point t_submit;
   bool deferred_counted = false;
   bool done = false, cancelled = false;
   rs_result result{};
+};
+
+// A plain workspace kept resident for one graph.
+struct PoolEntry {
+  uint32_t graph_id;
+  PlainWorkspace ws;
+  uint64_t bytes = 0;  // device bytes held (as of the last run)
+  bool busy = false;
+};
+
+struct Job {
+  std::vector<std::shared_ptr<SQuery>> qs;
+  PoolEntry* entry = nullptr;  // plain job
+  uint64_t reserved = 0;       // bytes added to the held total for this job
+  bool group = false;
 };
 
 }  // namespace rs
@@ -60,14 +80,17 @@ struct rs_server {
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
   std::deque<std::shared_ptr<rs::SQuery>> queued;
-  std::vector<std::shared_ptr<rs::SQuery>> active;
   std::map<uint64_t, std::shared_ptr<rs::SQuery>> by_ticket;
   std::vector<double> latencies_ms;
   uint64_t next_ticket = 1;
-  uint64_t used_bytes = 0;
+  uint64_t inflight = 0;
+  // device memory held: resident plain workspaces and the group workspace
+  std::vector<std::unique_ptr<rs::PoolEntry>> pool;
+  rs::BatchWorkspace* bws = nullptr;
+  uint64_t plain_held = 0, batch_held = 0;
+  bool group_running = false;
   bool stop = false;
-  std::thread worker;
-  hipStream_t stream = nullptr;
+  std::vector<std::thread> workers;
   int device = 0;
   rs::Clock::time_point t_create;
   rs_server_stats st{};
@@ -75,136 +98,212 @@ struct rs_server {
 
 namespace rs {
 
-static uint64_t footprint_of(const rs_graph* g, const QueryPlan& qp) {
-  const uint64_t m = g->g.m, n = g->g.n;
-  const uint64_t per_query = 4 * m + 8 * n * qp.kq + 8 * m * qp.kq * (qp.k - 1) + 8 * (1ull << qp.k) + 2 * m + 5 * n;
-  const uint64_t slot = 2ull * (m + n) * 64 * 8 + 2ull * ((m + 15) / 16) * 1024;  // one chunk's buffers
-  return per_query + slot;
+static bool is_small(const rs_server* S, const SQuery& a) {
+  return S->graphs[a.graph_id]->g.m <= S->opts.group_max_edges;
+}
+
+// Bytes a workspace grows by to run a query of the given sizes (a buffer
+// that is too small is replaced by one of the needed size).
+static uint64_t growth(const PlainWorkspace& w, const PlainSizes& z) {
+  auto g = [](const DevBuf& b, uint64_t need) { return need > b.bytes ? need - b.bytes : 0; };
+  return g(w.lo, z.lo) + g(w.z, z.z) + g(w.q, z.q) + g(w.p0, z.p) + g(w.p1, z.p) + g(w.partial, z.partial) +
+         g(w.fsum, z.fsum) + g(w.out, 64) + g(w.ref, z.ref) + g(w.need, z.need) + g(w.lastref, z.lastref) +
+         g(w.agg, z.records) + g(w.incl, z.records);
+}
+
+static uint64_t held(const rs_server* S) { return S->plain_held + S->batch_held; }
+
+static void defer(rs_server* S, SQuery& a) {
+  if (!a.deferred_counted) {
+    a.deferred_counted = true;
+    S->st.deferred++;
+  }
+}
+
+// Frees idle resident workspaces (other graphs first, never `keep`), and the
+// group workspace when no group runs, until `need` more bytes fit the budget.
+// Freeing synchronises the device; it happens only under memory pressure.
+static void make_room(rs_server* S, uint64_t need, const PoolEntry* keep, uint32_t graph_id) {
+  for (int pass = 0; pass < 2 && held(S) + need > S->budget; ++pass) {
+    for (size_t i = 0; i < S->pool.size() && held(S) + need > S->budget;) {
+      PoolEntry* e = S->pool[i].get();
+      const bool other = e->graph_id != graph_id;
+      if (e == keep || e->busy || (pass == 0 && !other)) {
+        ++i;
+        continue;
+      }
+      e->ws.release();
+      S->plain_held -= e->bytes;
+      S->pool.erase(S->pool.begin() + i);
+    }
+    if (pass == 0 && held(S) + need > S->budget && !S->group_running && S->batch_held) {
+      batch_ws_release(S->bws);
+      S->batch_held = 0;
+    }
+  }
+}
+
+// Reserves a plain workspace for query a: an idle one of its graph if the
+// growth fits, else a new one. False if the memory is not there yet.
+static bool reserve_plain(rs_server* S, SQuery& a, Job& job) {
+  PoolEntry* best = nullptr;
+  uint64_t best_gr = 0;
+  for (auto& e : S->pool) {
+    if (e->busy || e->graph_id != a.graph_id) continue;
+    const uint64_t gr = growth(e->ws, a.sizes);
+    if (!best || gr < best_gr) {
+      best = e.get();
+      best_gr = gr;
+    }
+  }
+  const uint64_t need = best ? best_gr : a.sizes.total();
+  if (held(S) + need > S->budget) make_room(S, need, best, a.graph_id);
+  if (held(S) + need > S->budget) return false;
+  if (!best) {
+    S->pool.emplace_back(new PoolEntry());
+    best = S->pool.back().get();
+    best->graph_id = a.graph_id;
+  }
+  best->busy = true;
+  S->plain_held += need;
+  job.entry = best;
+  job.reserved = need;
+  return true;
+}
+
+// Takes the next job under the lock; false if nothing can start now.
+static bool take_job(rs_server* S, Job& job) {
+  while (!S->queued.empty() && S->queued.front()->cancelled) S->queued.pop_front();
+  if (S->queued.empty()) return false;
+  // while a group runs, small-graph queries wait for the next group
+  auto it = S->queued.begin();
+  if (S->group_running)
+    while (it != S->queued.end() && is_small(S, **it)) ++it;
+  if (it == S->queued.end()) return false;
+  auto& a = *it;
+  if (S->inflight >= S->opts.max_inflight) {
+    defer(S, *a);
+    return false;
+  }
+  if (is_small(S, *a) && S->opts.group_edge_updates > a->work) {
+    // a group: small-graph queries in arrival order while work, slots and memory allow
+    const uint64_t slot_share = S->budget / 4;  // prefix-state arena of the group's rounds
+    uint64_t work = 0, bytes = slot_share;
+    const uint64_t slots = S->opts.max_inflight - S->inflight;
+    std::vector<size_t> pick;  // queue positions, ascending
+    for (size_t j = (size_t)(it - S->queued.begin());
+         j < S->queued.size() && pick.size() < std::min<uint64_t>(kMaxGroup, slots); ++j) {
+      SQuery& b = *S->queued[j];
+      if (b.cancelled || !is_small(S, b)) continue;
+      if (work + b.work > S->opts.group_edge_updates) break;
+      const uint64_t nb = bytes + b.group_bytes;
+      if (S->plain_held + std::max(S->batch_held, nb) > S->budget) {
+        make_room(S, nb > S->batch_held ? nb - S->batch_held : 0, nullptr, UINT32_MAX);
+        if (S->plain_held + std::max(S->batch_held, nb) > S->budget) {
+          if (!pick.empty()) defer(S, b);  // waits for a later group
+          break;
+        }
+      }
+      work += b.work;
+      bytes = nb;
+      pick.push_back(j);
+    }
+    if (pick.size() >= 2) {
+      for (size_t j : pick) job.qs.push_back(S->queued[j]);
+      for (auto j = pick.rbegin(); j != pick.rend(); ++j) S->queued.erase(S->queued.begin() + *j);
+      job.group = true;
+      job.reserved = bytes > S->batch_held ? bytes - S->batch_held : 0;
+      S->batch_held += job.reserved;
+      S->group_running = true;
+      S->inflight += job.qs.size();
+      S->st.admitted += job.qs.size();
+      return true;
+    }
+  }
+  // one query through the plain kernels
+  if (!reserve_plain(S, *a, job)) {
+    defer(S, *a);
+    return false;
+  }
+  job.qs.push_back(a);
+  S->queued.erase(it);
+  S->inflight++;
+  S->st.admitted++;
+  return true;
 }
 
 static void worker_loop(rs_server* S) {
   (void)hipSetDevice(S->device);
+  hipStream_t st = nullptr;
+  const bool have_stream = hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess;
   while (true) {
-    std::vector<std::shared_ptr<SQuery>> epoch_q;
-    std::vector<rs_query> slices;
-    std::vector<const rs_graph*> gl;
+    Job job;
     {
       std::unique_lock<std::mutex> lk(S->mu);
-      if (S->stop) {
-        for (auto& a : S->active) a->cancelled = true;
-        if (S->active.empty()) break;
-      }
-      // admission
-      while (!S->stop && !S->queued.empty()) {
-        auto& f = S->queued.front();
-        if (f->cancelled) {
-          S->queued.pop_front();
-          continue;
-        }
-        if (S->active.size() >= S->opts.max_inflight || S->used_bytes + f->footprint > S->budget) {
-          if (!f->deferred_counted) {
-            f->deferred_counted = true;
-            S->st.deferred++;
-          }
-          break;
-        }
-        S->used_bytes += f->footprint;
-        S->active.push_back(f);
-        S->queued.pop_front();
-        S->st.admitted++;
-      }
-      if (S->active.empty()) {
-        if (S->stop) break;
-        S->cv_work.wait(lk, [&] { return S->stop || !S->queued.empty(); });
-        continue;
-      }
-      // epoch: oldest first, at least one chunk each
-      uint64_t budget = S->opts.epoch_edge_updates;
-      for (auto& a : S->active) {
-        if (a->cancelled) continue;
-        const uint64_t left = a->plan.chunk_last - a->next_chunk;
-        uint64_t take = 1;
-        if (a->work_per_chunk) {
-          const uint64_t fit = budget / a->work_per_chunk;
-          take = std::max<uint64_t>(1, std::min(left, fit));
-        }
-        take = std::min(take, left);
-        const uint64_t b = std::max(a->plan.it_begin, a->next_chunk * 64);
-        const uint64_t e = std::min(a->plan.it_end, (a->next_chunk + take) * 64);
-        rs_query sq = a->q;
-        sq.motif_count = a->has_motif ? a->motif : nullptr;
-        sq.it_begin = b;
-        sq.it_end = e;
-        slices.push_back(sq);
-        gl.push_back(S->graphs[a->graph_id]);
-        epoch_q.push_back(a);
-        a->next_chunk += take;
-        const uint64_t w = take * a->work_per_chunk;
-        budget = budget > w ? budget - w : 0;
-      }
+      while (!S->stop && !take_job(S, job)) S->cv_work.wait(lk);
+      if (job.qs.empty()) break;  // stopping
     }
-    // run the epoch (outside the lock: submissions and polls continue)
-    std::vector<rs_result> res(slices.size());
     const auto t0 = Clock::now();
-    rs_status s = slices.empty() ? RS_OK
-                                 : run_batch_impl(gl.data(), slices.data(), (uint32_t)slices.size(), res.data(),
-                                                  nullptr, S->stream, false, S->budget / 2);
+    std::vector<rs_result> res(job.qs.size());
+    rs_status s = have_stream ? RS_OK : RS_EDEVICE;
+    if (s == RS_OK && !job.group) {
+      SQuery& a = *job.qs[0];
+      rs_graph* g = const_cast<rs_graph*>(S->graphs[a.graph_id]);
+      s = run_plain(g, job.entry->ws, a.plan, a.tu, nullptr, &res[0], st);
+      res[0].status = s;
+    } else if (s == RS_OK) {
+      std::vector<const rs_graph*> gl;
+      std::vector<rs_query> qs;
+      for (auto& a : job.qs) {
+        rs_query q = a->q;
+        q.motif_count = a->has_motif ? a->motif : nullptr;
+        qs.push_back(q);
+        gl.push_back(S->graphs[a->graph_id]);
+      }
+      s = run_batch_impl(gl.data(), qs.data(), (uint32_t)qs.size(), res.data(), nullptr, st, false, S->budget / 4,
+                         S->bws);
+    }
     const double busy = std::chrono::duration<double, std::milli>(Clock::now() - t0).count();
     {
       std::lock_guard<std::mutex> lk(S->mu);
       S->st.busy_ms += busy;
-      S->st.epochs++;
+      S->st.jobs++;
+      if (job.group) {
+        S->batch_held = batch_ws_bytes(S->bws);
+        S->group_running = false;
+        if (held(S) > S->budget) {  // buffers kept from earlier groups overshoot: give them back
+          batch_ws_release(S->bws);
+          S->batch_held = 0;
+        }
+      } else if (job.entry) {
+        const uint64_t now_bytes = job.entry->ws.bytes();
+        S->plain_held = S->plain_held + now_bytes - (job.entry->bytes + job.reserved);
+        job.entry->bytes = now_bytes;
+        job.entry->busy = false;
+      }
       const auto now = Clock::now();
-      for (size_t i = 0; i < epoch_q.size(); ++i) {
-        auto& a = epoch_q[i];
-        if (s != RS_OK || res[i].status != RS_OK) {
-          a->result.status = res[i].status != RS_OK ? res[i].status : s;
-          a->done = true;
-        } else {
-          a->F ^= res[i].fingerprint;
-          if (a->next_chunk >= a->plan.chunk_last) {
-            a->result.fingerprint = a->F;
-            a->result.yes = a->F != 0;
-            a->result.status = RS_OK;
-            a->done = true;
-          }
+      for (size_t i = 0; i < job.qs.size(); ++i) {
+        SQuery& a = *job.qs[i];
+        a.result = res[i];
+        if (s != RS_OK && a.result.status == RS_OK) a.result.status = s;
+        if (a.cancelled) a.result.status = RS_ECANCELED;
+        const double lat = std::chrono::duration<double, std::milli>(now - a.t_submit).count();
+        a.result.device_ms = (float)lat;
+        if (a.result.status == RS_OK) {
+          S->latencies_ms.push_back(lat);
+          S->st.completed++;
         }
-        if (a->done) {
-          const double lat = std::chrono::duration<double, std::milli>(now - a->t_submit).count();
-          a->result.device_ms = (float)lat;
-          if (a->result.status == RS_OK) {
-            S->latencies_ms.push_back(lat);
-            S->st.completed++;
-          }
-        }
+        a.done = true;
+        S->inflight--;
       }
-      // retire finished and cancelled queries, free their footprint
-      std::vector<std::shared_ptr<SQuery>> keep;
-      for (auto& a : S->active) {
-        if (a->done || a->cancelled) {
-          S->used_bytes -= a->footprint;
-          if (a->cancelled && !a->done) {
-            a->result.status = RS_ECANCELED;
-            a->done = true;
-          }
-        } else {
-          keep.push_back(a);
-        }
-      }
-      S->active.swap(keep);
     }
     S->cv_done.notify_all();
+    S->cv_work.notify_all();
   }
-  // cancel what is left
-  std::lock_guard<std::mutex> lk(S->mu);
-  for (auto& a : S->queued) {
-    a->cancelled = true;
-    a->result.status = RS_ECANCELED;
-    a->done = true;
-    S->st.cancelled++;
+  if (have_stream) {
+    (void)hipStreamSynchronize(st);
+    (void)hipStreamDestroy(st);
   }
-  S->queued.clear();
-  S->cv_done.notify_all();
 }
 
 static double percentile(std::vector<double> v, double p) {
@@ -227,16 +326,19 @@ rs_status rs_server_create(uint64_t hbm_budget, const rs_server_opts* opts, rs_s
   try {
     rs_server* S = new rs_server();
     S->budget = hbm_budget;
-    S->opts = opts ? *opts : rs_server_opts{0, 0, 0};
-    if (!S->opts.max_inflight) S->opts.max_inflight = 64;
-    if (!S->opts.epoch_edge_updates) S->opts.epoch_edge_updates = 4000000000ull;
-    if (!S->opts.streams) S->opts.streams = 1;
-    if (hipGetDevice(&S->device) != hipSuccess || hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking) != hipSuccess) {
+    S->opts = opts ? *opts : rs_server_opts{0, 0, 0, 0};
+    if (!S->opts.max_inflight) S->opts.max_inflight = 256;
+    if (!S->opts.group_edge_updates) S->opts.group_edge_updates = kGroupEdgeUpdates;
+    if (!S->opts.streams) S->opts.streams = 4;
+    S->opts.streams = std::min(S->opts.streams, kMaxWorkers);
+    if (!S->opts.group_max_edges) S->opts.group_max_edges = kGroupMaxEdges;
+    if (hipGetDevice(&S->device) != hipSuccess) {
       delete S;
       return RS_EDEVICE;
     }
+    S->bws = batch_ws_create();
     S->t_create = Clock::now();
-    S->worker = std::thread(worker_loop, S);
+    for (uint32_t i = 0; i < S->opts.streams; ++i) S->workers.emplace_back(worker_loop, S);
     *out = S;
     return RS_OK;
   } catch (...) {
@@ -265,11 +367,15 @@ rs_status rs_server_submit(rs_server* s, uint32_t graph_id, const rs_query* q, u
       s->st.rejected++;
       return st;
     }
-    a->footprint = footprint_of(g, a->plan);
-    if (a->footprint > s->budget) {
+    const uint64_t m = g->g.m, n = g->g.n;
+    a->tu = resolve_tuning(g, a->plan.k, nullptr);
+    a->sizes = plain_sizes(m, n, a->plan, a->tu);
+    if (a->sizes.total() > s->budget) {  // can never run alone
       s->st.rejected++;
       return RS_ENOMEM;
     }
+    a->group_bytes = table_lo_bytes(m) + table_z_bytes(n, a->plan.kq) + table_q_bytes(m, a->plan.k, a->plan.kq) +
+                     table_need_bytes(m) + 8 * (1ull << a->plan.k) + 2048;
     a->ticket = s->next_ticket++;
     a->graph_id = graph_id;
     a->q = *q;
@@ -278,10 +384,9 @@ rs_status rs_server_submit(rs_server* s, uint32_t graph_id, const rs_query* q, u
       memset(a->motif, 0, sizeof(a->motif));
       for (uint32_t c = 0; c < g->info.n_colours; ++c) a->motif[c] = q->motif_count[c];
     }
-    a->next_chunk = a->plan.chunk_first;
-    a->work_per_chunk = 64ull * (a->plan.k - 1) * g->g.m;
+    a->work = (a->plan.it_end - a->plan.it_begin) * (uint64_t)(a->plan.k - 1) * m;
     a->t_submit = Clock::now();
-    const bool trivial = g->g.m == 0 || a->plan.k > g->g.n || a->plan.it_end == a->plan.it_begin;
+    const bool trivial = m == 0 || a->plan.k > n || a->plan.it_end == a->plan.it_begin;
     if (trivial) {  // F = 0 exactly, nothing to run
       a->done = true;
       a->result = rs_result{0, 0, RS_OK, 0.0f};
@@ -328,7 +433,7 @@ rs_status rs_server_cancel(rs_server* s, uint64_t ticket) {
   if (a->done) return RS_OK;
   a->cancelled = true;
   s->st.cancelled++;
-  // queued queries finish at once; admitted ones when the current epoch ends
+  // a queued query finishes at once; a running one when its job completes
   for (auto q = s->queued.begin(); q != s->queued.end(); ++q) {
     if (*q == a) {
       s->queued.erase(q);
@@ -346,7 +451,8 @@ rs_status rs_server_stats_get(rs_server* s, rs_server_stats* out) {
   std::lock_guard<std::mutex> lk(s->mu);
   *out = s->st;
   out->queued = s->queued.size();
-  out->inflight = s->active.size();
+  out->inflight = s->inflight;
+  out->held_bytes = s->plain_held + s->batch_held;
   const double secs = std::chrono::duration<double>(Clock::now() - s->t_create).count();
   out->qps = secs > 0 ? (double)s->st.completed / secs : 0.0;
   out->p50_ms = percentile(s->latencies_ms, 0.50);
@@ -359,12 +465,20 @@ rs_status rs_server_destroy(rs_server* s) {
   {
     std::lock_guard<std::mutex> lk(s->mu);
     s->stop = true;
-    for (auto& a : s->active) a->cancelled = true;
+    for (auto& a : s->queued) {
+      a->cancelled = true;
+      a->result.status = RS_ECANCELED;
+      a->done = true;
+      s->st.cancelled++;
+    }
+    s->queued.clear();
   }
   s->cv_work.notify_all();
-  if (s->worker.joinable()) s->worker.join();
-  (void)hipStreamSynchronize(s->stream);
-  (void)hipStreamDestroy(s->stream);
+  s->cv_done.notify_all();
+  for (auto& w : s->workers)
+    if (w.joinable()) w.join();
+  for (auto& e : s->pool) e->ws.release();
+  if (s->bws) batch_ws_destroy(s->bws);
   delete s;
   return RS_OK;
 }

@@ -1,6 +1,7 @@
-"""GPU: the serving loop (rs_server_*) returns, for every query of a stream
-of arrivals, the fingerprint the plain path gives for it alone, while it
-admits queries against an HBM budget, slices long queries across epochs,
+"""GPU: the server (rs_server_*) returns, for every query of a stream of
+arrivals, the fingerprint the plain path gives for it alone, whether the
+query runs in a group (shared batched launches) or alone on one of several
+concurrent worker streams, while it admits queries against an HBM budget,
 cancels, and is driven from several threads."""
 import sys
 import threading
@@ -61,14 +62,19 @@ def graphs():
     return [g1, g2, g3]
 
 
-def test_server_alone_vs_mix():
+@pytest.mark.parametrize("label,opts", [
+    ("grouped", dict(group_edge_updates=2_000_000)),
+    ("grouped small graphs, g2 alone", dict(group_max_edges=5000, streams=3)),
+    ("all alone, 6 streams", dict(group_edge_updates=1, streams=6)),
+])
+def test_server_alone_vs_mix(label, opts):
     gs = graphs()
     gds = [R.Graph.from_inputs(g) for g in gs]
     qs = mixed_queries(30, 4, seed=17, k_range=(2, 10))
     which = [i % 3 for i in range(len(qs))]
     alone = [plain(gds[w], q) for q, w in zip(qs, which)]
-    say("[server] 30 arrivals over 3 graphs")
-    srv = R.Server(hbm_budget=8 << 30, epoch_edge_updates=2_000_000)
+    say(f"[server] 30 arrivals over 3 graphs, {label}")
+    srv = R.Server(hbm_budget=8 << 30, **opts)
     ids = [srv.add_graph(gd) for gd in gds]
     tickets = []
     for q, w in zip(qs, which):
@@ -78,8 +84,9 @@ def test_server_alone_vs_mix():
     assert all(r is not None and r.status == R.RS_OK for r in got)
     assert [r.fingerprint for r in got] == alone
     st = srv.stats()
-    assert st["completed"] == len(qs) and st["epochs"] >= 1
+    assert st["completed"] == len(qs) and st["jobs"] >= 1
     assert st["p99_ms"] >= st["p50_ms"] > 0
+    assert 0 < st["held_bytes"] <= 8 << 30
     srv.close()
 
 
@@ -91,7 +98,7 @@ def test_server_budget_deferral_cancel_and_threads():
     fp = max(R.footprint(gd, q.k, q.delta) for q in qs)
     # room for about two queries at a time: the rest must wait
     say("[server] budget for about two queries, 4 submitting threads")
-    srv = R.Server(hbm_budget=int(fp * 2.2), max_inflight=64, epoch_edge_updates=1_000_000)
+    srv = R.Server(hbm_budget=int(fp * 2.2), max_inflight=64, group_edge_updates=1_000_000)
     gid = srv.add_graph(gd)
     with pytest.raises(R.RSError):
         srv.submit(gid, inputs.Query(k=17, delta=1, seed=1))  # invalid k
@@ -114,6 +121,7 @@ def test_server_budget_deferral_cancel_and_threads():
     assert [r.fingerprint for r in got] == alone
     st = srv.stats()
     assert st["deferred"] > 0 and st["completed"] >= len(qs)
+    assert st["held_bytes"] <= int(fp * 2.2)
     small = R.Server(hbm_budget=1024)
     gid2 = small.add_graph(gd)
     with pytest.raises(R.RSError):
