@@ -157,10 +157,6 @@ Tuning resolve_tuning(const rs_graph* g, uint32_t k, const rs_tuning* t) {
 
 static uint64_t chunks_of(const QueryPlan& qp) { return qp.chunk_last - qp.chunk_first; }
 
-
-// Algorithmic HBM bytes of one prefix-level launch: per edge and chunk two
-// 512-byte window gathers (one z row at level 2) and one 512-byte prefix
-// store, plus the edge's indices and q row.
 // Algorithmic HBM bytes of one level launch over `chunks` 64-iteration
 // chunks: what the exact computation has to move once edges whose window is
 // empty, or whose product reaches no read slot, are skipped and only read

@@ -315,8 +315,8 @@ __device__ uint64_t tile_open_part(const TileCtx& c, uint32_t j, uint32_t lane, 
 constexpr uint32_t kFallbackSpins = 256;
 
 // XOR of the level values of the segment part preceding tile `tile`. Each
-// round probes the 64 predecessor tiles tile-1-lane at once (lane l reads the
-// tags of tile top-l's lane-0 words), then absorbs the leading run of
+// round probes up to 64 predecessor tiles at once (lane l reads the tags of
+// tile top-l's lane-0 words), then absorbs the leading run of
 // published tiles up to and including the nearest one that published its
 // inclusive prefix, every lane validating its own record words; a carry that
 // has to cross d tiles costs about d/64 memory round trips. A predecessor
@@ -329,13 +329,19 @@ __device__ uint64_t look_back(const TileCtx& c, uint32_t tile, uint32_t lane, co
   int64_t top = (int64_t)tile - 1;  // nearest tile not absorbed yet
   uint32_t spins = 0;
   const uint32_t t_agg = rec_tag(c.epoch, kFlagAgg), t_inc = rec_tag(c.epoch, kFlagIncl);
+  // Probes cover the 4 nearest predecessors until a run of published tiles
+  // has been absorbed: most walks end at the first one (a segment starts in
+  // it), and each probed tile costs two tag fetches of other XCDs' writes.
+  uint32_t width = 4;
   while (top >= 0) {
     const int64_t j = top - (int64_t)lane;
     bool ready = false, inc = false;
-    if (j >= 0) {
+    if (j >= 0 && lane < width) {
       const uint64_t fi = c.row0 + (uint64_t)j;
-      inc = hi32(ld_dev64(c.incl + fi * kLanes * 2)) == t_inc;
-      ready = inc || hi32(ld_dev64(c.agg + fi * kLanes * 2)) == t_agg;
+      const uint32_t ti = hi32(ld_dev64(c.incl + fi * kLanes * 2));  // both loads in flight together
+      const uint32_t ta = hi32(ld_dev64(c.agg + fi * kLanes * 2));
+      inc = ti == t_inc;
+      ready = inc || ta == t_agg;
     }
     const uint64_t ready_mask = __ballot(ready);
     const uint64_t inc_mask = __ballot(inc);
@@ -365,6 +371,7 @@ __device__ uint64_t look_back(const TileCtx& c, uint32_t tile, uint32_t lane, co
         if (ends) break;
         top -= take;
         spins = 0;
+        width = kLanes;  // a long run of published tiles: probe wide
         continue;
       }
     }
