@@ -39,6 +39,39 @@ def host_cores():
         return os.cpu_count() or 1
 
 
+# Sources whose change invalidates the committed HBM counter figures of the
+# level kernel (kernel code, launch shapes, defaults).
+KERNEL_SOURCES = ("rs_device.h", "rs_level.h", "rs_kernels.hip", "rs_engine.hip", "rs_internal.h")
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "k_scan_config2_counters.md")
+
+
+def kernel_source_hash():
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2010_08423_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def committed_traffic():
+    """HBM bytes per level_scan launch from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel sources; else None."""
+    try:
+        fields = {}
+        with open(COUNTERS_FILE) as f:
+            for line in f:
+                if ":" in line and line.startswith("- "):
+                    k, v = line[2:].split(":", 1)
+                    fields[k.strip()] = v.strip().strip("`")
+        if fields.get("kernel-source-sha256") != kernel_source_hash():
+            return None
+        return float(fields["traffic-bytes-per-launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def cpu_model():
     try:
         with open("/proc/cpuinfo") as f:
@@ -174,7 +207,7 @@ def main():
                    "n": info["n"], "m": m, "k": q.k, "delta": q.delta, "seed": q.seed,
                    "edge_updates_per_query": upd, "fingerprint": f"{r.fingerprint:#018x}"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": committed_traffic(),
                      "kernel": "k_scan<kq=8,E=16>, prefix levels 3..k-1, 4 chunks per launch",
                      "avg_launch_ms": avg_scan_ms, "launches": n_scan,
                      "algorithmic_bytes_per_launch": bytes_scan / max(n_scan, 1),

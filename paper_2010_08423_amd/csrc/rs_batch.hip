@@ -222,8 +222,10 @@ __device__ __forceinline__ uint32_t find_unit(cu32* ubegin, uint32_t from, uint3
 // each of the unit's chunks in turn, so a tile's indices and rows are loaded
 // from HBM once and then hit the cache, and the predecessor tile of every
 // chunk is on the neighbouring wave working on the same chunk at the same time.
+// (At most 128 VGPRs, so that four waves fit per SIMD as for the per-level
+// kernel; without the hint the unit bookkeeping pushes it to three.)
 template <int KQ, int E, bool FIRST>
-__global__ __launch_bounds__(256) void kb_scan(const MUnit* __restrict__ units, const uint32_t* __restrict__ ubegin_p,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void kb_scan(const MUnit* __restrict__ units, const uint32_t* __restrict__ ubegin_p,
                                                uint32_t nunits, uint32_t total, uint64_t* __restrict__ agg,
                                                uint64_t* __restrict__ incl) {
   extern __shared__ uint64_t dyn_lds[];  // [waves][16][64]; starts at LDS address 0
@@ -274,7 +276,7 @@ __global__ __launch_bounds__(256) void kb_scan(const MUnit* __restrict__ units, 
       c.row0 = row00 + (uint64_t)ch * c.n_tiles;
       TileIn<KQ, E> in;
       load_tile<KQ, E, FIRST, false>(c, tile, lane, in);
-      scan_tile<KQ, E, FIRST, false>(c, tile, in, lane, mk, tab);
+      scan_tile<KQ, E, FIRST, false>(c, tile, in, lane, mk, tab, [] {});
     }
   }
 }

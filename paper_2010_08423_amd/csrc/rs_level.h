@@ -314,8 +314,10 @@ __device__ uint64_t tile_open_part(const TileCtx& c, uint32_t j, uint32_t lane, 
 // stops relying on its predecessor and recomputes that tile's part itself.
 constexpr uint32_t kFallbackSpins = 256;
 
-// XOR of the level values of the segment part preceding tile `tile`. Each
-// round probes up to 64 predecessor tiles at once (lane l reads the tags of
+// XOR of the level values of the segment part preceding tile `tile`. The
+// nearest predecessor's records are read first, which ends most walks in one
+// memory round trip. After that, each round probes up to 64 predecessor tiles
+// at once (lane l reads the tags of
 // tile top-l's lane-0 words), then absorbs the leading run of
 // published tiles up to and including the nearest one that published its
 // inclusive prefix, every lane validating its own record words; a carry that
@@ -329,6 +331,18 @@ __device__ uint64_t look_back(const TileCtx& c, uint32_t tile, uint32_t lane, co
   int64_t top = (int64_t)tile - 1;  // nearest tile not absorbed yet
   uint32_t spins = 0;
   const uint32_t t_agg = rec_tag(c.epoch, kFlagAgg), t_inc = rec_tag(c.epoch, kFlagIncl);
+  {
+    // Usual case first: both records of the nearest predecessor in one round
+    // trip; its inclusive prefix ends the walk, its aggregate is absorbed.
+    uint64_t vi, va;
+    const bool oki = read_rec(c.incl, c.row0 + (uint64_t)top, lane, t_inc, &vi);
+    const bool oka = read_rec(c.agg, c.row0 + (uint64_t)top, lane, t_agg, &va);
+    if (__ballot(!oki) == 0) return vi;
+    if (__ballot(!oka) == 0) {
+      carry = va;
+      --top;
+    }
+  }
   // Probes cover the 4 nearest predecessors until a run of published tiles
   // has been absorbed: most walks end at the first one (a segment starts in
   // it), and each probed tile costs two tag fetches of other XCDs' writes.
@@ -410,9 +424,11 @@ __device__ __forceinline__ void load_tile(const TileCtx& c, uint32_t tile, uint3
 }
 
 // One tile of E edges of a prefix level (2..k-1), inputs already loaded.
-template <int KQ, int E, bool FIRST, bool COHERENT>
+// `between` runs after the tile has published its record and before it waits
+// on its predecessors (the caller issues the next tile's loads there).
+template <int KQ, int E, bool FIRST, bool COHERENT, class Between>
 __device__ __forceinline__ void scan_tile(const TileCtx& c, uint32_t tile, const TileIn<KQ, E>& in,
-                                          uint32_t lane, const uint32_t (&mk)[6], uint64_t* tab) {
+                                          uint32_t lane, const uint32_t (&mk)[6], uint64_t* tab, Between between) {
   cu32* e_out = as_const(c.e_out);
   const uint32_t m = c.m;
   const uint32_t e0 = tile * (uint32_t)E;
@@ -455,6 +471,7 @@ __device__ __forceinline__ void scan_tile(const TileCtx& c, uint32_t tile, const
   const uint64_t fi = c.row0 + tile;
   if (next_cont)
     publish(started ? c.incl : c.agg, fi, lane, acc, rec_tag(c.epoch, started ? kFlagIncl : kFlagAgg));
+  between();
   uint64_t carry = 0;
   if (cont) {
     carry = look_back<KQ, E, FIRST, COHERENT>(c, tile, lane, mk, tab);
@@ -475,16 +492,26 @@ __device__ __forceinline__ void scan_tile(const TileCtx& c, uint32_t tile, const
   }
 }
 
-// Tiles first, first + stride, ... below n_tiles. (Loading the next tile's
-// inputs during this tile's compute was measured slower: the extra live
-// registers cost more occupancy than the overlap gains.)
+// Tiles first, first + stride, ... below n_tiles. The next tile's inputs are
+// requested once this tile's products are done, so their latency overlaps
+// this tile's look-back and stores. (Requesting them before the products
+// was measured slower: both tiles' window sums live at once cost occupancy.)
 template <int KQ, int E, bool FIRST, bool COHERENT>
 __device__ __forceinline__ void scan_tiles(const TileCtx& c, uint32_t first, uint32_t stride, uint32_t lane,
                                            const uint32_t (&mk)[6], uint64_t* tab) {
-  for (uint32_t tile = first; tile < c.n_tiles; tile += stride) {
-    TileIn<KQ, E> in;
-    load_tile<KQ, E, FIRST, COHERENT>(c, tile, lane, in);
-    scan_tile<KQ, E, FIRST, COHERENT>(c, tile, in, lane, mk, tab);
+  if (first >= c.n_tiles) return;
+  TileIn<KQ, E> cur;
+  load_tile<KQ, E, FIRST, COHERENT>(c, first, lane, cur);
+  for (uint32_t tile = first;;) {
+    const uint32_t nt = tile + stride;
+    const bool more = nt < c.n_tiles;
+    TileIn<KQ, E> nxt;
+    scan_tile<KQ, E, FIRST, COHERENT>(c, tile, cur, lane, mk, tab, [&]() {
+      if (more) load_tile<KQ, E, FIRST, COHERENT>(c, nt, lane, nxt);
+    });
+    if (!more) break;
+    cur = nxt;
+    tile = nt;
   }
 }
 
