@@ -75,9 +75,11 @@ struct MUnit {
   uint32_t m;
   uint32_t n_items;    // edge tiles, or edge ranges
   uint32_t epoch;      // record tag epoch of this launch
-  uint32_t nchunks;    // prefix-level units: consecutive chunks of the query run per tile
+  uint32_t nchunks;    // prefix-level units: consecutive chunks of the query
+  uint32_t waves;      // prefix-level units: waves per chunk
+  uint32_t pad_;
 };
-static_assert(sizeof(MUnit) == 136, "MUnit layout");
+static_assert(sizeof(MUnit) == 144, "MUnit layout");
 // Units are read through the constant address space: scalar loads into SGPRs.
 typedef __attribute__((address_space(4))) const MUnit cMUnit;
 
@@ -218,12 +220,11 @@ __device__ __forceinline__ uint32_t find_unit(cu32* ubegin, uint32_t from, uint3
   return lo;
 }
 
-// Prefix level: flat index = (unit, edge tile); the wave runs the tile for
-// each of the unit's chunks in turn, so a tile's indices and rows are loaded
-// from HBM once and then hit the cache, and the predecessor tile of every
-// chunk is on the neighbouring wave working on the same chunk at the same time.
-// (At most 128 VGPRs, so that four waves fit per SIMD as for the per-level
-// kernel; without the hint the unit bookkeeping pushes it to three.)
+// Prefix level: the launch's waves are partitioned over (unit, chunk) pairs,
+// unit u's chunks getting `waves` waves each, in proportion to its tiles;
+// within a pair the waves run the per-level kernel's schedule (wave i takes
+// tiles i, i + waves, ...), so a tile's predecessor is on the neighbouring
+// wave of the same pair and no wave ever waits on another pair.
 template <int KQ, int E, bool FIRST>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void kb_scan(const MUnit* __restrict__ units, const uint32_t* __restrict__ ubegin_p,
                                                uint32_t nunits, uint32_t total, uint64_t* __restrict__ agg,
@@ -231,54 +232,35 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   extern __shared__ uint64_t dyn_lds[];  // [waves][16][64]; starts at LDS address 0
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform for the compiler
+  const uint32_t wave = blockIdx.x * (blockDim.x >> 6) + wv;
+  if (wave >= total) return;
   uint64_t* tab = dyn_lds + wv * 16 * kLanes + lane;
   tab[0] = 0;
   uint32_t mk[6];
   lane_masks(lane, mk);
   cu32* ubegin = as_const(ubegin_p);
-  const uint32_t waves = gridDim.x * (blockDim.x >> 6);
-  uint32_t u = 0, u_begin = 0, u_end = 0;  // empty until the first search
+  const uint32_t u = find_unit(ubegin, 0u, nunits, wave);
+  cMUnit& U = ((cMUnit*)units)[u];
+  const uint32_t local = wave - ubegin[u];
+  const uint32_t ch = local / U.waves, idx = local - ch * U.waves;
   TileCtx c;
+  c.e_src = U.e_src;
+  c.e_out = U.e_out;
+  c.hi = U.hi;
+  c.lo = U.lo;
+  c.q = U.q;
+  c.z = U.z;
+  c.pp = U.pp + ch * U.p_stride;
+  c.pc = U.pc + ch * U.p_stride;
+  c.cb = U.cb + (uint64_t)ch * kLanes;
+  c.m = U.m;
+  c.n_tiles = U.n_items;
+  c.epoch = U.epoch;
+  c.row0 = U.row0 + (uint64_t)ch * U.n_items;
   c.agg = agg;
   c.incl = incl;
-  const uint64_t* pp0 = nullptr;
-  uint64_t* pc0 = nullptr;
-  uint64_t cb0 = 0, row00 = 0, pstride = 0;
-  uint32_t nch = 1;
-  for (uint32_t t = blockIdx.x * (blockDim.x >> 6) + wv; t < total; t += waves) {
-    if (t >= u_end) {
-      u = find_unit(ubegin, u_end == 0 ? 0u : u + 1, nunits, t);
-      u_begin = ubegin[u];
-      u_end = u + 1 < nunits ? ubegin[u + 1] : total;
-      cMUnit& U = ((cMUnit*)units)[u];
-      c.e_src = U.e_src;
-      c.e_out = U.e_out;
-      c.hi = U.hi;
-      c.lo = U.lo;
-      c.q = U.q;
-      c.z = U.z;
-      c.m = U.m;
-      c.epoch = U.epoch;
-      c.need = U.need;
-      nch = U.nchunks;
-      c.n_tiles = U.n_items;
-      pp0 = U.pp;
-      pc0 = U.pc;
-      cb0 = U.cb;
-      row00 = U.row0;
-      pstride = U.p_stride;
-    }
-    const uint32_t tile = t - u_begin;
-    for (uint32_t ch = 0; ch < nch; ++ch) {
-      c.pp = pp0 + ch * pstride;
-      c.pc = pc0 + ch * pstride;
-      c.cb = cb0 + (uint64_t)ch * kLanes;
-      c.row0 = row00 + (uint64_t)ch * c.n_tiles;
-      TileIn<KQ, E> in;
-      load_tile<KQ, E, FIRST, false>(c, tile, lane, in);
-      scan_tile<KQ, E, FIRST, false>(c, tile, in, lane, mk, tab, [] {});
-    }
-  }
+  c.need = U.need;
+  scan_tiles<KQ, E, FIRST, false>(c, idx, U.waves, lane, mk, tab);
 }
 
 // Last level: flat index = (unit, edge range of top_edges edges). A wave keeps
@@ -506,17 +488,22 @@ rs_status batch_plan(const rs_graph* const* graphs, const rs_query* queries, uin
   std::vector<std::pair<size_t, size_t>> rounds;
   {
     size_t r0 = 0;
-    uint64_t bytes = 0;
+    uint64_t bytes = 0, items = 0;
+    auto tiles_of = [&](uint64_t m) { return (m + E - 1) / E; };
     for (size_t c = 0; c < chunks.size(); ++c) {
       const BQuery& Q = P.qs[chunks[c].query];
       const uint64_t b = chunk_bytes(Q.m, Q.n, E);
-      const bool full = c > r0 && (bytes + b > slot_budget || (tu.max_slots && c - r0 >= tu.max_slots));
+      // (and at most 2^30 prefix-level items, so flat item indices stay 32-bit)
+      const bool full = c > r0 && (bytes + b > slot_budget || (tu.max_slots && c - r0 >= tu.max_slots) ||
+                                   items + tiles_of(Q.m) > (1u << 30));
       if (full) {
         rounds.push_back({r0, c});
         r0 = c;
         bytes = 0;
+        items = 0;
       }
       bytes += b;
+      items += tiles_of(Q.m);
     }
     rounds.push_back({r0, chunks.size()});
   }
@@ -584,7 +571,7 @@ rs_status batch_plan(const rs_graph* const* graphs, const rs_query* queries, uin
             U.n_items = top ? (Q.m + TE - 1) / TE : (Q.m + E - 1) / E;
             U.epoch = 0;  // set per call
             P.ubegin.push_back(L.total);
-            L.total += U.n_items;
+            L.total += U.n_items * (top ? 1u : nch);  // prefix levels: tiles (waves assigned later)
             P.units.push_back(U);
             P.unit_query.push_back(qi);
             ++L.nunits;
@@ -706,12 +693,37 @@ static const void* pick_top(uint32_t kq, bool first) {
 
 // Grid of every launch: about as many blocks as are resident, at most one
 // wave per work item.
+// Prefix-level launches: waves per (unit, chunk) pair in proportion to the
+// unit's tiles, at least one each, all of them resident when the pairs fit
+// (a pair whose waves are not all resident is still correct: waits are
+// bounded, and a single wave never waits). Then the grid of every launch:
+// about as many blocks as are resident, at most one wave per work item.
 static void size_grids(BatchPlan& P) {
   const uint32_t wpb = P.tu.waves_per_block;
   const size_t lds = (size_t)wpb * 16 * kLanes * 8;
   for (BLaunch& L : P.launches) {
     const void* kern = L.top ? pick_top(L.kq, L.first) : pick_scan(L.kq, P.tu.edges_per_tile, L.first);
-    L.grid = std::max(1u, std::min(resident_blocks_of(kern, 64 * wpb, lds), (L.total + wpb - 1) / wpb));
+    const uint32_t resident = resident_blocks_of(kern, 64 * wpb, lds);
+    if (!L.top) {
+      uint64_t pairs = 0, tiles = 0;
+      for (uint32_t j = 0; j < L.nunits; ++j) {
+        const MUnit& U = P.units[L.unit_off + j];
+        pairs += U.nchunks;
+        tiles += (uint64_t)U.nchunks * U.n_items;
+      }
+      const uint64_t spare = (uint64_t)resident * wpb > pairs ? (uint64_t)resident * wpb - pairs : 0;
+      uint32_t w0 = 0;
+      for (uint32_t j = 0; j < L.nunits; ++j) {
+        MUnit& U = P.units[L.unit_off + j];
+        U.waves = (uint32_t)std::min<uint64_t>(U.n_items, 1 + (uint64_t)U.n_items * spare / std::max<uint64_t>(tiles, 1));
+        P.ubegin[L.unit_off + j] = w0;
+        w0 += U.waves * U.nchunks;
+      }
+      L.total = w0;
+      L.grid = std::max(1u, (L.total + wpb - 1) / wpb);
+    } else {
+      L.grid = std::max(1u, std::min(resident, (L.total + wpb - 1) / wpb));
+    }
     P.key += "g" + std::to_string(L.grid);
   }
 }

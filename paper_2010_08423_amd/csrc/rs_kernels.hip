@@ -18,7 +18,7 @@ namespace rs {
 // waits a bounded time and then recomputes it (see look_back).
 // ---------------------------------------------------------------------------
 template <int KQ, int E, bool FIRST>
-__global__ __launch_bounds__(256) void k_scan(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_scan(
     const uint32_t* __restrict__ e_src, const uint32_t* __restrict__ e_out,
     const uint32_t* __restrict__ hi_idx, const uint32_t* __restrict__ lo_idx,
     const uint64_t* __restrict__ q, const uint64_t* __restrict__ z,

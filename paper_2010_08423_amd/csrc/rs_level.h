@@ -435,7 +435,17 @@ __device__ __forceinline__ void scan_tile(const TileCtx& c, uint32_t tile, const
   const uint32_t ne = min((uint32_t)E, m - e0);
   const bool cont = e0 > 0 && e_out[e0] == e_out[e0 - 1] + 1u;
 
-  uint64_t pref[E];
+  // Two store orders. Late: the running values stay in registers and every
+  // read slot is stored after the look-back, the open part (slots before the
+  // tile's first segment start) with the carry from the preceding tiles.
+  // Early: each read slot is stored as soon as its value is known, the open
+  // part without the carry, which is XORed into those slots once the
+  // look-back has it. Early frees E registers per lane, which lifts the
+  // 16-edge prefix levels from three to four waves per SIMD; elsewhere the
+  // occupancy does not change and late is faster, because a look-back wait
+  // also waits for stores issued before it.
+  constexpr bool kEarly = !FIRST && E >= 16;
+  uint64_t pref[kEarly ? 1 : E];
   uint64_t acc = 0;
   uint32_t first_len = 0;
   bool started = !cont;
@@ -446,14 +456,21 @@ __device__ __forceinline__ void scan_tile(const TileCtx& c, uint32_t tile, const
   auto needs = [&](int i) {
     return (uint32_t)i < ne && (FIRST ? ((in.need.v[i / 4] >> (8 * (i % 4) + 2)) & 1u) != 0 : in.ia[i] != 0);
   };
+  // Only slots that some non-empty window reads are stored (the others are
+  // never read: empty windows gather the zero row). A segment's leading slot
+  // (just before its first edge's slot) holds 0; writing it here lets P
+  // buffers be reused across graphs without clearing.
+  auto flag = [&](int i) { return (in.need.v[i / 4] >> (8 * (i % 4))) & 3u; };
+  auto slot_ptr = [&](uint32_t slot) { return c.pc + (uint64_t)slot * kLanes + lane; };
 #pragma unroll
   for (int i = 0; i < E; ++i) {
-    pref[i] = 0;
+    if (!kEarly) pref[i] = 0;
     if ((uint32_t)i < ne) {
       if (i == 0 ? !cont : in.slot[i] != last_slot + 1u) {
         acc = 0;
         started = true;
         seg_starts |= 1u << i;
+        if (kEarly && (flag(i) & 2u)) p_store<COHERENT>(slot_ptr(in.slot[i] - 1u), 0);
       }
       if (!started) first_len = (uint32_t)i + 1u;
       if (needs(i)) {
@@ -461,7 +478,11 @@ __device__ __forceinline__ void scan_tile(const TileCtx& c, uint32_t tile, const
         const uint64_t wv = FIRST ? subset_xor<KQ, E>(in.zr, i, c.cb, mk) : in.w[i];
         acc ^= gf_mul(tab, aL, wv);
       }
-      pref[i] = acc;
+      if (kEarly) {
+        if (flag(i) & 1u) p_store<COHERENT>(slot_ptr(in.slot[i]), acc);
+      } else {
+        pref[i] = acc;
+      }
       last_slot = in.slot[i];
     }
   }
@@ -477,17 +498,22 @@ __device__ __forceinline__ void scan_tile(const TileCtx& c, uint32_t tile, const
     carry = look_back<KQ, E, FIRST, COHERENT>(c, tile, lane, mk, tab);
     if (next_cont && !started) publish(c.incl, fi, lane, carry ^ acc, rec_tag(c.epoch, kFlagIncl));
   }
-  // Only slots that some non-empty window reads are stored (the others are
-  // never read: empty windows gather the zero row).
+  if (kEarly) {
+    // the open part's stored slots get the carry (same lane and address as
+    // the store above, so the XOR lands on the stored value)
+    if (carry) {
 #pragma unroll
-  for (int i = 0; i < E; ++i) {
-    const uint32_t nf = (in.need.v[i / 4] >> (8 * (i % 4))) & 3u;
-    if ((uint32_t)i < ne) {
-      if (nf & 1u)
-        p_store<COHERENT>(c.pc + (uint64_t)in.slot[i] * kLanes + lane, pref[i] ^ ((uint32_t)i < first_len ? carry : 0));
-      // the segment's leading slot (just before its first edge's slot) holds 0;
-      // writing it here lets P buffers be reused across graphs without clearing
-      if (((seg_starts >> i) & 1u) && (nf & 2u)) p_store<COHERENT>(c.pc + (uint64_t)(in.slot[i] - 1u) * kLanes + lane, 0);
+      for (int i = 0; i < E; ++i)
+        if ((uint32_t)i < first_len && (flag(i) & 1u))
+          atomicXor((unsigned long long*)slot_ptr(in.slot[i]), (unsigned long long)carry);
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      if ((uint32_t)i < ne) {
+        if (flag(i) & 1u) p_store<COHERENT>(slot_ptr(in.slot[i]), pref[i] ^ ((uint32_t)i < first_len ? carry : 0));
+        if (((seg_starts >> i) & 1u) && (flag(i) & 2u)) p_store<COHERENT>(slot_ptr(in.slot[i] - 1u), 0);
+      }
     }
   }
 }
