@@ -13,13 +13,16 @@
 // bounded look-back of rs_level.h.
 //
 // Each launch walks a device work table: units[] (descriptors uploaded per
-// call) and ubegin[] (the first flat work index of each unit). The grid holds
-// about as many waves as are resident; wave w takes flat indices w, w + W, ...
-// and locates the unit by a binary search that is only repeated when the
-// index leaves the current unit. The whole launch sequence (per-query setup,
-// the level launches of every round, per-query reductions) is captured once
-// per batch shape into a hipGraph; later calls with the same shape upload new
-// descriptors and replay it.
+// call) and ubegin[] (the first flat index of each unit). In a prefix launch
+// the flat index is a wave: the launch's resident waves are partitioned over
+// the (unit, chunk) pairs in proportion to their tiles, and each pair runs the
+// per-level kernel's tile schedule on its own waves. In a last-level launch the
+// flat index is an edge range: wave w takes w, w + W, ... and locates the unit
+// by a binary search repeated only when the index leaves the current unit.
+// The whole launch sequence (per-query setup, the level launches of every
+// round, per-query reductions) is captured once per batch shape into a
+// hipGraph; later calls with the same shape upload new descriptors and replay
+// it.
 #include <string.h>
 
 #include <algorithm>
@@ -32,7 +35,6 @@
 #include "rs_level.h"
 
 namespace rs {
-
 
 // Per-query descriptor of the setup kernels and the final reduction.
 struct BQuery {
@@ -260,7 +262,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   c.agg = agg;
   c.incl = incl;
   c.need = U.need;
-  scan_tiles<KQ, E, FIRST, false>(c, idx, U.waves, lane, mk, tab);
+  scan_tiles<KQ, E, FIRST>(c, idx, U.waves, lane, mk, tab);
 }
 
 // Last level: flat index = (unit, edge range of top_edges edges). A wave keeps
@@ -312,7 +314,7 @@ __global__ __launch_bounds__(256) void kb_top(const MUnit* __restrict__ units, c
     }
     const uint32_t e0 = (t - u_begin) * top_edges;
     const uint32_t e1 = min(m, e0 + top_edges);
-    top_range<KQ, FIRST, false>(e_src, hi, lo, q, z, pp, cb, e0, e1, lane, mk, tab, r);
+    top_range<KQ, FIRST>(e_src, hi, lo, q, z, pp, cb, e0, e1, lane, mk, tab, r);
   }
   if (u_end != 0) flush();
 }

@@ -52,7 +52,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   c.incl = incl;
   c.need = need;
   const uint32_t waves = gridDim.x * (blockDim.x >> 6);
-  scan_tiles<KQ, E, FIRST, false>(c, blockIdx.x * (blockDim.x >> 6) + wv, waves, lane, mk, tab);
+  scan_tiles<KQ, E, FIRST>(c, blockIdx.x * (blockDim.x >> 6) + wv, waves, lane, mk, tab);
 }
 
 // ---------------------------------------------------------------------------
@@ -81,7 +81,7 @@ __global__ __launch_bounds__(256) void k_top(
   for (uint64_t wave_id = (uint64_t)blockIdx.x * nw + wv; wave_id * edges_per_wave < m; wave_id += waves) {
     const uint64_t e0 = wave_id * edges_per_wave;
     const uint32_t e1 = (uint32_t)min((uint64_t)m, e0 + edges_per_wave);
-    top_range<KQ, FIRST, false>(e_src, hi_idx, lo_idx, q, z, p_prev + (uint64_t)chunk * p_stride, cb,
+    top_range<KQ, FIRST>(e_src, hi_idx, lo_idx, q, z, p_prev + (uint64_t)chunk * p_stride, cb,
                                 (uint32_t)e0, e1, lane, mk, tab, r);
   }
   const uint64_t f = gf_reduce(r);

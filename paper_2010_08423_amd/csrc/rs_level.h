@@ -51,41 +51,14 @@ __device__ __forceinline__ void st_dev64(uint64_t* p, uint64_t v) {
 __device__ __forceinline__ uint64_t ld_dev64(const uint64_t* p) {
   return __hip_atomic_load(const_cast<uint64_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ void st_dev32(uint32_t* p, uint32_t v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ uint32_t ld_dev32(const uint32_t* p) {
-  return __hip_atomic_load(const_cast<uint32_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-// Orders this wave's earlier memory operations before later ones by waiting
-// for them to complete (vmcnt = 0); no cache writeback or invalidation.
-__device__ __forceinline__ void order_release() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-  __builtin_amdgcn_s_waitcnt(0xF70);
-}
-__device__ __forceinline__ void order_acquire() {
-  __builtin_amdgcn_s_waitcnt(0xF70);
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-}
 
-// P-state accesses: plain (kernel boundaries order levels) or device-coherent
-// (levels ordered inside one persistent kernel).
-// Plain P loads go through the global address space explicitly: a generic
-// (flat) load would also count against the LDS wait counter and make every
-// table lookup wait for the gathers.
+// P-state accesses (kernel boundaries order the levels). Loads go through
+// the global address space explicitly: a generic (flat) load would also count
+// against the LDS wait counter and make every table lookup wait for the
+// gathers.
 typedef __attribute__((address_space(1))) const uint64_t gu64;
-template <bool COHERENT>
-__device__ __forceinline__ uint64_t p_load(const uint64_t* p) {
-  if (COHERENT) return ld_dev64(p);
-  return *(gu64*)p;
-}
-template <bool COHERENT>
-__device__ __forceinline__ void p_store(uint64_t* p, uint64_t v) {
-  if (COHERENT)
-    st_dev64(p, v);
-  else
-    *p = v;
-}
+__device__ __forceinline__ uint64_t p_load(const uint64_t* p) { return *(gu64*)p; }
+__device__ __forceinline__ void p_store(uint64_t* p, uint64_t v) { *p = v; }
 
 // Per-lane subset XOR  XOR_{j in L} row[j]  for the iteration L = cb + lane
 // (cb a multiple of 64): bits 0..5 of L come from the lane, higher bits from cb.
@@ -241,7 +214,7 @@ __device__ __forceinline__ uint64_t subset_xor(const RowBlock<KQ, N>& rb, int i,
 // Loads the tile's indices (three scalar loads) and issues all of its window
 // gathers at once, without branches: an edge whose window is empty (hi == lo,
 // its sum is zero) or that lies past the tile end gathers the zero row.
-template <int KQ, int E, bool FIRST, bool COHERENT>
+template <int KQ, int E, bool FIRST>
 __device__ __forceinline__ void tile_inputs(const TileCtx& c, uint32_t e0, uint32_t ne, uint32_t lane,
                                             const IdxN<E / 4>& need, uint32_t (&slot)[E], uint32_t (&ia)[E],
                                             uint64_t (&w)[E]) {
@@ -262,7 +235,7 @@ __device__ __forceinline__ void tile_inputs(const TileCtx& c, uint32_t e0, uint3
       const bool live = (uint32_t)i < ne && h.v[i] != l.v[i] && ((need.v[i / 4] >> (8 * (i % 4) + 2)) & 1u);
       const uint64_t* pa = live ? c.pp + (uint64_t)h.v[i] * kLanes + lane : zero;
       const uint64_t* pb = live ? c.pp + (uint64_t)l.v[i] * kLanes + lane : zero;
-      w[i] = p_load<COHERENT>(pa) ^ p_load<COHERENT>(pb);
+      w[i] = p_load(pa) ^ p_load(pb);
       ia[i] = live;
     }
   }
@@ -282,7 +255,7 @@ __device__ __forceinline__ uint64_t edge_value(const TileCtx& c, uint32_t e, uin
 // inside the tile, else from the tile start). *started tells whether a
 // segment starts inside the tile, i.e. whether the value is inclusive. A
 // rarely taken path, written edge by edge to keep register use low.
-template <int KQ, int E, bool FIRST, bool COHERENT>
+template <int KQ, int E, bool FIRST>
 __device__ uint64_t tile_open_part(const TileCtx& c, uint32_t j, uint32_t lane, const uint32_t (&mk)[6],
                                    uint64_t* tab, bool* started) {
   cu32* e_out = as_const(c.e_out);
@@ -302,8 +275,8 @@ __device__ uint64_t tile_open_part(const TileCtx& c, uint32_t j, uint32_t lane, 
     if (!FIRST && hi_idx[e] == lo_idx[e]) continue;  // empty window: contributes zero
     if (!(c.need[e] & 4u)) continue;                  // reaches no read slot
     const uint64_t w = FIRST ? 0
-                             : p_load<COHERENT>(c.pp + (uint64_t)hi_idx[e] * kLanes + lane) ^
-                                   p_load<COHERENT>(c.pp + (uint64_t)lo_idx[e] * kLanes + lane);
+                             : p_load(c.pp + (uint64_t)hi_idx[e] * kLanes + lane) ^
+                                   p_load(c.pp + (uint64_t)lo_idx[e] * kLanes + lane);
     acc ^= edge_value<KQ, E, FIRST>(c, e, FIRST ? e_src[e] : 0u, w, mk, tab);
   }
   *started = st;
@@ -324,7 +297,7 @@ constexpr uint32_t kFallbackSpins = 256;
 // has to cross d tiles costs about d/64 memory round trips. A predecessor
 // that stays unpublished is recomputed here, so every wait is bounded
 // whatever order the tiles run in.
-template <int KQ, int E, bool FIRST, bool COHERENT>
+template <int KQ, int E, bool FIRST>
 __device__ uint64_t look_back(const TileCtx& c, uint32_t tile, uint32_t lane, const uint32_t (&mk)[6],
                               uint64_t* tab) {
   uint64_t carry = 0;
@@ -391,7 +364,7 @@ __device__ uint64_t look_back(const TileCtx& c, uint32_t tile, uint32_t lane, co
     }
     if (++spins > kFallbackSpins) {
       bool started = false;
-      carry ^= tile_open_part<KQ, E, FIRST, COHERENT>(c, (uint32_t)top, lane, mk, tab, &started);
+      carry ^= tile_open_part<KQ, E, FIRST>(c, (uint32_t)top, lane, mk, tab, &started);
       if (started) break;
       --top;
       spins = 0;
@@ -413,20 +386,20 @@ struct TileIn {
   IdxN<E / 4> need;        // store flags, four edges per word
 };
 
-template <int KQ, int E, bool FIRST, bool COHERENT>
+template <int KQ, int E, bool FIRST>
 __device__ __forceinline__ void load_tile(const TileCtx& c, uint32_t tile, uint32_t lane, TileIn<KQ, E>& in) {
   const uint32_t e0 = tile * (uint32_t)E;
   const uint32_t ne = min((uint32_t)E, c.m - e0);
   in.need = load_idx<E / 4>((const uint32_t*)(c.need + e0));
   load_qrows<KQ, E>(in.qr, c.q, e0, lane);
   if (FIRST) load_zrows<KQ, E>(in.zr, c.z, c.e_src, e0, ne, lane);
-  tile_inputs<KQ, E, FIRST, COHERENT>(c, e0, ne, lane, in.need, in.slot, in.ia, in.w);
+  tile_inputs<KQ, E, FIRST>(c, e0, ne, lane, in.need, in.slot, in.ia, in.w);
 }
 
 // One tile of E edges of a prefix level (2..k-1), inputs already loaded.
 // `between` runs after the tile has published its record and before it waits
 // on its predecessors (the caller issues the next tile's loads there).
-template <int KQ, int E, bool FIRST, bool COHERENT, class Between>
+template <int KQ, int E, bool FIRST, class Between>
 __device__ __forceinline__ void scan_tile(const TileCtx& c, uint32_t tile, const TileIn<KQ, E>& in,
                                           uint32_t lane, const uint32_t (&mk)[6], uint64_t* tab, Between between) {
   cu32* e_out = as_const(c.e_out);
@@ -470,7 +443,7 @@ __device__ __forceinline__ void scan_tile(const TileCtx& c, uint32_t tile, const
         acc = 0;
         started = true;
         seg_starts |= 1u << i;
-        if (kEarly && (flag(i) & 2u)) p_store<COHERENT>(slot_ptr(in.slot[i] - 1u), 0);
+        if (kEarly && (flag(i) & 2u)) p_store(slot_ptr(in.slot[i] - 1u), 0);
       }
       if (!started) first_len = (uint32_t)i + 1u;
       if (needs(i)) {
@@ -479,7 +452,7 @@ __device__ __forceinline__ void scan_tile(const TileCtx& c, uint32_t tile, const
         acc ^= gf_mul(tab, aL, wv);
       }
       if (kEarly) {
-        if (flag(i) & 1u) p_store<COHERENT>(slot_ptr(in.slot[i]), acc);
+        if (flag(i) & 1u) p_store(slot_ptr(in.slot[i]), acc);
       } else {
         pref[i] = acc;
       }
@@ -495,7 +468,7 @@ __device__ __forceinline__ void scan_tile(const TileCtx& c, uint32_t tile, const
   between();
   uint64_t carry = 0;
   if (cont) {
-    carry = look_back<KQ, E, FIRST, COHERENT>(c, tile, lane, mk, tab);
+    carry = look_back<KQ, E, FIRST>(c, tile, lane, mk, tab);
     if (next_cont && !started) publish(c.incl, fi, lane, carry ^ acc, rec_tag(c.epoch, kFlagIncl));
   }
   if (kEarly) {
@@ -511,8 +484,8 @@ __device__ __forceinline__ void scan_tile(const TileCtx& c, uint32_t tile, const
 #pragma unroll
     for (int i = 0; i < E; ++i) {
       if ((uint32_t)i < ne) {
-        if (flag(i) & 1u) p_store<COHERENT>(slot_ptr(in.slot[i]), pref[i] ^ ((uint32_t)i < first_len ? carry : 0));
-        if (((seg_starts >> i) & 1u) && (flag(i) & 2u)) p_store<COHERENT>(slot_ptr(in.slot[i] - 1u), 0);
+        if (flag(i) & 1u) p_store(slot_ptr(in.slot[i]), pref[i] ^ ((uint32_t)i < first_len ? carry : 0));
+        if (((seg_starts >> i) & 1u) && (flag(i) & 2u)) p_store(slot_ptr(in.slot[i] - 1u), 0);
       }
     }
   }
@@ -522,18 +495,18 @@ __device__ __forceinline__ void scan_tile(const TileCtx& c, uint32_t tile, const
 // requested once this tile's products are done, so their latency overlaps
 // this tile's look-back and stores. (Requesting them before the products
 // was measured slower: both tiles' window sums live at once cost occupancy.)
-template <int KQ, int E, bool FIRST, bool COHERENT>
+template <int KQ, int E, bool FIRST>
 __device__ __forceinline__ void scan_tiles(const TileCtx& c, uint32_t first, uint32_t stride, uint32_t lane,
                                            const uint32_t (&mk)[6], uint64_t* tab) {
   if (first >= c.n_tiles) return;
   TileIn<KQ, E> cur;
-  load_tile<KQ, E, FIRST, COHERENT>(c, first, lane, cur);
+  load_tile<KQ, E, FIRST>(c, first, lane, cur);
   for (uint32_t tile = first;;) {
     const uint32_t nt = tile + stride;
     const bool more = nt < c.n_tiles;
     TileIn<KQ, E> nxt;
-    scan_tile<KQ, E, FIRST, COHERENT>(c, tile, cur, lane, mk, tab, [&]() {
-      if (more) load_tile<KQ, E, FIRST, COHERENT>(c, nt, lane, nxt);
+    scan_tile<KQ, E, FIRST>(c, tile, cur, lane, mk, tab, [&]() {
+      if (more) load_tile<KQ, E, FIRST>(c, nt, lane, nxt);
     });
     if (!more) break;
     cur = nxt;
@@ -545,7 +518,7 @@ __device__ __forceinline__ void scan_tiles(const TileCtx& c, uint32_t first, uin
 // Edges go in batches of 8: one scalar load per index array and batch, and
 // the next batch's gathers and rows in flight during this batch's products;
 // empty windows gather the zero row and skip their product.
-template <int KQ, bool FIRST, bool COHERENT>
+template <int KQ, bool FIRST>
 __device__ __forceinline__ void top_range(const uint32_t* e_src_p, const uint32_t* hi_p,
                                           const uint32_t* lo_p, const uint64_t* q_p,
                                           const uint64_t* z_p, const uint64_t* pp, uint64_t cb,
@@ -575,7 +548,7 @@ __device__ __forceinline__ void top_range(const uint32_t* e_src_p, const uint32_
         const bool live = eb + (uint32_t)i < e1 && h.v[i] != l.v[i];
         const uint64_t* pa = live ? pp + (uint64_t)h.v[i] * kLanes + lane : zero;
         const uint64_t* pb = live ? pp + (uint64_t)l.v[i] * kLanes + lane : zero;
-        b.w[i] = p_load<COHERENT>(pa) ^ p_load<COHERENT>(pb);
+        b.w[i] = p_load(pa) ^ p_load(pb);
         b.live.v[i] = live;
       }
     }

@@ -180,3 +180,13 @@ def test_autotune_keeps_results():
     after = [plain(gd, q) for q in qs]
     assert after == before
     check_batch([g], [gd], qs, [0] * len(qs), None, "after autotune")
+
+
+def test_batch_more_chunk_pairs_than_waves():
+    """48 queries of k = 13 (128 chunks each) on one small graph: more
+    (query, chunk) pairs in a prefix launch than resident waves, so every
+    pair runs on a single wave; results equal the plain path."""
+    g = inputs.uniform_graph(60, 700, 10, seed=43)
+    gd = R.Graph.from_inputs(g)
+    qs = [inputs.Query(k=13, delta=2 + i % 3, seed=500 + i) for i in range(48)]
+    check_batch([g], [gd], qs, [0] * len(qs), R.Tuning(no_graph=1), "more pairs than waves")
