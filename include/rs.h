@@ -238,7 +238,10 @@ typedef struct {
                                   queries; 0 = 4e9; a query whose own work
                                   reaches the cap runs alone, so 1 turns
                                   grouping off) */
-  uint32_t streams;            /* worker threads and streams (0 = 4, at most 16) */
+  uint32_t streams;            /* worker threads and streams (0 = 2, at most 16);
+                                  level kernels size their grids to fill the
+                                  GPU, so more than two concurrent jobs mostly
+                                  compete for the same CUs */
   uint64_t group_max_edges;    /* graphs with at most this many edges are
                                   grouped (0 = 262144) */
 } rs_server_opts;

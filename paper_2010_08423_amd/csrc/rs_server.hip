@@ -329,7 +329,7 @@ rs_status rs_server_create(uint64_t hbm_budget, const rs_server_opts* opts, rs_s
     S->opts = opts ? *opts : rs_server_opts{0, 0, 0, 0};
     if (!S->opts.max_inflight) S->opts.max_inflight = 256;
     if (!S->opts.group_edge_updates) S->opts.group_edge_updates = kGroupEdgeUpdates;
-    if (!S->opts.streams) S->opts.streams = 4;
+    if (!S->opts.streams) S->opts.streams = 2;
     S->opts.streams = std::min(S->opts.streams, kMaxWorkers);
     if (!S->opts.group_max_edges) S->opts.group_max_edges = kGroupMaxEdges;
     if (hipGetDevice(&S->device) != hipSuccess) {
