@@ -96,9 +96,9 @@ def test_server_budget_deferral_cancel_and_threads():
     qs = mixed_queries(16, 4, seed=19, k_range=(6, 9))
     alone = [plain(gd, q) for q in qs]
     fp = max(R.footprint(gd, q.k, q.delta) for q in qs)
-    # room for about two queries at a time: the rest must wait
-    say("[server] budget for about two queries, 4 submitting threads")
-    srv = R.Server(hbm_budget=int(fp * 2.2), max_inflight=64, group_edge_updates=1_000_000)
+    # four workers, room for about two queries at a time: the rest must wait
+    say("[server] budget for about two queries, 4 workers, 4 submitting threads")
+    srv = R.Server(hbm_budget=int(fp * 2.2), max_inflight=64, group_edge_updates=1_000_000, streams=4)
     gid = srv.add_graph(gd)
     with pytest.raises(R.RSError):
         srv.submit(gid, inputs.Query(k=17, delta=1, seed=1))  # invalid k
