@@ -43,6 +43,7 @@ def host_cores():
 # level kernel (kernel code, launch shapes, defaults).
 KERNEL_SOURCES = ("rs_device.h", "rs_level.h", "rs_kernels.hip", "rs_engine.hip", "rs_internal.h")
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "k_scan_config2_counters.md")
+SQ_FILE = os.path.join(ROOT, "profiles", "k_scan_config2_sq.md")
 
 
 def kernel_source_hash():
@@ -55,21 +56,29 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def committed_traffic():
-    """HBM bytes per level_scan launch from the committed rocprofv3 counter
-    summary, if it was taken on the current kernel sources; else None."""
+def committed_figures(path):
+    """The `- key: value` lines of a committed rocprofv3 summary, if it was
+    taken on the current kernel sources; else {}."""
     try:
         fields = {}
-        with open(COUNTERS_FILE) as f:
+        with open(path) as f:
             for line in f:
                 if ":" in line and line.startswith("- "):
                     k, v = line[2:].split(":", 1)
                     fields[k.strip()] = v.strip().strip("`")
-        if fields.get("kernel-source-sha256") != kernel_source_hash():
-            return None
-        return float(fields["traffic-bytes-per-launch"])
-    except (OSError, KeyError, ValueError):
-        return None
+        return fields if fields.get("kernel-source-sha256") == kernel_source_hash() else {}
+    except OSError:
+        return {}
+
+
+def committed_traffic():
+    """HBM bytes per level_scan launch from the committed counter summary."""
+    v = committed_figures(COUNTERS_FILE).get("traffic-bytes-per-launch")
+    return float(v) if v is not None else None
+
+
+def _float(v):
+    return float(v) if v is not None else None
 
 
 def cpu_model():
@@ -211,7 +220,10 @@ def main():
                      "kernel": "k_scan<kq=8,E=16>, prefix levels 3..k-1, 4 chunks per launch",
                      "avg_launch_ms": avg_scan_ms, "launches": n_scan,
                      "algorithmic_bytes_per_launch": bytes_scan / max(n_scan, 1),
-                     "dense_equivalent_GBps": dense},
+                     "dense_equivalent_GBps": dense,
+                     # issue rates of the same kernel from the committed SQ counter summary
+                     "valu_frac": _float(committed_figures(SQ_FILE).get("valu-frac")),
+                     "salu_frac": _float(committed_figures(SQ_FILE).get("salu-frac"))},
         "kernels": classes,
     }
     if rank == 0 and not args.no_cpu_baseline:
