@@ -42,8 +42,8 @@ def host_cores():
 # Sources whose change invalidates the committed HBM counter figures of the
 # level kernel (kernel code, launch shapes, defaults).
 KERNEL_SOURCES = ("rs_device.h", "rs_level.h", "rs_kernels.hip", "rs_engine.hip", "rs_internal.h")
-COUNTERS_FILE = os.path.join(ROOT, "profiles", "k_scan_config2_counters.md")
-SQ_FILE = os.path.join(ROOT, "profiles", "k_scan_config2_sq.md")
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "k_scan_chunglu_m1e6_k8_counters.md")
+SQ_FILE = os.path.join(ROOT, "profiles", "k_scan_chunglu_m1e6_k8_sq.md")
 
 
 def kernel_source_hash():
