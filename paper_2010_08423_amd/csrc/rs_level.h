@@ -285,7 +285,11 @@ __device__ uint64_t tile_open_part(const TileCtx& c, uint32_t j, uint32_t lane, 
 
 // Spins (each a flag round trip plus a short sleep) before a waiting tile
 // stops relying on its predecessor and recomputes that tile's part itself.
-constexpr uint32_t kFallbackSpins = 256;
+// A predecessor that is merely late (its wave still walking back through a
+// long segment) is better waited for than recomputed, since a walk that
+// recomputes would meet the next late predecessor and pay the wait again;
+// on the 10^6-edge graph 64, 256 and 2048 spins time the same.
+constexpr uint32_t kFallbackSpins = 2048;
 
 // XOR of the level values of the segment part preceding tile `tile`. The
 // nearest predecessor's records are read first, which ends most walks in one

@@ -190,3 +190,15 @@ def test_batch_more_chunk_pairs_than_waves():
     gd = R.Graph.from_inputs(g)
     qs = [inputs.Query(k=13, delta=2 + i % 3, seed=500 + i) for i in range(48)]
     check_batch([g], [gd], qs, [0] * len(qs), R.Tuning(no_graph=1), "more pairs than waves")
+
+
+def test_batch_full_size_graph():
+    """Four queries of uneven k on the 10^6-edge Chung-Lu graph in one batch
+    (every prefix launch partitions the GPU's waves over their chunk pairs),
+    bit-identical to the plain path."""
+    g, _ = inputs.config_path_scale()
+    gd = R.Graph.from_inputs(g)
+    qs = [inputs.Query(k=7, delta=10, seed=901), inputs.Query(k=9, delta=25, seed=902),
+          inputs.Query(k=5, delta=3, seed=903, motif=np.array([1, 0, 2, 0, 1, 0, 1, 0], np.uint8)),
+          inputs.Query(k=8, delta=40, seed=904, it_begin=17, it_end=200)]
+    check_batch([g], [gd], qs, [0] * len(qs), R.Tuning(no_graph=1), "full-size graph")
