@@ -198,7 +198,7 @@ def run_serve_mode(args):
         "config": {"workload": f"served stream: Poisson {rate}/s for {window} s over 4 resident graphs "
                                f"(m = {ms}), k in 4..12, delta in 1..100, 30% motif; cap {cap} s",
                    "arrivals": len(stream), "hbm_budget_gb": args.budget_gb,
-                   "group_edge_updates": args.group_updates, "streams": args.streams or 2},
+                   "group_edge_updates": args.group_updates or 4e9, "streams": args.streams or 2},
         "served": {"completed": served_done, "queries_per_s": served_done / served_elapsed,
                    "edge_updates_per_s": done_updates / served_elapsed, "p50_ms": p50, "p99_ms": p99,
                    "jobs": st["jobs"], "deferred": st["deferred"], "held_gb": st["held_bytes"] / 2**30,

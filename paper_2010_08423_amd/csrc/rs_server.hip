@@ -35,7 +35,7 @@ namespace rs {
 using Clock = std::chrono::steady_clock;
 
 constexpr uint64_t kGroupMaxEdges = 262144;  // default: graphs this small are grouped
-constexpr uint64_t kGroupEdgeUpdates = 4000000000ull;
+constexpr uint64_t kGroupEdgeUpdates = 4000000000ull;  // about 20 ms of level work
 constexpr uint32_t kMaxGroup = 64;
 constexpr uint32_t kMaxWorkers = 16;
 
