@@ -2,7 +2,6 @@
 rocprofv3 summaries only while the kernel sources hash to the value the
 summary records."""
 import os
-import shutil
 import sys
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
