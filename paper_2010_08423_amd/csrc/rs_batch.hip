@@ -166,20 +166,23 @@ __global__ void kb_clear_ref(const BQuery* __restrict__ qs, uint32_t qi) {
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words; i += (uint64_t)gridDim.x * blockDim.x)
     r[i] = 0;
 }
-__global__ __launch_bounds__(256) void kb_mark_ref(const BQuery* __restrict__ qs, uint32_t qi) {
+// Flags of prefix level l: slots read by the windows of level l+1's product
+// edges (every non-empty window when l+1 is the last level).
+__global__ __launch_bounds__(256) void kb_mark_ref(const BQuery* __restrict__ qs, uint32_t qi, uint32_t l) {
   const BQuery& Q = qs[qi];
   const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < Q.m) mark_ref(Q.hi, Q.lo, e, Q.ref);
+  const uint8_t* next = l + 1 < Q.k ? Q.need + (uint64_t)(l - 1) * need_stride(Q.m) : nullptr;
+  if (e < Q.m) mark_ref(Q.hi, Q.lo, next, e, Q.ref);
 }
 __global__ __launch_bounds__(256) void kb_mark_last(const BQuery* __restrict__ qs, uint32_t qi) {
   const BQuery& Q = qs[qi];
   const uint32_t u = blockIdx.x * blockDim.x + threadIdx.x;
   if (u < Q.n) mark_last(Q.in_off, Q.ref, u, Q.lastref);
 }
-__global__ __launch_bounds__(256) void kb_mark_need(const BQuery* __restrict__ qs, uint32_t qi) {
+__global__ __launch_bounds__(256) void kb_mark_need(const BQuery* __restrict__ qs, uint32_t qi, uint32_t l) {
   const BQuery& Q = qs[qi];
   const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < Q.m) mark_need(Q.e_out, Q.e_dst, Q.ref, Q.lastref, e, Q.need);
+  if (e < Q.m) mark_need(Q.e_out, Q.e_dst, Q.ref, Q.lastref, e, Q.need + (uint64_t)(l - 2) * need_stride(Q.m));
 }
 
 __global__ void kb_clear_fsum(const BQuery* __restrict__ qs, uint32_t qi) {
@@ -465,7 +468,7 @@ rs_status batch_plan(const rs_graph* const* graphs, const rs_query* queries, uin
     Q.q = (uint64_t*)(uintptr_t)pq_off;
     pq_off += align256(table_q_bytes(m, qp.k, qp.kq));
     Q.need = (uint8_t*)(uintptr_t)pq_off;
-    pq_off += align256(table_need_bytes(m));
+    pq_off += align256(table_need_bytes(m, qp.k));
     P.ref_bytes = std::max<uint64_t>(P.ref_bytes, (m + n + 3) & ~3ull);
     P.n_max = std::max<uint64_t>(P.n_max, n);
     Q.fsum = (uint64_t*)(uintptr_t)pq_off;
@@ -566,7 +569,8 @@ rs_status batch_plan(const rs_graph* const* graphs, const rs_query* queries, uin
             U.it_begin = Q.it_begin;
             U.it_end = Q.it_end;
             U.row0 = row0[c - rd.first];
-            U.need = Q.need;  // offset, rebased later
+            // this level's flags (prefix levels; unused at the last level): offset, rebased later
+            U.need = (const uint8_t*)((uintptr_t)Q.need + (top ? 0 : (uint64_t)(l - 2) * need_stride(Q.m)));
             U.m = Q.m;
             U.nchunks = nch;
             U.p_stride = 2 * half / 8;
@@ -599,7 +603,8 @@ static rs_status resolve_plan(BatchPlan& P, BatchWorkspace& W, uint32_t epoch0) 
   char* pq = W.per_query.as<char>();
   char* pa = W.parena.as<char>();
   // per-query tables: byte offsets -> pointers
-  std::vector<uint64_t> lo_off(P.qs.size()), z_off(P.qs.size()), q_off(P.qs.size()), f_off(P.qs.size());
+  std::vector<uint64_t> lo_off(P.qs.size()), z_off(P.qs.size()), q_off(P.qs.size()), f_off(P.qs.size()),
+      need_off(P.qs.size());
   for (size_t i = 0; i < P.qs.size(); ++i) {
     BQuery& Q = P.qs[i];
     f_off[i] = (uintptr_t)Q.fsum;
@@ -608,14 +613,14 @@ static rs_status resolve_plan(BatchPlan& P, BatchWorkspace& W, uint32_t epoch0) 
     lo_off[i] = (uintptr_t)Q.lo;
     z_off[i] = (uintptr_t)Q.z;
     q_off[i] = (uintptr_t)Q.q;
-    const uint64_t need_off = (uintptr_t)Q.need;
-    if (need_off + table_need_bytes(Q.m) > W.per_query.bytes) return RS_EINVAL;
+    need_off[i] = (uintptr_t)Q.need;
+    if (need_off[i] + table_need_bytes(Q.m, Q.k) > W.per_query.bytes) return RS_EINVAL;
     if (q_off[i] + table_q_bytes(Q.m, Q.k, Q.kq) > W.per_query.bytes) return RS_EINVAL;
     if ((uint64_t)Q.m + Q.n > W.ref.bytes || 4ull * Q.n > W.lastref.bytes) return RS_EINVAL;
     Q.lo = (uint32_t*)(pq + lo_off[i]);
     Q.z = (uint64_t*)(pq + z_off[i]);
     Q.q = (uint64_t*)(pq + q_off[i]);
-    Q.need = (uint8_t*)(pq + need_off);
+    Q.need = (uint8_t*)(pq + need_off[i]);
     Q.ref = W.ref.as<uint8_t>();
     Q.lastref = W.lastref.as<uint32_t>();
   }
@@ -635,7 +640,9 @@ static rs_status resolve_plan(BatchPlan& P, BatchWorkspace& W, uint32_t epoch0) 
       if (q_level + 8ull * Q.m * Q.kq > q_off[qi] + 8ull * Q.m * Q.kq * (Q.k - 1)) return RS_EINVAL;
       U.q = (const uint64_t*)(pq + q_level);
       U.lo = Q.lo;
-      U.need = Q.need;
+      const uint64_t need_level = (uintptr_t)U.need - need_off[qi];  // offset of this level's flags
+      if (need_level + need_stride(Q.m) > table_need_bytes(Q.m, Q.k)) return RS_EINVAL;
+      U.need = Q.need + need_level;
       U.z = Q.z;
       U.pp = (const uint64_t*)(pa + pp_off);
       U.pc = (uint64_t*)(pa + pc_off);
@@ -737,11 +744,14 @@ static rs_status batch_enqueue(BatchPlan& P, BatchWorkspace& W, hipStream_t st) 
     const BQuery& Q = P.qs[qi];
     hipLaunchKernelGGL(kb_ztable, dim3((uint32_t)(((uint64_t)Q.n * Q.kq + 255) / 256)), dim3(256), 0, st, dq, qi);
     hipLaunchKernelGGL(kb_window, dim3((Q.m + 255) / 256), dim3(256), 0, st, dq, qi);
-    hipLaunchKernelGGL(kb_clear_ref, dim3((uint32_t)std::min<uint64_t>(((uint64_t)Q.m + Q.n + 1023) / 1024, 1024)),
-                       dim3(256), 0, st, dq, qi);
-    hipLaunchKernelGGL(kb_mark_ref, dim3((Q.m + 255) / 256), dim3(256), 0, st, dq, qi);
-    hipLaunchKernelGGL(kb_mark_last, dim3((Q.n + 255) / 256), dim3(256), 0, st, dq, qi);
-    hipLaunchKernelGGL(kb_mark_need, dim3((Q.m + 255) / 256), dim3(256), 0, st, dq, qi);
+    for (uint32_t l = Q.k - 1; l >= 2 && Q.k >= 3; --l) {  // flags per prefix level, last one first
+      hipLaunchKernelGGL(kb_clear_ref,
+                         dim3((uint32_t)std::min<uint64_t>(((uint64_t)Q.m + Q.n + 1023) / 1024, 1024)), dim3(256), 0,
+                         st, dq, qi);
+      hipLaunchKernelGGL(kb_mark_ref, dim3((Q.m + 255) / 256), dim3(256), 0, st, dq, qi, l);
+      hipLaunchKernelGGL(kb_mark_last, dim3((Q.n + 255) / 256), dim3(256), 0, st, dq, qi);
+      hipLaunchKernelGGL(kb_mark_need, dim3((Q.m + 255) / 256), dim3(256), 0, st, dq, qi, l);
+    }
     switch (Q.kq) {
       case 4: hipLaunchKernelGGL(kb_qtable<4>, dim3((Q.m + 255) / 256), dim3(256), 0, st, dq, qi); break;
       case 8: hipLaunchKernelGGL(kb_qtable<8>, dim3((Q.m + 255) / 256), dim3(256), 0, st, dq, qi); break;

@@ -178,7 +178,7 @@ double top_bytes(const NeedCounts& nc, uint64_t m, uint32_t kq, uint64_t chunks,
 uint64_t table_lo_bytes(uint64_t m) { return 4 * (m + kEdgePad); }
 uint64_t table_z_bytes(uint64_t n, uint32_t kq) { return 8 * n * kq; }
 uint64_t table_q_bytes(uint64_t m, uint32_t k, uint32_t kq) { return 8 * (m * (k - 1) + kEdgePad) * kq; }
-uint64_t table_need_bytes(uint64_t m) { return m + kEdgePad; }
+uint64_t table_need_bytes(uint64_t m, uint32_t k) { return (uint64_t)need_levels(k) * need_stride(m); }
 
 // ---------------------------------------------------------------------------
 // Plain path: setup kernels, then per chunk group levels 2..k.
@@ -203,7 +203,7 @@ PlainSizes plain_sizes(uint64_t m, uint64_t n, const QueryPlan& qp, const Tuning
   s.partial = 8 * 64 * cpl * (uint64_t)tblocks;
   s.fsum = 8 * (1ull << k);
   s.ref = (m + n + 3) & ~3ull;
-  s.need = table_need_bytes(m);
+  s.need = table_need_bytes(m, k);
   s.lastref = 4 * n;
   s.records = 1024 * cpl * tiles;
   return s;
@@ -250,6 +250,7 @@ rs_status run_plain(rs_graph* g, PlainWorkspace& ws, const QueryPlan& qp, const 
         ws.out.reserve(64, st, false) || ws.ref.reserve(sz.ref, st, false) || ws.need.reserve(sz.need, st, false) ||
         ws.lastref.reserve(sz.lastref, st, false))
       return RS_ENOMEM;
+    auto need_of = [&](uint32_t l) { return ws.need.as<uint8_t>() + (uint64_t)(l - 2) * need_stride(m); };
     if (ws.agg.bytes < sz.records || ws.incl.bytes < sz.records) {
       // tagged records start at epoch 0, which no launch uses
       if (ws.agg.reserve(sz.records, st, true) || ws.incl.reserve(sz.records, st, true)) return RS_ENOMEM;
@@ -263,32 +264,50 @@ rs_status run_plain(rs_graph* g, PlainWorkspace& ws, const QueryPlan& qp, const 
       ProfScope ps(KC_WINDOW, st, 16.0 * m);
       RS_HIP(launch_window(G.e_src.as<uint32_t>(), G.e_t.as<uint32_t>(), G.in_off.as<uint32_t>(),
                            ws.lo.as<uint32_t>(), (uint32_t)m, qp.delta, st));
-      RS_HIP(launch_need(G.in_off.as<uint32_t>(), G.e_dst.as<uint32_t>(), G.e_out.as<uint32_t>(),
-                         G.hi.as<uint32_t>(), ws.lo.as<uint32_t>(), (uint32_t)m, (uint32_t)n, ws.ref.as<uint8_t>(),
-                         ws.lastref.as<uint32_t>(), ws.need.as<uint8_t>(), st));
+      // Flags per prefix level, from the last one down: level l stores the
+      // slots the windows of level l+1's product edges read, and forms a
+      // product only for edges at or before the last such slot of their
+      // segment (level k-1: the windows of every last-level edge).
+      for (uint32_t l = k - 1; l >= 2 && k >= 3; --l)
+        RS_HIP(launch_need(G.in_off.as<uint32_t>(), G.e_dst.as<uint32_t>(), G.e_out.as<uint32_t>(),
+                           G.hi.as<uint32_t>(), ws.lo.as<uint32_t>(), (uint32_t)m, (uint32_t)n,
+                           l + 1 < k ? need_of(l + 1) : nullptr, ws.ref.as<uint8_t>(), ws.lastref.as<uint32_t>(),
+                           need_of(l), st));
     }
     // Counts for the byte accounting of timed launches: measured once per
-    // delta (a synchronising read-back), only while kernel timing is on.
-    NeedCounts nc;
+    // (delta, k) (a synchronising read-back), only while kernel timing is on.
+    std::vector<NeedCounts> ncs(k + 1);
     if (profiling_on()) {
       std::lock_guard<std::mutex> lk(g->counts_mu);
-      auto it = g->need_counts.find(qp.delta);
+      auto it = g->need_counts.find({qp.delta, k});
       if (it == g->need_counts.end()) {
-        unsigned long long h[5] = {0, 0, 0, 0, 0};
         if (g->counts_dev.reserve(64, st, true)) return RS_ENOMEM;
-        RS_HIP(launch_fill64(g->counts_dev.as<uint64_t>(), 0, 8, st));
-        RS_HIP(launch_need_counts(G.hi.as<uint32_t>(), ws.lo.as<uint32_t>(), ws.need.as<uint8_t>(), (uint32_t)m,
-                                  g->counts_dev.as<unsigned long long>(), st));
-        RS_HIP(hipMemcpyAsync(h, g->counts_dev.p, sizeof(h), hipMemcpyDeviceToHost, st));
-        RS_HIP(hipStreamSynchronize(st));
-        nc.live = h[0];
-        nc.live_needed = h[1];
-        nc.needed = h[2];
-        nc.ref_slots = h[3];
-        nc.ref_lead = h[4];
-        g->need_counts[qp.delta] = nc;
+        for (uint32_t l = 2; l < k; ++l) {
+          unsigned long long h[5] = {0, 0, 0, 0, 0};
+          RS_HIP(launch_fill64(g->counts_dev.as<uint64_t>(), 0, 8, st));
+          RS_HIP(launch_need_counts(G.hi.as<uint32_t>(), ws.lo.as<uint32_t>(), need_of(l), (uint32_t)m,
+                                    g->counts_dev.as<unsigned long long>(), st));
+          RS_HIP(hipMemcpyAsync(h, g->counts_dev.p, sizeof(h), hipMemcpyDeviceToHost, st));
+          RS_HIP(hipStreamSynchronize(st));
+          ncs[l].live = h[0];
+          ncs[l].live_needed = h[1];
+          ncs[l].needed = h[2];
+          ncs[l].ref_slots = h[3];
+          ncs[l].ref_lead = h[4];
+        }
+        ncs[k] = ncs[k > 2 ? k - 1 : k];  // the last level needs only the window count
+        if (k == 2) {  // no prefix level: count the windows alone
+          unsigned long long h[5] = {0, 0, 0, 0, 0};
+          RS_HIP(launch_fill64(g->counts_dev.as<uint64_t>(), 0, 8, st));
+          RS_HIP(launch_need_counts(G.hi.as<uint32_t>(), ws.lo.as<uint32_t>(), need_of(2), (uint32_t)m,
+                                    g->counts_dev.as<unsigned long long>(), st));
+          RS_HIP(hipMemcpyAsync(h, g->counts_dev.p, sizeof(h), hipMemcpyDeviceToHost, st));
+          RS_HIP(hipStreamSynchronize(st));
+          ncs[2].live = h[0];
+        }
+        g->need_counts[{qp.delta, k}] = ncs;
       } else {
-        nc = it->second;
+        ncs = it->second;
       }
     }
     {
@@ -327,8 +346,8 @@ rs_status run_plain(rs_graph* g, PlainWorkspace& ws, const QueryPlan& qp, const 
           a.epoch = ws.epoch;
           a.agg = ws.agg.as<uint64_t>();
           a.incl = ws.incl.as<uint64_t>();
-          a.need = ws.need.as<uint8_t>();
-          ProfScope ps(first ? KC_FIRST : KC_SCAN, st, scan_bytes(nc, m, kq, gc, first));
+          a.need = need_of(l);
+          ProfScope ps(first ? KC_FIRST : KC_SCAN, st, scan_bytes(ncs[l], m, kq, gc, first));
           RS_HIP(launch_scan(a, first, kq, gc, tu, st));
           std::swap(prev, cur);
         } else {
@@ -348,7 +367,7 @@ rs_status run_plain(rs_graph* g, PlainWorkspace& ws, const QueryPlan& qp, const 
           a.k = k;
           a.partial = ws.partial.as<uint64_t>();
           a.fsum = ws.fsum.as<uint64_t>();
-          ProfScope ps(KC_TOP, st, top_bytes(nc, m, kq, gc, first));
+          ProfScope ps(KC_TOP, st, top_bytes(ncs[k], m, kq, gc, first));
           RS_HIP(launch_top(a, first, kq, gc, tu, st));
         }
       }

@@ -138,11 +138,19 @@ struct NeedCounts {
 // ref_slots, ref_lead.
 hipError_t launch_need_counts(const uint32_t* hi, const uint32_t* lo, const uint8_t* need, uint32_t m,
                               unsigned long long* counts, hipStream_t st);
-// Store and product flags: ref[m+n] and lastref[n] are scratch, need[m] the
-// per-edge flags.
+// Store and product flags of one prefix level l: the slots read by the
+// windows of the level-(l+1) readers, given by `next` (the flags of level l+1;
+// null for l = k-1, whose readers are every non-empty window of the last
+// level). ref[m+n] and lastref[n] are scratch, need[m] the per-edge flags.
 hipError_t launch_need(const uint32_t* in_off, const uint32_t* e_dst, const uint32_t* e_out, const uint32_t* hi,
-                       const uint32_t* lo, uint32_t m, uint32_t n, uint8_t* ref, uint32_t* lastref, uint8_t* need,
-                       hipStream_t st);
+                       const uint32_t* lo, uint32_t m, uint32_t n, const uint8_t* next, uint8_t* ref,
+                       uint32_t* lastref, uint8_t* need, hipStream_t st);
+// Flag arrays of a query: one per prefix level 2..k-1 (at least one), each
+// m + kEdgePad bytes, level l at offset (l - 2) * need_stride(m); the stride
+// keeps every level's array 256-byte aligned (the kernels read the flags four
+// edges per 32-bit word).
+inline uint32_t need_levels(uint32_t k) { return k > 3 ? k - 2 : 1; }
+__host__ __device__ inline uint64_t need_stride(uint64_t m) { return (m + kEdgePad + 255) & ~255ull; }
 hipError_t launch_qtable(const uint32_t* e_src, const uint32_t* e_dst, const uint32_t* e_t,
                          const uint64_t* z, uint64_t* q, uint32_t m, const QueryPlan& qp,
                          hipStream_t st);
@@ -157,12 +165,12 @@ hipError_t launch_xor_reduce(const uint64_t* f, uint64_t begin, uint64_t end, ui
 
 // Bytes of a query's per-query tables on a graph with n vertices, m edges:
 // window starts lo[m], substitution rows z[n][kq], product rows
-// q[k-1][m][kq] and per-edge flags need[m] (each padded past m as the level
+// q[k-1][m][kq] and per-edge flags need[levels][m] (each padded past m as the level
 // kernels expect).
 uint64_t table_lo_bytes(uint64_t m);
 uint64_t table_z_bytes(uint64_t n, uint32_t kq);
 uint64_t table_q_bytes(uint64_t m, uint32_t k, uint32_t kq);
-uint64_t table_need_bytes(uint64_t m);
+uint64_t table_need_bytes(uint64_t m, uint32_t k);
 struct PlainWorkspace;
 // Plain path (rs_engine.hip): one query through workspace ws on stream st.
 rs_status run_plain(rs_graph* g, PlainWorkspace& ws, const QueryPlan& qp, const Tuning& tu, uint64_t* per_it_host,
@@ -253,9 +261,9 @@ struct rs_graph {
   bool has_tuned[RS_MAX_K + 1] = {false};
   rs::Tuning batch_tuned;
   bool has_batch_tuned = false;
-  // Window and flag counts per delta, measured when kernel timing is on;
+  // Window and flag counts per (delta, k) and prefix level, measured when kernel timing is on;
   // guarded by counts_mu.
   std::mutex counts_mu;
-  std::map<uint32_t, rs::NeedCounts> need_counts;
+  std::map<std::pair<uint32_t, uint32_t>, std::vector<rs::NeedCounts>> need_counts;  // by (delta, k), per level
   rs::DevBuf counts_dev;
 };

@@ -183,9 +183,10 @@ __global__ __launch_bounds__(256) void k_window(const uint32_t* __restrict__ e_s
 }
 
 __global__ __launch_bounds__(256) void k_mark_ref(const uint32_t* __restrict__ hi, const uint32_t* __restrict__ lo,
-                                                  uint32_t m, uint8_t* __restrict__ ref) {
+                                                  const uint8_t* __restrict__ next, uint32_t m,
+                                                  uint8_t* __restrict__ ref) {
   const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < m) mark_ref(hi, lo, e, ref);
+  if (e < m) mark_ref(hi, lo, next, e, ref);
 }
 
 __global__ __launch_bounds__(256) void k_mark_last(const uint32_t* __restrict__ in_off,
@@ -329,12 +330,12 @@ hipError_t launch_need_counts(const uint32_t* hi, const uint32_t* lo, const uint
 }
 
 hipError_t launch_need(const uint32_t* in_off, const uint32_t* e_dst, const uint32_t* e_out, const uint32_t* hi,
-                       const uint32_t* lo, uint32_t m, uint32_t n, uint8_t* ref, uint32_t* lastref, uint8_t* need,
-                       hipStream_t st) {
+                       const uint32_t* lo, uint32_t m, uint32_t n, const uint8_t* next, uint8_t* ref,
+                       uint32_t* lastref, uint8_t* need, hipStream_t st) {
   if (!m) return hipSuccess;
   hipError_t e = launch_fill32((uint32_t*)ref, 0, ((uint64_t)m + n + 3) / 4, st);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_mark_ref, dim3(div_up(m, 256)), dim3(256), 0, st, hi, lo, m, ref);
+  hipLaunchKernelGGL(k_mark_ref, dim3(div_up(m, 256)), dim3(256), 0, st, hi, lo, next, m, ref);
   hipLaunchKernelGGL(k_mark_last, dim3(div_up(n, 256)), dim3(256), 0, st, in_off, ref, n, lastref);
   hipLaunchKernelGGL(k_mark_need, dim3(div_up(m, 256)), dim3(256), 0, st, e_out, e_dst, ref, lastref, m, need);
   return hipGetLastError();

@@ -584,9 +584,13 @@ __device__ __forceinline__ void top_range(const uint32_t* e_src_p, const uint32_
 //          at a prefix level reaches a value that is read.
 // A prefix level skips the product of an edge without bit 2 (it only reaches
 // slots nothing reads) and stores only slots with bit 0 / bit 1.
-__device__ __forceinline__ void mark_ref(const uint32_t* hi, const uint32_t* lo, uint64_t e, uint8_t* ref) {
+// Marks the two slots of edge e's window, when the window is non-empty and
+// e is one of the readers (next == null: every edge; else edges whose
+// next-level product is needed, bit 2 of next[e]).
+__device__ __forceinline__ void mark_ref(const uint32_t* hi, const uint32_t* lo, const uint8_t* next, uint64_t e,
+                                         uint8_t* ref) {
   const uint32_t h = hi[e], l = lo[e];
-  if (h != l) {
+  if (h != l && (!next || (next[e] & 4u))) {
     ref[h] = 1;
     ref[l] = 1;
   }

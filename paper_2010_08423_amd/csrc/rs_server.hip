@@ -375,7 +375,7 @@ rs_status rs_server_submit(rs_server* s, uint32_t graph_id, const rs_query* q, u
       return RS_ENOMEM;
     }
     a->group_bytes = table_lo_bytes(m) + table_z_bytes(n, a->plan.kq) + table_q_bytes(m, a->plan.k, a->plan.kq) +
-                     table_need_bytes(m) + 8 * (1ull << a->plan.k) + 2048;
+                     table_need_bytes(m, a->plan.k) + 8 * (1ull << a->plan.k) + 2048;
     a->ticket = s->next_ticket++;
     a->graph_id = graph_id;
     a->q = *q;
