@@ -213,6 +213,16 @@ rs_status rs_autotune(const rs_graph* g, const rs_query* sample, uint32_t ns, rs
  * timing is on; that first query synchronises once to read them back.
  * ---------------------------------------------------------------------- */
 rs_status rs_profile_enable(int on);
+/* Launch trace of the plain path (rs_run, rs_run_ex): while on, every launch
+ * is followed by a synchronisation of the query's stream and one line on
+ * stderr naming the step (workspace, setup, product rows, prefix level l,
+ * last level) with the host wall time since the previous line; prefix levels
+ * add the look-back counters: predecessor tiles recomputed after the bounded
+ * wait, and probe rounds that found no published record. Initially on when
+ * the environment variable RS_TRACE is set to anything but "0". For
+ * diagnosing large queries: it serialises the launches with the host and so
+ * changes timings. Results are unchanged. Never fails. */
+rs_status rs_trace_enable(int on);
 rs_status rs_profile_reset(void);
 /* launches and summed milliseconds of a kernel class since the last reset. */
 rs_status rs_profile_get(const char* kernel_class, uint64_t* launches, double* total_ms,

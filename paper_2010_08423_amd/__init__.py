@@ -101,6 +101,7 @@ _SIGNATURES = {
     "rs_autotune": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(_Query), ctypes.c_uint32,
                                      ctypes.POINTER(_Tuning)]),
     "rs_profile_enable": (ctypes.c_int32, [ctypes.c_int]),
+    "rs_trace_enable": (ctypes.c_int32, [ctypes.c_int]),
     "rs_profile_reset": (ctypes.c_int32, []),
     "rs_profile_get": (ctypes.c_int32, [ctypes.c_char_p, _u64p, ctypes.POINTER(ctypes.c_double),
                                         ctypes.POINTER(ctypes.c_double)]),
@@ -342,6 +343,11 @@ def autotune(graph: Graph, sample_queries) -> Tuning:
 
 def profile_enable(on=True):
     _check(_load().rs_profile_enable(1 if on else 0), "rs_profile_enable")
+
+
+def trace_enable(on=True):
+    """rs_trace_enable: per-launch trace lines of the plain path on stderr."""
+    _check(_load().rs_trace_enable(1 if on else 0), "rs_trace_enable")
 
 
 def profile_reset():

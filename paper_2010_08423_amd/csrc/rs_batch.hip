@@ -227,11 +227,12 @@ __device__ __forceinline__ uint32_t find_unit(cu32* ubegin, uint32_t from, uint3
 
 // Prefix level: the launch's waves are partitioned over (unit, chunk) pairs,
 // unit u's chunks getting `waves` waves each, in proportion to its tiles;
-// within a pair the waves run the per-level kernel's schedule (wave i takes
-// tiles i, i + waves, ...), so a tile's predecessor is on the neighbouring
-// wave of the same pair and no wave ever waits on another pair.
+// within a pair the waves run the per-level kernel's schedule (wave i scans
+// the i-th of `waves` contiguous runs of tiles), so a run's predecessor is
+// the neighbouring wave of the same pair and no wave ever waits on another
+// pair.
 template <int KQ, int E, bool FIRST>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void kb_scan(const MUnit* __restrict__ units, const uint32_t* __restrict__ ubegin_p,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void kb_scan(const MUnit* __restrict__ units, const uint32_t* __restrict__ ubegin_p,
                                                uint32_t nunits, uint32_t total, uint64_t* __restrict__ agg,
                                                uint64_t* __restrict__ incl) {
   extern __shared__ uint64_t dyn_lds[];  // [waves][16][64]; starts at LDS address 0
@@ -265,7 +266,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   c.agg = agg;
   c.incl = incl;
   c.need = U.need;
-  scan_tiles<KQ, E, FIRST>(c, idx, U.waves, lane, mk, tab);
+  c.lb_stats = nullptr;
+  scan_run<KQ, E, FIRST>(c, idx, U.waves, lane, mk, tab);
 }
 
 // Last level: flat index = (unit, edge range of top_edges edges). A wave keeps
@@ -809,7 +811,7 @@ rs_status run_batch_impl(const rs_graph* const* graphs, const rs_query* queries,
     if (tune->no_graph) use_graph = false;
   }
   if (tu.edges_per_tile != 8 && tu.edges_per_tile != 16) tu.edges_per_tile = 16;
-  if (tu.waves_per_block != 1 && tu.waves_per_block != 2 && tu.waves_per_block != 4) tu.waves_per_block = 4;
+  if (tu.waves_per_block != 1 && tu.waves_per_block != 2 && tu.waves_per_block != 4) tu.waves_per_block = 2;
   tu.top_edges_per_tile = std::min(std::max(tu.top_edges_per_tile, 1u), 4096u);
   BatchPlan P;
   RS_TRY(batch_plan(graphs, queries, nq, tu, slot_budget ? slot_budget : default_slot_budget(), results, P));
@@ -921,9 +923,9 @@ rs_status autotune_impl(rs_graph* g, const rs_query* sample, uint32_t ns, rs_tun
   // plain path, per k present in the sample
   std::vector<Tuning> cands;
   for (uint32_t E : {8u, 16u})
-    for (uint32_t wpb : {2u, 4u})
+    for (uint32_t wpb : {1u, 2u, 4u})
       for (uint32_t top : {16u, 64u})
-        for (uint32_t cpl : {1u, 2u}) {
+        for (uint32_t cpl : {2u, 4u}) {
           Tuning t;
           t.edges_per_tile = E;
           t.waves_per_block = wpb;
@@ -970,7 +972,7 @@ rs_status autotune_impl(rs_graph* g, const rs_query* sample, uint32_t ns, rs_tun
   double best = 1e30;
   Tuning bb;
   for (uint32_t E : {8u, 16u})
-    for (uint32_t wpb : {2u, 4u})
+    for (uint32_t wpb : {1u, 2u, 4u})
       for (uint32_t top : {64u, 256u}) {
         rs_tuning t{E, top, 0, wpb, 0, 1};
         double tmin = 1e30;

@@ -1,9 +1,12 @@
 // Query engine and C ABI: graph lifetime, query validation, the plain
 // level-by-level launch sequence, device workspaces and kernel timing.
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
+#include <chrono>
 #include <map>
 #include <mutex>
 #include <new>
@@ -17,6 +20,24 @@ namespace rs {
 rs_status graph_build(uint32_t n, uint64_t m, const uint32_t* src, const uint32_t* dst,
                       const uint32_t* t, const uint8_t* colour, uint32_t n_colours, bool host_ptrs,
                       hipStream_t st, rs_graph** out);
+
+// Launch trace of the plain path (rs_trace_enable; initially on when the
+// environment variable RS_TRACE is set to anything but "0"): each launch is
+// followed by a stream synchronisation and one line on stderr with its wall
+// time and, for a prefix level, the look-back counters (predecessors
+// recomputed, probe rounds without an answer). Meant for diagnosing large
+// queries; it serialises the launches with the host.
+static std::atomic<int> g_trace{-1};
+static bool trace_on() {
+  int v = g_trace.load(std::memory_order_relaxed);
+  if (v < 0) {
+    const char* e = getenv("RS_TRACE");
+    int want = e && *e && strcmp(e, "0") != 0 ? 1 : 0;
+    g_trace.compare_exchange_strong(v, want);
+    v = g_trace.load(std::memory_order_relaxed);
+  }
+  return v > 0;
+}
 
 static thread_local std::string g_last_error;
 void set_last_error(const std::string& s) { g_last_error = s; }
@@ -150,7 +171,7 @@ Tuning resolve_tuning(const rs_graph* g, uint32_t k, const rs_tuning* t) {
   }
   if (tu.edges_per_tile != 8 && tu.edges_per_tile != 16) tu.edges_per_tile = 16;
   tu.top_edges_per_tile = std::min(std::max(tu.top_edges_per_tile, 1u), 4096u);
-  if (tu.waves_per_block != 1 && tu.waves_per_block != 2 && tu.waves_per_block != 4) tu.waves_per_block = 4;
+  if (tu.waves_per_block != 1 && tu.waves_per_block != 2 && tu.waves_per_block != 4) tu.waves_per_block = 2;
   if (tu.chunks_per_launch < 1) tu.chunks_per_launch = 1;
   return tu;
 }
@@ -256,6 +277,27 @@ rs_status run_plain(rs_graph* g, PlainWorkspace& ws, const QueryPlan& qp, const 
       if (ws.agg.reserve(sz.records, st, true) || ws.incl.reserve(sz.records, st, true)) return RS_ENOMEM;
       ws.epoch = 0;
     }
+    const bool tr = trace_on();
+    if (tr && ws.lb_stats.reserve(16, st, true)) return RS_ENOMEM;
+    auto t_last = std::chrono::steady_clock::now();
+    // one trace line: waits for the launches so far, reads the counters
+    auto trace = [&](const char* what, uint32_t l, uint64_t c0, uint32_t gc, bool counters) -> rs_status {
+      RS_HIP(hipStreamSynchronize(st));
+      unsigned long long h[2] = {0, 0};
+      if (counters) RS_HIP(hipMemcpy(h, ws.lb_stats.p, sizeof(h), hipMemcpyDeviceToHost));
+      const auto now = std::chrono::steady_clock::now();
+      fprintf(stderr, "[rs-trace] %s level %u chunks %llu..%llu: %.3f ms", what, l, (unsigned long long)c0,
+              (unsigned long long)(c0 + gc), std::chrono::duration<double, std::milli>(now - t_last).count());
+      if (counters) fprintf(stderr, ", look-back recomputes %llu, unanswered probe rounds %llu", h[0], h[1]);
+      fprintf(stderr, "\n");
+      fflush(stderr);
+      t_last = std::chrono::steady_clock::now();
+      return RS_OK;
+    };
+    if (tr) {
+      const rs_status ts = trace("workspace", 0, 0, 0, false);
+      if (ts != RS_OK) return ts;
+    }
     {
       ProfScope ps(KC_ZTABLE, st, 8.0 * n * kq);
       RS_HIP(launch_ztable(ws.z.as<uint64_t>(), (uint32_t)n, qp, G.colour.as<uint8_t>(), st));
@@ -273,6 +315,10 @@ rs_status run_plain(rs_graph* g, PlainWorkspace& ws, const QueryPlan& qp, const 
                            G.hi.as<uint32_t>(), ws.lo.as<uint32_t>(), (uint32_t)m, (uint32_t)n,
                            l + 1 < k ? need_of(l + 1) : nullptr, ws.ref.as<uint8_t>(), ws.lastref.as<uint32_t>(),
                            need_of(l), st));
+    }
+    if (tr) {
+      const rs_status ts = trace("setup (z table, windows, flags)", 0, 0, 0, false);
+      if (ts != RS_OK) return ts;
     }
     // Counts for the byte accounting of timed launches: measured once per
     // (delta, k) (a synchronising read-back), only while kernel timing is on.
@@ -315,6 +361,10 @@ rs_status run_plain(rs_graph* g, PlainWorkspace& ws, const QueryPlan& qp, const 
       RS_HIP(launch_qtable(G.e_src.as<uint32_t>(), G.e_dst.as<uint32_t>(), G.e_t.as<uint32_t>(),
                            ws.z.as<uint64_t>(), ws.q.as<uint64_t>(), (uint32_t)m, qp, st));
     }
+    if (tr) {
+      const rs_status ts = trace("product rows", 0, 0, 0, false);
+      if (ts != RS_OK) return ts;
+    }
     RS_HIP(launch_fill64(ws.fsum.as<uint64_t>(), 0, 1ull << k, st));
     for (uint64_t c0 = qp.chunk_first; c0 < qp.chunk_last; c0 += cpl) {
       const uint32_t gc = (uint32_t)std::min<uint64_t>(cpl, qp.chunk_last - c0);
@@ -347,8 +397,18 @@ rs_status run_plain(rs_graph* g, PlainWorkspace& ws, const QueryPlan& qp, const 
           a.agg = ws.agg.as<uint64_t>();
           a.incl = ws.incl.as<uint64_t>();
           a.need = need_of(l);
-          ProfScope ps(first ? KC_FIRST : KC_SCAN, st, scan_bytes(ncs[l], m, kq, gc, first));
-          RS_HIP(launch_scan(a, first, kq, gc, tu, st));
+          if (tr) {
+            RS_HIP(launch_fill64(ws.lb_stats.as<uint64_t>(), 0, 2, st));
+            a.lb_stats = ws.lb_stats.as<unsigned long long>();
+          }
+          {
+            ProfScope ps(first ? KC_FIRST : KC_SCAN, st, scan_bytes(ncs[l], m, kq, gc, first));
+            RS_HIP(launch_scan(a, first, kq, gc, tu, st));
+          }
+          if (tr) {
+            const rs_status ts = trace("prefix", l, c0, gc, true);
+            if (ts != RS_OK) return ts;
+          }
           std::swap(prev, cur);
         } else {
           TopArgs a;
@@ -367,8 +427,14 @@ rs_status run_plain(rs_graph* g, PlainWorkspace& ws, const QueryPlan& qp, const 
           a.k = k;
           a.partial = ws.partial.as<uint64_t>();
           a.fsum = ws.fsum.as<uint64_t>();
-          ProfScope ps(KC_TOP, st, top_bytes(ncs[k], m, kq, gc, first));
-          RS_HIP(launch_top(a, first, kq, gc, tu, st));
+          {
+            ProfScope ps(KC_TOP, st, top_bytes(ncs[k], m, kq, gc, first));
+            RS_HIP(launch_top(a, first, kq, gc, tu, st));
+          }
+          if (tr) {
+            const rs_status ts = trace("last", l, c0, gc, false);
+            if (ts != RS_OK) return ts;
+          }
         }
       }
     }
@@ -499,6 +565,11 @@ rs_status rs_run_ex(const rs_graph* gc, const rs_query* q, const rs_tuning* tune
 
 rs_status rs_run(const rs_graph* g, const rs_query* q, rs_result* r, void* hip_stream) {
   return rs_run_ex(g, q, nullptr, nullptr, r, hip_stream);
+}
+
+rs_status rs_trace_enable(int on) {
+  g_trace.store(on != 0 ? 1 : 0);
+  return RS_OK;
 }
 
 rs_status rs_profile_enable(int on) {

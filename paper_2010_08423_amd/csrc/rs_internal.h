@@ -65,7 +65,7 @@ struct Tuning {
   uint32_t edges_per_tile = 16;      // scan levels: 8 or 16
   uint32_t top_edges_per_tile = 8;   // last level
   uint32_t chunks_per_launch = 4;
-  uint32_t waves_per_block = 4;
+  uint32_t waves_per_block = 2;
   uint32_t max_slots = 0;  // batched path; 0 = as many as fit
 };
 
@@ -98,6 +98,7 @@ struct ScanArgs {
   uint64_t* agg;           // [chunks][n_tiles][64][2] tagged records
   uint64_t* incl;          // [chunks][n_tiles][64][2]
   const uint8_t* need;     // [m] store flags
+  unsigned long long* lb_stats = nullptr;  // null, or [2] look-back counters (see TileCtx)
 };
 
 // Arguments of the last level k.
@@ -220,17 +221,20 @@ namespace rs {
 // the largest query run through them and stay allocated until release().
 struct PlainWorkspace {
   DevBuf lo, z, q, p0, p1, partial, agg, incl, fsum, out, ref, need, lastref;
+  DevBuf lb_stats;  // look-back counters, allocated only while launches are traced
   uint32_t epoch = 0;
   uint64_t p_elems_per_chunk = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   uint64_t bytes() const {
     uint64_t t = 0;
-    for (const DevBuf* b : {&lo, &z, &q, &p0, &p1, &partial, &agg, &incl, &fsum, &out, &ref, &need, &lastref})
+    for (const DevBuf* b : {&lo, &z, &q, &p0, &p1, &partial, &agg, &incl, &fsum, &out, &ref, &need, &lastref,
+                            &lb_stats})
       t += b->bytes;
     return t;
   }
   void release() {
-    for (DevBuf* b : {&lo, &z, &q, &p0, &p1, &partial, &agg, &incl, &fsum, &out, &ref, &need, &lastref}) b->release();
+    for (DevBuf* b : {&lo, &z, &q, &p0, &p1, &partial, &agg, &incl, &fsum, &out, &ref, &need, &lastref, &lb_stats})
+      b->release();
     if (ev0) (void)hipEventDestroy(ev0);
     if (ev1) (void)hipEventDestroy(ev1);
     ev0 = ev1 = nullptr;

@@ -12,19 +12,20 @@ namespace rs {
 
 // ---------------------------------------------------------------------------
 // Prefix levels 2..k-1. The grid holds about as many waves as fit on the GPU;
-// wave w takes tiles w, w + W, w + 2W, ... (W waves in all), so a tile's
-// predecessor is normally being processed by the neighbouring wave in the
-// same round. No atomics: a tile whose predecessor has not published yet
-// waits a bounded time and then recomputes it (see look_back).
+// wave w of W scans the w-th of W contiguous runs of tiles (see scan_run), so
+// carries flow in registers along a run and the waves meet once, at the run
+// ends, through the look-back records. A run whose predecessor has not
+// published after a bounded wait recomputes that run's tail (see look_back).
 // ---------------------------------------------------------------------------
 template <int KQ, int E, bool FIRST>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_scan(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_scan(
     const uint32_t* __restrict__ e_src, const uint32_t* __restrict__ e_out,
     const uint32_t* __restrict__ hi_idx, const uint32_t* __restrict__ lo_idx,
     const uint64_t* __restrict__ q, const uint64_t* __restrict__ z,
     const uint64_t* __restrict__ p_prev, uint64_t* __restrict__ p_cur, uint64_t p_stride,
     uint64_t chunk_base, uint32_t m, uint32_t n_tiles, uint32_t epoch,
-    uint64_t* __restrict__ agg, uint64_t* __restrict__ incl, const uint8_t* __restrict__ need) {
+    uint64_t* __restrict__ agg, uint64_t* __restrict__ incl, const uint8_t* __restrict__ need,
+    unsigned long long* __restrict__ lb_stats) {
   extern __shared__ uint64_t dyn_lds[];  // [waves][16][64]; starts at LDS address 0
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform for the compiler
@@ -51,8 +52,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   c.agg = agg;
   c.incl = incl;
   c.need = need;
+  c.lb_stats = lb_stats;
   const uint32_t waves = gridDim.x * (blockDim.x >> 6);
-  scan_tiles<KQ, E, FIRST>(c, blockIdx.x * (blockDim.x >> 6) + wv, waves, lane, mk, tab);
+  scan_run<KQ, E, FIRST>(c, blockIdx.x * (blockDim.x >> 6) + wv, waves, lane, mk, tab);
 }
 
 // ---------------------------------------------------------------------------
@@ -370,7 +372,7 @@ static void scan_one(const ScanArgs& a, uint32_t chunks, uint32_t wpb, hipStream
   dim3 g(std::min(div_up(a.n_tiles, wpb), fit), chunks), b(64 * wpb);
   hipLaunchKernelGGL((k_scan<KQ, E, FIRST>), g, b, lds, st, a.e_src, a.e_out, a.hi, a.lo, a.q, a.z,
                      a.p_prev, a.p_cur, a.p_stride, a.chunk_base, a.m, a.n_tiles, a.epoch, a.agg,
-                     a.incl, a.need);
+                     a.incl, a.need, a.lb_stats);
 }
 
 template <int KQ>

@@ -24,10 +24,13 @@
 // empty (hi == lo): at levels >= 3 such an edge contributes exactly zero, so
 // the wave skips its gathers and product on a uniform branch.
 //
-// Prefix levels keep a running XOR per lane along a tile of E consecutive
-// edges; a segment that crosses tiles receives its carry through a decoupled
-// look-back on self-validating per-tile records (device-scope atomic stores
-// and loads that bypass the per-XCD L2; no fences, no atomic read-modify-write).
+// Prefix levels cut the edge list into one contiguous run of tiles (E
+// consecutive edges each) per wave and keep a running XOR per lane along the
+// run, so a segment receives its carry from the preceding tiles in registers.
+// Only a segment that crosses into a run from the one before needs a carry
+// from another wave: it comes through one decoupled look-back per run on
+// self-validating per-run records (device-scope atomic stores and loads that
+// bypass the per-XCD L2; no fences, no atomic read-modify-write).
 #pragma once
 
 #include "rs_device.h"
@@ -122,6 +125,7 @@ struct TileCtx {
   uint64_t* agg;       // [tiles][64][2] records: XOR of the tile's open segment part
   uint64_t* incl;      // [tiles][64][2] records: inclusive prefix of that segment
   const uint8_t* need; // per edge: which of its P slots some window reads (see mark_need)
+  unsigned long long* lb_stats;  // null, or [2]: recomputed predecessors, unanswered probe rounds
 };
 
 // N consecutive entries of an index array in one scalar load (the arrays are
@@ -283,49 +287,46 @@ __device__ uint64_t tile_open_part(const TileCtx& c, uint32_t j, uint32_t lane, 
   return acc;
 }
 
-// Spins (each a flag round trip plus a short sleep) before a waiting tile
-// stops relying on its predecessor and recomputes that tile's part itself.
-// A predecessor that is merely late (its wave still walking back through a
-// long segment) is better waited for than recomputed, since a walk that
-// recomputes would meet the next late predecessor and pay the wait again;
-// on the 10^6-edge graph 64, 256 and 2048 spins time the same.
-constexpr uint32_t kFallbackSpins = 2048;
+// Spins (each a flag round trip plus a short sleep) before a waiting wave
+// stops relying on its predecessor's record and recomputes that part itself.
+// Records are published once per wave, when its run of tiles is done, so a
+// predecessor is usually just finishing: it is waited for. The budget only
+// bounds the wait (about 10 ms) for a predecessor that never got to run.
+constexpr uint32_t kFallbackSpins = 4096;
 
-// XOR of the level values of the segment part preceding tile `tile`. The
-// nearest predecessor's records are read first, which ends most walks in one
-// memory round trip. After that, each round probes up to 64 predecessor tiles
-// at once (lane l reads the tags of
-// tile top-l's lane-0 words), then absorbs the leading run of
-// published tiles up to and including the nearest one that published its
-// inclusive prefix, every lane validating its own record words; a carry that
-// has to cross d tiles costs about d/64 memory round trips. A predecessor
-// that stays unpublished is recomputed here, so every wait is bounded
-// whatever order the tiles run in.
+// XOR of the level values of the segment part preceding tile `tile`, the
+// first tile of a wave's run. Records sit at the last tile of every run, so
+// the predecessors' records are `tile - 1`, `tile - 1 - stride`, ... (stride =
+// tiles per run). The nearest one's two records are read first, which ends
+// most walks in one memory round trip. After that, each round probes up to 64
+// predecessor records at once (lane l reads the tags of record top - l*stride,
+// lane-0 words), then absorbs the leading run of published records up to and
+// including the nearest inclusive one, every lane validating its own words; a
+// carry that has to cross d runs costs about d/64 memory round trips. A
+// predecessor that stays unpublished is recomputed here, tile by tile from
+// the end of its run, so every wait is bounded whatever order the waves run
+// in.
 template <int KQ, int E, bool FIRST>
-__device__ uint64_t look_back(const TileCtx& c, uint32_t tile, uint32_t lane, const uint32_t (&mk)[6],
-                              uint64_t* tab) {
+__device__ uint64_t look_back(const TileCtx& c, uint32_t tile, uint32_t stride, uint32_t lane,
+                              const uint32_t (&mk)[6], uint64_t* tab) {
   uint64_t carry = 0;
-  int64_t top = (int64_t)tile - 1;  // nearest tile not absorbed yet
-  uint32_t spins = 0;
+  int64_t top = (int64_t)tile - 1;  // record of the nearest run not absorbed yet
+  const int64_t st = (int64_t)stride;
+  uint32_t spins = 0, spin_total = 0;
   const uint32_t t_agg = rec_tag(c.epoch, kFlagAgg), t_inc = rec_tag(c.epoch, kFlagIncl);
   {
-    // Usual case first: both records of the nearest predecessor in one round
-    // trip; its inclusive prefix ends the walk, its aggregate is absorbed.
     uint64_t vi, va;
     const bool oki = read_rec(c.incl, c.row0 + (uint64_t)top, lane, t_inc, &vi);
     const bool oka = read_rec(c.agg, c.row0 + (uint64_t)top, lane, t_agg, &va);
     if (__ballot(!oki) == 0) return vi;
     if (__ballot(!oka) == 0) {
       carry = va;
-      --top;
+      top -= st;
     }
   }
-  // Probes cover the 4 nearest predecessors until a run of published tiles
-  // has been absorbed: most walks end at the first one (a segment starts in
-  // it), and each probed tile costs two tag fetches of other XCDs' writes.
   uint32_t width = 4;
   while (top >= 0) {
-    const int64_t j = top - (int64_t)lane;
+    const int64_t j = top - (int64_t)lane * st;
     bool ready = false, inc = false;
     if (j >= 0 && lane < width) {
       const uint64_t fi = c.row0 + (uint64_t)j;
@@ -343,7 +344,6 @@ __device__ uint64_t look_back(const TileCtx& c, uint32_t tile, uint32_t lane, co
     if (take > 0) {
       uint64_t part = 0;
       bool ok = true;
-      // 4 records per step, all loads of a step in flight together
       for (uint32_t i0 = 0; i0 < take; i0 += 4) {
 #pragma unroll
         for (uint32_t d = 0; d < 4; ++d) {
@@ -351,7 +351,7 @@ __device__ uint64_t look_back(const TileCtx& c, uint32_t tile, uint32_t lane, co
           if (i < take) {
             const bool use_inc = ends && i == first_inc;
             uint64_t v;
-            ok &= read_rec(use_inc ? c.incl : c.agg, c.row0 + (uint64_t)(top - i), lane,
+            ok &= read_rec(use_inc ? c.incl : c.agg, c.row0 + (uint64_t)(top - (int64_t)i * st), lane,
                            use_inc ? t_inc : t_agg, &v);
             part ^= v;
           }
@@ -360,22 +360,28 @@ __device__ uint64_t look_back(const TileCtx& c, uint32_t tile, uint32_t lane, co
       if (__ballot(!ok) == 0) {  // every lane's words were complete
         carry ^= part;
         if (ends) break;
-        top -= take;
+        top -= (int64_t)take * st;
         spins = 0;
-        width = kLanes;  // a long run of published tiles: probe wide
+        width = kLanes;  // a long run of published records: probe wide
         continue;
       }
     }
+    ++spin_total;
     if (++spins > kFallbackSpins) {
+      // recompute the predecessor run backwards from its last tile
+      if (c.lb_stats && lane == 0) atomicAdd(c.lb_stats, 1ull);
       bool started = false;
-      carry ^= tile_open_part<KQ, E, FIRST>(c, (uint32_t)top, lane, mk, tab, &started);
+      const int64_t run_first = top - st + 1;
+      for (int64_t j = top; j >= run_first && j >= 0 && !started; --j)
+        carry ^= tile_open_part<KQ, E, FIRST>(c, (uint32_t)j, lane, mk, tab, &started);
       if (started) break;
-      --top;
+      top -= st;
       spins = 0;
       continue;
     }
-    __builtin_amdgcn_s_sleep(2);
+    __builtin_amdgcn_s_sleep(8);
   }
+  if (c.lb_stats && spin_total && lane == 0) atomicAdd(c.lb_stats + 1, (unsigned long long)spin_total);
   return carry;
 }
 
@@ -400,121 +406,92 @@ __device__ __forceinline__ void load_tile(const TileCtx& c, uint32_t tile, uint3
   tile_inputs<KQ, E, FIRST>(c, e0, ne, lane, in.need, in.slot, in.ia, in.w);
 }
 
-// One tile of E edges of a prefix level (2..k-1), inputs already loaded.
-// `between` runs after the tile has published its record and before it waits
-// on its predecessors (the caller issues the next tile's loads there).
-template <int KQ, int E, bool FIRST, class Between>
-__device__ __forceinline__ void scan_tile(const TileCtx& c, uint32_t tile, const TileIn<KQ, E>& in,
-                                          uint32_t lane, const uint32_t (&mk)[6], uint64_t* tab, Between between) {
+// One prefix level (2..k-1) over the run of tiles of wave w of W: the tiles
+// are cut into W contiguous runs of ceil(n_tiles / W), and a wave scans its
+// run in order, so the running XOR of the level values flows from tile to
+// tile in registers and every read slot is stored as soon as its value is
+// known. Only the segment part at the start of a run (before the run's first
+// segment start) lacks the carry of the segment's part in the preceding runs:
+// its slots are stored without it, and once the run is done the wave
+// publishes its own record (the trailing segment part's XOR, inclusive if a
+// segment starts in the run), collects the carry by one look-back and XORs it
+// into those slots. A segment's leading slot (just before its first edge's
+// slot) holds 0; writing it here lets P buffers be reused across graphs
+// without clearing. Only slots that some window of the next level reads are
+// stored; empty windows gather the zero row.
+template <int KQ, int E, bool FIRST>
+__device__ __forceinline__ void scan_run(const TileCtx& c, uint32_t w, uint32_t W, uint32_t lane,
+                                         const uint32_t (&mk)[6], uint64_t* tab) {
+  const uint32_t R = (c.n_tiles + W - 1) / W;
+  const uint32_t t0 = w * R;
+  if (t0 >= c.n_tiles) return;
+  const uint32_t t1 = min(t0 + R, c.n_tiles);
   cu32* e_out = as_const(c.e_out);
   const uint32_t m = c.m;
-  const uint32_t e0 = tile * (uint32_t)E;
-  const uint32_t ne = min((uint32_t)E, m - e0);
-  const bool cont = e0 > 0 && e_out[e0] == e_out[e0 - 1] + 1u;
-
-  // Two store orders. Late: the running values stay in registers and every
-  // read slot is stored after the look-back, the open part (slots before the
-  // tile's first segment start) with the carry from the preceding tiles.
-  // Early: each read slot is stored as soon as its value is known, the open
-  // part without the carry, which is XORed into those slots once the
-  // look-back has it. Early frees E registers per lane, which lifts the
-  // 16-edge prefix levels from three to four waves per SIMD; elsewhere the
-  // occupancy does not change and late is faster, because a look-back wait
-  // also waits for stores issued before it.
-  constexpr bool kEarly = !FIRST && E >= 16;
-  uint64_t pref[kEarly ? 1 : E];
+  const uint32_t e_begin = t0 * (uint32_t)E;
+  const bool cont = e_begin > 0 && e_out[e_begin] == e_out[e_begin - 1] + 1u;
+  bool started = !cont;        // a segment starts in the run (its own first edge included)
+  uint32_t open_end = e_begin; // edges [e_begin, open_end) precede the run's first segment start
   uint64_t acc = 0;
-  uint32_t first_len = 0;
-  bool started = !cont;
-  uint32_t last_slot = 0;
-  uint32_t seg_starts = 0;  // bit i: a segment starts at edge i of the tile
-  // an edge needs a product when it reaches a read slot (need bit 2) and, at
-  // levels >= 3, its window is non-empty (an empty window contributes zero)
-  auto needs = [&](int i) {
-    return (uint32_t)i < ne && (FIRST ? ((in.need.v[i / 4] >> (8 * (i % 4) + 2)) & 1u) != 0 : in.ia[i] != 0);
-  };
-  // Only slots that some non-empty window reads are stored (the others are
-  // never read: empty windows gather the zero row). A segment's leading slot
-  // (just before its first edge's slot) holds 0; writing it here lets P
-  // buffers be reused across graphs without clearing.
-  auto flag = [&](int i) { return (in.need.v[i / 4] >> (8 * (i % 4))) & 3u; };
+  uint32_t last_slot = cont ? e_out[e_begin] - 1u : 0u;
   auto slot_ptr = [&](uint32_t slot) { return c.pc + (uint64_t)slot * kLanes + lane; };
-#pragma unroll
-  for (int i = 0; i < E; ++i) {
-    if (!kEarly) pref[i] = 0;
-    if ((uint32_t)i < ne) {
-      if (i == 0 ? !cont : in.slot[i] != last_slot + 1u) {
-        acc = 0;
-        started = true;
-        seg_starts |= 1u << i;
-        if (kEarly && (flag(i) & 2u)) p_store(slot_ptr(in.slot[i] - 1u), 0);
-      }
-      if (!started) first_len = (uint32_t)i + 1u;
-      if (needs(i)) {
-        const uint64_t aL = subset_xor<KQ, E>(in.qr, i, c.cb, mk);
-        const uint64_t wv = FIRST ? subset_xor<KQ, E>(in.zr, i, c.cb, mk) : in.w[i];
-        acc ^= gf_mul(tab, aL, wv);
-      }
-      if (kEarly) {
-        if (flag(i) & 1u) p_store(slot_ptr(in.slot[i]), acc);
-      } else {
-        pref[i] = acc;
-      }
-      last_slot = in.slot[i];
-    }
-  }
 
-  const uint32_t e_end = e0 + ne;
-  const bool next_cont = e_end < m && e_out[e_end] == last_slot + 1u;
-  const uint64_t fi = c.row0 + tile;
-  if (next_cont)
-    publish(started ? c.incl : c.agg, fi, lane, acc, rec_tag(c.epoch, started ? kFlagIncl : kFlagAgg));
-  between();
-  uint64_t carry = 0;
-  if (cont) {
-    carry = look_back<KQ, E, FIRST>(c, tile, lane, mk, tab);
-    if (next_cont && !started) publish(c.incl, fi, lane, carry ^ acc, rec_tag(c.epoch, kFlagIncl));
-  }
-  if (kEarly) {
-    // the open part's stored slots get the carry (same lane and address as
-    // the store above, so the XOR lands on the stored value)
-    if (carry) {
-#pragma unroll
-      for (int i = 0; i < E; ++i)
-        if ((uint32_t)i < first_len && (flag(i) & 1u))
-          atomicXor((unsigned long long*)slot_ptr(in.slot[i]), (unsigned long long)carry);
-    }
-  } else {
+  TileIn<KQ, E> cur;
+  load_tile<KQ, E, FIRST>(c, t0, lane, cur);
+  for (uint32_t tile = t0;;) {
+    const uint32_t e0 = tile * (uint32_t)E;
+    const uint32_t ne = min((uint32_t)E, m - e0);
+    const TileIn<KQ, E>& in = cur;
+    // an edge needs a product when it reaches a read slot (need bit 2) and, at
+    // levels >= 3, its window is non-empty (an empty window contributes zero)
+    auto needs = [&](int i) {
+      return (uint32_t)i < ne && (FIRST ? ((in.need.v[i / 4] >> (8 * (i % 4) + 2)) & 1u) != 0 : in.ia[i] != 0);
+    };
+    auto flag = [&](int i) { return (in.need.v[i / 4] >> (8 * (i % 4))) & 3u; };
 #pragma unroll
     for (int i = 0; i < E; ++i) {
       if ((uint32_t)i < ne) {
-        if (flag(i) & 1u) p_store(slot_ptr(in.slot[i]), pref[i] ^ ((uint32_t)i < first_len ? carry : 0));
-        if (((seg_starts >> i) & 1u) && (flag(i) & 2u)) p_store(slot_ptr(in.slot[i] - 1u), 0);
+        if (in.slot[i] != last_slot + 1u || (tile == t0 && i == 0 && !cont)) {
+          acc = 0;
+          if (!started) {
+            started = true;
+            open_end = e0 + (uint32_t)i;
+          }
+          if (flag(i) & 2u) p_store(slot_ptr(in.slot[i] - 1u), 0);
+        }
+        if (needs(i)) {
+          const uint64_t aL = subset_xor<KQ, E>(in.qr, i, c.cb, mk);
+          const uint64_t wv = FIRST ? subset_xor<KQ, E>(in.zr, i, c.cb, mk) : in.w[i];
+          acc ^= gf_mul(tab, aL, wv);
+        }
+        if (flag(i) & 1u) p_store(slot_ptr(in.slot[i]), acc);
+        last_slot = in.slot[i];
       }
     }
+    if (tile + 1 >= t1) break;
+    load_tile<KQ, E, FIRST>(c, tile + 1, lane, cur);
+    ++tile;
   }
-}
+  if (!started) open_end = min(t1 * (uint32_t)E, m);
 
-// Tiles first, first + stride, ... below n_tiles. The next tile's inputs are
-// requested once this tile's products are done, so their latency overlaps
-// this tile's look-back and stores. (Requesting them before the products
-// was measured slower: both tiles' window sums live at once cost occupancy.)
-template <int KQ, int E, bool FIRST>
-__device__ __forceinline__ void scan_tiles(const TileCtx& c, uint32_t first, uint32_t stride, uint32_t lane,
-                                           const uint32_t (&mk)[6], uint64_t* tab) {
-  if (first >= c.n_tiles) return;
-  TileIn<KQ, E> cur;
-  load_tile<KQ, E, FIRST>(c, first, lane, cur);
-  for (uint32_t tile = first;;) {
-    const uint32_t nt = tile + stride;
-    const bool more = nt < c.n_tiles;
-    TileIn<KQ, E> nxt;
-    scan_tile<KQ, E, FIRST>(c, tile, cur, lane, mk, tab, [&]() {
-      if (more) load_tile<KQ, E, FIRST>(c, nt, lane, nxt);
-    });
-    if (!more) break;
-    cur = nxt;
-    tile = nt;
+  const uint32_t e_end = min(t1 * (uint32_t)E, m);
+  const bool next_cont = e_end < m && e_out[e_end] == last_slot + 1u;
+  const uint64_t fi = c.row0 + (t1 - 1);
+  if (next_cont)
+    publish(started ? c.incl : c.agg, fi, lane, acc, rec_tag(c.epoch, started ? kFlagIncl : kFlagAgg));
+  if (!cont) return;
+  const uint64_t carry = look_back<KQ, E, FIRST>(c, t0, R, lane, mk, tab);
+  if (next_cont && !started) publish(c.incl, fi, lane, carry ^ acc, rec_tag(c.epoch, kFlagIncl));
+  if (!carry) return;
+  // the run's leading segment part: its stored slots get the carry (same lane
+  // and address as the stores above, so the XOR lands on the stored value)
+  for (uint32_t e0 = e_begin; e0 < open_end; e0 += E) {
+    const IdxN<E> so = load_idx<E>(c.e_out + e0);
+    const IdxN<E / 4> nd = load_idx<E / 4>((const uint32_t*)(c.need + e0));
+#pragma unroll
+    for (int i = 0; i < E; ++i)
+      if (e0 + (uint32_t)i < open_end && ((nd.v[i / 4] >> (8 * (i % 4))) & 1u))
+        atomicXor((unsigned long long*)slot_ptr(so.v[i]), (unsigned long long)carry);
   }
 }
 
