@@ -267,7 +267,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
   c.incl = incl;
   c.need = U.need;
   c.lb_stats = nullptr;
-  scan_run<KQ, E, FIRST>(c, idx, U.waves, lane, mk, tab);
+  scan_level<KQ, E, FIRST>(c, idx, U.waves, lane, mk, tab);
 }
 
 // Last level: flat index = (unit, edge range of top_edges edges). A wave keeps
@@ -792,6 +792,14 @@ static uint64_t default_slot_budget() {
   return (uint64_t)(free_b / 3);
 }
 
+// At most this many bytes of prefix state and records per round. The level
+// launches gather prefix rows at random over the whole round, and rounds
+// larger than a plain launch's four chunks of a 10^6-edge graph ran slower
+// per chunk (64 mixed queries on that graph: 1.71 s with 4 chunks per round,
+// 1.88 s with 8, 2.14 s unbounded); small graphs still pack hundreds of
+// chunks into a round.
+constexpr uint64_t kRoundStateBytes = 5ull << 30;
+
 rs_status run_batch_impl(const rs_graph* const* graphs, const rs_query* queries, uint32_t nq, rs_result* results,
                          const rs_tuning* tune, hipStream_t st, bool use_graph, uint64_t slot_budget,
                          BatchWorkspace* ws) {
@@ -814,7 +822,9 @@ rs_status run_batch_impl(const rs_graph* const* graphs, const rs_query* queries,
   if (tu.waves_per_block != 1 && tu.waves_per_block != 2 && tu.waves_per_block != 4) tu.waves_per_block = 2;
   tu.top_edges_per_tile = std::min(std::max(tu.top_edges_per_tile, 1u), 4096u);
   BatchPlan P;
-  RS_TRY(batch_plan(graphs, queries, nq, tu, slot_budget ? slot_budget : default_slot_budget(), results, P));
+  RS_TRY(batch_plan(graphs, queries, nq, tu,
+                    std::min<uint64_t>(slot_budget ? slot_budget : default_slot_budget(), kRoundStateBytes), results,
+                    P));
   rs_status first_err = RS_OK;
   for (uint32_t i = 0; i < nq; ++i)
     if (results[i].status != RS_OK && first_err == RS_OK) first_err = results[i].status;

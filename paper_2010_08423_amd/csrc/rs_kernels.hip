@@ -12,8 +12,9 @@ namespace rs {
 
 // ---------------------------------------------------------------------------
 // Prefix levels 2..k-1. The grid holds about as many waves as fit on the GPU;
-// wave w of W scans the w-th of W contiguous runs of tiles (see scan_run), so
-// carries flow in registers along a run and the waves meet once, at the run
+// at levels >= 3 wave w of W scans the w-th of W contiguous runs of tiles
+// (scan_run), at level 2 a few runs spread over the edge list (scan_runs), so
+// carries flow in registers along a run and the waves meet only at the run
 // ends, through the look-back records. A run whose predecessor has not
 // published after a bounded wait recomputes that run's tail (see look_back).
 // ---------------------------------------------------------------------------
@@ -54,7 +55,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
   c.need = need;
   c.lb_stats = lb_stats;
   const uint32_t waves = gridDim.x * (blockDim.x >> 6);
-  scan_run<KQ, E, FIRST>(c, blockIdx.x * (blockDim.x >> 6) + wv, waves, lane, mk, tab);
+  scan_level<KQ, E, FIRST>(c, blockIdx.x * (blockDim.x >> 6) + wv, waves, lane, mk, tab);
 }
 
 // ---------------------------------------------------------------------------

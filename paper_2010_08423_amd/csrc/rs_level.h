@@ -495,6 +495,150 @@ __device__ __forceinline__ void scan_run(const TileCtx& c, uint32_t w, uint32_t 
   }
 }
 
+// Runs per wave at level 2. Which edges need a level-2 product varies
+// strongly along the edge list (hub destinations need most of theirs), so
+// with one contiguous run per wave the slowest wave took 2.4x the mean time
+// on the 10^6-edge Chung-Lu graph; a wave takes kRunsPerWave runs spread
+// evenly over the list instead. At levels >= 3 the spread is smaller and
+// interleaved runs measured slower than one run per wave.
+constexpr uint32_t kRunsPerWave = 4;
+
+// Level 2 (and any prefix level), the share of wave w of W. The tiles (E
+// consecutive edges each) are cut into kRunsPerWave * W contiguous runs of
+// equal length, and wave w scans runs w, w + W, w + 2W, ... in order. Along a
+// run the running XOR of the level values flows from tile to tile in
+// registers and every read slot is stored as soon as its value is known; a
+// segment's leading slot (just before its first edge's slot) is stored as 0,
+// which lets P buffers be reused across graphs without clearing. Only slots
+// that some window of the next level reads are stored (empty windows gather
+// the zero row).
+//
+// The part of a run before its first segment start lacks the carry of that
+// segment's part in the preceding runs: its slots are stored without it. Each
+// run publishes its record (the XOR of its trailing segment part, inclusive
+// if a segment starts in the run) as soon as it is done, so the work phase
+// never waits. Once all of its runs are done, the wave collects each run's
+// carry by a look-back, publishes the inclusive record of a run without a
+// segment start, and XORs the carry into the stored slots of the run's
+// leading part.
+template <int KQ, int E, bool FIRST>
+__device__ __forceinline__ void scan_runs(const TileCtx& c, uint32_t w, uint32_t W, uint32_t lane,
+                                          const uint32_t (&mk)[6], uint64_t* tab) {
+  const uint32_t n_runs = kRunsPerWave * W;
+  const uint32_t R = (c.n_tiles + n_runs - 1) / n_runs;  // tiles per run
+  auto run_first = [&](uint32_t k) { return (w + k * W) * R; };
+  auto has_run = [&](uint32_t k) { return k < kRunsPerWave && run_first(k) < c.n_tiles; };
+  if (!has_run(0)) return;
+  cu32* e_out = as_const(c.e_out);
+  const uint32_t m = c.m;
+  auto slot_ptr = [&](uint32_t slot) { return c.pc + (uint64_t)slot * kLanes + lane; };
+  auto continues = [&](uint32_t e) { return e > 0 && e < m && e_out[e] == e_out[e - 1] + 1u; };
+  const uint32_t t_agg = rec_tag(c.epoch, kFlagAgg), t_inc = rec_tag(c.epoch, kFlagIncl);
+
+  uint32_t started_mask = 0;  // bit k: a segment starts in run k
+  uint32_t k = 0;
+  TileIn<KQ, E> cur;
+  load_tile<KQ, E, FIRST>(c, run_first(0), lane, cur);
+#pragma unroll 1
+  for (;;) {
+    const uint32_t t0 = run_first(k), t1 = min(t0 + R, c.n_tiles);
+    const uint32_t e_begin = t0 * (uint32_t)E;
+    const bool cont = continues(e_begin);
+    bool started = !cont;  // a segment starts in the run (its own first edge included)
+    uint64_t acc = 0;
+    uint32_t last_slot = cont ? e_out[e_begin] - 1u : 0u;
+#pragma unroll 1
+    for (uint32_t tile = t0;;) {
+      const uint32_t e0 = tile * (uint32_t)E;
+      const uint32_t ne = min((uint32_t)E, m - e0);
+      const TileIn<KQ, E>& in = cur;
+      // an edge needs a product when it reaches a read slot (need bit 2) and,
+      // at levels >= 3, its window is non-empty (an empty window contributes zero)
+      auto needs = [&](int i) {
+        return (uint32_t)i < ne && (FIRST ? ((in.need.v[i / 4] >> (8 * (i % 4) + 2)) & 1u) != 0 : in.ia[i] != 0);
+      };
+      auto flag = [&](int i) { return (in.need.v[i / 4] >> (8 * (i % 4))) & 3u; };
+#pragma unroll
+      for (int i = 0; i < E; ++i) {
+        if ((uint32_t)i < ne) {
+          if (in.slot[i] != last_slot + 1u || (tile == t0 && i == 0 && !cont)) {
+            acc = 0;
+            started = true;
+            if (flag(i) & 2u) p_store(slot_ptr(in.slot[i] - 1u), 0);
+          }
+          if (needs(i)) {
+            const uint64_t aL = subset_xor<KQ, E>(in.qr, i, c.cb, mk);
+            const uint64_t wv = FIRST ? subset_xor<KQ, E>(in.zr, i, c.cb, mk) : in.w[i];
+            acc ^= gf_mul(tab, aL, wv);
+          }
+          if (flag(i) & 1u) p_store(slot_ptr(in.slot[i]), acc);
+          last_slot = in.slot[i];
+        }
+      }
+      // the next tile: of this run, else the first of the wave's next run
+      const bool more_here = tile + 1 < t1;
+      const bool more = more_here || has_run(k + 1);
+      if (more) load_tile<KQ, E, FIRST>(c, more_here ? tile + 1 : run_first(k + 1), lane, cur);
+      if (!more_here) break;
+      ++tile;
+    }
+    const uint32_t e_end = min(t1 * (uint32_t)E, m);
+    if (e_end < m && e_out[e_end] == last_slot + 1u)
+      publish(started ? c.incl : c.agg, c.row0 + (t1 - 1), lane, acc, started ? t_inc : t_agg);
+    if (started) started_mask |= 1u << k;
+    if (!has_run(k + 1)) break;
+    ++k;
+  }
+
+  // carries of the runs that begin inside a segment
+#pragma unroll 1
+  for (uint32_t r = 0; r <= k; ++r) {
+    const uint32_t t0 = run_first(r), t1 = min(t0 + R, c.n_tiles);
+    const uint32_t e_begin = t0 * (uint32_t)E, e_end = min(t1 * (uint32_t)E, m);
+    if (!continues(e_begin)) continue;
+    const uint64_t carry = look_back<KQ, E, FIRST>(c, t0, R, lane, mk, tab);
+    if (!((started_mask >> r) & 1u) && continues(e_end)) {
+      // no segment starts in the run: its inclusive prefix is the carry and
+      // its own aggregate, published above
+      uint64_t own = 0;
+      (void)read_rec(c.agg, c.row0 + (t1 - 1), lane, t_agg, &own);
+      publish(c.incl, c.row0 + (t1 - 1), lane, carry ^ own, t_inc);
+    }
+    // the run's leading segment part: its stored slots get the carry (same
+    // lane and address as the stores above, so the XOR lands on the stored value)
+    uint32_t prev = e_out[e_begin] - 1u;
+    bool open = true;
+#pragma unroll 1
+    for (uint32_t e0 = e_begin; open && e0 < e_end; e0 += E) {
+      const IdxN<E> so = load_idx<E>(c.e_out + e0);
+      const IdxN<E / 4> nd = load_idx<E / 4>((const uint32_t*)(c.need + e0));
+#pragma unroll
+      for (int i = 0; i < E; ++i) {
+        if (open && e0 + (uint32_t)i < e_end) {
+          if (so.v[i] != prev + 1u) {
+            open = false;
+          } else {
+            if (((nd.v[i / 4] >> (8 * (i % 4))) & 1u) && carry)
+              atomicXor((unsigned long long*)slot_ptr(so.v[i]), (unsigned long long)carry);
+            prev = so.v[i];
+          }
+        }
+      }
+    }
+  }
+}
+
+// The schedule of a prefix level: interleaved runs at level 2, one
+// contiguous run per wave above it.
+template <int KQ, int E, bool FIRST>
+__device__ __forceinline__ void scan_level(const TileCtx& c, uint32_t w, uint32_t W, uint32_t lane,
+                                           const uint32_t (&mk)[6], uint64_t* tab) {
+  if constexpr (FIRST)
+    scan_runs<KQ, E, FIRST>(c, w, W, lane, mk, tab);
+  else
+    scan_run<KQ, E, FIRST>(c, w, W, lane, mk, tab);
+}
+
 // Last level k over edges [e0, e1): unreduced per-lane sum of c_k(e) into r.
 // Edges go in batches of 8: one scalar load per index array and batch, and
 // the next batch's gathers and rows in flight during this batch's products;
