@@ -124,7 +124,7 @@ def main():
     ap.add_argument("--rate", type=float, default=200.0)
     ap.add_argument("--window", type=float, default=5.0)
     ap.add_argument("--cap", type=float, default=40.0)
-    ap.add_argument("--budget-gb", type=float, default=96.0)
+    ap.add_argument("--budget-gb", type=float, default=200.0)
     ap.add_argument("--group-updates", type=float, default=0, help="group work cap (0: the library default)")
     ap.add_argument("--streams", type=int, default=0)
     ap.add_argument("--sizes", default="10000,100000,1000000,10000000", help="edge counts of the served graphs")
