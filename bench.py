@@ -45,6 +45,21 @@ KERNEL_SOURCES = ("rs_device.h", "rs_level.h", "rs_kernels.hip", "rs_engine.hip"
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "k_scan_chunglu_m1e6_k8_counters.md")
 SQ_FILE = os.path.join(ROOT, "profiles", "k_scan_chunglu_m1e6_k8_sq.md")
 
+# Plain-mode workloads: input generator, description, and the committed
+# rocprofv3 summaries (HBM traffic, SQ issue rates) of their level kernel.
+WORKLOADS = {
+    "path-scale": ("config_path_scale",
+                   "k-RestlessPath plain sieve, Chung-Lu(2.5) n=100000 m=1000000 t in [1,1000], delta=10, k=8 "
+                   "(256 iterations), seed 2", COUNTERS_FILE, SQ_FILE),
+    "motif-scale": ("config_motif_scale",
+                    "k-RestlessMotif plain sieve, Chung-Lu(2.2) n=1000000 m=10000000, t in [1,10000] in 100 "
+                    "Gaussian bursts (sigma 20), 8 colours, delta=20, motif of k=10 colours (1024 iterations), seed 3",
+                    os.path.join(ROOT, "profiles", "k_scan_chunglu_m1e7_motif_k10_counters.md"), None),
+    "small": ("config_small",
+              "k-RestlessPath plain sieve, uniform n=1000 m=10000 t in [1,100], delta=5, k=5 (32 iterations), seed 1",
+              None, None),
+}
+
 
 def kernel_source_hash():
     import hashlib
@@ -71,9 +86,11 @@ def committed_figures(path):
         return {}
 
 
-def committed_traffic():
-    """HBM bytes per level_scan launch from the committed counter summary."""
-    v = committed_figures(COUNTERS_FILE).get("traffic-bytes-per-launch")
+def committed_traffic(path=COUNTERS_FILE):
+    """HBM bytes per level_scan launch from a committed counter summary."""
+    if path is None:
+        return None
+    v = committed_figures(path).get("traffic-bytes-per-launch")
     return float(v) if v is not None else None
 
 
@@ -98,14 +115,15 @@ def cpu_baseline(g, q, m_dedup, budget_s=20.0):
     import oracle
 
     cores = min(host_cores(), 64)
+    kw = dict(colour=g.colour, n_colours=g.n_colours, motif=q.motif) if q.motif is not None else {}
     t0 = time.perf_counter()
-    oracle.sieve(g.n, g.src, g.dst, g.t, q.k, q.delta, q.seed, it_begin=1, it_end=2, threads=1)
+    oracle.sieve(g.n, g.src, g.dst, g.t, q.k, q.delta, q.seed, it_begin=1, it_end=2, threads=1, **kw)
     one = max(time.perf_counter() - t0, 1e-3)
     n_it = int(max(1, min((1 << q.k) - 1, budget_s * cores / one)))
     n_it = max(cores, (n_it // cores) * cores) if n_it >= cores else n_it
     n_it = min(n_it, (1 << q.k) - 1)
     t0 = time.perf_counter()
-    oracle.sieve(g.n, g.src, g.dst, g.t, q.k, q.delta, q.seed, it_begin=1, it_end=1 + n_it, threads=cores)
+    oracle.sieve(g.n, g.src, g.dst, g.t, q.k, q.delta, q.seed, it_begin=1, it_end=1 + n_it, threads=cores, **kw)
     dt = time.perf_counter() - t0
     upd = n_it * (q.k - 1) * m_dedup
     return {"value": upd / dt, "unit": "edge-updates/s", "cores": cores, "kind": "oracle",
@@ -120,6 +138,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--mode", default="plain", choices=["plain", "batch", "serve", "copy"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", default="path-scale", choices=sorted(WORKLOADS),
+                    help="plain mode: the query timed (default: the 10^6-edge path query)")
     # serve mode: offered load, arrival window, wall-clock cap, server budget
     ap.add_argument("--rate", type=float, default=200.0)
     ap.add_argument("--window", type=float, default=5.0)
@@ -161,8 +181,9 @@ def main():
         print(json.dumps(out), flush=True)
         return
 
+    gen, desc, counters_file, sq_file = WORKLOADS[args.workload]
     log("generating graph")
-    g, q = inputs.config_path_scale()
+    g, q = getattr(inputs, gen)()
     gd = R.Graph.from_inputs(g)
     info = gd.info()
     m = info["m"]
@@ -171,7 +192,7 @@ def main():
     # window counts (used for the byte accounting) happens before the timed region.
     R.profile_enable(True)
     for _ in range(max(args.warmup, 1)):
-        r = R.run(gd, q.k, q.delta, q.seed)
+        r = R.run(gd, q.k, q.delta, q.seed, motif=q.motif)
     F = r.fingerprint
 
     # Timed region: K full queries, kernel timing live on the launch stream.
@@ -179,7 +200,7 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        r = R.run(gd, q.k, q.delta, q.seed)
+        r = R.run(gd, q.k, q.delta, q.seed, motif=q.motif)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     R.profile_enable(False)
@@ -202,7 +223,7 @@ def main():
     # i.e. the bytes a dense evaluation of the levels would move; its rate
     # exceeds the HBM peak because the skipped updates are never done.
     kq = (q.k + 3) // 4 * 4
-    chunks_per_launch = min(4, (1 << q.k) // 64)
+    chunks_per_launch = max(1, min(4, (1 << q.k) // 64))
     dense_bytes = (1536.0 * chunks_per_launch + 12 + 8 * kq) * m
     dense = dense_bytes / (avg_scan_ms * 1e-3) / 1e9
     classes = {}
@@ -222,20 +243,19 @@ def main():
         "vs_baseline": None,
         "dtype": "u64",
         "data": "synthetic",
-        "config": {"workload": "k-RestlessPath plain sieve, Chung-Lu(2.5) n=100000 m=1000000 t in [1,1000], "
-                               "delta=10, k=8 (256 iterations), seed 2",
+        "config": {"workload": desc,
                    "n": info["n"], "m": m, "k": q.k, "delta": q.delta, "seed": q.seed,
                    "edge_updates_per_query": upd, "fingerprint": f"{r.fingerprint:#018x}"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": committed_traffic(),
-                     "kernel": "k_scan<kq=8,E=16>, prefix levels 3..k-1, 4 chunks per launch",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": committed_traffic(counters_file),
+                     "kernel": f"k_scan<kq={kq},E=16>, prefix levels 3..k-1, {chunks_per_launch} chunks per launch",
                      "avg_launch_ms": avg_scan_ms, "launches": n_scan,
                      "algorithmic_bytes_per_launch": alg_bytes,
                      # the dense evaluation's bytes at the same per-unit figure, and their rate
                      "dense_equivalent_bytes_per_launch": dense_bytes, "dense_equivalent_GBps": dense,
                      # issue rates of the same kernel from the committed SQ counter summary
-                     "valu_frac": _float(committed_figures(SQ_FILE).get("valu-frac")),
-                     "salu_frac": _float(committed_figures(SQ_FILE).get("salu-frac"))},
+                     "valu_frac": _float(committed_figures(sq_file).get("valu-frac")) if sq_file else None,
+                     "salu_frac": _float(committed_figures(sq_file).get("salu-frac")) if sq_file else None},
         "kernels": classes,
     }
     if rank == 0 and not args.no_cpu_baseline:
