@@ -267,6 +267,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
   c.incl = incl;
   c.need = U.need;
   c.lb_stats = nullptr;
+  c.bounds = nullptr;
   scan_level<KQ, E, FIRST>(c, idx, U.waves, lane, mk, tab);
 }
 
@@ -700,19 +701,7 @@ static rs_status resolve_plan(BatchPlan& P, BatchWorkspace& W, uint32_t epoch0) 
 }
 
 static uint32_t resident_blocks_of(const void* kern, uint32_t threads, size_t lds) {
-  static std::mutex mu;
-  static std::map<std::pair<const void*, uint32_t>, uint32_t> cache;
-  std::lock_guard<std::mutex> lk(mu);
-  auto it = cache.find({kern, threads});
-  if (it != cache.end()) return it->second;
-  int dev = 0, cus = 0, per_cu = 0;
-  (void)hipGetDevice(&dev);
-  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, (int)threads, lds) != hipSuccess || per_cu < 1)
-    per_cu = 1;
-  const uint32_t v = (uint32_t)std::max(cus, 1) * (uint32_t)per_cu;
-  cache[{kern, threads}] = v;
-  return v;
+  return resident_blocks(kern, threads, lds);
 }
 
 template <int KQ, int E>

@@ -302,6 +302,7 @@ rs_status run_plain(rs_graph* g, PlainWorkspace& ws, const QueryPlan& qp, const 
       ProfScope ps(KC_ZTABLE, st, 8.0 * n * kq);
       RS_HIP(launch_ztable(ws.z.as<uint64_t>(), (uint32_t)n, qp, G.colour.as<uint8_t>(), st));
     }
+    uint32_t run_w2 = 0, run_w3 = 0, run_stride = 0;
     {
       ProfScope ps(KC_WINDOW, st, 16.0 * m);
       RS_HIP(launch_window(G.e_src.as<uint32_t>(), G.e_t.as<uint32_t>(), G.in_off.as<uint32_t>(),
@@ -315,9 +316,26 @@ rs_status run_plain(rs_graph* g, PlainWorkspace& ws, const QueryPlan& qp, const 
                            G.hi.as<uint32_t>(), ws.lo.as<uint32_t>(), (uint32_t)m, (uint32_t)n,
                            l + 1 < k ? need_of(l + 1) : nullptr, ws.ref.as<uint8_t>(), ws.lastref.as<uint32_t>(),
                            need_of(l), st));
+      // work-balanced runs of the prefix levels, cut for the grid width of
+      // the first chunk group (later groups launch the same width)
+      if (k >= 3) {
+        const uint32_t gc0 = (uint32_t)cpl;
+        run_w2 = scan_waves(kq, E, true, (uint32_t)tiles, gc0, tu.waves_per_block);
+        run_w3 = scan_waves(kq, E, false, (uint32_t)tiles, gc0, tu.waves_per_block);
+        run_stride = std::max(run_w2, run_w3) + 1;
+        const uint64_t levels = k - 2, nb = (tiles + 1023) / 1024;
+        if (ws.run_pre.reserve(4 * tiles * levels, st, false) || ws.run_bsum.reserve(4 * nb * levels, st, false) ||
+            ws.run_boff.reserve(4 * nb * levels, st, false) ||
+            ws.run_bounds.reserve(4ull * run_stride * levels, st, false))
+          return RS_ENOMEM;
+        RS_HIP(launch_run_bounds(G.hi.as<uint32_t>(), ws.lo.as<uint32_t>(), need_of(2), need_stride(m), (uint32_t)m, E,
+                                 (uint32_t)levels, run_w2, run_w3, ws.run_pre.as<uint32_t>(),
+                                 ws.run_bsum.as<uint32_t>(), ws.run_boff.as<uint32_t>(),
+                                 ws.run_bounds.as<uint32_t>(), run_stride, st));
+      }
     }
     if (tr) {
-      const rs_status ts = trace("setup (z table, windows, flags)", 0, 0, 0, false);
+      const rs_status ts = trace("setup (z table, windows, flags, runs)", 0, 0, 0, false);
       if (ts != RS_OK) return ts;
     }
     // Counts for the byte accounting of timed launches: measured once per
@@ -397,6 +415,8 @@ rs_status run_plain(rs_graph* g, PlainWorkspace& ws, const QueryPlan& qp, const 
           a.agg = ws.agg.as<uint64_t>();
           a.incl = ws.incl.as<uint64_t>();
           a.need = need_of(l);
+          a.bounds = ws.run_bounds.as<uint32_t>() + (uint64_t)(l - 2) * run_stride;
+          a.waves = first ? run_w2 : run_w3;
           if (tr) {
             RS_HIP(launch_fill64(ws.lb_stats.as<uint64_t>(), 0, 2, st));
             a.lb_stats = ws.lb_stats.as<unsigned long long>();

@@ -99,7 +99,24 @@ struct ScanArgs {
   uint64_t* incl;          // [chunks][n_tiles][64][2]
   const uint8_t* need;     // [m] store flags
   unsigned long long* lb_stats = nullptr;  // null, or [2] look-back counters (see TileCtx)
+  const uint32_t* bounds = nullptr;        // null, or [waves+1] work-balanced first tile of each run
+  uint32_t waves = 0;                      // waves per chunk the bounds were cut for
 };
+// Blocks of a kernel with this block size and dynamic LDS that fit on the
+// whole GPU at once (cached).
+uint32_t resident_blocks(const void* kern, uint32_t threads, size_t lds);
+// Waves per chunk of a prefix-level launch of this shape (grid width times
+// waves per block).
+uint32_t scan_waves(uint32_t kq, uint32_t E, bool first, uint32_t n_tiles, uint32_t chunks, uint32_t wpb);
+// Work-balanced run bounds of the prefix levels 2 .. 2 + levels - 1 of a
+// query: per level (need flags at need + y * need_stride_b) the per-tile
+// costs, their prefix (scratch pre[levels][n_tiles], bsum and boff
+// [levels][ceil(n_tiles / 1024)]) and bounds[levels][b_stride] for w_first
+// waves per chunk at level 2 and w_rest above it (b_stride > both).
+hipError_t launch_run_bounds(const uint32_t* hi, const uint32_t* lo, const uint8_t* need, uint64_t need_stride_b,
+                             uint32_t m, uint32_t E, uint32_t levels, uint32_t w_first, uint32_t w_rest,
+                             uint32_t* pre, uint32_t* bsum, uint32_t* boff, uint32_t* bounds, uint32_t b_stride,
+                             hipStream_t st);
 
 // Arguments of the last level k.
 struct TopArgs {
@@ -222,18 +239,20 @@ namespace rs {
 struct PlainWorkspace {
   DevBuf lo, z, q, p0, p1, partial, agg, incl, fsum, out, ref, need, lastref;
   DevBuf lb_stats;  // look-back counters, allocated only while launches are traced
+  DevBuf run_pre, run_bsum, run_boff, run_bounds;  // work-balanced runs of the prefix levels
   uint32_t epoch = 0;
   uint64_t p_elems_per_chunk = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   uint64_t bytes() const {
     uint64_t t = 0;
     for (const DevBuf* b : {&lo, &z, &q, &p0, &p1, &partial, &agg, &incl, &fsum, &out, &ref, &need, &lastref,
-                            &lb_stats})
+                            &lb_stats, &run_pre, &run_bsum, &run_boff, &run_bounds})
       t += b->bytes;
     return t;
   }
   void release() {
-    for (DevBuf* b : {&lo, &z, &q, &p0, &p1, &partial, &agg, &incl, &fsum, &out, &ref, &need, &lastref, &lb_stats})
+    for (DevBuf* b : {&lo, &z, &q, &p0, &p1, &partial, &agg, &incl, &fsum, &out, &ref, &need, &lastref, &lb_stats,
+                      &run_pre, &run_bsum, &run_boff, &run_bounds})
       b->release();
     if (ev0) (void)hipEventDestroy(ev0);
     if (ev1) (void)hipEventDestroy(ev1);

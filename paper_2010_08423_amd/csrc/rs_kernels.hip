@@ -5,6 +5,7 @@
 #include <map>
 #include <mutex>
 #include <tuple>
+#include <type_traits>
 
 #include "rs_level.h"
 
@@ -26,7 +27,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
     const uint64_t* __restrict__ p_prev, uint64_t* __restrict__ p_cur, uint64_t p_stride,
     uint64_t chunk_base, uint32_t m, uint32_t n_tiles, uint32_t epoch,
     uint64_t* __restrict__ agg, uint64_t* __restrict__ incl, const uint8_t* __restrict__ need,
-    unsigned long long* __restrict__ lb_stats) {
+    unsigned long long* __restrict__ lb_stats, const uint32_t* __restrict__ bounds) {
   extern __shared__ uint64_t dyn_lds[];  // [waves][16][64]; starts at LDS address 0
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform for the compiler
@@ -54,6 +55,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
   c.incl = incl;
   c.need = need;
   c.lb_stats = lb_stats;
+  c.bounds = bounds;
   const uint32_t waves = gridDim.x * (blockDim.x >> 6);
   scan_level<KQ, E, FIRST>(c, blockIdx.x * (blockDim.x >> 6) + wv, waves, lane, mk, tab);
 }
@@ -271,9 +273,16 @@ __global__ __launch_bounds__(1024) void k_xor_reduce(const uint64_t* __restrict_
 // ---------------------------------------------------------------------------
 static inline uint32_t div_up(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
 
+// LDS a CU gives to resident blocks, as measured on MI355X: with 8 KB of LDS
+// per wave, 18 waves per CU started at once and the 19th and 20th only when
+// others had finished (16 with 32 KB blocks), although the occupancy query
+// counts 20. Grids sized by the query left a tenth of their waves to start
+// late, after the launch had run for about half its time.
+constexpr size_t kUsableLdsPerCu = 144 * 1024;
+
 // Blocks of `kern` that fit on the whole GPU at once (cached per kernel and
 // block shape).
-static uint32_t resident_blocks(const void* kern, uint32_t threads, size_t lds) {
+uint32_t resident_blocks(const void* kern, uint32_t threads, size_t lds) {
   static std::mutex mu;
   static std::map<std::tuple<const void*, uint32_t, size_t>, uint32_t> cache;
   std::lock_guard<std::mutex> lk(mu);
@@ -285,6 +294,7 @@ static uint32_t resident_blocks(const void* kern, uint32_t threads, size_t lds) 
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, (int)threads, lds) != hipSuccess || per_cu < 1)
     per_cu = 1;
+  if (lds > 0) per_cu = std::max(1, std::min(per_cu, (int)(kUsableLdsPerCu / lds)));
   const uint32_t v = (uint32_t)std::max(cus, 1) * (uint32_t)per_cu;
   cache[key] = v;
   return v;
@@ -301,6 +311,128 @@ hipError_t launch_ztable(uint64_t* z, uint32_t n, const QueryPlan& qp, const uin
   if (cnt == 0) return hipSuccess;
   hipLaunchKernelGGL(k_ztable, dim3(div_up(cnt, 256)), dim3(256), 0, st, z, n, qp.k, qp.kq, qp.seed,
                      qp.motif ? 1 : 0, colour_d, sh);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Work-balanced runs of the prefix levels. The cost of a tile is
+// kTileCostBase plus kProductCost per edge that forms a product at that
+// level (need bit 2, and at levels >= 3 a non-empty window); runs are cut at
+// equal shares of the level's total cost. blockIdx.y is the level index
+// (level 2 + y); per level the arrays are pre[n_tiles], bsum[nb], boff[nb],
+// bounds[W+1], at the strides given.
+// ---------------------------------------------------------------------------
+// Per-wave clocks of the equal-length runs fit 4.5-4.8 us per tile plus
+// 0.9-1.2 us per product (correlation 0.91-0.93 with the products of the run),
+// so a tile counts 9 and a product 2.
+constexpr uint32_t kTileCostBase = 9;
+constexpr uint32_t kProductCost = 2;
+constexpr uint32_t kCostBlock = 1024;  // tiles per block of the cost prefix (256 threads x 4)
+
+template <int E>
+__global__ __launch_bounds__(256) void k_tile_cost(const uint32_t* __restrict__ hi, const uint32_t* __restrict__ lo,
+                                                   const uint8_t* __restrict__ need, uint64_t need_stride_b,
+                                                   uint32_t m, uint32_t n_tiles, uint32_t* __restrict__ pre,
+                                                   uint32_t* __restrict__ bsum) {
+  __shared__ uint32_t part[256];
+  const uint32_t lvl = blockIdx.y;
+  const uint8_t* nd = need + (uint64_t)lvl * need_stride_b;
+  const uint32_t t_base = blockIdx.x * kCostBlock + threadIdx.x * 4;
+  uint32_t cost[4];
+  uint32_t sum = 0;
+  for (int j = 0; j < 4; ++j) {
+    const uint32_t t = t_base + j;
+    uint32_t c = 0;
+    if (t < n_tiles) {
+      c = kTileCostBase;
+      const uint32_t e0 = t * (uint32_t)E, e1 = min(e0 + (uint32_t)E, m);
+      for (uint32_t e = e0; e < e1; ++e)
+        c += kProductCost * (((nd[e] >> 2) & 1u) && (lvl == 0 || hi[e] != lo[e]));
+    }
+    sum += c;
+    cost[j] = sum;  // inclusive within the thread's four tiles
+  }
+  part[threadIdx.x] = sum;
+  __syncthreads();
+  for (uint32_t d = 1; d < 256; d <<= 1) {  // inclusive scan of the thread sums
+    const uint32_t v = threadIdx.x >= d ? part[threadIdx.x - d] : 0u;
+    __syncthreads();
+    part[threadIdx.x] += v;
+    __syncthreads();
+  }
+  const uint32_t before = threadIdx.x ? part[threadIdx.x - 1] : 0u;
+  uint32_t* pl = pre + (uint64_t)lvl * n_tiles;
+  for (int j = 0; j < 4; ++j)
+    if (t_base + j < n_tiles) pl[t_base + j] = before + cost[j];
+  if (threadIdx.x == 255) bsum[(uint64_t)lvl * gridDim.x + blockIdx.x] = part[255];
+}
+
+// Exclusive prefix of the block totals of each level (one block per level).
+__global__ __launch_bounds__(1024) void k_cost_block_offsets(const uint32_t* __restrict__ bsum, uint32_t nb,
+                                                             uint32_t* __restrict__ boff) {
+  __shared__ uint32_t part[1024];
+  const uint32_t* bs = bsum + (uint64_t)blockIdx.x * nb;
+  uint32_t* bo = boff + (uint64_t)blockIdx.x * nb;
+  uint32_t carry = 0;
+  for (uint32_t b0 = 0; b0 < nb; b0 += 1024) {
+    const uint32_t b = b0 + threadIdx.x;
+    const uint32_t v = b < nb ? bs[b] : 0u;
+    part[threadIdx.x] = v;
+    __syncthreads();
+    for (uint32_t d = 1; d < 1024; d <<= 1) {
+      const uint32_t u = threadIdx.x >= d ? part[threadIdx.x - d] : 0u;
+      __syncthreads();
+      part[threadIdx.x] += u;
+      __syncthreads();
+    }
+    if (b < nb) bo[b] = carry + part[threadIdx.x] - v;
+    carry += part[1023];
+    __syncthreads();
+  }
+}
+
+// bounds[w] = first tile of run w: the first tile whose exclusive cost prefix
+// reaches ceil(total * w / W). Thread t writes the w whose boundary falls on
+// tile t; runs whose boundary lies past the last tile's start stay at n_tiles
+// (filled beforehand), and so does bounds[W].
+__global__ __launch_bounds__(256) void k_run_bounds(const uint32_t* __restrict__ pre, const uint32_t* __restrict__ boff,
+                                                    uint32_t nb, uint32_t n_tiles, uint32_t w_first,
+                                                    uint32_t w_rest, uint32_t b_stride,
+                                                    uint32_t* __restrict__ bounds) {
+  const uint32_t lvl = blockIdx.y;
+  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_tiles) return;
+  const uint32_t* pl = pre + (uint64_t)lvl * n_tiles;
+  const uint32_t* bo = boff + (uint64_t)lvl * nb;
+  auto incl = [&](uint32_t i) { return (uint64_t)pl[i] + bo[i / kCostBlock]; };
+  const uint64_t total = incl(n_tiles - 1);
+  const uint64_t W = lvl == 0 ? w_first : w_rest;
+  const uint64_t excl_t = t ? incl(t - 1) : 0;          // cost before tile t
+  const uint64_t excl_p = t > 1 ? incl(t - 2) : 0;      // cost before tile t - 1
+  const uint64_t w_hi = excl_t * W / total;
+  const uint64_t w_lo = t ? excl_p * W / total + 1 : 0;
+  uint32_t* bl = bounds + (uint64_t)lvl * b_stride;
+  for (uint64_t w = w_lo; w <= w_hi && w < W; ++w) bl[w] = t;
+}
+
+hipError_t launch_run_bounds(const uint32_t* hi, const uint32_t* lo, const uint8_t* need, uint64_t need_stride_b,
+                             uint32_t m, uint32_t E, uint32_t levels, uint32_t w_first, uint32_t w_rest,
+                             uint32_t* pre, uint32_t* bsum, uint32_t* boff, uint32_t* bounds, uint32_t b_stride,
+                             hipStream_t st) {
+  if (!m || !levels) return hipSuccess;
+  const uint32_t n_tiles = div_up(m, E);
+  const uint32_t nb = div_up(n_tiles, kCostBlock);
+  hipError_t e = launch_fill32(bounds, n_tiles, (uint64_t)levels * b_stride, st);
+  if (e != hipSuccess) return e;
+  if (E == 8)
+    hipLaunchKernelGGL(k_tile_cost<8>, dim3(nb, levels), dim3(256), 0, st, hi, lo, need, need_stride_b, m, n_tiles,
+                       pre, bsum);
+  else
+    hipLaunchKernelGGL(k_tile_cost<16>, dim3(nb, levels), dim3(256), 0, st, hi, lo, need, need_stride_b, m,
+                       n_tiles, pre, bsum);
+  hipLaunchKernelGGL(k_cost_block_offsets, dim3(levels), dim3(1024), 0, st, bsum, nb, boff);
+  hipLaunchKernelGGL(k_run_bounds, dim3(div_up(n_tiles, 256), levels), dim3(256), 0, st, pre, boff, nb, n_tiles,
+                     w_first, w_rest, b_stride, bounds);
   return hipGetLastError();
 }
 
@@ -367,13 +499,40 @@ hipError_t launch_qtable(const uint32_t* e_src, const uint32_t* e_dst, const uin
 }
 
 template <int KQ, int E, bool FIRST>
-static void scan_one(const ScanArgs& a, uint32_t chunks, uint32_t wpb, hipStream_t st) {
+static uint32_t scan_blocks_one(uint32_t n_tiles, uint32_t chunks, uint32_t wpb) {
   const size_t lds = (size_t)wpb * 16 * kLanes * 8;
   const uint32_t fit = std::max(1u, resident_blocks((const void*)k_scan<KQ, E, FIRST>, 64 * wpb, lds) / chunks);
-  dim3 g(std::min(div_up(a.n_tiles, wpb), fit), chunks), b(64 * wpb);
+  return std::min(div_up(n_tiles, wpb), fit);
+}
+
+template <int KQ, int E, bool FIRST>
+static void scan_one(const ScanArgs& a, uint32_t chunks, uint32_t wpb, hipStream_t st) {
+  const size_t lds = (size_t)wpb * 16 * kLanes * 8;
+  // with run bounds the grid is the one the bounds were cut for
+  const uint32_t gx = a.bounds ? a.waves / wpb : scan_blocks_one<KQ, E, FIRST>(a.n_tiles, chunks, wpb);
+  dim3 g(gx, chunks), b(64 * wpb);
   hipLaunchKernelGGL((k_scan<KQ, E, FIRST>), g, b, lds, st, a.e_src, a.e_out, a.hi, a.lo, a.q, a.z,
                      a.p_prev, a.p_cur, a.p_stride, a.chunk_base, a.m, a.n_tiles, a.epoch, a.agg,
-                     a.incl, a.need, a.lb_stats);
+                     a.incl, a.need, a.lb_stats, a.bounds);
+}
+
+uint32_t scan_waves(uint32_t kq, uint32_t E, bool first, uint32_t n_tiles, uint32_t chunks, uint32_t wpb) {
+  uint32_t b = 0;
+  auto pick = [&](auto kqc) {
+    constexpr int K = decltype(kqc)::value;
+    if (E == 8)
+      b = first ? scan_blocks_one<K, 8, true>(n_tiles, chunks, wpb) : scan_blocks_one<K, 8, false>(n_tiles, chunks, wpb);
+    else
+      b = first ? scan_blocks_one<K, 16, true>(n_tiles, chunks, wpb)
+                : scan_blocks_one<K, 16, false>(n_tiles, chunks, wpb);
+  };
+  switch (kq) {
+    case 4: pick(std::integral_constant<int, 4>{}); break;
+    case 8: pick(std::integral_constant<int, 8>{}); break;
+    case 12: pick(std::integral_constant<int, 12>{}); break;
+    default: pick(std::integral_constant<int, 16>{}); break;
+  }
+  return b * wpb;
 }
 
 template <int KQ>

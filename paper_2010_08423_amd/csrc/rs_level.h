@@ -126,7 +126,16 @@ struct TileCtx {
   uint64_t* incl;      // [tiles][64][2] records: inclusive prefix of that segment
   const uint8_t* need; // per edge: which of its P slots some window reads (see mark_need)
   unsigned long long* lb_stats;  // null, or [2]: recomputed predecessors, unanswered probe rounds
+  const uint32_t* bounds;        // null (runs of equal length), or [W+1] first tile of each run
 };
+
+// First tile of run r of a prefix level: from the bounds array when the runs
+// are balanced by work, else r equal runs of `len` tiles (clamped at the end).
+__device__ __forceinline__ uint32_t run_begin(const TileCtx& c, int64_t r, uint32_t len) {
+  if (c.bounds) return as_const(c.bounds)[r];
+  const uint64_t t = (uint64_t)r * len;
+  return t < c.n_tiles ? (uint32_t)t : c.n_tiles;
+}
 
 // N consecutive entries of an index array in one scalar load (the arrays are
 // padded past m, so the load stays in bounds for the last tile).
@@ -294,46 +303,55 @@ __device__ uint64_t tile_open_part(const TileCtx& c, uint32_t j, uint32_t lane, 
 // bounds the wait (about 10 ms) for a predecessor that never got to run.
 constexpr uint32_t kFallbackSpins = 4096;
 
-// XOR of the level values of the segment part preceding tile `tile`, the
-// first tile of a wave's run. Records sit at the last tile of every run, so
-// the predecessors' records are `tile - 1`, `tile - 1 - stride`, ... (stride =
-// tiles per run). The nearest one's two records are read first, which ends
-// most walks in one memory round trip. After that, each round probes up to 64
-// predecessor records at once (lane l reads the tags of record top - l*stride,
-// lane-0 words), then absorbs the leading run of published records up to and
-// including the nearest inclusive one, every lane validating its own words; a
-// carry that has to cross d runs costs about d/64 memory round trips. A
-// predecessor that stays unpublished is recomputed here, tile by tile from
-// the end of its run, so every wait is bounded whatever order the waves run
-// in.
+// XOR of the level values of the segment part preceding run `run` (its first
+// tile continues a segment). Runs publish one record each, at their last
+// tile; run r covers tiles run_begin(r) .. run_begin(r + 1) - 1, and a run
+// without tiles (possible when the runs are balanced by work) publishes
+// nothing and is skipped. The nearest non-empty predecessor's two records are
+// read first, which ends most walks in one memory round trip. After that,
+// each round probes up to 64 predecessor runs at once (lane l reads the tags
+// of run top - l's record, lane-0 words), then absorbs the leading run of
+// published records up to and including the nearest inclusive one, every
+// lane validating its own words; a carry that has to cross d runs costs about
+// d/64 memory round trips. A predecessor that stays unpublished is recomputed
+// here, tile by tile from the end of its run, so every wait is bounded
+// whatever order the waves run in.
 template <int KQ, int E, bool FIRST>
-__device__ uint64_t look_back(const TileCtx& c, uint32_t tile, uint32_t stride, uint32_t lane,
-                              const uint32_t (&mk)[6], uint64_t* tab) {
+__device__ uint64_t look_back(const TileCtx& c, uint32_t run, uint32_t len, uint32_t lane, const uint32_t (&mk)[6],
+                              uint64_t* tab) {
   uint64_t carry = 0;
-  int64_t top = (int64_t)tile - 1;  // record of the nearest run not absorbed yet
-  const int64_t st = (int64_t)stride;
   uint32_t spins = 0, spin_total = 0;
   const uint32_t t_agg = rec_tag(c.epoch, kFlagAgg), t_inc = rec_tag(c.epoch, kFlagIncl);
+  const uint32_t t0 = run_begin(c, run, len);
+  // nearest non-empty predecessor run: the one holding tile t0 - 1
+  int64_t top = (int64_t)run - 1;
+  while (top > 0 && run_begin(c, top, len) == t0) --top;
   {
     uint64_t vi, va;
-    const bool oki = read_rec(c.incl, c.row0 + (uint64_t)top, lane, t_inc, &vi);
-    const bool oka = read_rec(c.agg, c.row0 + (uint64_t)top, lane, t_agg, &va);
+    const uint64_t fi = c.row0 + (t0 - 1);
+    const bool oki = read_rec(c.incl, fi, lane, t_inc, &vi);
+    const bool oka = read_rec(c.agg, fi, lane, t_agg, &va);
     if (__ballot(!oki) == 0) return vi;
     if (__ballot(!oka) == 0) {
       carry = va;
-      top -= st;
+      --top;
     }
   }
   uint32_t width = 4;
   while (top >= 0) {
-    const int64_t j = top - (int64_t)lane * st;
+    const int64_t r = top - (int64_t)lane;
     bool ready = false, inc = false;
-    if (j >= 0 && lane < width) {
-      const uint64_t fi = c.row0 + (uint64_t)j;
-      const uint32_t ti = hi32(ld_dev64(c.incl + fi * kLanes * 2));  // both loads in flight together
-      const uint32_t ta = hi32(ld_dev64(c.agg + fi * kLanes * 2));
-      inc = ti == t_inc;
-      ready = inc || ta == t_agg;
+    if (r >= 0 && lane < width) {
+      const uint32_t b0 = run_begin(c, r, len), b1 = run_begin(c, r + 1, len);
+      if (b0 == b1) {
+        ready = true;  // no tiles, no record: transparent
+      } else {
+        const uint64_t fi = c.row0 + (b1 - 1);
+        const uint32_t ti = hi32(ld_dev64(c.incl + fi * kLanes * 2));  // both loads in flight together
+        const uint32_t ta = hi32(ld_dev64(c.agg + fi * kLanes * 2));
+        inc = ti == t_inc;
+        ready = inc || ta == t_agg;
+      }
     }
     const uint64_t ready_mask = __ballot(ready);
     const uint64_t inc_mask = __ballot(inc);
@@ -349,18 +367,21 @@ __device__ uint64_t look_back(const TileCtx& c, uint32_t tile, uint32_t stride, 
         for (uint32_t d = 0; d < 4; ++d) {
           const uint32_t i = i0 + d;
           if (i < take) {
-            const bool use_inc = ends && i == first_inc;
-            uint64_t v;
-            ok &= read_rec(use_inc ? c.incl : c.agg, c.row0 + (uint64_t)(top - (int64_t)i * st), lane,
-                           use_inc ? t_inc : t_agg, &v);
-            part ^= v;
+            const int64_t ri = top - (int64_t)i;
+            const uint32_t b0 = run_begin(c, ri, len), b1 = run_begin(c, ri + 1, len);
+            if (b0 != b1) {
+              const bool use_inc = ends && i == first_inc;
+              uint64_t v;
+              ok &= read_rec(use_inc ? c.incl : c.agg, c.row0 + (b1 - 1), lane, use_inc ? t_inc : t_agg, &v);
+              part ^= v;
+            }
           }
         }
       }
       if (__ballot(!ok) == 0) {  // every lane's words were complete
         carry ^= part;
         if (ends) break;
-        top -= (int64_t)take * st;
+        top -= (int64_t)take;
         spins = 0;
         width = kLanes;  // a long run of published records: probe wide
         continue;
@@ -371,11 +392,11 @@ __device__ uint64_t look_back(const TileCtx& c, uint32_t tile, uint32_t stride, 
       // recompute the predecessor run backwards from its last tile
       if (c.lb_stats && lane == 0) atomicAdd(c.lb_stats, 1ull);
       bool started = false;
-      const int64_t run_first = top - st + 1;
-      for (int64_t j = top; j >= run_first && j >= 0 && !started; --j)
+      const int64_t first = run_begin(c, top, len);
+      for (int64_t j = (int64_t)run_begin(c, top + 1, len) - 1; j >= first && !started; --j)
         carry ^= tile_open_part<KQ, E, FIRST>(c, (uint32_t)j, lane, mk, tab, &started);
       if (started) break;
-      top -= st;
+      --top;
       spins = 0;
       continue;
     }
@@ -422,10 +443,9 @@ __device__ __forceinline__ void load_tile(const TileCtx& c, uint32_t tile, uint3
 template <int KQ, int E, bool FIRST>
 __device__ __forceinline__ void scan_run(const TileCtx& c, uint32_t w, uint32_t W, uint32_t lane,
                                          const uint32_t (&mk)[6], uint64_t* tab) {
-  const uint32_t R = (c.n_tiles + W - 1) / W;
-  const uint32_t t0 = w * R;
-  if (t0 >= c.n_tiles) return;
-  const uint32_t t1 = min(t0 + R, c.n_tiles);
+  const uint32_t R = (c.n_tiles + W - 1) / W;  // tiles per run when the runs are of equal length
+  const uint32_t t0 = run_begin(c, w, R), t1 = run_begin(c, w + 1, R);
+  if (t0 >= t1) return;
   cu32* e_out = as_const(c.e_out);
   const uint32_t m = c.m;
   const uint32_t e_begin = t0 * (uint32_t)E;
@@ -480,7 +500,7 @@ __device__ __forceinline__ void scan_run(const TileCtx& c, uint32_t w, uint32_t 
   if (next_cont)
     publish(started ? c.incl : c.agg, fi, lane, acc, rec_tag(c.epoch, started ? kFlagIncl : kFlagAgg));
   if (!cont) return;
-  const uint64_t carry = look_back<KQ, E, FIRST>(c, t0, R, lane, mk, tab);
+  const uint64_t carry = look_back<KQ, E, FIRST>(c, w, R, lane, mk, tab);
   if (next_cont && !started) publish(c.incl, fi, lane, carry ^ acc, rec_tag(c.epoch, kFlagIncl));
   if (!carry) return;
   // the run's leading segment part: its stored slots get the carry (same lane
@@ -596,7 +616,7 @@ __device__ __forceinline__ void scan_runs(const TileCtx& c, uint32_t w, uint32_t
     const uint32_t t0 = run_first(r), t1 = min(t0 + R, c.n_tiles);
     const uint32_t e_begin = t0 * (uint32_t)E, e_end = min(t1 * (uint32_t)E, m);
     if (!continues(e_begin)) continue;
-    const uint64_t carry = look_back<KQ, E, FIRST>(c, t0, R, lane, mk, tab);
+    const uint64_t carry = look_back<KQ, E, FIRST>(c, w + r * W, R, lane, mk, tab);
     if (!((started_mask >> r) & 1u) && continues(e_end)) {
       // no segment starts in the run: its inclusive prefix is the carry and
       // its own aggregate, published above
@@ -633,7 +653,7 @@ __device__ __forceinline__ void scan_runs(const TileCtx& c, uint32_t w, uint32_t
 template <int KQ, int E, bool FIRST>
 __device__ __forceinline__ void scan_level(const TileCtx& c, uint32_t w, uint32_t W, uint32_t lane,
                                            const uint32_t (&mk)[6], uint64_t* tab) {
-  if constexpr (FIRST)
+  if (FIRST && !c.bounds)
     scan_runs<KQ, E, FIRST>(c, w, W, lane, mk, tab);
   else
     scan_run<KQ, E, FIRST>(c, w, W, lane, mk, tab);
