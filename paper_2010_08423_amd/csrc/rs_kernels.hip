@@ -315,22 +315,19 @@ hipError_t launch_ztable(uint64_t* z, uint32_t n, const QueryPlan& qp, const uin
 }
 
 // ---------------------------------------------------------------------------
-// Work-balanced runs of the prefix levels. The cost of a tile is
-// kTileCostBase plus kProductCost per edge that forms a product at that
-// level (need bit 2, and at levels >= 3 a non-empty window); runs are cut at
-// equal shares of the level's total cost. blockIdx.y is the level index
+// Work-balanced runs of the prefix levels. The cost of a tile is a weight per
+// tile plus a weight per edge that forms a product at that level (need bit
+// 2, and at levels >= 3 a non-empty window); runs are cut at equal shares of
+// the level's total cost. blockIdx.y is the level index
 // (level 2 + y); per level the arrays are pre[n_tiles], bsum[nb], boff[nb],
 // bounds[W+1], at the strides given.
 // ---------------------------------------------------------------------------
-// Per-wave clocks of the equal-length runs fit 4.5-4.8 us per tile plus
-// 0.9-1.2 us per product (correlation 0.91-0.93 with the products of the run),
-// so a tile counts 9 and a product 2.
-constexpr uint32_t kTileCostBase = 9;
-constexpr uint32_t kProductCost = 2;
-// Level 2 gathers no windows, so a tile costs less there relative to a
-// product: its clocks fit 2.8 us per tile plus 1.05 us per product, and a
-// weight of 3 per tile measured best (3: 0.77 ms, 5: 0.79 ms, 9: 0.82 ms).
-constexpr uint32_t kTileCostBaseFirst = 3;
+// Weights of a tile and of a product, from per-wave clocks regressed on the
+// tiles and products of each wave's run (10^6-edge graph): levels >= 3 fit
+// 2.4 us per tile plus 1.3-1.4 us per product, level 2 2.1 us per tile plus
+// 1.2 us per product (level 2 gathers no windows).
+constexpr uint32_t kTileCost = 5, kProductCost = 3;
+constexpr uint32_t kTileCostFirst = 7, kProductCostFirst = 4;
 constexpr uint32_t kCostBlock = 1024;  // tiles per block of the cost prefix (256 threads x 4)
 
 template <int E>
@@ -348,10 +345,11 @@ __global__ __launch_bounds__(256) void k_tile_cost(const uint32_t* __restrict__ 
     const uint32_t t = t_base + j;
     uint32_t c = 0;
     if (t < n_tiles) {
-      c = lvl == 0 ? kTileCostBaseFirst : kTileCostBase;
+      c = lvl == 0 ? kTileCostFirst : kTileCost;
+      const uint32_t pc = lvl == 0 ? kProductCostFirst : kProductCost;
       const uint32_t e0 = t * (uint32_t)E, e1 = min(e0 + (uint32_t)E, m);
       for (uint32_t e = e0; e < e1; ++e)
-        c += kProductCost * (((nd[e] >> 2) & 1u) && (lvl == 0 || hi[e] != lo[e]));
+        c += pc * (((nd[e] >> 2) & 1u) && (lvl == 0 || hi[e] != lo[e]));
     }
     sum += c;
     cost[j] = sum;  // inclusive within the thread's four tiles
