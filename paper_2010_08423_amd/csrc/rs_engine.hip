@@ -309,13 +309,17 @@ rs_status run_plain(rs_graph* g, PlainWorkspace& ws, const QueryPlan& qp, const 
                            ws.lo.as<uint32_t>(), (uint32_t)m, qp.delta, st));
       // Flags per prefix level, from the last one down: level l stores the
       // slots the windows of level l+1's product edges read, and forms a
-      // product only for edges at or before the last such slot of their
-      // segment (level k-1: the windows of every last-level edge).
+      // product only for edges inside one of those windows (level k-1: the
+      // windows of every last-level edge).
+      if (k >= 3) {
+        const uint64_t slots = m + n + 1, nb = (slots + 1023) / 1024;
+        if (ws.cov_diff.reserve(4 * slots, st, false) || ws.cov_b.reserve(8 * nb, st, false)) return RS_ENOMEM;
+      }
       for (uint32_t l = k - 1; l >= 2 && k >= 3; --l)
-        RS_HIP(launch_need(G.in_off.as<uint32_t>(), G.e_dst.as<uint32_t>(), G.e_out.as<uint32_t>(),
-                           G.hi.as<uint32_t>(), ws.lo.as<uint32_t>(), (uint32_t)m, (uint32_t)n,
-                           l + 1 < k ? need_of(l + 1) : nullptr, ws.ref.as<uint8_t>(), ws.lastref.as<uint32_t>(),
-                           need_of(l), st));
+        RS_HIP(launch_need_cover(G.e_out.as<uint32_t>(), G.hi.as<uint32_t>(), ws.lo.as<uint32_t>(), (uint32_t)m,
+                                 (uint32_t)n, l + 1 < k ? need_of(l + 1) : nullptr, ws.ref.as<uint8_t>(),
+                                 ws.cov_diff.as<uint32_t>(), ws.cov_b.as<uint32_t>(),
+                                 ws.cov_b.as<uint32_t>() + (m + n + 1 + 1023) / 1024, need_of(l), st));
       // work-balanced runs of the prefix levels, cut for the grid width of
       // the first chunk group (later groups launch the same width)
       if (k >= 3) {

@@ -163,6 +163,11 @@ hipError_t launch_need_counts(const uint32_t* hi, const uint32_t* lo, const uint
 hipError_t launch_need(const uint32_t* in_off, const uint32_t* e_dst, const uint32_t* e_out, const uint32_t* hi,
                        const uint32_t* lo, uint32_t m, uint32_t n, const uint8_t* next, uint8_t* ref,
                        uint32_t* lastref, uint8_t* need, hipStream_t st);
+// The same flags with bit 2 by window cover (see mark_cover): scratch
+// ref[m+n], diff[m+n+1], bsum and boff [ceil((m+n+1) / 1024)].
+hipError_t launch_need_cover(const uint32_t* e_out, const uint32_t* hi, const uint32_t* lo, uint32_t m, uint32_t n,
+                             const uint8_t* next, uint8_t* ref, uint32_t* diff, uint32_t* bsum, uint32_t* boff,
+                             uint8_t* need, hipStream_t st);
 // Flag arrays of a query: one per prefix level 2..k-1 (at least one), each
 // m + kEdgePad bytes, level l at offset (l - 2) * need_stride(m); the stride
 // keeps every level's array 256-byte aligned (the kernels read the flags four
@@ -240,19 +245,20 @@ struct PlainWorkspace {
   DevBuf lo, z, q, p0, p1, partial, agg, incl, fsum, out, ref, need, lastref;
   DevBuf lb_stats;  // look-back counters, allocated only while launches are traced
   DevBuf run_pre, run_bsum, run_boff, run_bounds;  // work-balanced runs of the prefix levels
+  DevBuf cov_diff, cov_b;                          // window-cover scratch of the flags
   uint32_t epoch = 0;
   uint64_t p_elems_per_chunk = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   uint64_t bytes() const {
     uint64_t t = 0;
     for (const DevBuf* b : {&lo, &z, &q, &p0, &p1, &partial, &agg, &incl, &fsum, &out, &ref, &need, &lastref,
-                            &lb_stats, &run_pre, &run_bsum, &run_boff, &run_bounds})
+                            &lb_stats, &run_pre, &run_bsum, &run_boff, &run_bounds, &cov_diff, &cov_b})
       t += b->bytes;
     return t;
   }
   void release() {
     for (DevBuf* b : {&lo, &z, &q, &p0, &p1, &partial, &agg, &incl, &fsum, &out, &ref, &need, &lastref, &lb_stats,
-                      &run_pre, &run_bsum, &run_boff, &run_bounds})
+                      &run_pre, &run_bsum, &run_boff, &run_bounds, &cov_diff, &cov_b})
       b->release();
     if (ev0) (void)hipEventDestroy(ev0);
     if (ev1) (void)hipEventDestroy(ev1);

@@ -328,7 +328,6 @@ hipError_t launch_ztable(uint64_t* z, uint32_t n, const QueryPlan& qp, const uin
 // 1.2 us per product (level 2 gathers no windows).
 constexpr uint32_t kTileCost = 5, kProductCost = 3;
 constexpr uint32_t kTileCostFirst = 7, kProductCostFirst = 4;
-constexpr uint32_t kCostBlock = 1024;  // tiles per block of the cost prefix (256 threads x 4)
 
 template <int E>
 __global__ __launch_bounds__(256) void k_tile_cost(const uint32_t* __restrict__ hi, const uint32_t* __restrict__ lo,
@@ -475,6 +474,64 @@ hipError_t launch_need(const uint32_t* in_off, const uint32_t* e_dst, const uint
   hipLaunchKernelGGL(k_mark_ref, dim3(div_up(m, 256)), dim3(256), 0, st, hi, lo, next, m, ref);
   hipLaunchKernelGGL(k_mark_last, dim3(div_up(n, 256)), dim3(256), 0, st, in_off, ref, n, lastref);
   hipLaunchKernelGGL(k_mark_need, dim3(div_up(m, 256)), dim3(256), 0, st, e_out, e_dst, ref, lastref, m, need);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_mark_cover(const uint32_t* __restrict__ hi, const uint32_t* __restrict__ lo,
+                                                    const uint8_t* __restrict__ next, uint32_t m,
+                                                    uint8_t* __restrict__ ref, uint32_t* __restrict__ diff) {
+  const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < m) mark_cover(hi, lo, next, e, ref, diff);
+}
+
+// In-place inclusive prefix (modulo 2^32) within blocks of kCostBlock entries
+// of v[count]; the block totals go to bsum.
+__global__ __launch_bounds__(256) void k_block_prefix(uint32_t* __restrict__ v, uint64_t count,
+                                                      uint32_t* __restrict__ bsum) {
+  __shared__ uint32_t part[256];
+  const uint64_t base = (uint64_t)blockIdx.x * kCostBlock + threadIdx.x * 4;
+  uint32_t x[4];
+  uint32_t sum = 0;
+  for (int j = 0; j < 4; ++j) {
+    sum += base + j < count ? v[base + j] : 0u;
+    x[j] = sum;
+  }
+  part[threadIdx.x] = sum;
+  __syncthreads();
+  for (uint32_t d = 1; d < 256; d <<= 1) {
+    const uint32_t u = threadIdx.x >= d ? part[threadIdx.x - d] : 0u;
+    __syncthreads();
+    part[threadIdx.x] += u;
+    __syncthreads();
+  }
+  const uint32_t before = threadIdx.x ? part[threadIdx.x - 1] : 0u;
+  for (int j = 0; j < 4; ++j)
+    if (base + j < count) v[base + j] = before + x[j];
+  if (threadIdx.x == 255) bsum[blockIdx.x] = part[255];
+}
+
+__global__ __launch_bounds__(256) void k_mark_need_cover(const uint32_t* __restrict__ e_out,
+                                                         const uint8_t* __restrict__ ref,
+                                                         const uint32_t* __restrict__ pre,
+                                                         const uint32_t* __restrict__ boff, uint32_t m,
+                                                         uint8_t* __restrict__ need) {
+  const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < m) mark_need_cover(e_out, ref, pre, boff, e, need);
+}
+
+hipError_t launch_need_cover(const uint32_t* e_out, const uint32_t* hi, const uint32_t* lo, uint32_t m, uint32_t n,
+                             const uint8_t* next, uint8_t* ref, uint32_t* diff, uint32_t* bsum, uint32_t* boff,
+                             uint8_t* need, hipStream_t st) {
+  if (!m) return hipSuccess;
+  const uint64_t slots = (uint64_t)m + n + 1;  // slots 0 .. m+n-1, and one past the last window end
+  const uint32_t nb = (uint32_t)((slots + kCostBlock - 1) / kCostBlock);
+  hipError_t e = launch_fill32((uint32_t*)ref, 0, ((uint64_t)m + n + 3) / 4, st);
+  if (e == hipSuccess) e = launch_fill32(diff, 0, slots, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_mark_cover, dim3(div_up(m, 256)), dim3(256), 0, st, hi, lo, next, m, ref, diff);
+  hipLaunchKernelGGL(k_block_prefix, dim3(nb), dim3(256), 0, st, diff, slots, bsum);
+  hipLaunchKernelGGL(k_cost_block_offsets, dim3(1), dim3(1024), 0, st, bsum, nb, boff);
+  hipLaunchKernelGGL(k_mark_need_cover, dim3(div_up(m, 256)), dim3(256), 0, st, e_out, ref, diff, boff, m, need);
   return hipGetLastError();
 }
 

@@ -756,4 +756,38 @@ __device__ __forceinline__ void mark_need(const uint32_t* e_out, const uint32_t*
   need[e] = (uint8_t)f;
 }
 
+// Entries per block of the block-wise prefix sums (tile costs, window cover):
+// 256 threads x 4.
+constexpr uint32_t kCostBlock = 1024;
+
+// Product flags by window cover (plain path). A window reads P[hi] ^ P[lo],
+// the XOR of the level values of the edges with slots in (lo, hi]; a value
+// before lo enters both prefixes and cancels. So an edge's product is needed
+// only when its slot lies in the window of some reader, and leaving out every
+// other product leaves every window sum unchanged. Each reader adds +1 at
+// slot lo + 1 and -1 at slot hi + 1 of a difference array (windows never
+// leave their segment); its prefix sum at e's slot counts the readers whose
+// window covers e. The read slots are marked in ref as for mark_ref.
+__device__ __forceinline__ void mark_cover(const uint32_t* hi, const uint32_t* lo, const uint8_t* next, uint64_t e,
+                                           uint8_t* ref, uint32_t* diff) {
+  const uint32_t h = hi[e], l = lo[e];
+  if (h != l && (!next || (next[e] & 4u))) {
+    ref[h] = 1;
+    ref[l] = 1;
+    atomicAdd(&diff[l + 1], 1u);
+    atomicAdd(&diff[h + 1], ~0u);  // -1 modulo 2^32
+  }
+}
+// need[e]: bits 0 and 1 as in mark_need; bit 2 when e's slot is covered, with
+// cover(s) = pre[s] + boff[s / kCostBlock] (modulo 2^32) the prefix sum of
+// the difference array.
+__device__ __forceinline__ void mark_need_cover(const uint32_t* e_out, const uint8_t* ref, const uint32_t* pre,
+                                                const uint32_t* boff, uint64_t e, uint8_t* need) {
+  const uint32_t slot = e_out[e];
+  uint32_t f = ref[slot];
+  if (e == 0 || e_out[e - 1] + 1u != slot) f |= (uint32_t)ref[slot - 1] << 1;
+  if (pre[slot] + boff[slot / kCostBlock] != 0u) f |= 4u;
+  need[e] = (uint8_t)f;
+}
+
 }  // namespace rs
