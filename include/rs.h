@@ -160,7 +160,7 @@ typedef struct {
 /* HBM bytes rs_run needs for this query on this graph beyond the graph
  * itself: window indices 4m, substitution table 8nk, per-level products
  * 8m*kq*(k-1) (kq = k rounded up to a multiple of 4), store and product
- * flags (k-2)*m plus m+5n of scratch, two prefix-state buffers
+ * flags (k-2)*m plus about 5(m+n) bytes of scratch, two prefix-state buffers
  * 2*8*(m+n)*64 per concurrent chunk, look-back state and 8*2^k of
  * per-iteration sums. */
 rs_status rs_query_footprint(const rs_graph* g, const rs_query* q, uint64_t* bytes);

@@ -51,7 +51,9 @@ struct BQuery {
   uint64_t* fsum;
   uint8_t* need;     // store and product flags
   uint8_t* ref;      // slot marks (scratch shared by the queries of a batch)
-  uint32_t* lastref; // last read slot per vertex (scratch, shared)
+  uint32_t* cov;     // window-cover difference array [m+n+1], then its block-wise prefix (scratch, shared)
+  uint32_t* cbsum;   // its block totals (scratch, shared)
+  uint32_t* cboff;   // its block offsets (scratch, shared)
   uint64_t seed, it_begin, it_end;
   uint32_t n, m, k, kq, delta, motif;
   uint8_t mu[RS_MAX_COLOURS];
@@ -158,31 +160,37 @@ __global__ __launch_bounds__(256) void kb_qtable(const BQuery* __restrict__ qs, 
   }
 }
 
-// Store flags of query qi (see mark_need); ref is zeroed by kb_clear_ref.
-__global__ void kb_clear_ref(const BQuery* __restrict__ qs, uint32_t qi) {
+// Store and product flags of query qi, prefix level l (see mark_cover): ref
+// and the cover array are zeroed by kb_clear_cover; the readers are the
+// windows of level l+1's product edges (every non-empty window when l+1 is
+// the last level).
+__global__ void kb_clear_cover(const BQuery* __restrict__ qs, uint32_t qi) {
   const BQuery& Q = qs[qi];
-  const uint64_t words = ((uint64_t)Q.m + Q.n + 3) / 4;
+  const uint64_t words = ((uint64_t)Q.m + Q.n + 3) / 4, slots = (uint64_t)Q.m + Q.n + 1;
   uint32_t* r = (uint32_t*)Q.ref;
-  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words; i += (uint64_t)gridDim.x * blockDim.x)
-    r[i] = 0;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < slots; i += (uint64_t)gridDim.x * blockDim.x) {
+    if (i < words) r[i] = 0;
+    Q.cov[i] = 0;
+  }
 }
-// Flags of prefix level l: slots read by the windows of level l+1's product
-// edges (every non-empty window when l+1 is the last level).
-__global__ __launch_bounds__(256) void kb_mark_ref(const BQuery* __restrict__ qs, uint32_t qi, uint32_t l) {
+__global__ __launch_bounds__(256) void kb_mark_cover(const BQuery* __restrict__ qs, uint32_t qi, uint32_t l) {
   const BQuery& Q = qs[qi];
   const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const uint8_t* next = l + 1 < Q.k ? Q.need + (uint64_t)(l - 1) * need_stride(Q.m) : nullptr;
-  if (e < Q.m) mark_ref(Q.hi, Q.lo, next, e, Q.ref);
+  if (e < Q.m) mark_cover(Q.hi, Q.lo, next, e, Q.ref, Q.cov);
 }
-__global__ __launch_bounds__(256) void kb_mark_last(const BQuery* __restrict__ qs, uint32_t qi) {
+__global__ __launch_bounds__(256) void kb_cover_prefix(const BQuery* __restrict__ qs, uint32_t qi) {
   const BQuery& Q = qs[qi];
-  const uint32_t u = blockIdx.x * blockDim.x + threadIdx.x;
-  if (u < Q.n) mark_last(Q.in_off, Q.ref, u, Q.lastref);
+  block_prefix(Q.cov, (uint64_t)Q.m + Q.n + 1, Q.cbsum);
+}
+__global__ __launch_bounds__(1024) void kb_cover_offsets(const BQuery* __restrict__ qs, uint32_t qi) {
+  const BQuery& Q = qs[qi];
+  block_offsets(Q.cbsum, (uint32_t)(((uint64_t)Q.m + Q.n + kCostBlock) / kCostBlock), Q.cboff);
 }
 __global__ __launch_bounds__(256) void kb_mark_need(const BQuery* __restrict__ qs, uint32_t qi, uint32_t l) {
   const BQuery& Q = qs[qi];
   const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < Q.m) mark_need(Q.e_out, Q.e_dst, Q.ref, Q.lastref, e, Q.need + (uint64_t)(l - 2) * need_stride(Q.m));
+  if (e < Q.m) mark_need_cover(Q.e_out, Q.ref, Q.cov, Q.cboff, e, Q.need + (uint64_t)(l - 2) * need_stride(Q.m));
 }
 
 __global__ void kb_clear_fsum(const BQuery* __restrict__ qs, uint32_t qi) {
@@ -337,7 +345,7 @@ constexpr uint32_t kBatchLanes = 2;
 
 struct BatchWorkspace {
   std::mutex mu;
-  DevBuf qs, units, ubegin, per_query, parena, agg, incl, out, ref, lastref;
+  DevBuf qs, units, ubegin, per_query, parena, agg, incl, out, ref, cov;
   uint32_t epoch = 0;
   std::string key;  // shape of the captured graph
   hipGraphExec_t exec = nullptr;
@@ -365,12 +373,12 @@ struct BatchWorkspace {
   }
   void release() {
     drop_graph();
-    for (DevBuf* b : {&qs, &units, &ubegin, &per_query, &parena, &agg, &incl, &out, &ref, &lastref}) b->release();
+    for (DevBuf* b : {&qs, &units, &ubegin, &per_query, &parena, &agg, &incl, &out, &ref, &cov}) b->release();
     epoch = 0;
   }
   uint64_t bytes() const {
     uint64_t t = 0;
-    for (const DevBuf* b : {&qs, &units, &ubegin, &per_query, &parena, &agg, &incl, &out, &ref, &lastref})
+    for (const DevBuf* b : {&qs, &units, &ubegin, &per_query, &parena, &agg, &incl, &out, &ref, &cov})
       t += b->bytes;
     return t;
   }
@@ -663,13 +671,16 @@ static rs_status resolve_plan(BatchPlan& P, BatchWorkspace& W, uint32_t epoch0) 
     need_off[i] = (uintptr_t)Q.need;
     if (need_off[i] + table_need_bytes(Q.m, Q.k) > W.per_query.bytes) return RS_EINVAL;
     if (q_off[i] + table_q_bytes(Q.m, Q.k, Q.kq) > W.per_query.bytes) return RS_EINVAL;
-    if ((uint64_t)Q.m + Q.n > W.ref.bytes || 4ull * Q.n > W.lastref.bytes) return RS_EINVAL;
+    const uint64_t slots = (uint64_t)Q.m + Q.n + 1, nbq = (slots + kCostBlock - 1) / kCostBlock;
+    if ((uint64_t)Q.m + Q.n > W.ref.bytes || 4ull * (slots + 2 * nbq) > W.cov.bytes) return RS_EINVAL;
     Q.lo = (uint32_t*)(pq + lo_off[i]);
     Q.z = (uint64_t*)(pq + z_off[i]);
     Q.q = (uint64_t*)(pq + q_off[i]);
     Q.need = (uint8_t*)(pq + need_off[i]);
     Q.ref = W.ref.as<uint8_t>();
-    Q.lastref = W.lastref.as<uint32_t>();
+    Q.cov = W.cov.as<uint32_t>();
+    Q.cbsum = Q.cov + slots;
+    Q.cboff = Q.cbsum + nbq;
   }
   uint32_t scan_idx = 0;
   for (const BLaunch& L : P.launches) {
@@ -780,11 +791,13 @@ static rs_status batch_enqueue(BatchPlan& P, BatchWorkspace& W, hipStream_t st) 
     hipLaunchKernelGGL(kb_ztable, dim3((uint32_t)(((uint64_t)Q.n * Q.kq + 255) / 256)), dim3(256), 0, st, dq, qi);
     hipLaunchKernelGGL(kb_window, dim3((Q.m + 255) / 256), dim3(256), 0, st, dq, qi);
     for (uint32_t l = Q.k - 1; l >= 2 && Q.k >= 3; --l) {  // flags per prefix level, last one first
-      hipLaunchKernelGGL(kb_clear_ref,
-                         dim3((uint32_t)std::min<uint64_t>(((uint64_t)Q.m + Q.n + 1023) / 1024, 1024)), dim3(256), 0,
+      const uint64_t slots = (uint64_t)Q.m + Q.n + 1;
+      hipLaunchKernelGGL(kb_clear_cover, dim3((uint32_t)std::min<uint64_t>((slots + 1023) / 1024, 1024)), dim3(256), 0,
                          st, dq, qi);
-      hipLaunchKernelGGL(kb_mark_ref, dim3((Q.m + 255) / 256), dim3(256), 0, st, dq, qi, l);
-      hipLaunchKernelGGL(kb_mark_last, dim3((Q.n + 255) / 256), dim3(256), 0, st, dq, qi);
+      hipLaunchKernelGGL(kb_mark_cover, dim3((Q.m + 255) / 256), dim3(256), 0, st, dq, qi, l);
+      hipLaunchKernelGGL(kb_cover_prefix, dim3((uint32_t)((slots + kCostBlock - 1) / kCostBlock)), dim3(256), 0, st,
+                         dq, qi);
+      hipLaunchKernelGGL(kb_cover_offsets, dim3(1), dim3(1024), 0, st, dq, qi);
       hipLaunchKernelGGL(kb_mark_need, dim3((Q.m + 255) / 256), dim3(256), 0, st, dq, qi, l);
     }
     switch (Q.kq) {
@@ -873,14 +886,14 @@ rs_status run_batch_impl(const rs_graph* const* graphs, const rs_query* queries,
   if (P.qs.empty()) return first_err;
   // device memory; a reallocation invalidates the captured graph
   const void* before[10] = {W.qs.p,  W.units.p, W.ubegin.p, W.per_query.p, W.parena.p,
-                            W.agg.p, W.incl.p,  W.out.p,    W.ref.p,       W.lastref.p};
+                            W.agg.p, W.incl.p,  W.out.p,    W.ref.p,       W.cov.p};
   const uint64_t rec_bytes = 1024 * P.records;
   if (W.per_query.reserve(P.per_query_bytes, st, false) || W.qs.reserve(sizeof(BQuery) * P.qs.size(), st, false) ||
       W.units.reserve(sizeof(MUnit) * std::max<size_t>(P.units.size(), 1), st, false) ||
       W.ubegin.reserve(4 * std::max<size_t>(P.ubegin.size(), 1), st, false) ||
       W.parena.reserve(std::max<uint64_t>(P.parena_bytes, 256), st, false) ||
       W.out.reserve(8 * P.qs.size(), st, false) || W.ref.reserve(P.ref_bytes, st, false) ||
-      W.lastref.reserve(4 * P.n_max, st, false))
+      W.cov.reserve(4 * (P.ref_bytes + 1 + 2 * ((P.ref_bytes + kCostBlock) / kCostBlock)), st, false))
     return RS_ENOMEM;
   if (W.agg.bytes < rec_bytes || W.incl.bytes < rec_bytes) {
     // tagged records start at epoch 0, which no launch uses
@@ -888,7 +901,7 @@ rs_status run_batch_impl(const rs_graph* const* graphs, const rs_query* queries,
     W.epoch = 0;
   }
   const void* after[10] = {W.qs.p,  W.units.p, W.ubegin.p, W.per_query.p, W.parena.p,
-                           W.agg.p, W.incl.p,  W.out.p,    W.ref.p,       W.lastref.p};
+                           W.agg.p, W.incl.p,  W.out.p,    W.ref.p,       W.cov.p};
   if (memcmp(before, after, sizeof(before)) != 0) W.drop_graph();
   if ((uint64_t)W.epoch + P.scan_launches + 1 >= (1ull << 30)) {
     RS_HIP(launch_fill64(W.agg.as<uint64_t>(), 0, W.agg.bytes / 8, st));

@@ -225,12 +225,12 @@ PlainSizes plain_sizes(uint64_t m, uint64_t n, const QueryPlan& qp, const Tuning
   s.fsum = 8 * (1ull << k);
   s.ref = (m + n + 3) & ~3ull;
   s.need = table_need_bytes(m, k);
-  s.lastref = 4 * n;
+  s.cover = 4 * (m + n + 1) + 8 * ((m + n + 1 + 1023) / 1024);  // difference array and block sums
   s.records = 1024 * cpl * tiles;
   return s;
 }
 
-uint64_t PlainSizes::total() const { return lo + z + q + 2 * p + partial + fsum + 64 + ref + need + lastref + 2 * records; }
+uint64_t PlainSizes::total() const { return lo + z + q + 2 * p + partial + fsum + 64 + ref + need + cover + 2 * records; }
 
 uint64_t plain_footprint(const rs_graph* g, const QueryPlan& qp, const Tuning& tu) {
   return plain_sizes(g->g.m, g->g.n, qp, tu).total();
@@ -269,7 +269,7 @@ rs_status run_plain(rs_graph* g, PlainWorkspace& ws, const QueryPlan& qp, const 
         ws.p0.reserve(sz.p, st, true) || ws.p1.reserve(sz.p, st, true) ||
         ws.partial.reserve(sz.partial, st, false) || ws.fsum.reserve(sz.fsum, st, false) ||
         ws.out.reserve(64, st, false) || ws.ref.reserve(sz.ref, st, false) || ws.need.reserve(sz.need, st, false) ||
-        ws.lastref.reserve(sz.lastref, st, false))
+        ws.cov_diff.reserve(sz.cover, st, false))
       return RS_ENOMEM;
     auto need_of = [&](uint32_t l) { return ws.need.as<uint8_t>() + (uint64_t)(l - 2) * need_stride(m); };
     if (ws.agg.bytes < sz.records || ws.incl.bytes < sz.records) {
@@ -311,15 +311,13 @@ rs_status run_plain(rs_graph* g, PlainWorkspace& ws, const QueryPlan& qp, const 
       // slots the windows of level l+1's product edges read, and forms a
       // product only for edges inside one of those windows (level k-1: the
       // windows of every last-level edge).
-      if (k >= 3) {
-        const uint64_t slots = m + n + 1, nb = (slots + 1023) / 1024;
-        if (ws.cov_diff.reserve(4 * slots, st, false) || ws.cov_b.reserve(8 * nb, st, false)) return RS_ENOMEM;
-      }
+      uint32_t* cov = ws.cov_diff.as<uint32_t>();       // difference array [m+n+1]
+      uint32_t* cov_bsum = cov + (m + n + 1);            // block totals
+      uint32_t* cov_boff = cov_bsum + (m + n + 1 + 1023) / 1024;
       for (uint32_t l = k - 1; l >= 2 && k >= 3; --l)
         RS_HIP(launch_need_cover(G.e_out.as<uint32_t>(), G.hi.as<uint32_t>(), ws.lo.as<uint32_t>(), (uint32_t)m,
-                                 (uint32_t)n, l + 1 < k ? need_of(l + 1) : nullptr, ws.ref.as<uint8_t>(),
-                                 ws.cov_diff.as<uint32_t>(), ws.cov_b.as<uint32_t>(),
-                                 ws.cov_b.as<uint32_t>() + (m + n + 1 + 1023) / 1024, need_of(l), st));
+                                 (uint32_t)n, l + 1 < k ? need_of(l + 1) : nullptr, ws.ref.as<uint8_t>(), cov,
+                                 cov_bsum, cov_boff, need_of(l), st));
       // work-balanced runs of the prefix levels, cut for the grid width of
       // the first chunk group (later groups launch the same width)
       if (k >= 3) {

@@ -156,15 +156,11 @@ struct NeedCounts {
 // ref_slots, ref_lead.
 hipError_t launch_need_counts(const uint32_t* hi, const uint32_t* lo, const uint8_t* need, uint32_t m,
                               unsigned long long* counts, hipStream_t st);
-// Store and product flags of one prefix level l: the slots read by the
-// windows of the level-(l+1) readers, given by `next` (the flags of level l+1;
-// null for l = k-1, whose readers are every non-empty window of the last
-// level). ref[m+n] and lastref[n] are scratch, need[m] the per-edge flags.
-hipError_t launch_need(const uint32_t* in_off, const uint32_t* e_dst, const uint32_t* e_out, const uint32_t* hi,
-                       const uint32_t* lo, uint32_t m, uint32_t n, const uint8_t* next, uint8_t* ref,
-                       uint32_t* lastref, uint8_t* need, hipStream_t st);
-// The same flags with bit 2 by window cover (see mark_cover): scratch
-// ref[m+n], diff[m+n+1], bsum and boff [ceil((m+n+1) / 1024)].
+// Store and product flags of one prefix level l (see mark_cover): the readers
+// are the windows of the edges whose level-(l+1) product is needed, given by
+// `next` (the flags of level l+1; null for l = k-1, whose readers are every
+// non-empty window of the last level). Scratch ref[m+n], diff[m+n+1], bsum
+// and boff [ceil((m+n+1) / 1024)]; need[m] receives the flags.
 hipError_t launch_need_cover(const uint32_t* e_out, const uint32_t* hi, const uint32_t* lo, uint32_t m, uint32_t n,
                              const uint8_t* next, uint8_t* ref, uint32_t* diff, uint32_t* bsum, uint32_t* boff,
                              uint8_t* need, hipStream_t st);
@@ -242,23 +238,23 @@ namespace rs {
 // Device buffers of one plain-path query stream on one graph; they grow to
 // the largest query run through them and stay allocated until release().
 struct PlainWorkspace {
-  DevBuf lo, z, q, p0, p1, partial, agg, incl, fsum, out, ref, need, lastref;
+  DevBuf lo, z, q, p0, p1, partial, agg, incl, fsum, out, ref, need;
   DevBuf lb_stats;  // look-back counters, allocated only while launches are traced
   DevBuf run_pre, run_bsum, run_boff, run_bounds;  // work-balanced runs of the prefix levels
-  DevBuf cov_diff, cov_b;                          // window-cover scratch of the flags
+  DevBuf cov_diff;  // window-cover scratch of the flags: difference array and block sums
   uint32_t epoch = 0;
   uint64_t p_elems_per_chunk = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   uint64_t bytes() const {
     uint64_t t = 0;
-    for (const DevBuf* b : {&lo, &z, &q, &p0, &p1, &partial, &agg, &incl, &fsum, &out, &ref, &need, &lastref,
-                            &lb_stats, &run_pre, &run_bsum, &run_boff, &run_bounds, &cov_diff, &cov_b})
+    for (const DevBuf* b : {&lo, &z, &q, &p0, &p1, &partial, &agg, &incl, &fsum, &out, &ref, &need,
+                            &lb_stats, &run_pre, &run_bsum, &run_boff, &run_bounds, &cov_diff})
       t += b->bytes;
     return t;
   }
   void release() {
-    for (DevBuf* b : {&lo, &z, &q, &p0, &p1, &partial, &agg, &incl, &fsum, &out, &ref, &need, &lastref, &lb_stats,
-                      &run_pre, &run_bsum, &run_boff, &run_bounds, &cov_diff, &cov_b})
+    for (DevBuf* b : {&lo, &z, &q, &p0, &p1, &partial, &agg, &incl, &fsum, &out, &ref, &need, &lb_stats,
+                      &run_pre, &run_bsum, &run_boff, &run_bounds, &cov_diff})
       b->release();
     if (ev0) (void)hipEventDestroy(ev0);
     if (ev1) (void)hipEventDestroy(ev1);
@@ -270,7 +266,7 @@ struct PlainWorkspace {
 // Buffer sizes (bytes) a query needs in a plain workspace (p: each of the two
 // prefix-state arrays; records: each of the two look-back record arrays).
 struct PlainSizes {
-  uint64_t lo, z, q, p, partial, fsum, ref, need, lastref, records;
+  uint64_t lo, z, q, p, partial, fsum, ref, need, cover, records;
   uint64_t total() const;
 };
 PlainSizes plain_sizes(uint64_t m, uint64_t n, const QueryPlan& qp, const Tuning& tu);

@@ -187,29 +187,6 @@ __global__ __launch_bounds__(256) void k_window(const uint32_t* __restrict__ e_s
   lo[e] = a + v;
 }
 
-__global__ __launch_bounds__(256) void k_mark_ref(const uint32_t* __restrict__ hi, const uint32_t* __restrict__ lo,
-                                                  const uint8_t* __restrict__ next, uint32_t m,
-                                                  uint8_t* __restrict__ ref) {
-  const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < m) mark_ref(hi, lo, next, e, ref);
-}
-
-__global__ __launch_bounds__(256) void k_mark_last(const uint32_t* __restrict__ in_off,
-                                                   const uint8_t* __restrict__ ref, uint32_t n,
-                                                   uint32_t* __restrict__ lastref) {
-  const uint32_t u = blockIdx.x * blockDim.x + threadIdx.x;
-  if (u < n) mark_last(in_off, ref, u, lastref);
-}
-
-__global__ __launch_bounds__(256) void k_mark_need(const uint32_t* __restrict__ e_out,
-                                                   const uint32_t* __restrict__ e_dst,
-                                                   const uint8_t* __restrict__ ref,
-                                                   const uint32_t* __restrict__ lastref, uint32_t m,
-                                                   uint8_t* __restrict__ need) {
-  const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < m) mark_need(e_out, e_dst, ref, lastref, e, need);
-}
-
 // q[l-2][e][j] = z_{dst(e),j} * y_{e,l-1} for l = 2..k.
 template <int KQ>
 __global__ __launch_bounds__(256) void k_qtable(const uint32_t* __restrict__ e_src,
@@ -371,25 +348,7 @@ __global__ __launch_bounds__(256) void k_tile_cost(const uint32_t* __restrict__ 
 // Exclusive prefix of the block totals of each level (one block per level).
 __global__ __launch_bounds__(1024) void k_cost_block_offsets(const uint32_t* __restrict__ bsum, uint32_t nb,
                                                              uint32_t* __restrict__ boff) {
-  __shared__ uint32_t part[1024];
-  const uint32_t* bs = bsum + (uint64_t)blockIdx.x * nb;
-  uint32_t* bo = boff + (uint64_t)blockIdx.x * nb;
-  uint32_t carry = 0;
-  for (uint32_t b0 = 0; b0 < nb; b0 += 1024) {
-    const uint32_t b = b0 + threadIdx.x;
-    const uint32_t v = b < nb ? bs[b] : 0u;
-    part[threadIdx.x] = v;
-    __syncthreads();
-    for (uint32_t d = 1; d < 1024; d <<= 1) {
-      const uint32_t u = threadIdx.x >= d ? part[threadIdx.x - d] : 0u;
-      __syncthreads();
-      part[threadIdx.x] += u;
-      __syncthreads();
-    }
-    if (b < nb) bo[b] = carry + part[threadIdx.x] - v;
-    carry += part[1023];
-    __syncthreads();
-  }
+  block_offsets(bsum + (uint64_t)blockIdx.x * nb, nb, boff + (uint64_t)blockIdx.x * nb);
 }
 
 // bounds[w] = first tile of run w: the first tile whose exclusive cost prefix
@@ -465,18 +424,6 @@ hipError_t launch_need_counts(const uint32_t* hi, const uint32_t* lo, const uint
   return hipGetLastError();
 }
 
-hipError_t launch_need(const uint32_t* in_off, const uint32_t* e_dst, const uint32_t* e_out, const uint32_t* hi,
-                       const uint32_t* lo, uint32_t m, uint32_t n, const uint8_t* next, uint8_t* ref,
-                       uint32_t* lastref, uint8_t* need, hipStream_t st) {
-  if (!m) return hipSuccess;
-  hipError_t e = launch_fill32((uint32_t*)ref, 0, ((uint64_t)m + n + 3) / 4, st);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_mark_ref, dim3(div_up(m, 256)), dim3(256), 0, st, hi, lo, next, m, ref);
-  hipLaunchKernelGGL(k_mark_last, dim3(div_up(n, 256)), dim3(256), 0, st, in_off, ref, n, lastref);
-  hipLaunchKernelGGL(k_mark_need, dim3(div_up(m, 256)), dim3(256), 0, st, e_out, e_dst, ref, lastref, m, need);
-  return hipGetLastError();
-}
-
 __global__ __launch_bounds__(256) void k_mark_cover(const uint32_t* __restrict__ hi, const uint32_t* __restrict__ lo,
                                                     const uint8_t* __restrict__ next, uint32_t m,
                                                     uint8_t* __restrict__ ref, uint32_t* __restrict__ diff) {
@@ -484,30 +431,10 @@ __global__ __launch_bounds__(256) void k_mark_cover(const uint32_t* __restrict__
   if (e < m) mark_cover(hi, lo, next, e, ref, diff);
 }
 
-// In-place inclusive prefix (modulo 2^32) within blocks of kCostBlock entries
-// of v[count]; the block totals go to bsum.
+// In-place block-wise inclusive prefix of v[count] (see block_prefix).
 __global__ __launch_bounds__(256) void k_block_prefix(uint32_t* __restrict__ v, uint64_t count,
                                                       uint32_t* __restrict__ bsum) {
-  __shared__ uint32_t part[256];
-  const uint64_t base = (uint64_t)blockIdx.x * kCostBlock + threadIdx.x * 4;
-  uint32_t x[4];
-  uint32_t sum = 0;
-  for (int j = 0; j < 4; ++j) {
-    sum += base + j < count ? v[base + j] : 0u;
-    x[j] = sum;
-  }
-  part[threadIdx.x] = sum;
-  __syncthreads();
-  for (uint32_t d = 1; d < 256; d <<= 1) {
-    const uint32_t u = threadIdx.x >= d ? part[threadIdx.x - d] : 0u;
-    __syncthreads();
-    part[threadIdx.x] += u;
-    __syncthreads();
-  }
-  const uint32_t before = threadIdx.x ? part[threadIdx.x - 1] : 0u;
-  for (int j = 0; j < 4; ++j)
-    if (base + j < count) v[base + j] = before + x[j];
-  if (threadIdx.x == 255) bsum[blockIdx.x] = part[255];
+  block_prefix(v, count, bsum);
 }
 
 __global__ __launch_bounds__(256) void k_mark_need_cover(const uint32_t* __restrict__ e_out,

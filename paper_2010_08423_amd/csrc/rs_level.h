@@ -718,56 +718,75 @@ __device__ __forceinline__ void top_range(const uint32_t* e_src_p, const uint32_
   }
 }
 
-// Store and product flags of a query (they depend on the graph and delta
-// only). First every slot that a non-empty window reads is marked (ref, one
-// byte per slot, zeroed beforehand); then, per vertex, the last marked slot
-// of its segment is found by a backward scan (lastref, 0 if none; edge slots
-// are >= 1). Then need[e] says
+// Store and product flags of a query (they depend on the graph, delta and k).
+// Per prefix level l, for the readers of level l (the windows of level
+// l+1's product edges; every non-empty window when l+1 = k), need[e] says
 //   bit 0: e's own slot is read;
 //   bit 1: the leading slot of the segment e starts is read;
-//   bit 2: some slot at or after e's in its segment is read, i.e. e's product
-//          at a prefix level reaches a value that is read.
-// A prefix level skips the product of an edge without bit 2 (it only reaches
-// slots nothing reads) and stores only slots with bit 0 / bit 1.
-// Marks the two slots of edge e's window, when the window is non-empty and
-// e is one of the readers (next == null: every edge; else edges whose
-// next-level product is needed, bit 2 of next[e]).
-__device__ __forceinline__ void mark_ref(const uint32_t* hi, const uint32_t* lo, const uint8_t* next, uint64_t e,
-                                         uint8_t* ref) {
-  const uint32_t h = hi[e], l = lo[e];
-  if (h != l && (!next || (next[e] & 4u))) {
-    ref[h] = 1;
-    ref[l] = 1;
-  }
-}
-// Vertex u's slots are in_off[u] + u (leading) .. in_off[u+1] + u.
-__device__ __forceinline__ void mark_last(const uint32_t* in_off, const uint8_t* ref, uint32_t u, uint32_t* lastref) {
-  const uint32_t a = in_off[u] + u;
-  uint32_t s = in_off[u + 1] + u;
-  while (s > a && !ref[s]) --s;
-  lastref[u] = ref[s] ? s : 0u;
-}
-__device__ __forceinline__ void mark_need(const uint32_t* e_out, const uint32_t* e_dst, const uint8_t* ref,
-                                          const uint32_t* lastref, uint64_t e, uint8_t* need) {
-  const uint32_t slot = e_out[e];
-  uint32_t f = ref[slot];
-  if (e == 0 || e_out[e - 1] + 1u != slot) f |= (uint32_t)ref[slot - 1] << 1;
-  if (slot <= lastref[e_dst[e]]) f |= 4u;
-  need[e] = (uint8_t)f;
-}
+//   bit 2: e lies inside some reader's window, so its product at level l
+//          enters a window sum (see mark_cover).
+// A prefix level forms the product of an edge only with bit 2 and stores only
+// slots with bit 0 / bit 1.
 
 // Entries per block of the block-wise prefix sums (tile costs, window cover):
 // 256 threads x 4.
 constexpr uint32_t kCostBlock = 1024;
 
-// Product flags by window cover (plain path). A window reads P[hi] ^ P[lo],
+// In-place inclusive prefix (modulo 2^32) of v[count] within blocks of
+// kCostBlock entries (block b of a 256-thread grid); block totals to bsum[b].
+__device__ __forceinline__ void block_prefix(uint32_t* v, uint64_t count, uint32_t* bsum) {
+  __shared__ uint32_t part[256];
+  const uint64_t base = (uint64_t)blockIdx.x * kCostBlock + threadIdx.x * 4;
+  uint32_t x[4];
+  uint32_t sum = 0;
+  for (int j = 0; j < 4; ++j) {
+    sum += base + j < count ? v[base + j] : 0u;
+    x[j] = sum;
+  }
+  part[threadIdx.x] = sum;
+  __syncthreads();
+  for (uint32_t d = 1; d < 256; d <<= 1) {
+    const uint32_t u = threadIdx.x >= d ? part[threadIdx.x - d] : 0u;
+    __syncthreads();
+    part[threadIdx.x] += u;
+    __syncthreads();
+  }
+  const uint32_t before = threadIdx.x ? part[threadIdx.x - 1] : 0u;
+  for (int j = 0; j < 4; ++j)
+    if (base + j < count) v[base + j] = before + x[j];
+  if (threadIdx.x == 255) bsum[blockIdx.x] = part[255];
+}
+
+// Exclusive prefix (modulo 2^32) of bs[nb] into bo, by one 1024-thread block.
+__device__ __forceinline__ void block_offsets(const uint32_t* bs, uint32_t nb, uint32_t* bo) {
+  __shared__ uint32_t part[1024];
+  uint32_t carry = 0;
+  for (uint32_t b0 = 0; b0 < nb; b0 += 1024) {
+    const uint32_t b = b0 + threadIdx.x;
+    const uint32_t v = b < nb ? bs[b] : 0u;
+    part[threadIdx.x] = v;
+    __syncthreads();
+    for (uint32_t d = 1; d < 1024; d <<= 1) {
+      const uint32_t u = threadIdx.x >= d ? part[threadIdx.x - d] : 0u;
+      __syncthreads();
+      part[threadIdx.x] += u;
+      __syncthreads();
+    }
+    if (b < nb) bo[b] = carry + part[threadIdx.x] - v;
+    carry += part[1023];
+    __syncthreads();
+  }
+}
+
+// Product flags by window cover. A window reads P[hi] ^ P[lo],
 // the XOR of the level values of the edges with slots in (lo, hi]; a value
 // before lo enters both prefixes and cancels. So an edge's product is needed
 // only when its slot lies in the window of some reader, and leaving out every
 // other product leaves every window sum unchanged. Each reader adds +1 at
 // slot lo + 1 and -1 at slot hi + 1 of a difference array (windows never
 // leave their segment); its prefix sum at e's slot counts the readers whose
-// window covers e. The read slots are marked in ref as for mark_ref.
+// window covers e. The two slots a reader reads are marked in ref (one byte
+// per slot, zeroed beforehand).
 __device__ __forceinline__ void mark_cover(const uint32_t* hi, const uint32_t* lo, const uint8_t* next, uint64_t e,
                                            uint8_t* ref, uint32_t* diff) {
   const uint32_t h = hi[e], l = lo[e];
@@ -778,7 +797,7 @@ __device__ __forceinline__ void mark_cover(const uint32_t* hi, const uint32_t* l
     atomicAdd(&diff[h + 1], ~0u);  // -1 modulo 2^32
   }
 }
-// need[e]: bits 0 and 1 as in mark_need; bit 2 when e's slot is covered, with
+// need[e]: bits 0 and 1 as above; bit 2 when e's slot is covered, with
 // cover(s) = pre[s] + boff[s / kCostBlock] (modulo 2^32) the prefix sum of
 // the difference array.
 __device__ __forceinline__ void mark_need_cover(const uint32_t* e_out, const uint8_t* ref, const uint32_t* pre,

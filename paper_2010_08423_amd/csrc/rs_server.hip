@@ -107,7 +107,7 @@ static bool is_small(const rs_server* S, const SQuery& a) {
 static uint64_t growth(const PlainWorkspace& w, const PlainSizes& z) {
   auto g = [](const DevBuf& b, uint64_t need) { return need > b.bytes ? need - b.bytes : 0; };
   return g(w.lo, z.lo) + g(w.z, z.z) + g(w.q, z.q) + g(w.p0, z.p) + g(w.p1, z.p) + g(w.partial, z.partial) +
-         g(w.fsum, z.fsum) + g(w.out, 64) + g(w.ref, z.ref) + g(w.need, z.need) + g(w.lastref, z.lastref) +
+         g(w.fsum, z.fsum) + g(w.out, 64) + g(w.ref, z.ref) + g(w.need, z.need) + g(w.cov_diff, z.cover) +
          g(w.agg, z.records) + g(w.incl, z.records);
 }
 
