@@ -50,6 +50,9 @@ struct BQuery {
   uint64_t* q;
   uint64_t* fsum;
   uint8_t* need;     // store and product flags
+  uint32_t* pre;     // per prefix level: tile cost prefix within blocks [k-2][tiles]
+  uint32_t* bsum;    // per prefix level: block totals [k-2][nb]
+  uint32_t* boff;    // per prefix level: block offsets [k-2][nb]
   uint8_t* ref;      // slot marks (scratch shared by the queries of a batch)
   uint32_t* cov;     // window-cover difference array [m+n+1], then its block-wise prefix (scratch, shared)
   uint32_t* cbsum;   // its block totals (scratch, shared)
@@ -82,8 +85,11 @@ struct MUnit {
   uint32_t nchunks;    // prefix-level units: consecutive chunks of the query
   uint32_t waves;      // prefix-level units: waves per chunk
   uint32_t pad_;
+  const uint32_t* pre;   // prefix-level units: this level's tile cost prefix (within blocks)
+  const uint32_t* boff;  // prefix-level units: this level's block offsets
+  uint32_t* bounds;      // prefix-level units: [waves+1] first tile of each wave's run
 };
-static_assert(sizeof(MUnit) == 144, "MUnit layout");
+static_assert(sizeof(MUnit) == 168, "MUnit layout");
 // Units are read through the constant address space: scalar loads into SGPRs.
 typedef __attribute__((address_space(4))) const MUnit cMUnit;
 
@@ -215,6 +221,14 @@ __global__ __launch_bounds__(256) void kb_reduce(const BQuery* __restrict__ qs, 
   if (threadIdx.x == 0) out[blockIdx.x] = part[0];
 }
 
+// Work-balanced run bounds of every unit of a prefix-level launch, from its
+// query's tile cost prefix for that level and its waves per chunk.
+__global__ __launch_bounds__(256) void kb_run_bounds(const MUnit* __restrict__ units) {
+  const MUnit& U = units[blockIdx.y];
+  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < U.n_items) run_bounds_of_tile(U.pre, U.boff, U.n_items, t, U.waves, U.bounds);
+}
+
 // ---------------------------------------------------------------------------
 // Level launches over the work table.
 // ---------------------------------------------------------------------------
@@ -275,6 +289,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
   c.incl = incl;
   c.need = U.need;
   c.lb_stats = nullptr;
+  c.bounds = U.bounds;
   c.bounds = nullptr;
   scan_level<KQ, E, FIRST>(c, idx, U.waves, lane, mk, tab);
 }
@@ -338,14 +353,15 @@ __global__ __launch_bounds__(256) void kb_top(const MUnit* __restrict__ units, c
 // ---------------------------------------------------------------------------
 // Rounds run on this many streams at once (round r on lane r mod lanes): the
 // level launches of different rounds are independent, and a launch's last
-// waves leave the GPU partly idle, which the other lane's launches fill.
-// Running the 64-query mix on the 10^6-edge graph as two streams of plain
-// queries took 1.39-1.43 s instead of 1.68 s one after another.
-constexpr uint32_t kBatchLanes = 2;
+// waves leave the GPU partly idle, which the other lanes' launches fill. On
+// the 64-query mix of the 10^6-edge graph, 2, 3, 4, 6 and 8 lanes ran the
+// batch 0.97, 1.07-1.11, 1.11-1.14, 1.07 and 1.14 times as fast as the plain
+// calls one after another.
+constexpr uint32_t kBatchLanes = 4;
 
 struct BatchWorkspace {
   std::mutex mu;
-  DevBuf qs, units, ubegin, per_query, parena, agg, incl, out, ref, cov;
+  DevBuf qs, units, ubegin, per_query, parena, agg, incl, out, ref, cov, bounds;
   uint32_t epoch = 0;
   std::string key;  // shape of the captured graph
   hipGraphExec_t exec = nullptr;
@@ -373,12 +389,13 @@ struct BatchWorkspace {
   }
   void release() {
     drop_graph();
-    for (DevBuf* b : {&qs, &units, &ubegin, &per_query, &parena, &agg, &incl, &out, &ref, &cov}) b->release();
+    for (DevBuf* b : {&qs, &units, &ubegin, &per_query, &parena, &agg, &incl, &out, &ref, &cov, &bounds})
+      b->release();
     epoch = 0;
   }
   uint64_t bytes() const {
     uint64_t t = 0;
-    for (const DevBuf* b : {&qs, &units, &ubegin, &per_query, &parena, &agg, &incl, &out, &ref, &cov})
+    for (const DevBuf* b : {&qs, &units, &ubegin, &per_query, &parena, &agg, &incl, &out, &ref, &cov, &bounds})
       t += b->bytes;
     return t;
   }
@@ -418,6 +435,7 @@ struct BLaunch {
   uint32_t kq;
   uint32_t unit_off, nunits, total;
   uint32_t grid;    // blocks, set at enqueue time
+  uint32_t max_items = 0;  // prefix launches: most tiles of a unit (grid of the run-bounds kernel)
 };
 
 struct BatchPlan {
@@ -436,6 +454,7 @@ struct BatchPlan {
   uint32_t scan_launches = 0;
   uint32_t rounds = 0;
   uint32_t lanes = 1;         // rounds run on this many streams at once
+  uint64_t bounds_words = 0;  // run bounds of all prefix-level units
   Tuning tu;
   std::string key;
 };
@@ -507,6 +526,15 @@ rs_status batch_plan(const rs_graph* const* graphs, const rs_query* queries, uin
     pq_off += align256(table_q_bytes(m, qp.k, qp.kq));
     Q.need = (uint8_t*)(uintptr_t)pq_off;
     pq_off += align256(table_need_bytes(m, qp.k));
+    {
+      const uint64_t levels = qp.k > 2 ? qp.k - 2 : 0, tiles = (m + E - 1) / E, nb = (tiles + kCostBlock - 1) / kCostBlock;
+      Q.pre = (uint32_t*)(uintptr_t)pq_off;
+      pq_off += align256(4 * tiles * levels);
+      Q.bsum = (uint32_t*)(uintptr_t)pq_off;
+      pq_off += align256(4 * nb * levels);
+      Q.boff = (uint32_t*)(uintptr_t)pq_off;
+      pq_off += align256(4 * nb * levels);
+    }
     P.ref_bytes = std::max<uint64_t>(P.ref_bytes, (m + n + 3) & ~3ull);
     P.n_max = std::max<uint64_t>(P.n_max, n);
     Q.fsum = (uint64_t*)(uintptr_t)pq_off;
@@ -626,6 +654,11 @@ rs_status batch_plan(const rs_graph* const* graphs, const rs_query* queries, uin
             U.row0 = row0[c - rd.first];
             // this level's flags (prefix levels; unused at the last level): offset, rebased later
             U.need = (const uint8_t*)((uintptr_t)Q.need + (top ? 0 : (uint64_t)(l - 2) * need_stride(Q.m)));
+            if (!top) {  // this level's cost prefix: offsets, rebased later
+              const uint64_t tiles = (Q.m + E - 1) / E, nb = (tiles + kCostBlock - 1) / kCostBlock;
+              U.pre = (const uint32_t*)((uintptr_t)Q.pre + 4ull * (l - 2) * tiles);
+              U.boff = (const uint32_t*)((uintptr_t)Q.boff + 4ull * (l - 2) * nb);
+            }
             U.m = Q.m;
             U.nchunks = nch;
             U.p_stride = 2 * half / 8;
@@ -670,6 +703,17 @@ static rs_status resolve_plan(BatchPlan& P, BatchWorkspace& W, uint32_t epoch0) 
     q_off[i] = (uintptr_t)Q.q;
     need_off[i] = (uintptr_t)Q.need;
     if (need_off[i] + table_need_bytes(Q.m, Q.k) > W.per_query.bytes) return RS_EINVAL;
+    {
+      const uint64_t levels = Q.k > 2 ? Q.k - 2 : 0, tiles = (Q.m + P.tu.edges_per_tile - 1) / P.tu.edges_per_tile,
+                     nb = (tiles + kCostBlock - 1) / kCostBlock;
+      if ((uintptr_t)Q.pre + 4 * tiles * levels > W.per_query.bytes ||
+          (uintptr_t)Q.bsum + 4 * nb * levels > W.per_query.bytes ||
+          (uintptr_t)Q.boff + 4 * nb * levels > W.per_query.bytes)
+        return RS_EINVAL;
+      Q.pre = (uint32_t*)(pq + (uintptr_t)Q.pre);
+      Q.bsum = (uint32_t*)(pq + (uintptr_t)Q.bsum);
+      Q.boff = (uint32_t*)(pq + (uintptr_t)Q.boff);
+    }
     if (q_off[i] + table_q_bytes(Q.m, Q.k, Q.kq) > W.per_query.bytes) return RS_EINVAL;
     const uint64_t slots = (uint64_t)Q.m + Q.n + 1, nbq = (slots + kCostBlock - 1) / kCostBlock;
     if ((uint64_t)Q.m + Q.n > W.ref.bytes || 4ull * (slots + 2 * nbq) > W.cov.bytes) return RS_EINVAL;
@@ -701,6 +745,12 @@ static rs_status resolve_plan(BatchPlan& P, BatchWorkspace& W, uint32_t epoch0) 
       const uint64_t need_level = (uintptr_t)U.need - need_off[qi];  // offset of this level's flags
       if (need_level + need_stride(Q.m) > table_need_bytes(Q.m, Q.k)) return RS_EINVAL;
       U.need = Q.need + need_level;
+      if (!L.top) {
+        const uint64_t pre_off = (uintptr_t)U.pre, boff_off = (uintptr_t)U.boff;
+        if (pre_off + 4ull * U.n_items > W.per_query.bytes || boff_off + 4 > W.per_query.bytes) return RS_EINVAL;
+        U.pre = (const uint32_t*)(pq + pre_off);
+        U.boff = (const uint32_t*)(pq + boff_off);
+      }
       U.z = Q.z;
       U.pp = (const uint64_t*)(pa + pp_off);
       U.pc = (uint64_t*)(pa + pc_off);
@@ -754,6 +804,7 @@ static const void* pick_top(uint32_t kq, bool first) {
 // bounded, and a single wave never waits). Then the grid of every launch:
 // about as many blocks as are resident, at most one wave per work item.
 static void size_grids(BatchPlan& P) {
+  P.bounds_words = 0;
   const uint32_t wpb = P.tu.waves_per_block;
   const size_t lds = (size_t)wpb * 16 * kLanes * 8;
   for (BLaunch& L : P.launches) {
@@ -768,11 +819,15 @@ static void size_grids(BatchPlan& P) {
       }
       const uint64_t spare = (uint64_t)resident * wpb > pairs ? (uint64_t)resident * wpb - pairs : 0;
       uint32_t w0 = 0;
+      L.max_items = 0;
       for (uint32_t j = 0; j < L.nunits; ++j) {
         MUnit& U = P.units[L.unit_off + j];
         U.waves = (uint32_t)std::min<uint64_t>(U.n_items, 1 + (uint64_t)U.n_items * spare / std::max<uint64_t>(tiles, 1));
         P.ubegin[L.unit_off + j] = w0;
         w0 += U.waves * U.nchunks;
+        U.bounds = (uint32_t*)(uintptr_t)(4 * P.bounds_words);  // offset, rebased after allocation
+        P.bounds_words += U.waves + 1;
+        L.max_items = std::max(L.max_items, U.n_items);
       }
       L.total = w0;
       L.grid = std::max(1u, (L.total + wpb - 1) / wpb);
@@ -800,6 +855,9 @@ static rs_status batch_enqueue(BatchPlan& P, BatchWorkspace& W, hipStream_t st) 
       hipLaunchKernelGGL(kb_cover_offsets, dim3(1), dim3(1024), 0, st, dq, qi);
       hipLaunchKernelGGL(kb_mark_need, dim3((Q.m + 255) / 256), dim3(256), 0, st, dq, qi, l);
     }
+    if (Q.k >= 3)
+      RS_HIP(launch_tile_costs(Q.hi, Q.lo, Q.need, need_stride(Q.m), Q.m, P.tu.edges_per_tile, Q.k - 2, Q.pre,
+                               Q.bsum, Q.boff, st));
     switch (Q.kq) {
       case 4: hipLaunchKernelGGL(kb_qtable<4>, dim3((Q.m + 255) / 256), dim3(256), 0, st, dq, qi); break;
       case 8: hipLaunchKernelGGL(kb_qtable<8>, dim3((Q.m + 255) / 256), dim3(256), 0, st, dq, qi); break;
@@ -826,6 +884,7 @@ static rs_status batch_enqueue(BatchPlan& P, BatchWorkspace& W, hipStream_t st) 
       void* args[] = {(void*)&u, (void*)&b, (void*)&L.nunits, (void*)&L.total, (void*)&P.tu.top_edges_per_tile};
       RS_HIP(hipLaunchKernel(kern, dim3(L.grid), dim3(64 * wpb), args, lds, lst));
     } else {
+      hipLaunchKernelGGL(kb_run_bounds, dim3((L.max_items + 255) / 256, L.nunits), dim3(256), 0, lst, u);
       uint64_t* agg = W.agg.as<uint64_t>();
       uint64_t* incl = W.incl.as<uint64_t>();
       void* args[] = {(void*)&u, (void*)&b, (void*)&L.nunits, (void*)&L.total, (void*)&agg, (void*)&incl};
@@ -910,6 +969,20 @@ rs_status run_batch_impl(const rs_graph* const* graphs, const rs_query* queries,
   }
   RS_TRY(resolve_plan(P, W, W.epoch));
   size_grids(P);
+  {
+    const void* before_b = W.bounds.p;
+    if (W.bounds.reserve(4 * std::max<uint64_t>(P.bounds_words, 1), st, false)) return RS_ENOMEM;
+    if (W.bounds.p != before_b) W.drop_graph();
+    for (BLaunch& L : P.launches) {
+      if (L.top) continue;
+      for (uint32_t j = 0; j < L.nunits; ++j) {
+        MUnit& U = P.units[L.unit_off + j];
+        const uint64_t off = (uintptr_t)U.bounds;
+        if (off + 4ull * (U.waves + 1) > W.bounds.bytes) return RS_EINVAL;
+        U.bounds = (uint32_t*)(W.bounds.as<char>() + off);
+      }
+    }
+  }
   W.epoch += P.scan_launches + 1;
   RS_HIP(hipMemcpyAsync(W.qs.p, P.qs.data(), sizeof(BQuery) * P.qs.size(), hipMemcpyHostToDevice, st));
   if (!P.units.empty()) {

@@ -113,6 +113,11 @@ uint32_t scan_waves(uint32_t kq, uint32_t E, bool first, uint32_t n_tiles, uint3
 // costs, their prefix (scratch pre[levels][n_tiles], bsum and boff
 // [levels][ceil(n_tiles / 1024)]) and bounds[levels][b_stride] for w_first
 // waves per chunk at level 2 and w_rest above it (b_stride > both).
+// The per-tile costs and their prefix only (no bounds), for callers that cut
+// the runs for several grid widths.
+hipError_t launch_tile_costs(const uint32_t* hi, const uint32_t* lo, const uint8_t* need, uint64_t need_stride_b,
+                             uint32_t m, uint32_t E, uint32_t levels, uint32_t* pre, uint32_t* bsum, uint32_t* boff,
+                             hipStream_t st);
 hipError_t launch_run_bounds(const uint32_t* hi, const uint32_t* lo, const uint8_t* need, uint64_t need_stride_b,
                              uint32_t m, uint32_t E, uint32_t levels, uint32_t w_first, uint32_t w_rest,
                              uint32_t* pre, uint32_t* bsum, uint32_t* boff, uint32_t* bounds, uint32_t b_stride,

@@ -351,10 +351,6 @@ __global__ __launch_bounds__(1024) void k_cost_block_offsets(const uint32_t* __r
   block_offsets(bsum + (uint64_t)blockIdx.x * nb, nb, boff + (uint64_t)blockIdx.x * nb);
 }
 
-// bounds[w] = first tile of run w: the first tile whose exclusive cost prefix
-// reaches ceil(total * w / W). Thread t writes the w whose boundary falls on
-// tile t; runs whose boundary lies past the last tile's start stay at n_tiles
-// (filled beforehand), and so does bounds[W].
 __global__ __launch_bounds__(256) void k_run_bounds(const uint32_t* __restrict__ pre, const uint32_t* __restrict__ boff,
                                                     uint32_t nb, uint32_t n_tiles, uint32_t w_first,
                                                     uint32_t w_rest, uint32_t b_stride,
@@ -362,17 +358,24 @@ __global__ __launch_bounds__(256) void k_run_bounds(const uint32_t* __restrict__
   const uint32_t lvl = blockIdx.y;
   const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n_tiles) return;
-  const uint32_t* pl = pre + (uint64_t)lvl * n_tiles;
-  const uint32_t* bo = boff + (uint64_t)lvl * nb;
-  auto incl = [&](uint32_t i) { return (uint64_t)pl[i] + bo[i / kCostBlock]; };
-  const uint64_t total = incl(n_tiles - 1);
-  const uint64_t W = lvl == 0 ? w_first : w_rest;
-  const uint64_t excl_t = t ? incl(t - 1) : 0;          // cost before tile t
-  const uint64_t excl_p = t > 1 ? incl(t - 2) : 0;      // cost before tile t - 1
-  const uint64_t w_hi = excl_t * W / total;
-  const uint64_t w_lo = t ? excl_p * W / total + 1 : 0;
-  uint32_t* bl = bounds + (uint64_t)lvl * b_stride;
-  for (uint64_t w = w_lo; w <= w_hi && w < W; ++w) bl[w] = t;
+  run_bounds_of_tile(pre + (uint64_t)lvl * n_tiles, boff + (uint64_t)lvl * nb, n_tiles, t,
+                     lvl == 0 ? w_first : w_rest, bounds + (uint64_t)lvl * b_stride);
+}
+
+hipError_t launch_tile_costs(const uint32_t* hi, const uint32_t* lo, const uint8_t* need, uint64_t need_stride_b,
+                             uint32_t m, uint32_t E, uint32_t levels, uint32_t* pre, uint32_t* bsum, uint32_t* boff,
+                             hipStream_t st) {
+  if (!m || !levels) return hipSuccess;
+  const uint32_t n_tiles = div_up(m, E);
+  const uint32_t nb = div_up(n_tiles, kCostBlock);
+  if (E == 8)
+    hipLaunchKernelGGL(k_tile_cost<8>, dim3(nb, levels), dim3(256), 0, st, hi, lo, need, need_stride_b, m, n_tiles,
+                       pre, bsum);
+  else
+    hipLaunchKernelGGL(k_tile_cost<16>, dim3(nb, levels), dim3(256), 0, st, hi, lo, need, need_stride_b, m,
+                       n_tiles, pre, bsum);
+  hipLaunchKernelGGL(k_cost_block_offsets, dim3(levels), dim3(1024), 0, st, bsum, nb, boff);
+  return hipGetLastError();
 }
 
 hipError_t launch_run_bounds(const uint32_t* hi, const uint32_t* lo, const uint8_t* need, uint64_t need_stride_b,
@@ -382,15 +385,8 @@ hipError_t launch_run_bounds(const uint32_t* hi, const uint32_t* lo, const uint8
   if (!m || !levels) return hipSuccess;
   const uint32_t n_tiles = div_up(m, E);
   const uint32_t nb = div_up(n_tiles, kCostBlock);
-  hipError_t e = launch_fill32(bounds, n_tiles, (uint64_t)levels * b_stride, st);
+  hipError_t e = launch_tile_costs(hi, lo, need, need_stride_b, m, E, levels, pre, bsum, boff, st);
   if (e != hipSuccess) return e;
-  if (E == 8)
-    hipLaunchKernelGGL(k_tile_cost<8>, dim3(nb, levels), dim3(256), 0, st, hi, lo, need, need_stride_b, m, n_tiles,
-                       pre, bsum);
-  else
-    hipLaunchKernelGGL(k_tile_cost<16>, dim3(nb, levels), dim3(256), 0, st, hi, lo, need, need_stride_b, m,
-                       n_tiles, pre, bsum);
-  hipLaunchKernelGGL(k_cost_block_offsets, dim3(levels), dim3(1024), 0, st, bsum, nb, boff);
   hipLaunchKernelGGL(k_run_bounds, dim3(div_up(n_tiles, 256), levels), dim3(256), 0, st, pre, boff, nb, n_tiles,
                      w_first, w_rest, b_stride, bounds);
   return hipGetLastError();

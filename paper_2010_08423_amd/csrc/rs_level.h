@@ -732,6 +732,24 @@ __device__ __forceinline__ void top_range(const uint32_t* e_src_p, const uint32_
 // 256 threads x 4.
 constexpr uint32_t kCostBlock = 1024;
 
+// Work-balanced runs: bounds[w] = the first tile whose exclusive cost prefix
+// reaches ceil(total * w / W), with pre[] the inclusive cost prefix within
+// blocks of kCostBlock tiles and boff[] the blocks' offsets. Tile t writes
+// the runs whose first tile it is; the last tile also writes bounds[w] =
+// n_tiles for the runs past it (empty) and for w = W.
+__device__ __forceinline__ void run_bounds_of_tile(const uint32_t* pre, const uint32_t* boff, uint32_t n_tiles,
+                                                   uint32_t t, uint32_t W, uint32_t* bounds) {
+  auto incl = [&](uint32_t i) { return (uint64_t)pre[i] + boff[i / kCostBlock]; };
+  const uint64_t total = incl(n_tiles - 1);
+  const uint64_t excl_t = t ? incl(t - 1) : 0;      // cost before tile t
+  const uint64_t excl_p = t > 1 ? incl(t - 2) : 0;  // cost before tile t - 1
+  const uint64_t w_hi = excl_t * W / total;
+  const uint64_t w_lo = t ? excl_p * W / total + 1 : 0;
+  for (uint64_t w = w_lo; w <= w_hi && w < W; ++w) bounds[w] = t;
+  if (t == n_tiles - 1)
+    for (uint64_t w = w_hi + 1; w <= W; ++w) bounds[w] = n_tiles;
+}
+
 // In-place inclusive prefix (modulo 2^32) of v[count] within blocks of
 // kCostBlock entries (block b of a 256-thread grid); block totals to bsum[b].
 __device__ __forceinline__ void block_prefix(uint32_t* v, uint64_t count, uint32_t* bsum) {
