@@ -198,6 +198,15 @@ rs_status rs_run_batch(const rs_graph* const* graphs, const rs_query* queries, u
  * calls. */
 rs_status rs_autotune(const rs_graph* g, const rs_query* sample, uint32_t ns, rs_tuning* out);
 
+/* Batched path only: times candidate batched launch shapes (edges per tile,
+ * waves per block, last-level range) on the sample run as one batch, caches
+ * the fastest on g for later rs_run_batch calls with tune == NULL whose first
+ * graph is g, and returns it in *out (may be NULL). Use a sample shaped like
+ * the batches to come (several rounds of chunks exercise the stream lanes);
+ * the plain-path choices of rs_autotune are kept. RS_EINVAL for an invalid
+ * query or ns == 0. */
+rs_status rs_autotune_batch(const rs_graph* g, const rs_query* sample, uint32_t ns, rs_tuning* out);
+
 /* ------------------------------------------------------------------------
  * Kernel timing (hipEvents recorded around the launches of each kernel
  * class on the launch stream while enabled). Classes: "level_scan" (prefix

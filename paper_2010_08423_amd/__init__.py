@@ -100,6 +100,8 @@ _SIGNATURES = {
                                       ctypes.POINTER(_Result), ctypes.POINTER(_Tuning), ctypes.c_void_p]),
     "rs_autotune": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(_Query), ctypes.c_uint32,
                                      ctypes.POINTER(_Tuning)]),
+    "rs_autotune_batch": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(_Query), ctypes.c_uint32,
+                                           ctypes.POINTER(_Tuning)]),
     "rs_profile_enable": (ctypes.c_int32, [ctypes.c_int]),
     "rs_trace_enable": (ctypes.c_int32, [ctypes.c_int]),
     "rs_profile_reset": (ctypes.c_int32, []),
@@ -323,6 +325,21 @@ def run_batch(graphs, queries, tuning: Tuning | None = None, stream=None):
     del keep
     out = [Result(rs[i].fingerprint, bool(rs[i].yes), rs[i].status, rs[i].device_ms) for i in range(nq)]
     return out, s
+
+
+def autotune_batch(graph: Graph, sample_queries) -> Tuning:
+    """rs_autotune_batch: the batched launch shape only, timed on the sample as one batch."""
+    ns = len(sample_queries)
+    qs = (_Query * max(ns, 1))()
+    keep = []
+    for i, q in enumerate(sample_queries):
+        qs[i], mk = query_struct(q)
+        keep.append(mk)
+    out = _Tuning()
+    _check(_load().rs_autotune_batch(graph.handle, qs, ns, ctypes.byref(out)), "rs_autotune_batch")
+    del keep
+    return Tuning(out.edges_per_tile, out.top_edges_per_tile, out.chunks_per_launch, out.waves_per_block,
+                  out.max_slots, out.no_graph)
 
 
 def autotune(graph: Graph, sample_queries) -> Tuning:

@@ -56,7 +56,11 @@ def run_batch_mode(args):
     sample = [dataclasses.replace(q, it_begin=0, it_end=min(256, 1 << q.k)) for q in by_k.values()]
     _log("autotuning on", [(q.k, q.delta, q.it_end) for q in sample])
     t0 = time.perf_counter()
-    tuned = R.autotune(gd, sample)
+    R.autotune(gd, sample)
+    # the batched shape on a batch like the real one: every query of the mix,
+    # each cut to its first two chunks (many rounds, so the stream lanes overlap)
+    bsample = [dataclasses.replace(q, it_begin=0, it_end=min(128, 1 << q.k)) for q in qs]
+    tuned = R.autotune_batch(gd, bsample)
     tune_s = time.perf_counter() - t0
     # plain reference: one query at a time
     _log("plain: 64 queries one at a time")

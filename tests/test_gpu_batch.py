@@ -180,6 +180,11 @@ def test_autotune_keeps_results():
     after = [plain(gd, q) for q in qs]
     assert after == before
     check_batch([g], [gd], qs, [0] * len(qs), None, "after autotune")
+    say("[batch] autotune batched shape only")
+    tb = R.autotune_batch(gd, qs)
+    assert tb.edges_per_tile in (8, 16) and tb.waves_per_block in (1, 2, 4)
+    assert [plain(gd, q) for q in qs] == before
+    check_batch([g], [gd], qs, [0] * len(qs), None, "after batched autotune")
 
 
 def test_batch_more_chunk_pairs_than_waves():
