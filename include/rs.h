@@ -180,9 +180,11 @@ rs_status rs_run_ex(const rs_graph* g, const rs_query* q, const rs_tuning* tune,
 
 /* Batched path: nq queries, each on its own graph (graphs[i]; graphs may
  * repeat), evaluated together. Every (query, 64-iteration chunk) is a unit
- * with its own prefix-state buffers; units are packed into rounds that fit
- * the HBM budget (a third of free device memory, or max_slots units), and a
- * round runs level l of all its units in shared launches (one per product-row
+ * with its own prefix-state buffers; units are packed into rounds, and four
+ * stream lanes run one round each at a time. A round holds at most max_slots
+ * units and at most a quarter of the HBM budget (a third of free device
+ * memory) in prefix state, and never more than 20 GiB, so the lanes together
+ * stay within the budget. A round runs level l of all its units in shared launches (one per product-row
  * width), each walking a device table of unit descriptors. The launch
  * sequence is captured once per batch shape into a hipGraph and replayed with
  * new descriptors (tune->no_graph = 1 enqueues it directly).

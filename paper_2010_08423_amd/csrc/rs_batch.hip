@@ -906,14 +906,15 @@ static uint64_t default_slot_budget() {
   return (uint64_t)(free_b / 3);
 }
 
-// At most this many bytes of prefix state and records per round. The level
-// launches gather prefix rows at random over the whole round, and rounds
-// larger than a plain launch's four chunks of a 10^6-edge graph ran slower
-// per chunk (64 mixed queries on that graph: 1.71 s with 4 chunks per round,
-// 1.88 s with 8, 2.14 s unbounded); small graphs still pack hundreds of
-// chunks into a round.
-constexpr uint64_t kRoundStateBytes = 5ull << 30;
+// At most this many bytes of prefix state per round. On 64 mixed queries of
+// the 10^6-edge graph, rounds of at most 5, 10 and 20 GiB ran the batch in
+// 0.887, 0.879 and 0.854 s (four lanes). (Under the earlier per-tile
+// look-back and equal runs, larger rounds had run slower: 1.71 s with 4
+// chunks per round against 2.14 s unbounded.)
+constexpr uint64_t kRoundStateBytes = 20ull << 30;
 
+// slot_budget: bytes of prefix state the call may hold over all its stream
+// lanes (0 = a third of free device memory).
 rs_status run_batch_impl(const rs_graph* const* graphs, const rs_query* queries, uint32_t nq, rs_result* results,
                          const rs_tuning* tune, hipStream_t st, bool use_graph, uint64_t slot_budget,
                          BatchWorkspace* ws) {
@@ -936,9 +937,10 @@ rs_status run_batch_impl(const rs_graph* const* graphs, const rs_query* queries,
   if (tu.waves_per_block != 1 && tu.waves_per_block != 2 && tu.waves_per_block != 4) tu.waves_per_block = 2;
   tu.top_edges_per_tile = std::min(std::max(tu.top_edges_per_tile, 1u), 4096u);
   BatchPlan P;
-  RS_TRY(batch_plan(graphs, queries, nq, tu,
-                    std::min<uint64_t>(slot_budget ? slot_budget : default_slot_budget(), kRoundStateBytes), results,
-                    P));
+  // the lanes hold one round each at a time, so a round gets a lane's share
+  // of the budget and the whole prefix arena stays within it
+  const uint64_t budget = slot_budget ? slot_budget : default_slot_budget();
+  RS_TRY(batch_plan(graphs, queries, nq, tu, std::min<uint64_t>(budget / kBatchLanes, kRoundStateBytes), results, P));
   rs_status first_err = RS_OK;
   for (uint32_t i = 0; i < nq; ++i)
     if (results[i].status != RS_OK && first_err == RS_OK) first_err = results[i].status;
