@@ -63,7 +63,7 @@ constexpr uint32_t kFlagIncl = 2;  // record: full prefix of that segment
 
 struct Tuning {
   uint32_t edges_per_tile = 16;      // scan levels: 8 or 16
-  uint32_t top_edges_per_tile = 8;   // last level
+  uint32_t top_edges_per_tile = 64;  // last level: edges per wave's range
   uint32_t chunks_per_launch = 4;
   uint32_t waves_per_block = 2;
   uint32_t max_slots = 0;  // batched path; 0 = as many as fit

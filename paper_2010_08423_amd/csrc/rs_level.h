@@ -664,28 +664,42 @@ __device__ __forceinline__ void scan_level(const TileCtx& c, uint32_t w, uint32_
 }
 
 // Last level k over edges [e0, e1): unreduced per-lane sum of c_k(e) into r.
-// Edges go in batches of 8: one scalar load per index array and batch, and
-// the next batch's gathers and rows in flight during this batch's products;
-// empty windows gather the zero row and skip their product.
+// Edges go in batches of 8: one scalar load per index array and batch. Two
+// batches alternate, so the next batch's gathers and rows are in flight
+// during this batch's products; the two rows of a window stay apart until
+// the product, so no load waits for its partner. Empty windows gather the
+// zero row and skip their product. (On the 10^6-edge graph at k = 8 this
+// ran the last level in 0.519 ms against 0.550 ms for one batch at a time,
+// with 64 edges per wave's range.)
 template <int KQ, bool FIRST>
 __device__ __forceinline__ void top_range(const uint32_t* e_src_p, const uint32_t* hi_p,
                                           const uint32_t* lo_p, const uint64_t* q_p,
                                           const uint64_t* z_p, const uint64_t* pp, uint64_t cb,
                                           uint32_t e0, uint32_t e1, uint32_t lane,
                                           const uint32_t (&mk)[6], uint64_t* tab, Acc128& r) {
+  if (e0 >= e1) return;
   const uint32_t base = lds_addr(tab);
   constexpr int B = 8;
+  constexpr int P = RowBlock<KQ, B>::P;
   const uint64_t* zero = kZeroRow + lane;
   struct Batch {
-    uint64_t w[B];
+    uint64_t wh[B], wl[B];
     IdxN<B> live;
     RowBlock<KQ, B> qr, zr;
   };
-  Batch cur, nxt;
+  // Every load is issued whatever the batch holds (edges at or past e1 read
+  // the zero row, and their product rows are clamped to edge e1 - 1), so the
+  // number of loads in flight is fixed and a batch's products wait only for
+  // that batch's loads while the next batch's are in flight.
   auto gather = [&](uint32_t eb, Batch& b) {
-    load_qrows<KQ, B>(b.qr, q_p, eb, lane);
+    {
+      const uint32_t g = min(lane * P, (uint32_t)(B * KQ - P));
+      const uint32_t ei = min(eb + g / KQ, e1 - 1);
+#pragma unroll
+      for (int p = 0; p < P; ++p) b.qr.v[p] = *(gu64*)(q_p + (uint64_t)ei * KQ + g % KQ + p);
+    }
     if (FIRST) {
-      load_zrows<KQ, B>(b.zr, z_p, e_src_p, eb, e1 - eb, lane);
+      load_zrows<KQ, B>(b.zr, z_p, e_src_p, eb, e1 - min(eb, e1), lane);
 #pragma unroll
       for (int i = 0; i < B; ++i) b.live.v[i] = eb + (uint32_t)i < e1;
     } else {
@@ -693,28 +707,33 @@ __device__ __forceinline__ void top_range(const uint32_t* e_src_p, const uint32_
       const IdxN<B> l = load_idx<B>(lo_p + eb);
 #pragma unroll
       for (int i = 0; i < B; ++i) {
-        // levels >= 3: an empty window (hi == lo) contributes exactly zero
         const bool live = eb + (uint32_t)i < e1 && h.v[i] != l.v[i];
-        const uint64_t* pa = live ? pp + (uint64_t)h.v[i] * kLanes + lane : zero;
-        const uint64_t* pb = live ? pp + (uint64_t)l.v[i] * kLanes + lane : zero;
-        b.w[i] = p_load(pa) ^ p_load(pb);
+        b.wh[i] = p_load(live ? pp + (uint64_t)h.v[i] * kLanes + lane : zero);
+        b.wl[i] = p_load(live ? pp + (uint64_t)l.v[i] * kLanes + lane : zero);
         b.live.v[i] = live;
       }
     }
   };
-  if (e0 < e1) gather(e0, cur);
-  for (uint32_t eb = e0; eb < e1; eb += B) {
-    if (eb + B < e1) gather(eb + B, nxt);
+  auto compute = [&](const Batch& b) {
 #pragma unroll
     for (int i = 0; i < B; ++i) {
-      if (cur.live.v[i]) {
-        const uint64_t aL = subset_xor<KQ, B>(cur.qr, i, cb, mk);
-        const uint64_t wv = FIRST ? subset_xor<KQ, B>(cur.zr, i, cb, mk) : cur.w[i];
+      if (b.live.v[i]) {
+        const uint64_t aL = subset_xor<KQ, B>(b.qr, i, cb, mk);
+        const uint64_t wv = FIRST ? subset_xor<KQ, B>(b.zr, i, cb, mk) : b.wh[i] ^ b.wl[i];
         gf_table(tab, wv);
         gf_comb_acc(base, aL, r);
       }
     }
-    cur = nxt;
+  };
+  Batch x, y;
+  gather(e0, x);
+  for (uint32_t eb = e0;; eb += 2 * B) {
+    gather(eb + B, y);
+    compute(x);
+    if (eb + B >= e1) break;
+    gather(eb + 2 * B, x);
+    compute(y);
+    if (eb + 2 * B >= e1) break;
   }
 }
 
