@@ -196,7 +196,11 @@ __global__ __launch_bounds__(1024) void kb_cover_offsets(const BQuery* __restric
 __global__ __launch_bounds__(256) void kb_mark_need(const BQuery* __restrict__ qs, uint32_t qi, uint32_t l) {
   const BQuery& Q = qs[qi];
   const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < Q.m) mark_need_cover(Q.e_out, Q.ref, Q.cov, Q.cboff, e, Q.need + (uint64_t)(l - 2) * need_stride(Q.m));
+  uint8_t* need = Q.need + (uint64_t)(l - 2) * need_stride(Q.m);
+  if (e < Q.m)
+    mark_need_cover(Q.e_out, Q.ref, Q.cov, Q.cboff, l >= 3 ? Q.hi : nullptr, Q.lo, e, need);
+  else if (e < (uint64_t)Q.m + kEdgePad)
+    need[e] = 0;  // the padding a level's last tile reads
 }
 
 __global__ void kb_clear_fsum(const BQuery* __restrict__ qs, uint32_t qi) {
@@ -853,7 +857,7 @@ static rs_status batch_enqueue(BatchPlan& P, BatchWorkspace& W, hipStream_t st) 
       hipLaunchKernelGGL(kb_cover_prefix, dim3((uint32_t)((slots + kCostBlock - 1) / kCostBlock)), dim3(256), 0, st,
                          dq, qi);
       hipLaunchKernelGGL(kb_cover_offsets, dim3(1), dim3(1024), 0, st, dq, qi);
-      hipLaunchKernelGGL(kb_mark_need, dim3((Q.m + 255) / 256), dim3(256), 0, st, dq, qi, l);
+      hipLaunchKernelGGL(kb_mark_need, dim3((Q.m + kEdgePad + 255) / 256), dim3(256), 0, st, dq, qi, l);
     }
     if (Q.k >= 3)
       RS_HIP(launch_tile_costs(Q.hi, Q.lo, Q.need, need_stride(Q.m), Q.m, P.tu.edges_per_tile, Q.k - 2, Q.pre,

@@ -317,7 +317,7 @@ rs_status run_plain(rs_graph* g, PlainWorkspace& ws, const QueryPlan& qp, const 
       for (uint32_t l = k - 1; l >= 2 && k >= 3; --l)
         RS_HIP(launch_need_cover(G.e_out.as<uint32_t>(), G.hi.as<uint32_t>(), ws.lo.as<uint32_t>(), (uint32_t)m,
                                  (uint32_t)n, l + 1 < k ? need_of(l + 1) : nullptr, ws.ref.as<uint8_t>(), cov,
-                                 cov_bsum, cov_boff, need_of(l), st));
+                                 cov_bsum, cov_boff, need_of(l), l >= 3, st));
       // work-balanced runs of the prefix levels, cut for the grid width of
       // the first chunk group (later groups launch the same width)
       if (k >= 3) {

@@ -168,7 +168,7 @@ hipError_t launch_need_counts(const uint32_t* hi, const uint32_t* lo, const uint
 // and boff [ceil((m+n+1) / 1024)]; need[m] receives the flags.
 hipError_t launch_need_cover(const uint32_t* e_out, const uint32_t* hi, const uint32_t* lo, uint32_t m, uint32_t n,
                              const uint8_t* next, uint8_t* ref, uint32_t* diff, uint32_t* bsum, uint32_t* boff,
-                             uint8_t* need, hipStream_t st);
+                             uint8_t* need, bool window_level, hipStream_t st);
 // Flag arrays of a query: one per prefix level 2..k-1 (at least one), each
 // m + kEdgePad bytes, level l at offset (l - 2) * need_stride(m); the stride
 // keeps every level's array 256-byte aligned (the kernels read the flags four

@@ -436,15 +436,20 @@ __global__ __launch_bounds__(256) void k_block_prefix(uint32_t* __restrict__ v, 
 __global__ __launch_bounds__(256) void k_mark_need_cover(const uint32_t* __restrict__ e_out,
                                                          const uint8_t* __restrict__ ref,
                                                          const uint32_t* __restrict__ pre,
-                                                         const uint32_t* __restrict__ boff, uint32_t m,
+                                                         const uint32_t* __restrict__ boff,
+                                                         const uint32_t* __restrict__ hi,
+                                                         const uint32_t* __restrict__ lo, uint32_t m,
                                                          uint8_t* __restrict__ need) {
   const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < m) mark_need_cover(e_out, ref, pre, boff, e, need);
+  if (e < m)
+    mark_need_cover(e_out, ref, pre, boff, hi, lo, e, need);
+  else if (e < (uint64_t)m + kEdgePad)
+    need[e] = 0;  // the padding a level's last tile reads
 }
 
 hipError_t launch_need_cover(const uint32_t* e_out, const uint32_t* hi, const uint32_t* lo, uint32_t m, uint32_t n,
                              const uint8_t* next, uint8_t* ref, uint32_t* diff, uint32_t* bsum, uint32_t* boff,
-                             uint8_t* need, hipStream_t st) {
+                             uint8_t* need, bool window_level, hipStream_t st) {
   if (!m) return hipSuccess;
   const uint64_t slots = (uint64_t)m + n + 1;  // slots 0 .. m+n-1, and one past the last window end
   const uint32_t nb = (uint32_t)((slots + kCostBlock - 1) / kCostBlock);
@@ -454,7 +459,9 @@ hipError_t launch_need_cover(const uint32_t* e_out, const uint32_t* hi, const ui
   hipLaunchKernelGGL(k_mark_cover, dim3(div_up(m, 256)), dim3(256), 0, st, hi, lo, next, m, ref, diff);
   hipLaunchKernelGGL(k_block_prefix, dim3(nb), dim3(256), 0, st, diff, slots, bsum);
   hipLaunchKernelGGL(k_cost_block_offsets, dim3(1), dim3(1024), 0, st, bsum, nb, boff);
-  hipLaunchKernelGGL(k_mark_need_cover, dim3(div_up(m, 256)), dim3(256), 0, st, e_out, ref, diff, boff, m, need);
+  // window emptiness folds into the product flag at levels >= 3
+  hipLaunchKernelGGL(k_mark_need_cover, dim3(div_up((uint64_t)m + kEdgePad, 256)), dim3(256), 0, st, e_out, ref, diff,
+                     boff, window_level ? hi : nullptr, lo, m, need);
   return hipGetLastError();
 }
 
