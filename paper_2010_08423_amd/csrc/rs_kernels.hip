@@ -306,9 +306,11 @@ hipError_t launch_ztable(uint64_t* z, uint32_t n, const QueryPlan& qp, const uin
 constexpr uint32_t kTileCost = 5, kProductCost = 3;
 constexpr uint32_t kTileCostFirst = 7, kProductCostFirst = 4;
 
+// The product bit of the flags already requires a non-empty window at levels
+// >= 3, and the flag bytes past m are zero, so a tile's products are a
+// population count over its flag words.
 template <int E>
-__global__ __launch_bounds__(256) void k_tile_cost(const uint32_t* __restrict__ hi, const uint32_t* __restrict__ lo,
-                                                   const uint8_t* __restrict__ need, uint64_t need_stride_b,
+__global__ __launch_bounds__(256) void k_tile_cost(const uint8_t* __restrict__ need, uint64_t need_stride_b,
                                                    uint32_t m, uint32_t n_tiles, uint32_t* __restrict__ pre,
                                                    uint32_t* __restrict__ bsum) {
   __shared__ uint32_t part[256];
@@ -323,9 +325,11 @@ __global__ __launch_bounds__(256) void k_tile_cost(const uint32_t* __restrict__ 
     if (t < n_tiles) {
       c = lvl == 0 ? kTileCostFirst : kTileCost;
       const uint32_t pc = lvl == 0 ? kProductCostFirst : kProductCost;
-      const uint32_t e0 = t * (uint32_t)E, e1 = min(e0 + (uint32_t)E, m);
-      for (uint32_t e = e0; e < e1; ++e)
-        c += pc * (((nd[e] >> 2) & 1u) && (lvl == 0 || hi[e] != lo[e]));
+      const uint32_t* w = reinterpret_cast<const uint32_t*>(nd + (uint64_t)t * E);
+      uint32_t np = 0;
+#pragma unroll
+      for (int q = 0; q < E / 4; ++q) np += __popc(w[q] & 0x04040404u);  // bit 2 of four flag bytes
+      c += pc * np;
     }
     sum += c;
     cost[j] = sum;  // inclusive within the thread's four tiles
@@ -369,10 +373,10 @@ hipError_t launch_tile_costs(const uint32_t* hi, const uint32_t* lo, const uint8
   const uint32_t n_tiles = div_up(m, E);
   const uint32_t nb = div_up(n_tiles, kCostBlock);
   if (E == 8)
-    hipLaunchKernelGGL(k_tile_cost<8>, dim3(nb, levels), dim3(256), 0, st, hi, lo, need, need_stride_b, m, n_tiles,
+    hipLaunchKernelGGL(k_tile_cost<8>, dim3(nb, levels), dim3(256), 0, st, need, need_stride_b, m, n_tiles,
                        pre, bsum);
   else
-    hipLaunchKernelGGL(k_tile_cost<16>, dim3(nb, levels), dim3(256), 0, st, hi, lo, need, need_stride_b, m,
+    hipLaunchKernelGGL(k_tile_cost<16>, dim3(nb, levels), dim3(256), 0, st, need, need_stride_b, m,
                        n_tiles, pre, bsum);
   hipLaunchKernelGGL(k_cost_block_offsets, dim3(levels), dim3(1024), 0, st, bsum, nb, boff);
   return hipGetLastError();
