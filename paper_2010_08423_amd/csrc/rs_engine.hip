@@ -223,9 +223,9 @@ PlainSizes plain_sizes(uint64_t m, uint64_t n, const QueryPlan& qp, const Tuning
   s.p = 8 * (m + n) * 64 * cpl;
   s.partial = 8 * 64 * cpl * (uint64_t)tblocks;
   s.fsum = 8 * (1ull << k);
-  s.ref = (m + n + 3) & ~3ull;
+  s.ref = 2 * flag_ref_bytes(m, n);  // two levels' read marks, alternating
   s.need = table_need_bytes(m, k);
-  s.cover = 4 * (m + n + 1) + 8 * ((m + n + 1 + 1023) / 1024);  // difference array and block sums
+  s.cover = 8 * (m + n + 1) + 8 * ((m + n + 1 + 1023) / 1024);  // two difference arrays and block sums
   s.records = 1024 * cpl * tiles;
   return s;
 }
@@ -311,13 +311,9 @@ rs_status run_plain(rs_graph* g, PlainWorkspace& ws, const QueryPlan& qp, const 
       // slots the windows of level l+1's product edges read, and forms a
       // product only for edges inside one of those windows (level k-1: the
       // windows of every last-level edge).
-      uint32_t* cov = ws.cov_diff.as<uint32_t>();       // difference array [m+n+1]
-      uint32_t* cov_bsum = cov + (m + n + 1);            // block totals
-      uint32_t* cov_boff = cov_bsum + (m + n + 1 + 1023) / 1024;
-      for (uint32_t l = k - 1; l >= 2 && k >= 3; --l)
-        RS_HIP(launch_need_cover(G.e_out.as<uint32_t>(), G.hi.as<uint32_t>(), ws.lo.as<uint32_t>(), (uint32_t)m,
-                                 (uint32_t)n, l + 1 < k ? need_of(l + 1) : nullptr, ws.ref.as<uint8_t>(), cov,
-                                 cov_bsum, cov_boff, need_of(l), l >= 3, st));
+      RS_HIP(launch_flags(G.e_out.as<uint32_t>(), G.hi.as<uint32_t>(), ws.lo.as<uint32_t>(), (uint32_t)m,
+                          (uint32_t)n, k, need_of(2), need_stride(m), ws.ref.as<uint8_t>(), ws.cov_diff.as<uint32_t>(),
+                          st));
       // work-balanced runs of the prefix levels, cut for the grid width of
       // the first chunk group (later groups launch the same width)
       if (k >= 3) {

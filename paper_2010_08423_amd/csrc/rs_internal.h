@@ -161,14 +161,16 @@ struct NeedCounts {
 // ref_slots, ref_lead.
 hipError_t launch_need_counts(const uint32_t* hi, const uint32_t* lo, const uint8_t* need, uint32_t m,
                               unsigned long long* counts, hipStream_t st);
-// Store and product flags of one prefix level l (see mark_cover): the readers
-// are the windows of the edges whose level-(l+1) product is needed, given by
-// `next` (the flags of level l+1; null for l = k-1, whose readers are every
-// non-empty window of the last level). Scratch ref[m+n], diff[m+n+1], bsum
-// and boff [ceil((m+n+1) / 1024)]; need[m] receives the flags.
-hipError_t launch_need_cover(const uint32_t* e_out, const uint32_t* hi, const uint32_t* lo, uint32_t m, uint32_t n,
-                             const uint8_t* next, uint8_t* ref, uint32_t* diff, uint32_t* bsum, uint32_t* boff,
-                             uint8_t* need, bool window_level, hipStream_t st);
+// Store and product flags of prefix levels k-1 down to 2 (see mark_cover):
+// the readers of level l are the windows of the edges whose level-(l+1)
+// product is needed (level k-1: every non-empty window of the last level).
+// Level l's flags go to need + (l - 2) * need_stride_b. Scratch: ref, two
+// arrays of flag_ref_bytes(m, n); cov, two difference arrays [m+n+1] and the
+// block sums and offsets [ceil((m+n+1) / 1024)] each.
+inline uint64_t flag_ref_bytes(uint64_t m, uint64_t n) { return (m + n + 3) & ~3ull; }
+hipError_t launch_flags(const uint32_t* e_out, const uint32_t* hi, const uint32_t* lo, uint32_t m, uint32_t n,
+                        uint32_t k, uint8_t* need, uint64_t need_stride_b, uint8_t* ref, uint32_t* cov,
+                        hipStream_t st);
 // Flag arrays of a query: one per prefix level 2..k-1 (at least one), each
 // m + kEdgePad bytes, level l at offset (l - 2) * need_stride(m); the stride
 // keeps every level's array 256-byte aligned (the kernels read the flags four

@@ -431,41 +431,72 @@ __global__ __launch_bounds__(256) void k_mark_cover(const uint32_t* __restrict__
   if (e < m) mark_cover(hi, lo, next, e, ref, diff);
 }
 
-// In-place block-wise inclusive prefix of v[count] (see block_prefix).
-__global__ __launch_bounds__(256) void k_block_prefix(uint32_t* __restrict__ v, uint64_t count,
-                                                      uint32_t* __restrict__ bsum) {
-  block_prefix(v, count, bsum);
+// In-place block-wise inclusive prefix of this level's cover difference
+// array (see block_prefix). When a lower level follows, the grid also zeroes
+// the other pair of scratch arrays (ref_o, diff_o): the flag kernel of the
+// level above, their last reader, has finished, and this level's flag kernel
+// marks the lower level's windows into them.
+__global__ __launch_bounds__(256) void k_cover_prefix(uint32_t* __restrict__ diff, uint64_t slots,
+                                                      uint32_t* __restrict__ bsum, uint32_t* __restrict__ diff_o,
+                                                      uint32_t* __restrict__ ref_o, uint64_t ref_words) {
+  block_prefix(diff, slots, bsum);
+  if (!diff_o) return;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < slots; i += stride) diff_o[i] = 0;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ref_words; i += stride) ref_o[i] = 0;
 }
 
-__global__ __launch_bounds__(256) void k_mark_need_cover(const uint32_t* __restrict__ e_out,
+// The flags of level l (window emptiness folded into the product bit when
+// hi != null), the zero padding past m, and, when ref_n != null, the windows
+// of level l's product edges marked for level l - 1 (its readers).
+__global__ __launch_bounds__(256) void k_flags_and_marks(const uint32_t* __restrict__ e_out,
                                                          const uint8_t* __restrict__ ref,
                                                          const uint32_t* __restrict__ pre,
                                                          const uint32_t* __restrict__ boff,
                                                          const uint32_t* __restrict__ hi,
+                                                         const uint32_t* __restrict__ hi_all,
                                                          const uint32_t* __restrict__ lo, uint32_t m,
-                                                         uint8_t* __restrict__ need) {
+                                                         uint8_t* __restrict__ need, uint8_t* __restrict__ ref_n,
+                                                         uint32_t* __restrict__ diff_n) {
   const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < m)
+  if (e < m) {
     mark_need_cover(e_out, ref, pre, boff, hi, lo, e, need);
-  else if (e < (uint64_t)m + kEdgePad)
+    if (ref_n) mark_cover(hi_all, lo, need, e, ref_n, diff_n);  // reads back this thread's own flag byte
+  } else if (e < (uint64_t)m + kEdgePad) {
     need[e] = 0;  // the padding a level's last tile reads
+  }
 }
 
-hipError_t launch_need_cover(const uint32_t* e_out, const uint32_t* hi, const uint32_t* lo, uint32_t m, uint32_t n,
-                             const uint8_t* next, uint8_t* ref, uint32_t* diff, uint32_t* bsum, uint32_t* boff,
-                             uint8_t* need, bool window_level, hipStream_t st) {
-  if (!m) return hipSuccess;
+hipError_t launch_flags(const uint32_t* e_out, const uint32_t* hi, const uint32_t* lo, uint32_t m, uint32_t n,
+                        uint32_t k, uint8_t* need, uint64_t need_stride_b, uint8_t* ref, uint32_t* cov,
+                        hipStream_t st) {
+  if (!m || k < 3) return hipSuccess;
   const uint64_t slots = (uint64_t)m + n + 1;  // slots 0 .. m+n-1, and one past the last window end
   const uint32_t nb = (uint32_t)((slots + kCostBlock - 1) / kCostBlock);
-  hipError_t e = launch_fill32((uint32_t*)ref, 0, ((uint64_t)m + n + 3) / 4, st);
-  if (e == hipSuccess) e = launch_fill32(diff, 0, slots, st);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_mark_cover, dim3(div_up(m, 256)), dim3(256), 0, st, hi, lo, next, m, ref, diff);
-  hipLaunchKernelGGL(k_block_prefix, dim3(nb), dim3(256), 0, st, diff, slots, bsum);
-  hipLaunchKernelGGL(k_cost_block_offsets, dim3(1), dim3(1024), 0, st, bsum, nb, boff);
-  // window emptiness folds into the product flag at levels >= 3
-  hipLaunchKernelGGL(k_mark_need_cover, dim3(div_up((uint64_t)m + kEdgePad, 256)), dim3(256), 0, st, e_out, ref, diff,
-                     boff, window_level ? hi : nullptr, lo, m, need);
+  const uint64_t ref_bytes = flag_ref_bytes(m, n);
+  uint8_t* refs[2] = {ref, ref + ref_bytes};
+  uint32_t* diffs[2] = {cov, cov + slots};
+  uint32_t* bsum = cov + 2 * slots;
+  uint32_t* boff = bsum + nb;
+  // level k-1: its readers are every non-empty window of the last level
+  {
+    const uint32_t b = (k - 1) & 1u;
+    hipError_t e = launch_fill32((uint32_t*)refs[b], 0, ref_bytes / 4, st);
+    if (e == hipSuccess) e = launch_fill32(diffs[b], 0, slots, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_mark_cover, dim3(div_up(m, 256)), dim3(256), 0, st, hi, lo, nullptr, m, refs[b], diffs[b]);
+  }
+  for (uint32_t l = k - 1; l >= 2; --l) {
+    const uint32_t b = l & 1u, o = b ^ 1u;
+    const bool lower = l > 2;
+    hipLaunchKernelGGL(k_cover_prefix, dim3(nb), dim3(256), 0, st, diffs[b], slots, bsum, lower ? diffs[o] : nullptr,
+                       (uint32_t*)refs[o], ref_bytes / 4);
+    hipLaunchKernelGGL(k_cost_block_offsets, dim3(1), dim3(1024), 0, st, bsum, nb, boff);
+    hipLaunchKernelGGL(k_flags_and_marks, dim3(div_up((uint64_t)m + kEdgePad, 256)), dim3(256), 0, st, e_out,
+                       refs[b], diffs[b], boff, l >= 3 ? hi : nullptr, hi, lo, m,
+                       need + (uint64_t)(l - 2) * need_stride_b, lower ? refs[o] : nullptr,
+                       lower ? diffs[o] : nullptr);
+  }
   return hipGetLastError();
 }
 
