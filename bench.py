@@ -1,9 +1,11 @@
 """Benchmark: GF(2^64) sieve edge-updates per second on one MI355X.
 
-One step = one full k-RestlessPath query (all 2^k sieve iterations, levels
-2..k, setup kernels and the final XOR) on the 1,000,000-edge Chung-Lu graph
-(n=100,000, exponent 2.5, t in [1,1000]), delta=10, k=8, seed 2. The graph is
-resident in HBM before the timed region starts.
+One step = one full k-RestlessMotif query (all 2^k sieve iterations, levels
+2..k, setup kernels and the final XOR) on the 10,000,000-edge Chung-Lu graph
+(n=1,000,000, exponent 2.2, t in [1,10000] in 100 Gaussian bursts of sigma
+20, 8 vertex colours), delta=20, a motif of k=10 colours, seed 3: the largest
+single-query workload. The graph is resident in HBM before the timed region
+starts. --workload path-scale times the 10^6-edge path query (k=8) instead.
 
 An edge-update is one (edge, level l in 2..k, iteration L) triple, so a query
 performs 2^k (k-1) m of them.
@@ -54,7 +56,8 @@ WORKLOADS = {
     "motif-scale": ("config_motif_scale",
                     "k-RestlessMotif plain sieve, Chung-Lu(2.2) n=1000000 m=10000000, t in [1,10000] in 100 "
                     "Gaussian bursts (sigma 20), 8 colours, delta=20, motif of k=10 colours (1024 iterations), seed 3",
-                    os.path.join(ROOT, "profiles", "k_scan_chunglu_m1e7_motif_k10_counters.md"), None),
+                    os.path.join(ROOT, "profiles", "k_scan_chunglu_m1e7_motif_k10_counters.md"),
+                    os.path.join(ROOT, "profiles", "k_scan_chunglu_m1e7_motif_k10_sq.md")),
     "small": ("config_small",
               "k-RestlessPath plain sieve, uniform n=1000 m=10000 t in [1,100], delta=5, k=5 (32 iterations), seed 1",
               None, None),
@@ -111,7 +114,9 @@ def cpu_model():
 
 def cpu_baseline(g, q, m_dedup, budget_s=20.0):
     """The oracle (plain C, OpenMP over sieve iterations) on a bounded sample
-    of the same query: a range of iterations sized to about budget_s."""
+    of the same query: a range of iterations starting at 1, sized to about
+    budget_s. Returns the baseline record and the oracle's f_L over the range
+    (for the bit-exact check against the GPU's values)."""
     import oracle
 
     cores = min(host_cores(), 64)
@@ -123,12 +128,14 @@ def cpu_baseline(g, q, m_dedup, budget_s=20.0):
     n_it = max(cores, (n_it // cores) * cores) if n_it >= cores else n_it
     n_it = min(n_it, (1 << q.k) - 1)
     t0 = time.perf_counter()
-    oracle.sieve(g.n, g.src, g.dst, g.t, q.k, q.delta, q.seed, it_begin=1, it_end=1 + n_it, threads=cores, **kw)
+    _, per = oracle.sieve(g.n, g.src, g.dst, g.t, q.k, q.delta, q.seed, it_begin=1, it_end=1 + n_it, threads=cores,
+                          per_iteration=True, **kw)
     dt = time.perf_counter() - t0
     upd = n_it * (q.k - 1) * m_dedup
-    return {"value": upd / dt, "unit": "edge-updates/s", "cores": cores, "kind": "oracle",
-            "sample": f"iterations [1,{1 + n_it}) of the {1 << q.k} of the same query ({n_it} sieve iterations, "
-                      f"{dt:.1f} s, OpenMP over iterations on {cores} threads, {cpu_model()})"}
+    rec = {"value": upd / dt, "unit": "edge-updates/s", "cores": cores, "kind": "oracle",
+           "sample": f"iterations [1,{1 + n_it}) of the {1 << q.k} of the same query ({n_it} sieve iterations, "
+                     f"{dt:.1f} s, OpenMP over iterations on {cores} threads, {cpu_model()})"}
+    return rec, 1, per
 
 
 def main():
@@ -138,8 +145,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--mode", default="plain", choices=["plain", "batch", "serve", "copy"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="path-scale", choices=sorted(WORKLOADS),
-                    help="plain mode: the query timed (default: the 10^6-edge path query)")
+    ap.add_argument("--workload", default="motif-scale", choices=sorted(WORKLOADS),
+                    help="plain mode: the query timed (default: the 10^7-edge motif query)")
     # serve mode: offered load, arrival window, wall-clock cap, server budget
     ap.add_argument("--rate", type=float, default=200.0)
     ap.add_argument("--window", type=float, default=5.0)
@@ -258,9 +265,19 @@ def main():
                      "salu_frac": _float(committed_figures(sq_file).get("salu-frac")) if sq_file else None},
         "kernels": classes,
     }
+    exact = True
     if rank == 0 and not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(g, q, m)
+        rec, a, per = cpu_baseline(g, q, m)
+        out["cpu_baseline"] = rec
+        # bit-exact check outside the timed region: the GPU's f_L over the
+        # oracle's sample range of the same query
+        rg = R.run(gd, q.k, q.delta, q.seed, motif=q.motif, it_begin=a, it_end=a + len(per), per_iteration=True)
+        exact = [int(x) for x in rg.per_iteration] == [int(x) for x in per]
+        out["bit_exact"] = exact
+        out["bit_exact_sample"] = f"f_L of iterations [{a},{a + len(per)}) on the GPU vs the oracle"
     print(json.dumps(out), flush=True)
+    if not exact:
+        raise SystemExit("GPU per-iteration values differ from the oracle's")
 
 
 if __name__ == "__main__":

@@ -112,38 +112,36 @@ __global__ void k_hi(const uint32_t* __restrict__ e_src, const uint32_t* __restr
 
 static inline uint32_t grid_for(uint64_t n, uint32_t b = 256) { return (uint32_t)((n + b - 1) / b); }
 
-rs_status graph_build(uint32_t n, uint64_t m, const uint32_t* src, const uint32_t* dst,
-                      const uint32_t* t, const uint8_t* colour, uint32_t n_colours, bool host_ptrs,
-                      hipStream_t st, rs_graph** out) {
-  if (!out || (m && (!src || !dst || !t))) return RS_EINVAL;
-  if (n >= (1u << 31) || (uint64_t)m + n >= (1ull << 32)) return RS_EINVAL;
-  if ((colour == nullptr) != (n_colours == 0) || n_colours > RS_MAX_COLOURS) return RS_EINVAL;
-  rs_graph* g = new (std::nothrow) rs_graph();
-  if (!g) return RS_ENOMEM;
-  auto fail = [&](rs_status s) {
-    rs_graph_destroy(g);
-    return s;
-  };
+// Temporary device buffers of one upload; released on every exit path.
+struct UploadTemps {
+  DevBuf in_src, in_dst, in_t, stats, loops, perm_a, perm_b, key_a, key_b, k1a, k1b, keep, pos, tmp;
+  ~UploadTemps() {
+    for (DevBuf* b : {&in_src, &in_dst, &in_t, &stats, &loops, &perm_a, &perm_b, &key_a, &key_b, &k1a, &k1b, &keep,
+                      &pos, &tmp})
+      b->release();
+  }
+};
+
+// Fills g (already allocated) from the input edges; on failure the caller
+// destroys g.
+static rs_status graph_fill(rs_graph* g, uint32_t n, uint64_t m, const uint32_t* src, const uint32_t* dst,
+                            const uint32_t* t, const uint8_t* colour, uint32_t n_colours, bool host_ptrs,
+                            hipStream_t st) {
   RS_HIP(hipGetDevice(&g->device));
   GraphDev& G = g->g;
   G.n = n;
   G.n_colours = n_colours;
+  UploadTemps T;
+  DevBuf &in_src = T.in_src, &in_dst = T.in_dst, &in_t = T.in_t, &stats = T.stats, &loops = T.loops,
+         &perm_a = T.perm_a, &perm_b = T.perm_b, &key_a = T.key_a, &key_b = T.key_b, &k1a = T.k1a, &k1b = T.k1b,
+         &keep = T.keep, &pos = T.pos, &tmp = T.tmp;
 
   // Inputs on the device.
-  DevBuf in_src, in_dst, in_t, stats, loops, perm_a, perm_b, key_a, key_b, k1a, k1b, keep, pos, tmp;
-  auto cleanup = [&]() {
-    for (DevBuf* b : {&in_src, &in_dst, &in_t, &stats, &loops, &perm_a, &perm_b, &key_a, &key_b,
-                      &k1a, &k1b, &keep, &pos, &tmp})
-      b->release();
-  };
   const uint32_t *d_src = src, *d_dst = dst, *d_t = t;
   const size_t mb = (size_t)std::max<uint64_t>(m, 1);
   if (host_ptrs && m) {
     if (in_src.reserve(mb * 4, st, false) || in_dst.reserve(mb * 4, st, false) ||
-        in_t.reserve(mb * 4, st, false)) {
-      cleanup();
-      return fail(RS_ENOMEM);
-    }
+        in_t.reserve(mb * 4, st, false)) return RS_ENOMEM;
     RS_HIP(hipMemcpyAsync(in_src.p, src, m * 4, hipMemcpyHostToDevice, st));
     RS_HIP(hipMemcpyAsync(in_dst.p, dst, m * 4, hipMemcpyHostToDevice, st));
     RS_HIP(hipMemcpyAsync(in_t.p, t, m * 4, hipMemcpyHostToDevice, st));
@@ -151,10 +149,7 @@ rs_status graph_build(uint32_t n, uint64_t m, const uint32_t* src, const uint32_
     d_dst = in_dst.as<uint32_t>();
     d_t = in_t.as<uint32_t>();
   }
-  if (stats.reserve(16, st) || loops.reserve(8, st)) {
-    cleanup();
-    return fail(RS_ENOMEM);
-  }
+  if (stats.reserve(16, st) || loops.reserve(8, st)) return RS_ENOMEM;
   uint32_t init[4] = {0, 0xFFFFFFFFu, 0, 0};
   RS_HIP(hipMemcpyAsync(stats.p, init, 16, hipMemcpyHostToDevice, st));
   if (m) {
@@ -167,10 +162,7 @@ rs_status graph_build(uint32_t n, uint64_t m, const uint32_t* src, const uint32_
   RS_HIP(hipMemcpyAsync(hstats, stats.p, 16, hipMemcpyDeviceToHost, st));
   RS_HIP(hipMemcpyAsync(&hloops, loops.p, 8, hipMemcpyDeviceToHost, st));
   RS_HIP(hipStreamSynchronize(st));
-  if (hstats[0]) {
-    cleanup();
-    return fail(RS_EINVAL);
-  }
+  if (hstats[0]) return RS_EINVAL;
 
   uint64_t mk = 0;
   if (m) {
@@ -178,10 +170,7 @@ rs_status graph_build(uint32_t n, uint64_t m, const uint32_t* src, const uint32_
     if (perm_a.reserve(mb * 4, st, false) || perm_b.reserve(mb * 4, st, false) ||
         key_a.reserve(mb * 8, st, false) || key_b.reserve(mb * 8, st, false) ||
         k1a.reserve(mb * 4, st, false) || k1b.reserve(mb * 4, st, false) ||
-        keep.reserve(mb * 4, st, false) || pos.reserve(mb * 4, st, false)) {
-      cleanup();
-      return fail(RS_ENOMEM);
-    }
+        keep.reserve(mb * 4, st, false) || pos.reserve(mb * 4, st, false)) return RS_ENOMEM;
     hipLaunchKernelGGL(k_iota, dim3(grid_for(m)), dim3(256), 0, st, perm_a.as<uint32_t>(), m);
     RS_HIP(hipGetLastError());
     RS_HIP(hipMemcpyAsync(k1a.p, d_src, m * 4, hipMemcpyDeviceToDevice, st));
@@ -194,10 +183,7 @@ rs_status graph_build(uint32_t n, uint64_t m, const uint32_t* src, const uint32_
                                      perm_b.as<uint32_t>(), perm_a.as<uint32_t>(), (size_t)m, 0, 32 + nbits, st));
     RS_HIP(rocprim::exclusive_scan(nullptr, need3, keep.as<uint32_t>(), pos.as<uint32_t>(), 0u, (size_t)m,
                                    rocprim::plus<uint32_t>(), st));
-    if (tmp.reserve(std::max(need1, std::max(need2, need3)) + 256, st, false)) {
-      cleanup();
-      return fail(RS_ENOMEM);
-    }
+    if (tmp.reserve(std::max(need1, std::max(need2, need3)) + 256, st, false)) return RS_ENOMEM;
     size_t sz = tmp.bytes;
     RS_HIP(rocprim::radix_sort_pairs(tmp.p, sz, k1a.as<uint32_t>(), k1b.as<uint32_t>(),
                                      perm_a.as<uint32_t>(), perm_b.as<uint32_t>(), (size_t)m, 0, nbits, st));
@@ -221,20 +207,14 @@ rs_status graph_build(uint32_t n, uint64_t m, const uint32_t* src, const uint32_
     const size_t kb = (size_t)std::max<uint64_t>(mk, 1) + kEdgePad;
     if (G.e_src.reserve(kb * 4, st, false) || G.e_dst.reserve(kb * 4, st, false) ||
         G.e_t.reserve(kb * 4, st, false) || G.e_out.reserve(kb * 4, st, false) ||
-        G.hi.reserve(kb * 4, st, false)) {
-      cleanup();
-      return fail(RS_ENOMEM);
-    }
+        G.hi.reserve(kb * 4, st, false)) return RS_ENOMEM;
     hipLaunchKernelGGL(k_scatter, dim3(grid_for(m)), dim3(256), 0, st, perm_a.as<uint32_t>(), d_src,
                        key_b.as<uint64_t>(), keep.as<uint32_t>(), pos.as<uint32_t>(),
                        G.e_src.as<uint32_t>(), G.e_dst.as<uint32_t>(), G.e_t.as<uint32_t>(), m);
     RS_HIP(hipGetLastError());
   }
   G.m = mk;
-  if (G.in_off.reserve(((size_t)n + 1) * 4, st, true)) {
-    cleanup();
-    return fail(RS_ENOMEM);
-  }
+  if (G.in_off.reserve(((size_t)n + 1) * 4, st, true)) return RS_ENOMEM;
   uint32_t max_deg = 0;
   if (mk) {
     hipLaunchKernelGGL(k_in_off, dim3(grid_for((uint64_t)n + 1)), dim3(256), 0, st,
@@ -248,14 +228,10 @@ rs_status graph_build(uint32_t n, uint64_t m, const uint32_t* src, const uint32_
     RS_HIP(hipMemcpyAsync(&max_deg, stats.p, 4, hipMemcpyDeviceToHost, st));
   }
   if (colour) {
-    if (G.colour.reserve(std::max<size_t>(n, 1), st, false)) {
-      cleanup();
-      return fail(RS_ENOMEM);
-    }
+    if (G.colour.reserve(std::max<size_t>(n, 1), st, false)) return RS_ENOMEM;
     RS_HIP(hipMemcpyAsync(G.colour.p, colour, n, host_ptrs ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice, st));
   }
   RS_HIP(hipStreamSynchronize(st));
-  cleanup();
 
   rs_graph_info& I = g->info;
   I.n = n;
@@ -269,6 +245,23 @@ rs_status graph_build(uint32_t n, uint64_t m, const uint32_t* src, const uint32_
   I.max_in_degree = max_deg;
   I.device_bytes = G.e_src.bytes + G.e_dst.bytes + G.e_t.bytes + G.e_out.bytes + G.hi.bytes +
                    G.in_off.bytes + G.colour.bytes;
+  return RS_OK;
+}
+
+
+rs_status graph_build(uint32_t n, uint64_t m, const uint32_t* src, const uint32_t* dst,
+                      const uint32_t* t, const uint8_t* colour, uint32_t n_colours, bool host_ptrs,
+                      hipStream_t st, rs_graph** out) {
+  if (!out || (m && (!src || !dst || !t))) return RS_EINVAL;
+  if (n >= (1u << 31) || (uint64_t)m + n >= (1ull << 32)) return RS_EINVAL;
+  if ((colour == nullptr) != (n_colours == 0) || n_colours > RS_MAX_COLOURS) return RS_EINVAL;
+  rs_graph* g = new (std::nothrow) rs_graph();
+  if (!g) return RS_ENOMEM;
+  const rs_status s = graph_fill(g, n, m, src, dst, t, colour, n_colours, host_ptrs, st);
+  if (s != RS_OK) {
+    rs_graph_destroy(g);
+    return s;
+  }
   *out = g;
   return RS_OK;
 }

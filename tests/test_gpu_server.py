@@ -1,9 +1,9 @@
 """GPU: the server (rs_server_*) returns, for every query of a stream of
-arrivals, the fingerprint the plain path gives for it alone, whether the
-query runs in a group (shared batched launches) or alone on one of several
-concurrent worker streams, while it admits queries against an HBM budget,
-cancels, and is driven from several threads."""
-import sys
+arrivals, the oracle's fingerprint and the fingerprint the plain path gives
+for it alone, whether the query runs in a group (shared batched launches) or
+alone on one of several concurrent worker streams, while it admits queries
+against an HBM budget, cancels, and is driven from several threads."""
+import dataclasses
 import threading
 import time
 
@@ -11,6 +11,7 @@ import numpy as np
 import pytest
 
 from paper_2010_08423_amd import inputs
+from parity_util import oracle_cost, oracle_many, say
 
 pytestmark = pytest.mark.gpu
 
@@ -27,11 +28,6 @@ def setup_module(module):
 
     R = lib
     R.library()
-
-
-def say(*a):
-    print(*a, flush=True)
-    sys.stdout.flush()
 
 
 def mixed_queries(n_q, n_colours, seed, k_range=(2, 9), delta_range=(0, 6)):
@@ -55,11 +51,33 @@ def plain(gd, q):
     return R.run(gd, q.k, q.delta, q.seed, motif=q.motif, it_begin=q.it_begin, it_end=q.it_end).fingerprint
 
 
+_GRAPHS = None
+_ORACLE = {}
+
+
 def graphs():
-    g1 = inputs.add_colours(inputs.uniform_graph(300, 4000, 40, seed=31), 4, seed=31)
-    g2 = inputs.add_colours(inputs.chung_lu_graph(500, 9000, 2.3, 60, seed=32), 4, seed=32)
-    g3 = inputs.tiny_graph(33, n_max=8, m_max=30, n_colours=4)
-    return [g1, g2, g3]
+    global _GRAPHS
+    if _GRAPHS is None:
+        g1 = inputs.add_colours(inputs.uniform_graph(300, 4000, 40, seed=31), 4, seed=31)
+        g2 = inputs.add_colours(inputs.chung_lu_graph(500, 9000, 2.3, 60, seed=32), 4, seed=32)
+        g3 = inputs.tiny_graph(33, n_max=8, m_max=30, n_colours=4)
+        _GRAPHS = [g1, g2, g3]
+    return _GRAPHS
+
+
+def _qkey(q):
+    return (q.k, q.delta, q.seed, None if q.motif is None else tuple(int(x) for x in q.motif), q.it_begin, q.it_end)
+
+
+def oracle_fps(pairs):
+    """Oracle fingerprints of (graph, query) pairs, cached across the tests of
+    this module (the same arrivals recur under several server options)."""
+    todo = [(g, q) for g, q in pairs if (id(g), _qkey(q)) not in _ORACLE]
+    if todo:
+        say(f"[server] oracle for {len(todo)} queries")
+        for (g, q), F in zip(todo, oracle_many(todo)):
+            _ORACLE[(id(g), _qkey(q))] = (g, F)  # the graph is kept, so its id is not reused
+    return [_ORACLE[(id(g), _qkey(q))][1] for g, q in pairs]
 
 
 @pytest.mark.parametrize("label,opts", [
@@ -73,6 +91,8 @@ def test_server_alone_vs_mix(label, opts):
     qs = mixed_queries(30, 4, seed=17, k_range=(2, 10))
     which = [i % 3 for i in range(len(qs))]
     alone = [plain(gds[w], q) for q, w in zip(qs, which)]
+    want = oracle_fps([(gs[w], q) for q, w in zip(qs, which)])
+    assert alone == want
     say(f"[server] 30 arrivals over 3 graphs, {label}")
     srv = R.Server(hbm_budget=8 << 30, **opts)
     ids = [srv.add_graph(gd) for gd in gds]
@@ -82,7 +102,7 @@ def test_server_alone_vs_mix(label, opts):
         time.sleep(0.001)  # arrivals while earlier work is on the device
     got = [srv.poll(t, wait_ms=60000) for t in tickets]
     assert all(r is not None and r.status == R.RS_OK for r in got)
-    assert [r.fingerprint for r in got] == alone
+    assert [r.fingerprint for r in got] == want
     st = srv.stats()
     assert st["completed"] == len(qs) and st["jobs"] >= 1
     assert st["p99_ms"] >= st["p50_ms"] > 0
@@ -95,6 +115,7 @@ def test_server_budget_deferral_cancel_and_threads():
     gd = R.Graph.from_inputs(g)
     qs = mixed_queries(16, 4, seed=19, k_range=(6, 9))
     alone = [plain(gd, q) for q in qs]
+    assert alone == oracle_fps([(g, q) for q in qs])
     fp = max(R.footprint(gd, q.k, q.delta) for q in qs)
     # four workers, room for about two queries at a time: the rest must wait
     say("[server] budget for about two queries, 4 workers, 4 submitting threads")
@@ -127,4 +148,44 @@ def test_server_budget_deferral_cancel_and_threads():
     with pytest.raises(R.RSError):
         small.submit(gid2, qs[0])  # can never fit
     small.close()
+    srv.close()
+
+
+def test_server_config5_stream_vs_oracle():
+    """The served stream of the 4-graph workload (Poisson arrivals, k in
+    4..12, delta in 1..100, 30 % motif queries over 8 colours), on its two
+    smaller graphs (m = 10^4 uniform, m = 10^5 Chung-Lu 2.5, tau = m/100):
+    64 arrivals submitted at their (compressed) arrival times while earlier
+    ones run. A query whose oracle run would exceed 10^7 edge-updates keeps a
+    2-iteration range of its sieve at a seeded position (the range is part of
+    the served query). Every result equals the oracle's and the plain path's
+    for the query alone."""
+    gs = inputs.served_graphs(sizes=(10_000, 100_000))
+    gds = [R.Graph.from_inputs(g) for g in gs]
+    stream = inputs.served_stream(200.0, 60.0, len(gs))[:64]
+    rr = np.random.default_rng(55)
+    arrivals = []
+    for ta, gi, q in stream:
+        if oracle_cost(gs[gi], q) > 10_000_000:
+            a = int(rr.integers(0, (1 << q.k) - 1))
+            q = dataclasses.replace(q, it_begin=a, it_end=a + 2)
+        arrivals.append((ta, gi, q))
+    want = oracle_fps([(gs[gi], q) for _, gi, q in arrivals])
+    alone = [plain(gds[gi], q) for _, gi, q in arrivals]
+    assert alone == want
+    say(f"[server] config-5 stream: {len(arrivals)} arrivals on m = {[g.m for g in gs]}")
+    srv = R.Server(hbm_budget=16 << 30)
+    ids = [srv.add_graph(gd) for gd in gds]
+    tickets = []
+    t0 = time.perf_counter()
+    for ta, gi, q in arrivals:
+        d = t0 + ta / 10.0 - time.perf_counter()  # arrival times compressed tenfold
+        if d > 0:
+            time.sleep(d)
+        tickets.append(srv.submit(ids[gi], q))
+    got = [srv.poll(t, wait_ms=120000) for t in tickets]
+    assert all(r is not None and r.status == R.RS_OK for r in got)
+    assert [r.fingerprint for r in got] == want
+    st = srv.stats()
+    assert st["completed"] == len(arrivals)
     srv.close()

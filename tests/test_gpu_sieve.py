@@ -3,14 +3,14 @@
 Fingerprints are integer (GF(2^64)) results, so the bar is bit-exact equality,
 for the whole fingerprint and for the per-iteration values f_L.
 """
-import os
-import sys
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 import pytest
 
 import oracle
 from paper_2010_08423_amd import inputs
+from parity_util import host_threads, oracle_per, say
 
 pytestmark = pytest.mark.gpu
 
@@ -27,11 +27,6 @@ def setup_module(module):
 
     R = lib
     R.library()
-
-
-def say(*a):
-    print(*a, flush=True)
-    sys.stdout.flush()
 
 
 F1 = [(1, 2, 1), (2, 5, 4), (2, 4, 2), (3, 1, 3), (3, 7, 5), (4, 3, 3), (4, 5, 3), (4, 7, 4), (5, 7, 4), (7, 6, 5)]
@@ -246,54 +241,66 @@ def test_trace_lines(capfd):
     assert "[rs-trace]" not in capfd.readouterr().err  # off again
 
 
-def _threads():
-    try:
-        return max(1, min(16, len(os.sched_getaffinity(0))))
-    except Exception:  # noqa: BLE001
-        return 4
-
-
-def test_config_path_scale_sampled():
+def test_config_path_scale_all_iterations():
     """Chung-Lu n=1e5, m=1e6, delta=10, k=8 at full size in the default launch
-    shape; f_L of sampled iterations against the oracle, F = XOR of all f_L."""
+    shape (the benchmarked query): all 256 f_L against the oracle, and F =
+    XOR of all f_L."""
     g, q = inputs.config_path_scale()
     gd = R.Graph.from_inputs(g)
     r = R.run(gd, q.k, q.delta, q.seed, per_iteration=True)
     assert int(np.bitwise_xor.reduce(r.per_iteration)) == r.fingerprint
-    assert r.per_iteration[0] == 0
-    for it in (1, 77, 255):
-        say("cfg2 iteration", it)
-        f = oracle.sieve(g.n, g.src, g.dst, g.t, q.k, q.delta, q.seed, it_begin=it, it_end=it + 1,
-                         threads=_threads())
-        assert int(r.per_iteration[it]) == f, it
+    say("cfg2: oracle over all 256 iterations")
+    per = oracle_per(g, q, 0, 1 << q.k, threads=host_threads())
+    bad = [i for i in range(1 << q.k) if int(r.per_iteration[i]) != int(per[i])]
+    assert not bad, bad[:10]
+    assert r.fingerprint == int(np.bitwise_xor.reduce(per))
 
 
 def test_config_motif_scale_sampled():
     """Chung-Lu(2.2) n=1e6, m=1e7, bursty times, 8 colours, motif of k=10
-    colours, delta=20, at full size in the default launch shape: f_L of two
-    sampled ranges of iterations against the oracle and F = XOR of all f_L.
-    (A second launch shape, 8-edge tiles and one chunk per launch, ran for
-    over 140 s on this graph under the earlier per-tile look-back and is not
-    run here.)"""
+    colours, delta=20, at full size in the default launch shape (four groups
+    of four 64-iteration chunks): f_L of 16 iterations, four in each chunk
+    group, against the oracle, and F = XOR of all f_L."""
     say("cfg3 graph")
     g, q = inputs.config_motif_scale()
     gd = R.Graph.from_inputs(g)
     say("cfg3 GPU query")
     r = R.run(gd, q.k, q.delta, q.seed, motif=q.motif, per_iteration=True)
     assert int(np.bitwise_xor.reduce(r.per_iteration)) == r.fingerprint
-    # two ranges of 2 iterations, oracle calls side by side (each on 2 threads;
-    # one iteration of this workload is tens of seconds of oracle time)
-    from concurrent.futures import ThreadPoolExecutor
-
-    def oracle_range(a):
-        return oracle.sieve(g.n, g.src, g.dst, g.t, q.k, q.delta, q.seed, colour=g.colour, n_colours=g.n_colours,
-                            motif=q.motif, it_begin=a, it_end=a + 2, threads=2, per_iteration=True)[1]
-
-    starts = (517, 1022)
-    oracle._load()  # build/load once before the two calls run side by side
-    say("cfg3 oracle iterations", [(a, a + 2) for a in starts])
-    with ThreadPoolExecutor(max_workers=2) as ex:
-        pers = list(ex.map(oracle_range, starts))
+    starts = (62, 317, 517, 1020)  # one range in each group of 256 iterations
+    per_call = max(1, host_threads() // len(starts))
+    oracle._load()  # build or load once before the calls run side by side
+    say("cfg3 oracle iterations", [(a, a + 4) for a in starts], "threads per call", per_call)
+    with ThreadPoolExecutor(max_workers=len(starts)) as ex:
+        pers = list(ex.map(lambda a: oracle_per(g, q, a, a + 4, threads=per_call), starts))
     say("cfg3 oracle done")
     for a, per in zip(starts, pers):
-        assert [int(x) for x in r.per_iteration[a:a + 2]] == [int(x) for x in per], a
+        assert [int(x) for x in r.per_iteration[a:a + 4]] == [int(x) for x in per], a
+
+
+def test_graph_create_device_tensors():
+    """rs_graph_create_device with torch tensors in HBM (int32 and uint8,
+    including duplicates and self-loops): the same canonical graph and the
+    same fingerprints as the host upload and the oracle."""
+    import torch
+
+    g = inputs.add_colours(inputs.chung_lu_graph(400, 5000, 2.4, 30, seed=77), 5, seed=77)
+    rng = np.random.default_rng(78)
+    dup = rng.integers(0, g.m, 300)
+    src = np.concatenate([g.src, g.src[dup], np.array([3, 9], np.uint32)])
+    dst = np.concatenate([g.dst, g.dst[dup], np.array([3, 9], np.uint32)])
+    t = np.concatenate([g.t, g.t[dup], np.array([4, 7], np.uint32)])
+    gh = R.Graph(g.n, src, dst, t, colour=g.colour, n_colours=g.n_colours)
+    dev = torch.device("cuda", 0)
+    gt = R.Graph(g.n, torch.from_numpy(src.astype(np.int32)).to(dev), torch.from_numpy(dst.astype(np.int32)).to(dev),
+                 torch.from_numpy(t.astype(np.int32)).to(dev), colour=torch.from_numpy(g.colour).to(dev),
+                 n_colours=g.n_colours)
+    for a, b in zip(gh.edges(), gt.edges()):
+        assert np.array_equal(a, b)
+    ih, it = gh.info(), gt.info()
+    assert ih == it and it["self_loops"] == 2 and it["duplicates"] == 300
+    motif = np.array([2, 0, 1, 1, 1], np.uint8)
+    for k, delta, mot in ((6, 3, None), (5, 4, motif)):
+        F = oracle.sieve(g.n, g.src, g.dst, g.t, k, delta, 91, colour=g.colour, n_colours=g.n_colours, motif=mot)
+        assert R.run(gt, k, delta, 91, motif=mot).fingerprint == F
+        assert R.run(gh, k, delta, 91, motif=mot).fingerprint == F
