@@ -63,6 +63,13 @@ def _load():
     lib.orc_sieve.argtypes = graph_args + [u64, u64, u64, ctypes.c_int, _u64p, _u64p]
     lib.orc_closed_form.restype = ctypes.c_int
     lib.orc_closed_form.argtypes = graph_args + [u64, _u64p, _u64p]
+    lib.orc_sieve_ex.restype = ctypes.c_int
+    lib.orc_sieve_ex.argtypes = graph_args + [_u8p, _u8p, u64, u64, u64, ctypes.c_int, _u64p, _u64p]
+    lib.orc_fine_grained.restype = ctypes.c_int
+    lib.orc_fine_grained.argtypes = graph_args + [_u8p, _u8p, u64, u64, u64, ctypes.c_int, _u64p, _u64p, _u32p,
+                                                  _u64p]
+    lib.orc_closed_form_ex.restype = ctypes.c_int
+    lib.orc_closed_form_ex.argtypes = graph_args + [_u8p, _u8p, u64, _u64p, _u64p, _u64p, _u64p, _u64p]
     lib.orc_count_paths.restype = ctypes.c_int
     lib.orc_count_paths.argtypes = graph_args + [_u64p]
     lib.orc_gf_det.restype = u64
@@ -143,21 +150,89 @@ def z_table(n, k, seed, colour=None, n_colours=0, motif=None) -> np.ndarray:
     return z[:n]
 
 
+def _mask(n, vertices):
+    """uint8 membership array of a vertex list (None: no constraint)."""
+    if vertices is None:
+        return None
+    a = np.zeros(max(n, 1), dtype=np.uint8)
+    a[np.asarray(vertices, dtype=np.int64)] = 1
+    return a
+
+
 def sieve(n, src, dst, t, k, delta, seed, colour=None, n_colours=0, motif=None,
-          it_begin=0, it_end=0, threads=1, per_iteration=False):
+          it_begin=0, it_end=0, threads=1, per_iteration=False, sources=None, targets=None):
     """Fingerprint F over iterations [it_begin, it_end) (0, 0 = all 2^k).
+    sources / targets: vertex lists the paths must start / end in (None: any).
     With per_iteration=True returns (F, array of f_L for the range)."""
     args, keep = _graph_args(n, src, dst, t, colour, n_colours, k, delta, motif)
     F = ctypes.c_uint64(0)
     span = (it_end - it_begin) if (it_begin or it_end) else (1 << k)
     per = np.zeros(max(span, 1), dtype=np.uint64) if per_iteration else None
-    rc = _load().orc_sieve(*args, seed, it_begin, it_end, threads, ctypes.byref(F), _ptr(per, _u64p))
+    sm, tm = _mask(n, sources), _mask(n, targets)
+    rc = _load().orc_sieve_ex(*args, _ptr(sm, _u8p), _ptr(tm, _u8p), seed, it_begin, it_end, threads, ctypes.byref(F),
+                              _ptr(per, _u64p))
     del keep
     if rc:
         raise ValueError(f"orc_sieve rejected the query (rc={rc})")
     if per_iteration:
         return F.value, per[:span]
     return F.value
+
+
+UNREACHED = 0xFFFFFFFF
+
+
+def fine_grained(n, src, dst, t, k, delta, seed, colour=None, n_colours=0, motif=None, it_begin=0, it_end=0,
+                 threads=1, sources=None, targets=None):
+    """Fine-grained oracle (Alg. 1): returns (zeta, reach, F) with zeta[e] the
+    zeta_{u,k,i} of the slot (dst, t) of each canonical edge e (order of
+    canonical_edges), reach[u] = least i with zeta_{u,k,i} != 0 (UNREACHED if
+    none) and F the sum of all zeta."""
+    args, keep = _graph_args(n, src, dst, t, colour, n_colours, k, delta, motif)
+    m = len(keep[0])
+    zeta = np.zeros(max(m, 1), dtype=np.uint64)
+    reach = np.zeros(max(n, 1), dtype=np.uint32)
+    mc = ctypes.c_uint64(0)
+    F = ctypes.c_uint64(0)
+    sm, tm = _mask(n, sources), _mask(n, targets)
+    rc = _load().orc_fine_grained(*args, _ptr(sm, _u8p), _ptr(tm, _u8p), seed, it_begin, it_end, threads,
+                                  _ptr(zeta, _u64p), ctypes.byref(mc), _ptr(reach, _u32p), ctypes.byref(F))
+    del keep
+    if rc:
+        raise ValueError(f"orc_fine_grained rejected the query (rc={rc})")
+    return zeta[:mc.value], reach[:n], F.value
+
+
+def closed_form_slots(n, src, dst, t, k, delta, seed, colour=None, n_colours=0, motif=None, sources=None,
+                      targets=None):
+    """Closed form per slot: (zeta, count, F) with zeta[e] / count[e] the XOR of
+    (prod y) det Z_P / the number of (colour-agreeing) restless paths whose
+    last edge arrives at the slot (dst, t) of canonical edge e."""
+    args, keep = _graph_args(n, src, dst, t, colour, n_colours, k, delta, motif)
+    m = len(keep[0])
+    zeta = np.zeros(max(m, 1), dtype=np.uint64)
+    cnt = np.zeros(max(m, 1), dtype=np.uint64)
+    mc = ctypes.c_uint64(0)
+    F = ctypes.c_uint64(0)
+    npaths = ctypes.c_uint64(0)
+    sm, tm = _mask(n, sources), _mask(n, targets)
+    rc = _load().orc_closed_form_ex(*args, _ptr(sm, _u8p), _ptr(tm, _u8p), seed, ctypes.byref(F), ctypes.byref(npaths),
+                                    _ptr(zeta, _u64p), _ptr(cnt, _u64p), ctypes.byref(mc))
+    del keep
+    if rc:
+        raise ValueError(f"orc_closed_form_ex rejected the query (rc={rc})")
+    return zeta[:mc.value], cnt[:mc.value], F.value
+
+
+def canonical_edges(src, dst, t):
+    """The canonical edge list the oracle and the library index by: distinct
+    (src, dst, t) triples without self-loops, sorted by (dst, t, src)."""
+    src = np.asarray(src, dtype=np.int64)
+    dst = np.asarray(dst, dtype=np.int64)
+    t = np.asarray(t, dtype=np.int64)
+    keep = src != dst
+    trip = np.unique(np.stack([dst[keep], t[keep], src[keep]], axis=1), axis=0).reshape(-1, 3)
+    return trip[:, 2].astype(np.uint32), trip[:, 0].astype(np.uint32), trip[:, 1].astype(np.uint32)
 
 
 def closed_form(n, src, dst, t, k, delta, seed, colour=None, n_colours=0, motif=None):

@@ -284,10 +284,17 @@ static uint64_t orc_window(const orc_graph* g, const uint64_t* chi, uint32_t v, 
   return acc;
 }
 
-/* f_L for one subset L (bit j-1 of L <-> j in L). */
-static uint64_t orc_eval_L(const orc_graph* g, const uint64_t* z, uint32_t k, const uint32_t* delta,
-                           uint64_t seed, uint64_t L, uint64_t* zL, uint64_t* chi_prev,
-                           uint64_t* chi_cur) {
+/* chi_{u,k,i} for every slot (u, i), for one subset L (bit j-1 of L <-> j in
+ * L): levels 1..k of Eq. (poly-enc:1). With source_mask != NULL only the
+ * vertices u with source_mask[u] != 0 carry a level-1 term (chi_{u,1,i} =
+ * z^L_u for them, 0 for every other vertex), so only walks that start in
+ * that set are generated: the source constraint of the reachability problems
+ * of Sec. 3. Returns the array (chi_a or chi_b) that holds level k. */
+static uint64_t* orc_levels_L(const orc_graph* g, const uint64_t* z, uint32_t k, const uint32_t* delta,
+                              const uint8_t* source_mask, uint64_t seed, uint64_t L, uint64_t* zL,
+                              uint64_t* chi_a, uint64_t* chi_b) {
+  uint64_t* chi_prev = chi_a;
+  uint64_t* chi_cur = chi_b;
   for (uint32_t u = 0; u < g->n; u++) {
     uint64_t s = 0;
     for (uint32_t j = 1; j <= k; j++)
@@ -300,6 +307,7 @@ static uint64_t orc_eval_L(const orc_graph* g, const uint64_t* z, uint32_t k, co
       uint64_t acc = 0;
       for (uint64_t ei = g->slot_e[sl]; ei < g->slot_e[sl + 1]; ei++) {
         const orc_edge* e = &g->e[ei];
+        if (source_mask && !source_mask[e->src]) continue; /* chi_{src,1,.} = 0 */
         acc ^= orc_gf_mul_nibble(orc_y(seed, e->src, e->dst, e->t, 1), zL[e->src]);
       }
       chi_prev[sl] = orc_gf_mul_nibble(zL[u], acc);
@@ -322,8 +330,22 @@ static uint64_t orc_eval_L(const orc_graph* g, const uint64_t* z, uint32_t k, co
     chi_prev = chi_cur;
     chi_cur = tmp;
   }
+  return chi_prev;
+}
+
+/* f_L for one subset L: the sum of chi_{u,k,i} over all slots (u, i), or,
+ * with target_mask != NULL, over the slots of the vertices u with
+ * target_mask[u] != 0 (paths ending in that set: the destination of the
+ * problems of Sec. 3). */
+static uint64_t orc_eval_L(const orc_graph* g, const uint64_t* z, uint32_t k, const uint32_t* delta,
+                           const uint8_t* source_mask, const uint8_t* target_mask, uint64_t seed, uint64_t L,
+                           uint64_t* zL, uint64_t* chi_a, uint64_t* chi_b) {
+  const uint64_t* chi = orc_levels_L(g, z, k, delta, source_mask, seed, L, zL, chi_a, chi_b);
   uint64_t f = 0;
-  for (uint64_t sl = 0; sl < g->n_slots; sl++) f ^= chi_prev[sl];
+  for (uint32_t u = 0; u < g->n; u++) {
+    if (target_mask && !target_mask[u]) continue;
+    for (uint64_t sl = g->v_off[u]; sl < g->v_off[u + 1]; sl++) f ^= chi[sl];
+  }
   return f;
 }
 
@@ -332,6 +354,16 @@ int orc_sieve(uint32_t n, uint64_t m, const uint32_t* src, const uint32_t* dst,
               uint32_t k, const uint32_t* delta, const uint8_t* motif_count,
               uint64_t seed, uint64_t it_begin, uint64_t it_end, int threads,
               uint64_t* F_out, uint64_t* per_it) {
+  return orc_sieve_ex(n, m, src, dst, t, colour, n_colours, k, delta, motif_count, NULL, NULL, seed, it_begin,
+                      it_end, threads, F_out, per_it);
+}
+
+int orc_sieve_ex(uint32_t n, uint64_t m, const uint32_t* src, const uint32_t* dst,
+                 const uint32_t* t, const uint8_t* colour, uint32_t n_colours,
+                 uint32_t k, const uint32_t* delta, const uint8_t* motif_count,
+                 const uint8_t* source_mask, const uint8_t* target_mask,
+                 uint64_t seed, uint64_t it_begin, uint64_t it_end, int threads,
+                 uint64_t* F_out, uint64_t* per_it) {
   if (!F_out) return -1;
   int rc = orc_check_query(n, colour, n_colours, k, delta, motif_count);
   if (rc) return rc;
@@ -369,7 +401,7 @@ int orc_sieve(uint32_t n, uint64_t m, const uint32_t* src, const uint32_t* dst,
 #pragma omp for schedule(dynamic, 1)
 #endif
       for (int64_t it = (int64_t)it_begin; it < (int64_t)it_end; it++) {
-        uint64_t f = orc_eval_L(&g, z, k, delta, seed, (uint64_t)it, zL, c0, c1);
+        uint64_t f = orc_eval_L(&g, z, k, delta, source_mask, target_mask, seed, (uint64_t)it, zL, c0, c1);
         if (per_it) per_it[(uint64_t)it - it_begin] = f;
         F ^= f;
       }
@@ -383,6 +415,98 @@ int orc_sieve(uint32_t n, uint64_t m, const uint32_t* src, const uint32_t* dst,
   if (failed) return -2;
   *F_out = F;
   return 0;
+}
+
+/* ---------------------------------------------------------------------------
+ * Fine-grained oracle (Alg. 1, FineGrainedOracle): per slot (u, i), the sum
+ * over L of chi_{u,k,i}, i.e. zeta_{u,k,i}, without summing over (u, i).
+ * zeta_{u,k,i} != 0 says a restless path with k vertices ending at u at time
+ * i exists (Sec. 4.5); R_u is the least such i and D the vertices that have
+ * one. zeta_edge (may be NULL; m entries) receives, for each canonical edge
+ * (deduplicated, self-loops dropped, sorted by (dst, t, src)) in that order,
+ * the zeta of its slot (dst, t); *m_canon_out its number of edges. reach_out
+ * (n entries) receives R_u, or 0xFFFFFFFF where no slot of u is non-zero.
+ * F_out (may be NULL) receives the sum of zeta over the slots of the target
+ * vertices (all vertices when target_mask is NULL), which equals the
+ * orc_sieve_ex fingerprint of the same query.
+ * ------------------------------------------------------------------------ */
+int orc_fine_grained(uint32_t n, uint64_t m, const uint32_t* src, const uint32_t* dst,
+                     const uint32_t* t, const uint8_t* colour, uint32_t n_colours,
+                     uint32_t k, const uint32_t* delta, const uint8_t* motif_count,
+                     const uint8_t* source_mask, const uint8_t* target_mask, uint64_t seed,
+                     uint64_t it_begin, uint64_t it_end, int threads, uint64_t* zeta_edge,
+                     uint64_t* m_canon_out, uint32_t* reach_out, uint64_t* F_out) {
+  if (!reach_out) return -1;
+  int rc = orc_check_query(n, colour, n_colours, k, delta, motif_count);
+  if (rc) return rc;
+  uint64_t total = 1ull << k;
+  if (it_begin == 0 && it_end == 0) it_end = total;
+  if (it_begin > it_end || it_end > total) return -1;
+  orc_graph g;
+  rc = orc_graph_build(n, m, src, dst, t, &g);
+  if (rc) return rc;
+  uint64_t* z = (uint64_t*)malloc(sizeof(uint64_t) * ((uint64_t)n * k + 1));
+  uint64_t* zeta = (uint64_t*)calloc(g.n_slots + 1, sizeof(uint64_t));
+  if (!z || !zeta) {
+    free(z);
+    free(zeta);
+    orc_graph_free(&g);
+    return -2;
+  }
+  rc = orc_z_table(n, colour, n_colours, k, motif_count, seed, z);
+  int nthr = threads > 1 ? threads : 1;
+  int failed = 0;
+  if (!rc) {
+#ifdef _OPENMP
+#pragma omp parallel num_threads(nthr) reduction(| : failed)
+#endif
+    {
+      uint64_t* zL = (uint64_t*)malloc(sizeof(uint64_t) * ((uint64_t)n + 1));
+      uint64_t* c0 = (uint64_t*)malloc(sizeof(uint64_t) * (g.n_slots + 1));
+      uint64_t* c1 = (uint64_t*)malloc(sizeof(uint64_t) * (g.n_slots + 1));
+      uint64_t* mine = (uint64_t*)calloc(g.n_slots + 1, sizeof(uint64_t));
+      if (!zL || !c0 || !c1 || !mine) {
+        failed = 1;
+      } else {
+#ifdef _OPENMP
+#pragma omp for schedule(dynamic, 1)
+#endif
+        for (int64_t it = (int64_t)it_begin; it < (int64_t)it_end; it++) {
+          const uint64_t* chi = orc_levels_L(&g, z, k, delta, source_mask, seed, (uint64_t)it, zL, c0, c1);
+          for (uint64_t sl = 0; sl < g.n_slots; sl++) mine[sl] ^= chi[sl];
+        }
+#ifdef _OPENMP
+#pragma omp critical
+#endif
+        for (uint64_t sl = 0; sl < g.n_slots; sl++) zeta[sl] ^= mine[sl];
+      }
+      free(zL);
+      free(c0);
+      free(c1);
+      free(mine);
+    }
+  }
+  if (!rc && !failed) {
+    uint64_t F = 0;
+    for (uint32_t u = 0; u < n; u++) {
+      reach_out[u] = 0xFFFFFFFFu;
+      for (uint64_t sl = g.v_off[u]; sl < g.v_off[u + 1]; sl++) {
+        if (target_mask && !target_mask[u]) zeta[sl] = 0; /* only paths ending at a target count */
+        F ^= zeta[sl];
+        if (zeta[sl] && g.slot_t[sl] < reach_out[u]) reach_out[u] = g.slot_t[sl];
+      }
+    }
+    if (zeta_edge)
+      for (uint64_t sl = 0; sl < g.n_slots; sl++)
+        for (uint64_t ei = g.slot_e[sl]; ei < g.slot_e[sl + 1]; ei++) zeta_edge[ei] = zeta[sl];
+    if (m_canon_out) *m_canon_out = g.m;
+    if (F_out) *F_out = F;
+  }
+  free(z);
+  free(zeta);
+  orc_graph_free(&g);
+  if (rc) return rc;
+  return failed ? -2 : 0;
 }
 
 /* ---------------------------------------------------------------------------
@@ -450,6 +574,10 @@ typedef struct {
   uint32_t n_colours;
   const uint64_t* z; /* closed form only */
   uint64_t seed;
+  const uint8_t* source_mask; /* NULL = any start vertex */
+  const uint8_t* target_mask; /* NULL = any end vertex */
+  uint64_t* acc_edge;         /* NULL, or per canonical edge: sum of the paths whose last edge it is */
+  uint64_t* cnt_edge;         /* NULL, or per canonical edge: number of those paths */
   uint32_t path_v[32];
   uint64_t path_e[32];
   uint64_t count;
@@ -469,11 +597,17 @@ static int orc_colours_agree(const orc_dfs* d) {
 }
 
 static void orc_dfs_record(orc_dfs* d) {
+  if (d->target_mask && !d->target_mask[d->path_v[d->k - 1]]) return;
+  const uint64_t last = d->path_e[d->k - 2];
   if (!d->closed) {
-    if (!d->motif || orc_colours_agree(d)) d->count++;
+    if (!d->motif || orc_colours_agree(d)) {
+      d->count++;
+      if (d->cnt_edge) d->cnt_edge[last]++;
+    }
     return;
   }
   d->count++;
+  if (d->cnt_edge && (!d->motif || orc_colours_agree(d))) d->cnt_edge[last]++;
   uint64_t Y = 1;
   for (uint32_t p = 1; p < d->k; p++) {
     const orc_edge* e = &d->g->e[d->path_e[p - 1]];
@@ -482,7 +616,9 @@ static void orc_dfs_record(orc_dfs* d) {
   uint64_t Z[32 * 32];
   for (uint32_t p = 0; p < d->k; p++)
     for (uint32_t j = 0; j < d->k; j++) Z[p * d->k + j] = d->z[(uint64_t)d->path_v[p] * d->k + j];
-  d->F ^= orc_gf_mul(Y, orc_gf_det(Z, (int)d->k));
+  const uint64_t term = orc_gf_mul(Y, orc_gf_det(Z, (int)d->k));
+  d->F ^= term;
+  if (d->acc_edge) d->acc_edge[last] ^= term;
 }
 
 static void orc_dfs_extend(orc_dfs* d, uint32_t depth, uint32_t last_t) {
@@ -511,7 +647,9 @@ static void orc_dfs_extend(orc_dfs* d, uint32_t depth, uint32_t last_t) {
 static int orc_enumerate(uint32_t n, uint64_t m, const uint32_t* src, const uint32_t* dst,
                          const uint32_t* t, const uint8_t* colour, uint32_t n_colours,
                          uint32_t k, const uint32_t* delta, const uint8_t* motif_count,
-                         uint64_t seed, int closed, uint64_t* F_out, uint64_t* count_out) {
+                         const uint8_t* source_mask, const uint8_t* target_mask,
+                         uint64_t seed, int closed, uint64_t* F_out, uint64_t* count_out,
+                         uint64_t* zeta_edge, uint64_t* count_edge, uint64_t* m_canon_out) {
   int rc = orc_check_query(n, colour, n_colours, k, delta, motif_count);
   if (rc) return rc;
   if (k > 32) return -1;
@@ -528,8 +666,12 @@ static int orc_enumerate(uint32_t n, uint64_t m, const uint32_t* src, const uint
   d.n_colours = n_colours;
   d.seed = seed;
   d.closed = closed;
+  d.source_mask = source_mask;
+  d.target_mask = target_mask;
   d.out_off = (uint64_t*)calloc((size_t)n + 1, sizeof(uint64_t));
   d.out_e = (uint64_t*)malloc(sizeof(uint64_t) * (g.m ? g.m : 1));
+  if (zeta_edge) d.acc_edge = (uint64_t*)calloc(g.m + 1, sizeof(uint64_t));
+  if (count_edge) d.cnt_edge = (uint64_t*)calloc(g.m + 1, sizeof(uint64_t));
   uint64_t* z = NULL;
   if (closed) {
     z = (uint64_t*)malloc(sizeof(uint64_t) * ((uint64_t)n * k + 1));
@@ -544,15 +686,31 @@ static int orc_enumerate(uint32_t n, uint64_t m, const uint32_t* src, const uint
     for (uint64_t i = 0; i < g.m; i++) d.out_e[fill[g.e[i].src]++] = i;
     free(fill);
     for (uint32_t v = 0; v < n; v++) {
+      if (source_mask && !source_mask[v]) continue;
       d.path_v[0] = v;
       orc_dfs_extend(&d, 1, 0);
     }
     if (F_out) *F_out = d.F;
     if (count_out) *count_out = d.count;
+    /* per slot (dst, t): the sum (count) over the slot's edges, stored at each of them */
+    for (uint64_t sl = 0; sl < g.n_slots; sl++) {
+      uint64_t zs = 0, cs = 0;
+      for (uint64_t ei = g.slot_e[sl]; ei < g.slot_e[sl + 1]; ei++) {
+        if (d.acc_edge) zs ^= d.acc_edge[ei];
+        if (d.cnt_edge) cs += d.cnt_edge[ei];
+      }
+      for (uint64_t ei = g.slot_e[sl]; ei < g.slot_e[sl + 1]; ei++) {
+        if (zeta_edge) zeta_edge[ei] = zs;
+        if (count_edge) count_edge[ei] = cs;
+      }
+    }
+    if (m_canon_out) *m_canon_out = g.m;
   }
   free(z);
   free(d.out_off);
   free(d.out_e);
+  free(d.acc_edge);
+  free(d.cnt_edge);
   orc_graph_free(&g);
   return rc;
 }
@@ -561,14 +719,24 @@ int orc_closed_form(uint32_t n, uint64_t m, const uint32_t* src, const uint32_t*
                     const uint32_t* t, const uint8_t* colour, uint32_t n_colours,
                     uint32_t k, const uint32_t* delta, const uint8_t* motif_count,
                     uint64_t seed, uint64_t* F_out, uint64_t* n_paths_out) {
-  return orc_enumerate(n, m, src, dst, t, colour, n_colours, k, delta, motif_count, seed, 1, F_out,
-                       n_paths_out);
+  return orc_enumerate(n, m, src, dst, t, colour, n_colours, k, delta, motif_count, NULL, NULL, seed, 1, F_out,
+                       n_paths_out, NULL, NULL, NULL);
+}
+
+int orc_closed_form_ex(uint32_t n, uint64_t m, const uint32_t* src, const uint32_t* dst,
+                       const uint32_t* t, const uint8_t* colour, uint32_t n_colours,
+                       uint32_t k, const uint32_t* delta, const uint8_t* motif_count,
+                       const uint8_t* source_mask, const uint8_t* target_mask, uint64_t seed,
+                       uint64_t* F_out, uint64_t* n_paths_out, uint64_t* zeta_edge, uint64_t* count_edge,
+                       uint64_t* m_canon_out) {
+  return orc_enumerate(n, m, src, dst, t, colour, n_colours, k, delta, motif_count, source_mask, target_mask, seed,
+                       1, F_out, n_paths_out, zeta_edge, count_edge, m_canon_out);
 }
 
 int orc_count_paths(uint32_t n, uint64_t m, const uint32_t* src, const uint32_t* dst,
                     const uint32_t* t, const uint8_t* colour, uint32_t n_colours,
                     uint32_t k, const uint32_t* delta, const uint8_t* motif_count,
                     uint64_t* count_out) {
-  return orc_enumerate(n, m, src, dst, t, colour, n_colours, k, delta, motif_count, 0, 0, NULL,
-                       count_out);
+  return orc_enumerate(n, m, src, dst, t, colour, n_colours, k, delta, motif_count, NULL, NULL, 0, 0, NULL,
+                       count_out, NULL, NULL, NULL);
 }

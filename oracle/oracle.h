@@ -71,6 +71,35 @@ int orc_sieve(uint32_t n, uint64_t m, const uint32_t* src, const uint32_t* dst,
               uint64_t seed, uint64_t it_begin, uint64_t it_end, int threads,
               uint64_t* F_out, uint64_t* per_it);
 
+/* As orc_sieve, with the source and destination constraints of the problems
+ * of Sec. 3: source_mask (n bytes, NULL = every vertex) keeps only the walks
+ * that start at a vertex u with source_mask[u] != 0 (the level-1 terms of
+ * Eq. poly-enc:1 of every other vertex are 0); target_mask (n bytes, NULL =
+ * every vertex) sums the last level only over the end vertices u with
+ * target_mask[u] != 0. */
+int orc_sieve_ex(uint32_t n, uint64_t m, const uint32_t* src, const uint32_t* dst,
+                 const uint32_t* t, const uint8_t* colour, uint32_t n_colours,
+                 uint32_t k, const uint32_t* delta, const uint8_t* motif_count,
+                 const uint8_t* source_mask, const uint8_t* target_mask,
+                 uint64_t seed, uint64_t it_begin, uint64_t it_end, int threads,
+                 uint64_t* F_out, uint64_t* per_it);
+
+/* Fine-grained oracle (Alg. 1, FineGrainedOracle; Sec. 4.5): zeta_{u,k,i},
+ * the sum over the iterations of [it_begin, it_end) of the last level's value
+ * at slot (u, i), kept per slot. Outputs, for the canonical edge list
+ * (deduplicated, self-loops dropped, sorted by (dst, t, src); *m_canon_out
+ * edges): zeta_edge[e] = zeta of the slot (dst(e), t(e)) (NULL = not wanted;
+ * caller sizes it to m); reach_out[u] = least time i with zeta_{u,k,i} != 0,
+ * 0xFFFFFFFF if none (D = the vertices with a finite R_u); F_out (may be NULL)
+ * = the sum of all zeta, which is the orc_sieve_ex fingerprint. Masks as in
+ * orc_sieve_ex (slots of non-target vertices are 0). */
+int orc_fine_grained(uint32_t n, uint64_t m, const uint32_t* src, const uint32_t* dst,
+                     const uint32_t* t, const uint8_t* colour, uint32_t n_colours,
+                     uint32_t k, const uint32_t* delta, const uint8_t* motif_count,
+                     const uint8_t* source_mask, const uint8_t* target_mask, uint64_t seed,
+                     uint64_t it_begin, uint64_t it_end, int threads, uint64_t* zeta_edge,
+                     uint64_t* m_canon_out, uint32_t* reach_out, uint64_t* F_out);
+
 /* Closed form: XOR over all restless paths P with k vertices (motif mode:
  * z from the shade sum, so colour-mismatched paths contribute det = 0) of
  * (prod_p y_{e_p,p}) * det Z_P. n_paths_out counts the paths enumerated
@@ -79,6 +108,18 @@ int orc_closed_form(uint32_t n, uint64_t m, const uint32_t* src, const uint32_t*
                     const uint32_t* t, const uint8_t* colour, uint32_t n_colours,
                     uint32_t k, const uint32_t* delta, const uint8_t* motif_count,
                     uint64_t seed, uint64_t* F_out, uint64_t* n_paths_out);
+
+/* Closed form per slot, with the masks of orc_sieve_ex (paths that start at a
+ * source and end at a target): zeta_edge[e] (may be NULL; sized m) = XOR of
+ * (prod_p y) det Z_P over the paths whose last edge arrives at the slot
+ * (dst(e), t(e)); count_edge[e] (may be NULL) = the number of such paths
+ * (colour-agreeing ones in motif mode), for every edge of that slot. */
+int orc_closed_form_ex(uint32_t n, uint64_t m, const uint32_t* src, const uint32_t* dst,
+                       const uint32_t* t, const uint8_t* colour, uint32_t n_colours,
+                       uint32_t k, const uint32_t* delta, const uint8_t* motif_count,
+                       const uint8_t* source_mask, const uint8_t* target_mask, uint64_t seed,
+                       uint64_t* F_out, uint64_t* n_paths_out, uint64_t* zeta_edge, uint64_t* count_edge,
+                       uint64_t* m_canon_out);
 
 /* Exhaustive temporal DFS: number of restless paths with k vertices whose
  * colours agree with the motif (all paths when motif_count == NULL). */
