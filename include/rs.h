@@ -178,6 +178,24 @@ rs_status rs_run(const rs_graph* g, const rs_query* q, rs_result* r, void* hip_s
 rs_status rs_run_ex(const rs_graph* g, const rs_query* q, const rs_tuning* tune,
                     uint64_t* per_iteration, rs_result* r, void* hip_stream);
 
+/* For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc): rs_run_ex without
+ * tuning knobs, whose query workspace (window indices, substitution and
+ * product rows, flags, prefix states, look-back records, partial sums) is
+ * carved from one 256 MiB array in device memory that the library holds per
+ * GPU from the first such call until the process ends. The call allocates and
+ * frees no device memory and records no events (device_ms = 0; kernel timing
+ * and the launch trace skip it); it runs one 64-iteration chunk per launch.
+ * A query whose workspace exceeds the array (its footprint at one chunk per
+ * launch; about 1 KiB per edge-and-vertex slot plus 8 kq (k-1) bytes per edge)
+ * fails with RS_ENOMEM and rs_last_error() says by how much. All calls on one
+ * GPU share the array: the library serialises them (each returns after its
+ * kernels finish), and the array keeps the last call's contents, which the
+ * next call clears where it must (the look-back records). per_iteration as in
+ * rs_run_ex. */
+rs_status rs_run_noalloc(const rs_graph* g, const rs_query* q, uint64_t* per_iteration, rs_result* r,
+                         void* hip_stream);
+
 /* Batched path: nq queries, each on its own graph (graphs[i]; graphs may
  * repeat), evaluated together. Every (query, 64-iteration chunk) is a unit
  * with its own prefix-state buffers; units are packed into rounds, and four

@@ -96,6 +96,8 @@ _SIGNATURES = {
     "rs_run": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(_Query), ctypes.POINTER(_Result), ctypes.c_void_p]),
     "rs_run_ex": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(_Query), ctypes.POINTER(_Tuning), _u64p,
                                    ctypes.POINTER(_Result), ctypes.c_void_p]),
+    "rs_run_noalloc": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(_Query), _u64p, ctypes.POINTER(_Result),
+                                        ctypes.c_void_p]),
     "rs_run_batch": (ctypes.c_int32, [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(_Query), ctypes.c_uint32,
                                       ctypes.POINTER(_Result), ctypes.POINTER(_Tuning), ctypes.c_void_p]),
     "rs_autotune": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(_Query), ctypes.c_uint32,
@@ -302,6 +304,26 @@ def run(graph: Graph, k, delta, seed, motif=None, it_begin=0, it_end=0, tuning: 
                           _stream_handle(stream))
     del keep
     _check(s, "rs_run_ex")
+    res = Result(r.fingerprint, bool(r.yes), r.status, r.device_ms)
+    if per_iteration:
+        res.per_iteration = per[:span]
+    return res
+
+
+def run_noalloc(graph: Graph, k, delta, seed, motif=None, it_begin=0, it_end=0, per_iteration=False,
+                stream=None) -> Result:
+    """rs_run_noalloc: one query whose workspace lives in the library's
+    per-GPU scratch array (no device allocation during the call)."""
+    q, keep = _make_query(k, delta, seed, motif, it_begin, it_end)
+    r = _Result()
+    per = None
+    span = (it_end - it_begin) if (it_begin or it_end) else (1 << k)
+    if per_iteration:
+        per = np.zeros(max(span, 1), dtype=np.uint64)
+    s = _load().rs_run_noalloc(graph.handle, ctypes.byref(q), per.ctypes.data_as(_u64p) if per is not None else None,
+                               ctypes.byref(r), _stream_handle(stream))
+    del keep
+    _check(s, "rs_run_noalloc")
     res = Result(r.fingerprint, bool(r.yes), r.status, r.device_ms)
     if per_iteration:
         res.per_iteration = per[:span]

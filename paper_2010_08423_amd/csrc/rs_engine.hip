@@ -88,8 +88,8 @@ static double g_bytes[KC_COUNT];
 
 bool profiling_on() { return g_prof_on.load(std::memory_order_relaxed); }
 
-ProfScope::ProfScope(KernelClass k, hipStream_t s, double b) : kc(k), st(s), bytes(b) {
-  if (!profiling_on()) return;
+ProfScope::ProfScope(KernelClass k, hipStream_t s, double b, bool allowed) : kc(k), st(s), bytes(b) {
+  if (!allowed || !profiling_on()) return;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
     e0 = e1 = nullptr;
     return;
@@ -227,13 +227,94 @@ PlainSizes plain_sizes(uint64_t m, uint64_t n, const QueryPlan& qp, const Tuning
   s.need = table_need_bytes(m, k);
   s.cover = 8 * (m + n + 1) + 8 * ((m + n + 1 + 1023) / 1024);  // two difference arrays and block sums
   s.records = 1024 * cpl * tiles;
+  // work-balanced runs, cut for the grid width of a full chunk group
+  s.run_w2 = s.run_w3 = s.run_stride = 0;
+  s.run_pre = s.run_bsum = s.run_boff = s.run_bounds = 0;
+  if (k >= 3 && m) {
+    const uint32_t E = tu.edges_per_tile;
+    s.run_w2 = scan_waves(kq, E, true, (uint32_t)tiles, (uint32_t)cpl, tu.waves_per_block);
+    s.run_w3 = scan_waves(kq, E, false, (uint32_t)tiles, (uint32_t)cpl, tu.waves_per_block);
+    s.run_stride = std::max(s.run_w2, s.run_w3) + 1;
+    const uint64_t levels = k - 2, nb = (tiles + 1023) / 1024;
+    s.run_pre = 4 * tiles * levels;
+    s.run_bsum = s.run_boff = 4 * nb * levels;
+    s.run_bounds = 4ull * s.run_stride * levels;
+  }
   return s;
 }
 
-uint64_t PlainSizes::total() const { return lo + z + q + 2 * p + partial + fsum + 64 + ref + need + cover + 2 * records; }
+uint64_t PlainSizes::total() const {
+  return lo + z + q + 2 * p + partial + fsum + 64 + ref + need + cover + 2 * records + run_pre + run_bsum + run_boff +
+         run_bounds;
+}
 
 uint64_t plain_footprint(const rs_graph* g, const QueryPlan& qp, const Tuning& tu) {
   return plain_sizes(g->g.m, g->g.n, qp, tu).total();
+}
+
+// The buffers of one query in ws: reserved (grown) in an allocating
+// workspace, carved from the borrowed scratch region otherwise. p_elems is
+// the prefix-state size of one chunk of this graph.
+static rs_status acquire_buffers(PlainWorkspace& ws, const PlainSizes& sz, uint64_t p_elems, hipStream_t st) {
+  if (ws.scratch) {
+    uint64_t off = 0;
+    bool fits = true;
+    auto carve = [&](DevBuf& b, uint64_t bytes) {
+      bytes = std::max<uint64_t>((bytes + 255) & ~255ull, 256);
+      if (off + bytes > ws.scratch_bytes) fits = false;
+      b.p = fits ? ws.scratch + off : nullptr;
+      b.bytes = fits ? bytes : 0;
+      off += bytes;
+    };
+    carve(ws.agg, sz.records);
+    carve(ws.incl, sz.records);
+    carve(ws.lo, sz.lo);
+    carve(ws.z, sz.z);
+    carve(ws.q, sz.q);
+    carve(ws.p0, sz.p);
+    carve(ws.p1, sz.p);
+    carve(ws.partial, sz.partial);
+    carve(ws.fsum, sz.fsum);
+    carve(ws.out, 64);
+    carve(ws.ref, sz.ref);
+    carve(ws.need, sz.need);
+    carve(ws.cov_diff, sz.cover);
+    carve(ws.run_pre, sz.run_pre);
+    carve(ws.run_bsum, sz.run_bsum);
+    carve(ws.run_boff, sz.run_boff);
+    carve(ws.run_bounds, sz.run_bounds);
+    if (!fits) {
+      set_last_error("query workspace of " + std::to_string(off) + " bytes exceeds the " +
+                     std::to_string(ws.scratch_bytes) + "-byte scratch of the no-allocation entry point");
+      return RS_ENOMEM;
+    }
+    // The region keeps the previous call's contents: tagged look-back records
+    // must start at tag 0, which no launch uses (epochs restart at 1). The
+    // prefix states need no clearing (every slot a window reads is written
+    // before it is read, leading slots included).
+    RS_HIP(launch_fill64(ws.agg.as<uint64_t>(), 0, 2 * ws.agg.bytes / 8, st));  // agg and incl are adjacent
+    ws.epoch = 0;
+    ws.p_elems_per_chunk = p_elems;
+    return RS_OK;
+  }
+  if (ws.p_elems_per_chunk != p_elems) {  // slot layout differs: rezero
+    ws.p0.release();
+    ws.p1.release();
+    ws.p_elems_per_chunk = p_elems;
+  }
+  if (ws.lo.reserve(sz.lo, st, false) || ws.z.reserve(sz.z, st, false) || ws.q.reserve(sz.q, st, false) ||
+      ws.p0.reserve(sz.p, st, true) || ws.p1.reserve(sz.p, st, true) || ws.partial.reserve(sz.partial, st, false) ||
+      ws.fsum.reserve(sz.fsum, st, false) || ws.out.reserve(64, st, false) || ws.ref.reserve(sz.ref, st, false) ||
+      ws.need.reserve(sz.need, st, false) || ws.cov_diff.reserve(sz.cover, st, false) ||
+      ws.run_pre.reserve(sz.run_pre, st, false) || ws.run_bsum.reserve(sz.run_bsum, st, false) ||
+      ws.run_boff.reserve(sz.run_boff, st, false) || ws.run_bounds.reserve(sz.run_bounds, st, false))
+    return RS_ENOMEM;
+  if (ws.agg.bytes < sz.records || ws.incl.bytes < sz.records) {
+    // tagged records start at epoch 0, which no launch uses
+    if (ws.agg.reserve(sz.records, st, true) || ws.incl.reserve(sz.records, st, true)) return RS_ENOMEM;
+    ws.epoch = 0;
+  }
+  return RS_OK;
 }
 
 rs_status run_plain(rs_graph* g, PlainWorkspace& ws, const QueryPlan& qp, const Tuning& tu, uint64_t* per_it_host,
@@ -241,11 +322,12 @@ rs_status run_plain(rs_graph* g, PlainWorkspace& ws, const QueryPlan& qp, const 
   const GraphDev& G = g->g;
   const uint64_t m = G.m, n = G.n;
   const uint64_t span = qp.it_end - qp.it_begin;
-  if (!ws.ev0) {
+  const bool timed = !ws.scratch;  // the no-allocation workspace records no events
+  if (timed && !ws.ev0) {
     RS_HIP(hipEventCreate(&ws.ev0));
     RS_HIP(hipEventCreate(&ws.ev1));
   }
-  RS_HIP(hipEventRecord(ws.ev0, st));
+  if (timed) RS_HIP(hipEventRecord(ws.ev0, st));
   uint64_t F = 0;
   // No path with k distinct vertices can exist: F is exactly 0.
   const bool trivial = m == 0 || qp.k > n || span == 0;
@@ -256,28 +338,10 @@ rs_status run_plain(rs_graph* g, PlainWorkspace& ws, const QueryPlan& qp, const 
     const uint32_t E = tu.edges_per_tile;
     const uint64_t tiles = (m + E - 1) / E;
     const uint64_t p_elems = (m + n) * 64;
-    if (ws.p_elems_per_chunk != p_elems) {  // slot layout differs: rezero
-      ws.p0.release();
-      ws.p1.release();
-      ws.p_elems_per_chunk = p_elems;
-    }
-    TopArgs ta{};
-    ta.m = (uint32_t)m;
-    ta.edges_per_wave = tu.top_edges_per_tile;
     const PlainSizes sz = plain_sizes(m, n, qp, tu);
-    if (ws.lo.reserve(sz.lo, st, false) || ws.z.reserve(sz.z, st, false) || ws.q.reserve(sz.q, st, false) ||
-        ws.p0.reserve(sz.p, st, true) || ws.p1.reserve(sz.p, st, true) ||
-        ws.partial.reserve(sz.partial, st, false) || ws.fsum.reserve(sz.fsum, st, false) ||
-        ws.out.reserve(64, st, false) || ws.ref.reserve(sz.ref, st, false) || ws.need.reserve(sz.need, st, false) ||
-        ws.cov_diff.reserve(sz.cover, st, false))
-      return RS_ENOMEM;
+    RS_TRY(acquire_buffers(ws, sz, p_elems, st));
     auto need_of = [&](uint32_t l) { return ws.need.as<uint8_t>() + (uint64_t)(l - 2) * need_stride(m); };
-    if (ws.agg.bytes < sz.records || ws.incl.bytes < sz.records) {
-      // tagged records start at epoch 0, which no launch uses
-      if (ws.agg.reserve(sz.records, st, true) || ws.incl.reserve(sz.records, st, true)) return RS_ENOMEM;
-      ws.epoch = 0;
-    }
-    const bool tr = trace_on();
+    const bool tr = timed && trace_on();
     if (tr && ws.lb_stats.reserve(16, st, true)) return RS_ENOMEM;
     auto t_last = std::chrono::steady_clock::now();
     // one trace line: waits for the launches so far, reads the counters
@@ -299,12 +363,12 @@ rs_status run_plain(rs_graph* g, PlainWorkspace& ws, const QueryPlan& qp, const 
       if (ts != RS_OK) return ts;
     }
     {
-      ProfScope ps(KC_ZTABLE, st, 8.0 * n * kq);
+      ProfScope ps(KC_ZTABLE, st, 8.0 * n * kq, timed);
       RS_HIP(launch_ztable(ws.z.as<uint64_t>(), (uint32_t)n, qp, G.colour.as<uint8_t>(), st));
     }
-    uint32_t run_w2 = 0, run_w3 = 0, run_stride = 0;
+    const uint32_t run_w2 = sz.run_w2, run_w3 = sz.run_w3, run_stride = sz.run_stride;
     {
-      ProfScope ps(KC_WINDOW, st, 16.0 * m);
+      ProfScope ps(KC_WINDOW, st, 16.0 * m, timed);
       RS_HIP(launch_window(G.e_src.as<uint32_t>(), G.e_t.as<uint32_t>(), G.in_off.as<uint32_t>(),
                            ws.lo.as<uint32_t>(), (uint32_t)m, qp.delta, st));
       // Flags per prefix level, from the last one down: level l stores the
@@ -317,19 +381,9 @@ rs_status run_plain(rs_graph* g, PlainWorkspace& ws, const QueryPlan& qp, const 
       // work-balanced runs of the prefix levels, cut for the grid width of
       // the first chunk group (later groups launch the same width)
       if (k >= 3) {
-        const uint32_t gc0 = (uint32_t)cpl;
-        run_w2 = scan_waves(kq, E, true, (uint32_t)tiles, gc0, tu.waves_per_block);
-        run_w3 = scan_waves(kq, E, false, (uint32_t)tiles, gc0, tu.waves_per_block);
-        run_stride = std::max(run_w2, run_w3) + 1;
-        const uint64_t levels = k - 2, nb = (tiles + 1023) / 1024;
-        if (ws.run_pre.reserve(4 * tiles * levels, st, false) || ws.run_bsum.reserve(4 * nb * levels, st, false) ||
-            ws.run_boff.reserve(4 * nb * levels, st, false) ||
-            ws.run_bounds.reserve(4ull * run_stride * levels, st, false))
-          return RS_ENOMEM;
-        RS_HIP(launch_run_bounds(G.hi.as<uint32_t>(), ws.lo.as<uint32_t>(), need_of(2), need_stride(m), (uint32_t)m, E,
-                                 (uint32_t)levels, run_w2, run_w3, ws.run_pre.as<uint32_t>(),
-                                 ws.run_bsum.as<uint32_t>(), ws.run_boff.as<uint32_t>(),
-                                 ws.run_bounds.as<uint32_t>(), run_stride, st));
+        RS_HIP(launch_run_bounds(G.hi.as<uint32_t>(), ws.lo.as<uint32_t>(), need_of(2), need_stride(m), (uint32_t)m,
+                                 E, k - 2, run_w2, run_w3, ws.run_pre.as<uint32_t>(), ws.run_bsum.as<uint32_t>(),
+                                 ws.run_boff.as<uint32_t>(), ws.run_bounds.as<uint32_t>(), run_stride, st));
       }
     }
     if (tr) {
@@ -339,7 +393,7 @@ rs_status run_plain(rs_graph* g, PlainWorkspace& ws, const QueryPlan& qp, const 
     // Counts for the byte accounting of timed launches: measured once per
     // (delta, k) (a synchronising read-back), only while kernel timing is on.
     std::vector<NeedCounts> ncs(k + 1);
-    if (profiling_on()) {
+    if (timed && profiling_on()) {
       std::lock_guard<std::mutex> lk(g->counts_mu);
       auto it = g->need_counts.find({qp.delta, k});
       if (it == g->need_counts.end()) {
@@ -373,7 +427,7 @@ rs_status run_plain(rs_graph* g, PlainWorkspace& ws, const QueryPlan& qp, const 
       }
     }
     {
-      ProfScope ps(KC_QTABLE, st, (double)m * (12.0 + 8.0 * kq * (k - 1)));
+      ProfScope ps(KC_QTABLE, st, (double)m * (12.0 + 8.0 * kq * (k - 1)), timed);
       RS_HIP(launch_qtable(G.e_src.as<uint32_t>(), G.e_dst.as<uint32_t>(), G.e_t.as<uint32_t>(),
                            ws.z.as<uint64_t>(), ws.q.as<uint64_t>(), (uint32_t)m, qp, st));
     }
@@ -420,7 +474,7 @@ rs_status run_plain(rs_graph* g, PlainWorkspace& ws, const QueryPlan& qp, const 
             a.lb_stats = ws.lb_stats.as<unsigned long long>();
           }
           {
-            ProfScope ps(first ? KC_FIRST : KC_SCAN, st, scan_bytes(ncs[l], m, kq, gc, first));
+            ProfScope ps(first ? KC_FIRST : KC_SCAN, st, scan_bytes(ncs[l], m, kq, gc, first), timed);
             RS_HIP(launch_scan(a, first, kq, gc, tu, st));
           }
           if (tr) {
@@ -446,7 +500,7 @@ rs_status run_plain(rs_graph* g, PlainWorkspace& ws, const QueryPlan& qp, const 
           a.partial = ws.partial.as<uint64_t>();
           a.fsum = ws.fsum.as<uint64_t>();
           {
-            ProfScope ps(KC_TOP, st, top_bytes(ncs[k], m, kq, gc, first));
+            ProfScope ps(KC_TOP, st, top_bytes(ncs[k], m, kq, gc, first), timed);
             RS_HIP(launch_top(a, first, kq, gc, tu, st));
           }
           if (tr) {
@@ -461,21 +515,65 @@ rs_status run_plain(rs_graph* g, PlainWorkspace& ws, const QueryPlan& qp, const 
     if (per_it_host)
       RS_HIP(hipMemcpyAsync(per_it_host, ws.fsum.as<uint64_t>() + qp.it_begin, 8 * span,
                             hipMemcpyDeviceToHost, st));
-    RS_HIP(hipEventRecord(ws.ev1, st));
+    if (timed) RS_HIP(hipEventRecord(ws.ev1, st));
     RS_HIP(hipStreamSynchronize(st));
   } else {
     if (per_it_host)
       for (uint64_t i = 0; i < span; ++i) per_it_host[i] = 0;
-    RS_HIP(hipEventRecord(ws.ev1, st));
+    if (timed) RS_HIP(hipEventRecord(ws.ev1, st));
     RS_HIP(hipStreamSynchronize(st));
   }
   float ms = 0;
-  (void)hipEventElapsedTime(&ms, ws.ev0, ws.ev1);
+  if (timed) (void)hipEventElapsedTime(&ms, ws.ev0, ws.ev1);
   if (profiling_on()) profile_flush();
   r->fingerprint = F;
   r->yes = F != 0;
   r->status = RS_OK;
   r->device_ms = ms;
+  return RS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// No-allocation workspace: one file-scope device array per GPU. In host code
+// `scratch` names a host-side stand-in, not device memory; its address on a
+// device comes from hipGetSymbolAddress with that device current, taken once
+// per device and kept, and only that address is ever handed to kernels or
+// fills. The array keeps the last call's contents.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) uint8_t scratch[kNoAllocScratchBytes];
+
+struct NoAllocDevice {
+  std::mutex mu;            // one query at a time per device (each call syncs its stream)
+  uint8_t* base = nullptr;  // this device's copy of scratch
+  PlainWorkspace ws;        // buffers borrowed from base
+};
+static std::mutex g_noalloc_mu;
+static std::map<int, NoAllocDevice*> g_noalloc;  // by device; lives until process end
+
+static rs_status noalloc_device(int dev, NoAllocDevice** out) {
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  auto it = g_noalloc.find(dev);
+  if (it != g_noalloc.end()) {
+    *out = it->second;
+    return RS_OK;
+  }
+  int cur = 0;
+  RS_HIP(hipGetDevice(&cur));
+  if (cur != dev) RS_HIP(hipSetDevice(dev));
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (cur != dev) (void)hipSetDevice(cur);
+  if (e != hipSuccess || !p) {
+    set_last_error(std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    return RS_EDEVICE;
+  }
+  NoAllocDevice* d = new (std::nothrow) NoAllocDevice();
+  if (!d) return RS_ENOMEM;
+  d->base = static_cast<uint8_t*>(p);
+  d->ws.scratch = d->base;
+  d->ws.scratch_bytes = kNoAllocScratchBytes;
+  g_noalloc[dev] = d;
+  *out = d;
   return RS_OK;
 }
 
@@ -583,6 +681,33 @@ rs_status rs_run_ex(const rs_graph* gc, const rs_query* q, const rs_tuning* tune
 
 rs_status rs_run(const rs_graph* g, const rs_query* q, rs_result* r, void* hip_stream) {
   return rs_run_ex(g, q, nullptr, nullptr, r, hip_stream);
+}
+
+rs_status rs_run_noalloc(const rs_graph* gc, const rs_query* q, uint64_t* per_iteration, rs_result* r,
+                         void* hip_stream) {
+  if (!r) return RS_EINVAL;
+  QueryPlan qp;
+  rs_status s = plan_query(gc, q, qp);
+  if (s != RS_OK) {
+    r->status = s;
+    return s;
+  }
+  rs_graph* g = const_cast<rs_graph*>(gc);
+  try {
+    NoAllocDevice* d = nullptr;
+    s = noalloc_device(g->device, &d);
+    if (s == RS_OK) {
+      // one 64-iteration chunk per launch keeps the prefix state smallest
+      Tuning tu = resolve_tuning(g, qp.k, nullptr);
+      tu.chunks_per_launch = 1;
+      std::lock_guard<std::mutex> lk(d->mu);
+      s = run_plain(g, d->ws, qp, tu, per_iteration, r, (hipStream_t)hip_stream);
+    }
+  } catch (...) {
+    s = RS_ENOMEM;
+  }
+  r->status = s;
+  return s;
 }
 
 rs_status rs_trace_enable(int on) {

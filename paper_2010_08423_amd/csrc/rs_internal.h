@@ -229,8 +229,9 @@ struct GraphDev {
 enum KernelClass { KC_SCAN = 0, KC_FIRST, KC_TOP, KC_QTABLE, KC_ZTABLE, KC_WINDOW, KC_BATCH, KC_COUNT };
 bool profiling_on();
 struct ProfScope {
-  // Records events around one launch of class `kc` on `st` when profiling is on.
-  ProfScope(KernelClass kc, hipStream_t st, double algorithmic_bytes);
+  // Records events around one launch of class `kc` on `st` when profiling is
+  // on and the caller allows it (the no-allocation workspace does not).
+  ProfScope(KernelClass kc, hipStream_t st, double algorithmic_bytes, bool allowed = true);
   ~ProfScope();
   KernelClass kc;
   hipStream_t st;
@@ -244,6 +245,9 @@ void profile_flush();  // folds completed event pairs into the totals
 namespace rs {
 // Device buffers of one plain-path query stream on one graph; they grow to
 // the largest query run through them and stay allocated until release().
+// A workspace with `scratch` set instead borrows every buffer from that
+// device region (carved anew for each query, never allocated or freed); it
+// also records no events and takes no kernel timing or launch trace.
 struct PlainWorkspace {
   DevBuf lo, z, q, p0, p1, partial, agg, incl, fsum, out, ref, need;
   DevBuf lb_stats;  // look-back counters, allocated only while launches are traced
@@ -252,6 +256,8 @@ struct PlainWorkspace {
   uint32_t epoch = 0;
   uint64_t p_elems_per_chunk = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  uint8_t* scratch = nullptr;  // borrowed region (no-allocation workspace), or null
+  uint64_t scratch_bytes = 0;
   uint64_t bytes() const {
     uint64_t t = 0;
     for (const DevBuf* b : {&lo, &z, &q, &p0, &p1, &partial, &agg, &incl, &fsum, &out, &ref, &need,
@@ -260,6 +266,7 @@ struct PlainWorkspace {
     return t;
   }
   void release() {
+    if (scratch) return;  // borrowed buffers are never freed
     for (DevBuf* b : {&lo, &z, &q, &p0, &p1, &partial, &agg, &incl, &fsum, &out, &ref, &need, &lb_stats,
                       &run_pre, &run_bsum, &run_boff, &run_bounds, &cov_diff})
       b->release();
@@ -271,12 +278,18 @@ struct PlainWorkspace {
   }
 };
 // Buffer sizes (bytes) a query needs in a plain workspace (p: each of the two
-// prefix-state arrays; records: each of the two look-back record arrays).
+// prefix-state arrays; records: each of the two look-back record arrays;
+// run_*: the work-balanced run bounds of the prefix levels).
 struct PlainSizes {
   uint64_t lo, z, q, p, partial, fsum, ref, need, cover, records;
+  uint64_t run_pre, run_bsum, run_boff, run_bounds;
+  uint32_t run_w2, run_w3, run_stride;  // waves per chunk of level 2 and of levels >= 3; bounds stride
   uint64_t total() const;
 };
 PlainSizes plain_sizes(uint64_t m, uint64_t n, const QueryPlan& qp, const Tuning& tu);
+// Largest query workspace of the no-allocation entry point (bytes of its
+// per-device scratch array).
+constexpr uint64_t kNoAllocScratchBytes = 256ull << 20;
 }  // namespace rs
 
 // Opaque graph handle.
