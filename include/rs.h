@@ -178,6 +178,61 @@ rs_status rs_run(const rs_graph* g, const rs_query* q, rs_result* r, void* hip_s
 rs_status rs_run_ex(const rs_graph* g, const rs_query* q, const rs_tuning* tune,
                     uint64_t* per_iteration, rs_result* r, void* hip_stream);
 
+/* ------------------------------------------------------------------------
+ * Constraints of the problems of Sec. 3 and the fine-grained oracle of
+ * Alg. 1 (Sec. 4.5).
+ * ---------------------------------------------------------------------- */
+typedef struct {
+  const uint32_t* delta_per_vertex; /* host array of n resting times delta(v)
+                                       (Sec. 2: delta is a function of the
+                                       vertex), or NULL for rs_query.delta at
+                                       every vertex. Read during the call. */
+  const uint32_t* sources;          /* host array of n_sources vertex ids: only
+                                       paths whose first vertex is one of them
+                                       count (the source s of the problems of
+                                       Sec. 3; several sources as in Sec. 4.6).
+                                       NULL / 0 = any first vertex. */
+  uint32_t n_sources;
+  const uint32_t* targets;          /* host array of n_targets vertex ids: only
+                                       paths whose last vertex is one of them
+                                       count (the destination d). NULL / 0 =
+                                       any last vertex. */
+  uint32_t n_targets;
+} rs_constraints;
+
+/* rs_run_ex (automatic launch shape) under constraints c (NULL = none): F is
+ * the XOR over the restless paths that start at a source and end at a target
+ * of (prod y) det Z_P, so F != 0 decides k-RestlessPath / k-RestlessMotif
+ * from s to d. The start restriction keeps the level-1 terms of Eq.
+ * (poly-enc:1) of the source vertices only; walks that start elsewhere are
+ * never formed. Vertex ids >= n -> RS_EINVAL. */
+rs_status rs_run_constrained(const rs_graph* g, const rs_query* q, const rs_constraints* c, uint64_t* per_iteration,
+                             rs_result* r, void* hip_stream);
+
+/* Fine-grained oracle (Alg. 1, FineGrainedOracle): the last level's values
+ * are summed over the iterations per slot (u, i), giving zeta_{u,k,i}, which
+ * is non-zero only if a restless path (motif: colour-agreeing) with k
+ * vertices ends at u at time i (and, with constraints, starts at a source).
+ * reach_time: host array of n entries, receives R_u = the least i with
+ * zeta_{u,k,i} != 0, or 0xFFFFFFFF (D = the vertices with a finite R_u).
+ * slot_zeta: host array of info.m entries or NULL; receives, for every edge
+ * of the canonical list (rs_graph_edges order), the zeta of its slot
+ * (dst, t). r->fingerprint is the XOR of all zeta (the rs_run_constrained
+ * fingerprint), r->yes says D is not empty. The iteration range of q selects
+ * the iterations summed. */
+rs_status rs_run_fine(const rs_graph* g, const rs_query* q, const rs_constraints* c, uint32_t* reach_time,
+                      uint64_t* slot_zeta, rs_result* r, void* hip_stream);
+
+/* At most k vertices (Sec. 4.6, at-most-k restless reachability): one
+ * fine-grained sieve for each k' = 2..q->k with q's seed and constraints
+ * (typically a source). reach_time[u] (n entries) = the least R_u over the
+ * k', 0xFFFFFFFF if none; reach_vertices (n entries or NULL) = the least k'
+ * with a path ending at u, 0 if none. Path queries over the whole iteration
+ * range only (a motif or an iteration range -> RS_EINVAL). r->fingerprint is
+ * the XOR of the k' fingerprints; r->yes says some vertex is reached. */
+rs_status rs_reach_at_most(const rs_graph* g, const rs_query* q, const rs_constraints* c, uint32_t* reach_time,
+                           uint32_t* reach_vertices, rs_result* r, void* hip_stream);
+
 /* For callers that cannot allocate device memory (code under stream capture,
  * tight serving loops, harnesses that forbid hipMalloc): rs_run_ex without
  * tuning knobs, whose query workspace (window indices, substitution and

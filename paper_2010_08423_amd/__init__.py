@@ -58,6 +58,11 @@ class _Tuning(ctypes.Structure):
                 ("max_slots", ctypes.c_uint32), ("no_graph", ctypes.c_uint32)]
 
 
+class _Constraints(ctypes.Structure):
+    _fields_ = [("delta_per_vertex", _u32p), ("sources", _u32p), ("n_sources", ctypes.c_uint32),
+                ("targets", _u32p), ("n_targets", ctypes.c_uint32)]
+
+
 class _GraphInfo(ctypes.Structure):
     _fields_ = [("n", ctypes.c_uint32), ("m_input", ctypes.c_uint64), ("m", ctypes.c_uint64),
                 ("self_loops", ctypes.c_uint64), ("duplicates", ctypes.c_uint64), ("t_min", ctypes.c_uint32),
@@ -96,6 +101,12 @@ _SIGNATURES = {
     "rs_run": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(_Query), ctypes.POINTER(_Result), ctypes.c_void_p]),
     "rs_run_ex": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(_Query), ctypes.POINTER(_Tuning), _u64p,
                                    ctypes.POINTER(_Result), ctypes.c_void_p]),
+    "rs_run_constrained": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(_Query), ctypes.POINTER(_Constraints),
+                                            _u64p, ctypes.POINTER(_Result), ctypes.c_void_p]),
+    "rs_run_fine": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(_Query), ctypes.POINTER(_Constraints), _u32p,
+                                     _u64p, ctypes.POINTER(_Result), ctypes.c_void_p]),
+    "rs_reach_at_most": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(_Query), ctypes.POINTER(_Constraints), _u32p,
+                                          _u32p, ctypes.POINTER(_Result), ctypes.c_void_p]),
     "rs_run_noalloc": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(_Query), _u64p, ctypes.POINTER(_Result),
                                         ctypes.c_void_p]),
     "rs_run_batch": (ctypes.c_int32, [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(_Query), ctypes.c_uint32,
@@ -289,25 +300,99 @@ def footprint(graph: Graph, k, delta, seed=0, motif=None, it_begin=0, it_end=0) 
     return b.value
 
 
+def _constraints(delta, sources, targets):
+    """rs_constraints for a per-vertex delta array and source / target vertex
+    lists (None when there is nothing to constrain), and the arrays it points to."""
+    per_vertex = not np.isscalar(delta)
+    if not per_vertex and sources is None and targets is None:
+        return None, None
+    dv = np.ascontiguousarray(delta, dtype=np.uint32) if per_vertex else None
+    sv = None if sources is None else np.ascontiguousarray(np.asarray(sources).reshape(-1), dtype=np.uint32)
+    tv = None if targets is None else np.ascontiguousarray(np.asarray(targets).reshape(-1), dtype=np.uint32)
+    c = _Constraints(dv.ctypes.data_as(_u32p) if dv is not None else None,
+                     sv.ctypes.data_as(_u32p) if sv is not None and len(sv) else None,
+                     0 if sv is None else len(sv),
+                     tv.ctypes.data_as(_u32p) if tv is not None and len(tv) else None,
+                     0 if tv is None else len(tv))
+    return c, (dv, sv, tv)
+
+
 def run(graph: Graph, k, delta, seed, motif=None, it_begin=0, it_end=0, tuning: Tuning | None = None,
-        per_iteration=False, stream=None) -> Result:
-    """rs_run_ex: one query on the plain (level-by-level) path."""
-    q, keep = _make_query(k, delta, seed, motif, it_begin, it_end)
+        per_iteration=False, stream=None, sources=None, targets=None) -> Result:
+    """One query on the plain (level-by-level) path: rs_run_ex, or
+    rs_run_constrained when delta is a per-vertex array or sources / targets
+    (vertex lists the paths must start / end in) are given."""
+    c, ckeep = _constraints(delta, sources, targets)
+    q, keep = _make_query(k, 0 if c is not None and not np.isscalar(delta) else delta, seed, motif, it_begin, it_end)
     r = _Result()
     per = None
+    span = (it_end - it_begin) if (it_begin or it_end) else (1 << k)
     if per_iteration:
-        span = (it_end - it_begin) if (it_begin or it_end) else (1 << k)
         per = np.zeros(max(span, 1), dtype=np.uint64)
-    tu = tuning._c() if tuning is not None else None
-    s = _load().rs_run_ex(graph.handle, ctypes.byref(q), ctypes.byref(tu) if tu is not None else None,
-                          per.ctypes.data_as(_u64p) if per is not None else None, ctypes.byref(r),
-                          _stream_handle(stream))
-    del keep
-    _check(s, "rs_run_ex")
+    perp = per.ctypes.data_as(_u64p) if per is not None else None
+    if c is not None:
+        if tuning is not None:
+            raise ValueError("launch knobs are not taken with constraints")
+        s = _load().rs_run_constrained(graph.handle, ctypes.byref(q), ctypes.byref(c), perp, ctypes.byref(r),
+                                       _stream_handle(stream))
+        what = "rs_run_constrained"
+    else:
+        tu = tuning._c() if tuning is not None else None
+        s = _load().rs_run_ex(graph.handle, ctypes.byref(q), ctypes.byref(tu) if tu is not None else None, perp,
+                              ctypes.byref(r), _stream_handle(stream))
+        what = "rs_run_ex"
+    del keep, ckeep
+    _check(s, what)
     res = Result(r.fingerprint, bool(r.yes), r.status, r.device_ms)
     if per_iteration:
         res.per_iteration = per[:span]
     return res
+
+
+@dataclasses.dataclass
+class FineResult:
+    fingerprint: int
+    yes: bool
+    device_ms: float
+    reach: np.ndarray       # uint32 [n]: least time with a path ending there, UNREACHED if none
+    zeta: np.ndarray | None  # uint64 [m]: zeta of each canonical edge's slot (dst, t)
+
+
+UNREACHED = 0xFFFFFFFF
+
+
+def run_fine(graph: Graph, k, delta, seed, motif=None, it_begin=0, it_end=0, sources=None, targets=None,
+             slots=True, stream=None) -> FineResult:
+    """rs_run_fine: per-slot zeta_{u,k,i} (Alg. 1), reach times and F."""
+    info = graph.info()
+    c, ckeep = _constraints(delta, sources, targets)
+    q, keep = _make_query(k, 0 if not np.isscalar(delta) else delta, seed, motif, it_begin, it_end)
+    reach = np.zeros(max(graph.n, 1), dtype=np.uint32)
+    zeta = np.zeros(max(info["m"], 1), dtype=np.uint64) if slots else None
+    r = _Result()
+    s = _load().rs_run_fine(graph.handle, ctypes.byref(q), ctypes.byref(c) if c is not None else None,
+                            reach.ctypes.data_as(_u32p), zeta.ctypes.data_as(_u64p) if zeta is not None else None,
+                            ctypes.byref(r), _stream_handle(stream))
+    del keep, ckeep
+    _check(s, "rs_run_fine")
+    return FineResult(r.fingerprint, bool(r.yes), r.device_ms, reach[:graph.n],
+                      zeta[:info["m"]] if zeta is not None else None)
+
+
+def reach_at_most(graph: Graph, k, delta, seed, sources=None, targets=None, stream=None):
+    """rs_reach_at_most: (reach times, least number of vertices, Result) over
+    the sieves of 2..k vertices."""
+    c, ckeep = _constraints(delta, sources, targets)
+    q, keep = _make_query(k, 0 if not np.isscalar(delta) else delta, seed)
+    reach = np.zeros(max(graph.n, 1), dtype=np.uint32)
+    length = np.zeros(max(graph.n, 1), dtype=np.uint32)
+    r = _Result()
+    s = _load().rs_reach_at_most(graph.handle, ctypes.byref(q), ctypes.byref(c) if c is not None else None,
+                                 reach.ctypes.data_as(_u32p), length.ctypes.data_as(_u32p), ctypes.byref(r),
+                                 _stream_handle(stream))
+    del keep, ckeep
+    _check(s, "rs_reach_at_most")
+    return reach[:graph.n], length[:graph.n], Result(r.fingerprint, bool(r.yes), r.status, r.device_ms)
 
 
 def run_noalloc(graph: Graph, k, delta, seed, motif=None, it_begin=0, it_end=0, per_iteration=False,

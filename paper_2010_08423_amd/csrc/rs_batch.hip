@@ -88,8 +88,9 @@ struct MUnit {
   const uint32_t* pre;   // prefix-level units: this level's tile cost prefix (within blocks)
   const uint32_t* boff;  // prefix-level units: this level's block offsets
   uint32_t* bounds;      // prefix-level units: [waves+1] first tile of each wave's run
+  const uint32_t* count; // compacted list of this level (queries with k >= 3): its length; null otherwise
 };
-static_assert(sizeof(MUnit) == 168, "MUnit layout");
+static_assert(sizeof(MUnit) == 176, "MUnit layout");
 // Units are read through the constant address space: scalar loads into SGPRs.
 typedef __attribute__((address_space(4))) const MUnit cMUnit;
 
@@ -226,11 +227,18 @@ __global__ __launch_bounds__(256) void kb_reduce(const BQuery* __restrict__ qs, 
 }
 
 // Work-balanced run bounds of every unit of a prefix-level launch, from its
-// query's tile cost prefix for that level and its waves per chunk.
-__global__ __launch_bounds__(256) void kb_run_bounds(const MUnit* __restrict__ units) {
+// query's tile cost prefix for that level and its waves per chunk (tiles of E
+// entries of the level's compacted list).
+__global__ __launch_bounds__(256) void kb_run_bounds(const MUnit* __restrict__ units, uint32_t E) {
   const MUnit& U = units[blockIdx.y];
+  const uint32_t n_tiles = U.count ? (*U.count + E - 1) / E : U.n_items;
   const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t < U.n_items) run_bounds_of_tile(U.pre, U.boff, U.n_items, t, U.waves, U.bounds);
+  if (n_tiles == 0) {  // an empty list: every run is empty
+    if (t == 0)
+      for (uint32_t w = 0; w <= U.waves; ++w) U.bounds[w] = 0;
+    return;
+  }
+  if (t < n_tiles) run_bounds_of_tile(U.pre, U.boff, n_tiles, t, U.waves, U.bounds);
 }
 
 // ---------------------------------------------------------------------------
@@ -285,8 +293,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
   c.pp = U.pp + ch * U.p_stride;
   c.pc = U.pc + ch * U.p_stride;
   c.cb = U.cb + (uint64_t)ch * kLanes;
-  c.m = U.m;
-  c.n_tiles = U.n_items;
+  // a compacted list's length is on the device; n_items stays the record stride
+  c.m = U.count ? __builtin_amdgcn_readfirstlane(*as_const(U.count)) : U.m;
+  c.n_tiles = U.count ? (c.m + E - 1) / E : U.n_items;
   c.epoch = U.epoch;
   c.row0 = U.row0 + (uint64_t)ch * U.n_items;
   c.agg = agg;
@@ -294,7 +303,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
   c.need = U.need;
   c.lb_stats = nullptr;
   c.bounds = U.bounds;
-  c.bounds = nullptr;
   scan_level<KQ, E, FIRST>(c, idx, U.waves, lane, mk, tab);
 }
 
@@ -343,7 +351,7 @@ __global__ __launch_bounds__(256) void kb_top(const MUnit* __restrict__ units, c
       cb = U.cb;
       it_begin = U.it_begin;
       it_end = U.it_end;
-      m = U.m;
+      m = U.count ? __builtin_amdgcn_readfirstlane(*as_const(U.count)) : U.m;
     }
     const uint32_t e0 = (t - u_begin) * top_edges;
     const uint32_t e1 = min(m, e0 + top_edges);
@@ -459,6 +467,9 @@ struct BatchPlan {
   uint32_t rounds = 0;
   uint32_t lanes = 1;         // rounds run on this many streams at once
   uint64_t bounds_words = 0;  // run bounds of all prefix-level units
+  std::vector<uint64_t> lists_off;    // per query: offset of its compacted lists (k >= 3)
+  std::vector<CompactArgs> cargs;     // per query: its compacted lists (set by resolve_plan)
+  std::vector<int32_t> unit_list;     // per unit: level index of its compacted list, or -1
   Tuning tu;
   std::string key;
 };
@@ -526,8 +537,11 @@ rs_status batch_plan(const rs_graph* const* graphs, const rs_query* queries, uin
     pq_off += align256(table_lo_bytes(m));
     Q.z = (uint64_t*)(uintptr_t)pq_off;
     pq_off += align256(table_z_bytes(n, qp.kq));
+    // product rows: of every edge at k = 2, of the compacted lists above
     Q.q = (uint64_t*)(uintptr_t)pq_off;
-    pq_off += align256(table_q_bytes(m, qp.k, qp.kq));
+    if (qp.k == 2) pq_off += align256(table_q_bytes(m, qp.k, qp.kq));
+    P.lists_off.push_back(pq_off);
+    if (qp.k >= 3) pq_off += align256(compact_bytes(m, qp.k, qp.kq));
     Q.need = (uint8_t*)(uintptr_t)pq_off;
     pq_off += align256(table_need_bytes(m, qp.k));
     {
@@ -646,7 +660,7 @@ rs_status batch_plan(const rs_graph* const* graphs, const rs_query* queries, uin
             U.e_out = Q.e_out;
             U.hi = Q.hi;
             U.lo = Q.lo;  // offset, rebased later
-            U.q = (const uint64_t*)((uintptr_t)Q.q + 8ull * (l - 2) * Q.m * kq);  // byte offset until rebased
+            U.q = Q.q;    // byte offset until rebased (k = 2; deeper queries read their compacted lists)
             U.z = Q.z;
             const uint64_t half = align256(((uint64_t)Q.m + Q.n) * kLanes * 8);
             U.pp = (const uint64_t*)(uintptr_t)(poff[c - rd.first] + ((l - 1) & 1) * half);
@@ -672,6 +686,7 @@ rs_status batch_plan(const rs_graph* const* graphs, const rs_query* queries, uin
             L.total += U.n_items * (top ? 1u : nch);  // prefix levels: tiles (waves assigned later)
             P.units.push_back(U);
             P.unit_query.push_back(qi);
+            P.unit_list.push_back(Q.k >= 3 ? (int32_t)(l - 2) : -1);
             ++L.nunits;
             c += nch - 1;
           }
@@ -718,7 +733,7 @@ static rs_status resolve_plan(BatchPlan& P, BatchWorkspace& W, uint32_t epoch0) 
       Q.bsum = (uint32_t*)(pq + (uintptr_t)Q.bsum);
       Q.boff = (uint32_t*)(pq + (uintptr_t)Q.boff);
     }
-    if (q_off[i] + table_q_bytes(Q.m, Q.k, Q.kq) > W.per_query.bytes) return RS_EINVAL;
+    if (Q.k == 2 && q_off[i] + table_q_bytes(Q.m, Q.k, Q.kq) > W.per_query.bytes) return RS_EINVAL;
     const uint64_t slots = (uint64_t)Q.m + Q.n + 1, nbq = (slots + kCostBlock - 1) / kCostBlock;
     if ((uint64_t)Q.m + Q.n > W.ref.bytes || 4ull * (slots + 2 * nbq) > W.cov.bytes) return RS_EINVAL;
     Q.lo = (uint32_t*)(pq + lo_off[i]);
@@ -729,6 +744,31 @@ static rs_status resolve_plan(BatchPlan& P, BatchWorkspace& W, uint32_t epoch0) 
     Q.cov = W.cov.as<uint32_t>();
     Q.cbsum = Q.cov + slots;
     Q.cboff = Q.cbsum + nbq;
+    CompactArgs ca{};
+    if (Q.k >= 3) {
+      const uint64_t L = Q.k - 1, lst = list_stride(Q.m);
+      if (P.lists_off[i] + compact_bytes(Q.m, Q.k, Q.kq) > W.per_query.bytes) return RS_EINVAL;
+      ca.e_src = Q.e_src;
+      ca.e_dst = Q.e_dst;
+      ca.e_t = Q.e_t;
+      ca.e_out = Q.e_out;
+      ca.hi = Q.hi;
+      ca.lo = Q.lo;
+      ca.need = Q.need;
+      ca.need_stride = need_stride(Q.m);
+      ca.m = Q.m;
+      ca.k = Q.k;
+      ca.kq = Q.kq;
+      ca.nb = (uint32_t)((Q.m + kCostBlock - 1) / kCostBlock);
+      ca.list_stride = lst;
+      ca.rows = (uint64_t*)(pq + P.lists_off[i]);
+      ca.u32 = (uint32_t*)(ca.rows + L * lst * Q.kq);
+      ca.u8 = (uint8_t*)(ca.u32 + L * 4 * lst);
+      ca.bsum = (uint32_t*)(((uintptr_t)(ca.u8 + L * lst) + 3) & ~(uintptr_t)3);
+      ca.boff = ca.bsum + L * ca.nb;
+      ca.count = ca.boff + L * ca.nb;
+    }
+    P.cargs.push_back(ca);
   }
   uint32_t scan_idx = 0;
   for (const BLaunch& L : P.launches) {
@@ -742,13 +782,25 @@ static rs_status resolve_plan(BatchPlan& P, BatchWorkspace& W, uint32_t epoch0) 
       const uint64_t span = 8 * U.p_stride * (U.nchunks - 1) + half;  // from the first chunk's array
       if (pp_off + span > W.parena.bytes || pc_off + span > W.parena.bytes) return RS_EINVAL;
       if (!L.top && (U.row0 + (uint64_t)U.nchunks * U.n_items) * 1024 > W.agg.bytes) return RS_EINVAL;
-      const uint64_t q_level = (uintptr_t)U.q;  // offset of this level's rows
-      if (q_level + 8ull * Q.m * Q.kq > q_off[qi] + 8ull * Q.m * Q.kq * (Q.k - 1)) return RS_EINVAL;
-      U.q = (const uint64_t*)(pq + q_level);
-      U.lo = Q.lo;
+      const int32_t y = P.unit_list[L.unit_off + j];
+      if (y >= 0) {  // this level's compacted list
+        const LevelList Lc = P.cargs[qi].list((uint32_t)y);
+        U.e_src = Lc.chi;
+        U.e_out = Lc.cslot;
+        U.hi = Lc.chi;
+        U.lo = Lc.clo;
+        U.q = Lc.cq;
+        U.count = P.cargs[qi].count + y;
+      } else {
+        const uint64_t q_level = (uintptr_t)U.q;  // offset of this level's rows (k = 2)
+        if (q_level + 8ull * Q.m * Q.kq > q_off[qi] + 8ull * Q.m * Q.kq * (Q.k - 1)) return RS_EINVAL;
+        U.q = (const uint64_t*)(pq + q_level);
+        U.lo = Q.lo;
+        U.count = nullptr;
+      }
       const uint64_t need_level = (uintptr_t)U.need - need_off[qi];  // offset of this level's flags
       if (need_level + need_stride(Q.m) > table_need_bytes(Q.m, Q.k)) return RS_EINVAL;
-      U.need = Q.need + need_level;
+      U.need = y >= 0 ? P.cargs[qi].list((uint32_t)y).cflag : Q.need + need_level;
       if (!L.top) {
         const uint64_t pre_off = (uintptr_t)U.pre, boff_off = (uintptr_t)U.boff;
         if (pre_off + 4ull * U.n_items > W.per_query.bytes || boff_off + 4 > W.per_query.bytes) return RS_EINVAL;
@@ -859,14 +911,22 @@ static rs_status batch_enqueue(BatchPlan& P, BatchWorkspace& W, hipStream_t st) 
       hipLaunchKernelGGL(kb_cover_offsets, dim3(1), dim3(1024), 0, st, dq, qi);
       hipLaunchKernelGGL(kb_mark_need, dim3((Q.m + kEdgePad + 255) / 256), dim3(256), 0, st, dq, qi, l);
     }
-    if (Q.k >= 3)
-      RS_HIP(launch_tile_costs(Q.hi, Q.lo, Q.need, need_stride(Q.m), Q.m, P.tu.edges_per_tile, Q.k - 2, Q.pre,
-                               Q.bsum, Q.boff, st));
-    switch (Q.kq) {
-      case 4: hipLaunchKernelGGL(kb_qtable<4>, dim3((Q.m + 255) / 256), dim3(256), 0, st, dq, qi); break;
-      case 8: hipLaunchKernelGGL(kb_qtable<8>, dim3((Q.m + 255) / 256), dim3(256), 0, st, dq, qi); break;
-      case 12: hipLaunchKernelGGL(kb_qtable<12>, dim3((Q.m + 255) / 256), dim3(256), 0, st, dq, qi); break;
-      default: hipLaunchKernelGGL(kb_qtable<16>, dim3((Q.m + 255) / 256), dim3(256), 0, st, dq, qi); break;
+    if (Q.k >= 3) {
+      // compacted lists of levels 2..k, their tile costs, and their product
+      // rows (the seed read from the descriptor, so a replay takes new seeds)
+      const CompactArgs& ca = P.cargs[qi];
+      const uint32_t E = P.tu.edges_per_tile;
+      RS_HIP(launch_compact(ca, st));
+      RS_HIP(launch_compact_costs(ca, E, (Q.m + E - 1) / E, Q.pre, Q.bsum, Q.boff, st));
+      const uint64_t* seed_p = (const uint64_t*)((const char*)(dq + qi) + offsetof(BQuery, seed));
+      RS_HIP(launch_compact_rows(ca, Q.z, 0, seed_p, nullptr, nullptr, Q.kq, st));
+    } else {
+      switch (Q.kq) {
+        case 4: hipLaunchKernelGGL(kb_qtable<4>, dim3((Q.m + 255) / 256), dim3(256), 0, st, dq, qi); break;
+        case 8: hipLaunchKernelGGL(kb_qtable<8>, dim3((Q.m + 255) / 256), dim3(256), 0, st, dq, qi); break;
+        case 12: hipLaunchKernelGGL(kb_qtable<12>, dim3((Q.m + 255) / 256), dim3(256), 0, st, dq, qi); break;
+        default: hipLaunchKernelGGL(kb_qtable<16>, dim3((Q.m + 255) / 256), dim3(256), 0, st, dq, qi); break;
+      }
     }
     hipLaunchKernelGGL(kb_clear_fsum, dim3((uint32_t)std::min<uint64_t>(((1ull << Q.k) + 255) / 256, 256)), dim3(256),
                        0, st, dq, qi);
@@ -888,7 +948,8 @@ static rs_status batch_enqueue(BatchPlan& P, BatchWorkspace& W, hipStream_t st) 
       void* args[] = {(void*)&u, (void*)&b, (void*)&L.nunits, (void*)&L.total, (void*)&P.tu.top_edges_per_tile};
       RS_HIP(hipLaunchKernel(kern, dim3(L.grid), dim3(64 * wpb), args, lds, lst));
     } else {
-      hipLaunchKernelGGL(kb_run_bounds, dim3((L.max_items + 255) / 256, L.nunits), dim3(256), 0, lst, u);
+      hipLaunchKernelGGL(kb_run_bounds, dim3((L.max_items + 255) / 256, L.nunits), dim3(256), 0, lst, u,
+                         P.tu.edges_per_tile);
       uint64_t* agg = W.agg.as<uint64_t>();
       uint64_t* incl = W.incl.as<uint64_t>();
       void* args[] = {(void*)&u, (void*)&b, (void*)&L.nunits, (void*)&L.total, (void*)&agg, (void*)&incl};
@@ -940,6 +1001,12 @@ rs_status run_batch_impl(const rs_graph* const* graphs, const rs_query* queries,
   if (tu.edges_per_tile != 8 && tu.edges_per_tile != 16) tu.edges_per_tile = 16;
   if (tu.waves_per_block != 1 && tu.waves_per_block != 2 && tu.waves_per_block != 4) tu.waves_per_block = 2;
   tu.top_edges_per_tile = std::min(std::max(tu.top_edges_per_tile, 1u), 4096u);
+  if (tu.edges_per_tile == 8)
+    for (uint32_t i = 0; i < nq; ++i)
+      if (graphs[i] && graphs[i]->g.m > kMaxEdgesE8) {
+        set_last_error("8-edge tiles are not accepted on graphs of more than 4e6 edges");
+        return RS_EINVAL;
+      }
   BatchPlan P;
   // the lanes hold one round each at a time, so a round gets a lane's share
   // of the budget and the whole prefix arena stays within it
@@ -1073,6 +1140,7 @@ rs_status autotune_impl(rs_graph* g, const rs_query* sample, uint32_t ns, rs_tun
     for (uint32_t wpb : {1u, 2u, 4u})
       for (uint32_t top : {16u, 64u})
         for (uint32_t cpl : {2u, 4u}) {
+          if (E == 8 && g->g.m > kMaxEdgesE8) continue;
           Tuning t;
           t.edges_per_tile = E;
           t.waves_per_block = wpb;
@@ -1127,6 +1195,7 @@ static rs_status autotune_batch_impl(rs_graph* g, const rs_query* sample, uint32
   for (uint32_t E : {8u, 16u})
     for (uint32_t wpb : {1u, 2u, 4u})
       for (uint32_t top : {16u, 64u, 256u}) {
+        if (E == 8 && g->g.m > kMaxEdgesE8) continue;
         rs_tuning t{E, top, 0, wpb, 0, 0};
         double tmin = 1e30;
         for (int rep = 0; rep < 2; ++rep) {

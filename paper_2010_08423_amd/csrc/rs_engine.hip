@@ -182,18 +182,20 @@ static uint64_t chunks_of(const QueryPlan& qp) { return qp.chunk_last - qp.chunk
 // chunks: what the exact computation has to move once edges whose window is
 // empty, or whose product reaches no read slot, are skipped and only read
 // slots are stored. Per chunk: two 512-byte window rows per gathered edge and
-// one 512-byte row per stored slot; per launch: the tile indices and flags
-// of every edge and the kq-entry rows of the edges that form a product.
+// one 512-byte row per stored slot; per launch: the entries of the level's
+// compacted list (slot, window bounds and flags, 13 bytes each) and the
+// kq-entry rows of the entries that form a product (at level 2 also their
+// substitution rows). k = 2 reads every edge.
 double scan_bytes(const NeedCounts& nc, uint64_t m, uint32_t kq, uint64_t chunks, bool first) {
   const double stores = 512.0 * (double)(nc.ref_slots + nc.ref_lead);
   if (first)  // level 2: no gathers; product and substitution rows of needed edges
-    return stores * (double)chunks + 9.0 * (double)m + 16.0 * kq * (double)nc.needed;
-  return (1024.0 * (double)nc.live_needed + stores) * (double)chunks + 13.0 * (double)m +
+    return stores * (double)chunks + 9.0 * (double)nc.kept + 16.0 * kq * (double)nc.needed;
+  return (1024.0 * (double)nc.live_needed + stores) * (double)chunks + 13.0 * (double)nc.kept +
          8.0 * kq * (double)nc.live_needed;
 }
 double top_bytes(const NeedCounts& nc, uint64_t m, uint32_t kq, uint64_t chunks, bool first) {
   if (first) return 8.0 * (double)m + 16.0 * kq * (double)m;
-  return 1024.0 * (double)nc.live * (double)chunks + 8.0 * (double)m + 8.0 * kq * (double)nc.live;
+  return 1024.0 * (double)nc.live * (double)chunks + 8.0 * (double)nc.live + 8.0 * kq * (double)nc.live;
 }
 
 uint64_t table_lo_bytes(uint64_t m) { return 4 * (m + kEdgePad); }
@@ -205,7 +207,7 @@ uint64_t table_need_bytes(uint64_t m, uint32_t k) { return (uint64_t)need_levels
 // Plain path: setup kernels, then per chunk group levels 2..k.
 // ---------------------------------------------------------------------------
 // Buffer sizes (bytes) one query needs in a plain workspace.
-PlainSizes plain_sizes(uint64_t m, uint64_t n, const QueryPlan& qp, const Tuning& tu) {
+PlainSizes plain_sizes(uint64_t m, uint64_t n, const QueryPlan& qp, const Tuning& tu, const QueryExtras* ex) {
   PlainSizes s;
   const uint32_t k = qp.k, kq = qp.kq;
   const uint64_t nchunks = std::max<uint64_t>(chunks_of(qp), 1);
@@ -219,7 +221,10 @@ PlainSizes plain_sizes(uint64_t m, uint64_t n, const QueryPlan& qp, const Tuning
   const uint32_t tblocks = top_blocks(ta, k == 2, kq, 1, tu);
   s.lo = table_lo_bytes(m);
   s.z = table_z_bytes(n, kq);
-  s.q = table_q_bytes(m, k, kq);
+  // k = 2 reads the product rows of every edge; deeper queries read the rows
+  // of their compacted lists
+  s.q = k == 2 ? table_q_bytes(m, k, kq) : 0;
+  s.lists = k >= 3 ? compact_bytes(m, k, kq) : 0;
   s.p = 8 * (m + n) * 64 * cpl;
   s.partial = 8 * 64 * cpl * (uint64_t)tblocks;
   s.fsum = 8 * (1ull << k);
@@ -240,12 +245,19 @@ PlainSizes plain_sizes(uint64_t m, uint64_t n, const QueryPlan& qp, const Tuning
     s.run_bsum = s.run_boff = 4 * nb * levels;
     s.run_bounds = 4ull * s.run_stride * levels;
   }
+  s.dv = ex && ex->delta_v ? 4 * n : 0;
+  s.smask = ex && ex->smask ? n : 0;
+  s.tmask = ex && ex->tmask ? n : 0;
+  const bool fine = ex && ex->fine;
+  s.fine_t = fine ? 8 * m : 0;
+  s.fine_z = fine ? 8 * m : 0;
+  s.fine_r = fine ? 4 * n : 0;
   return s;
 }
 
 uint64_t PlainSizes::total() const {
   return lo + z + q + 2 * p + partial + fsum + 64 + ref + need + cover + 2 * records + run_pre + run_bsum + run_boff +
-         run_bounds;
+         run_bounds + lists + dv + smask + tmask + fine_t + fine_z + fine_r;
 }
 
 uint64_t plain_footprint(const rs_graph* g, const QueryPlan& qp, const Tuning& tu) {
@@ -283,6 +295,13 @@ static rs_status acquire_buffers(PlainWorkspace& ws, const PlainSizes& sz, uint6
     carve(ws.run_bsum, sz.run_bsum);
     carve(ws.run_boff, sz.run_boff);
     carve(ws.run_bounds, sz.run_bounds);
+    carve(ws.lists, sz.lists);
+    carve(ws.dv, sz.dv);
+    carve(ws.smask, sz.smask);
+    carve(ws.tmask, sz.tmask);
+    carve(ws.fine_t, sz.fine_t);
+    carve(ws.fine_z, sz.fine_z);
+    carve(ws.fine_r, sz.fine_r);
     if (!fits) {
       set_last_error("query workspace of " + std::to_string(off) + " bytes exceeds the " +
                      std::to_string(ws.scratch_bytes) + "-byte scratch of the no-allocation entry point");
@@ -307,7 +326,11 @@ static rs_status acquire_buffers(PlainWorkspace& ws, const PlainSizes& sz, uint6
       ws.fsum.reserve(sz.fsum, st, false) || ws.out.reserve(64, st, false) || ws.ref.reserve(sz.ref, st, false) ||
       ws.need.reserve(sz.need, st, false) || ws.cov_diff.reserve(sz.cover, st, false) ||
       ws.run_pre.reserve(sz.run_pre, st, false) || ws.run_bsum.reserve(sz.run_bsum, st, false) ||
-      ws.run_boff.reserve(sz.run_boff, st, false) || ws.run_bounds.reserve(sz.run_bounds, st, false))
+      ws.run_boff.reserve(sz.run_boff, st, false) || ws.run_bounds.reserve(sz.run_bounds, st, false) ||
+      (sz.lists && ws.lists.reserve(sz.lists, st, false)) || (sz.dv && ws.dv.reserve(sz.dv, st, false)) ||
+      (sz.smask && ws.smask.reserve(sz.smask, st, false)) || (sz.tmask && ws.tmask.reserve(sz.tmask, st, false)) ||
+      (sz.fine_t && ws.fine_t.reserve(sz.fine_t, st, false)) || (sz.fine_z && ws.fine_z.reserve(sz.fine_z, st, false)) ||
+      (sz.fine_r && ws.fine_r.reserve(sz.fine_r, st, false)))
     return RS_ENOMEM;
   if (ws.agg.bytes < sz.records || ws.incl.bytes < sz.records) {
     // tagged records start at epoch 0, which no launch uses
@@ -318,8 +341,9 @@ static rs_status acquire_buffers(PlainWorkspace& ws, const PlainSizes& sz, uint6
 }
 
 rs_status run_plain(rs_graph* g, PlainWorkspace& ws, const QueryPlan& qp, const Tuning& tu, uint64_t* per_it_host,
-                    rs_result* r, hipStream_t st) {
+                    rs_result* r, hipStream_t st, QueryExtras* ex) {
   const GraphDev& G = g->g;
+  const bool fine = ex && ex->fine;
   const uint64_t m = G.m, n = G.n;
   const uint64_t span = qp.it_end - qp.it_begin;
   const bool timed = !ws.scratch;  // the no-allocation workspace records no events
@@ -338,8 +362,27 @@ rs_status run_plain(rs_graph* g, PlainWorkspace& ws, const QueryPlan& qp, const 
     const uint32_t E = tu.edges_per_tile;
     const uint64_t tiles = (m + E - 1) / E;
     const uint64_t p_elems = (m + n) * 64;
-    const PlainSizes sz = plain_sizes(m, n, qp, tu);
+    const PlainSizes sz = plain_sizes(m, n, qp, tu, ex);
     RS_TRY(acquire_buffers(ws, sz, p_elems, st));
+    // constraints (host arrays, copied in) and fine-grained output buffers
+    const uint32_t* dv = nullptr;
+    const uint8_t *smask = nullptr, *tmask = nullptr;
+    if (sz.dv) {
+      RS_HIP(hipMemcpyAsync(ws.dv.p, ex->delta_v, 4 * n, hipMemcpyHostToDevice, st));
+      dv = ws.dv.as<uint32_t>();
+    }
+    if (sz.smask) {
+      RS_HIP(hipMemcpyAsync(ws.smask.p, ex->smask, n, hipMemcpyHostToDevice, st));
+      smask = ws.smask.as<uint8_t>();
+    }
+    if (sz.tmask) {
+      RS_HIP(hipMemcpyAsync(ws.tmask.p, ex->tmask, n, hipMemcpyHostToDevice, st));
+      tmask = ws.tmask.as<uint8_t>();
+    }
+    if (fine) {
+      RS_HIP(launch_fill64(ws.fine_t.as<uint64_t>(), 0, m, st));
+      RS_HIP(launch_fill32(ws.fine_r.as<uint32_t>(), 0xFFFFFFFFu, n, st));
+    }
     auto need_of = [&](uint32_t l) { return ws.need.as<uint8_t>() + (uint64_t)(l - 2) * need_stride(m); };
     const bool tr = timed && trace_on();
     if (tr && ws.lb_stats.reserve(16, st, true)) return RS_ENOMEM;
@@ -367,10 +410,33 @@ rs_status run_plain(rs_graph* g, PlainWorkspace& ws, const QueryPlan& qp, const 
       RS_HIP(launch_ztable(ws.z.as<uint64_t>(), (uint32_t)n, qp, G.colour.as<uint8_t>(), st));
     }
     const uint32_t run_w2 = sz.run_w2, run_w3 = sz.run_w3, run_stride = sz.run_stride;
+    CompactArgs ca{};
+    if (k >= 3) {
+      const uint64_t L = k - 1, lst = list_stride(m);
+      ca.e_src = G.e_src.as<uint32_t>();
+      ca.e_dst = G.e_dst.as<uint32_t>();
+      ca.e_t = G.e_t.as<uint32_t>();
+      ca.e_out = G.e_out.as<uint32_t>();
+      ca.hi = G.hi.as<uint32_t>();
+      ca.lo = ws.lo.as<uint32_t>();
+      ca.need = need_of(2);
+      ca.need_stride = need_stride(m);
+      ca.m = (uint32_t)m;
+      ca.k = k;
+      ca.kq = kq;
+      ca.nb = (uint32_t)((m + kCostBlock - 1) / kCostBlock);
+      ca.list_stride = lst;
+      ca.rows = ws.lists.as<uint64_t>();
+      ca.u32 = (uint32_t*)(ca.rows + L * lst * kq);
+      ca.u8 = (uint8_t*)(ca.u32 + L * 4 * lst);
+      ca.bsum = (uint32_t*)(((uintptr_t)(ca.u8 + L * lst) + 3) & ~(uintptr_t)3);
+      ca.boff = ca.bsum + L * ca.nb;
+      ca.count = ca.boff + L * ca.nb;
+    }
     {
       ProfScope ps(KC_WINDOW, st, 16.0 * m, timed);
       RS_HIP(launch_window(G.e_src.as<uint32_t>(), G.e_t.as<uint32_t>(), G.in_off.as<uint32_t>(),
-                           ws.lo.as<uint32_t>(), (uint32_t)m, qp.delta, st));
+                           ws.lo.as<uint32_t>(), (uint32_t)m, qp.delta, dv, st));
       // Flags per prefix level, from the last one down: level l stores the
       // slots the windows of level l+1's product edges read, and forms a
       // product only for edges inside one of those windows (level k-1: the
@@ -378,12 +444,14 @@ rs_status run_plain(rs_graph* g, PlainWorkspace& ws, const QueryPlan& qp, const 
       RS_HIP(launch_flags(G.e_out.as<uint32_t>(), G.hi.as<uint32_t>(), ws.lo.as<uint32_t>(), (uint32_t)m,
                           (uint32_t)n, k, need_of(2), need_stride(m), ws.ref.as<uint8_t>(), ws.cov_diff.as<uint32_t>(),
                           st));
-      // work-balanced runs of the prefix levels, cut for the grid width of
-      // the first chunk group (later groups launch the same width)
+      // compacted edge lists of levels 2..k and the work-balanced runs of
+      // the prefix lists, cut for the grid width of the first chunk group
+      // (later groups launch the same width)
       if (k >= 3) {
-        RS_HIP(launch_run_bounds(G.hi.as<uint32_t>(), ws.lo.as<uint32_t>(), need_of(2), need_stride(m), (uint32_t)m,
-                                 E, k - 2, run_w2, run_w3, ws.run_pre.as<uint32_t>(), ws.run_bsum.as<uint32_t>(),
-                                 ws.run_boff.as<uint32_t>(), ws.run_bounds.as<uint32_t>(), run_stride, st));
+        RS_HIP(launch_compact(ca, st));
+        RS_HIP(launch_compact_bounds(ca, E, (uint32_t)tiles, run_w2, run_w3, ws.run_pre.as<uint32_t>(),
+                                     ws.run_bsum.as<uint32_t>(), ws.run_boff.as<uint32_t>(),
+                                     ws.run_bounds.as<uint32_t>(), run_stride, st));
       }
     }
     if (tr) {
@@ -399,7 +467,7 @@ rs_status run_plain(rs_graph* g, PlainWorkspace& ws, const QueryPlan& qp, const 
       if (it == g->need_counts.end()) {
         if (g->counts_dev.reserve(64, st, true)) return RS_ENOMEM;
         for (uint32_t l = 2; l < k; ++l) {
-          unsigned long long h[5] = {0, 0, 0, 0, 0};
+          unsigned long long h[6] = {0, 0, 0, 0, 0, 0};
           RS_HIP(launch_fill64(g->counts_dev.as<uint64_t>(), 0, 8, st));
           RS_HIP(launch_need_counts(G.hi.as<uint32_t>(), ws.lo.as<uint32_t>(), need_of(l), (uint32_t)m,
                                     g->counts_dev.as<unsigned long long>(), st));
@@ -410,10 +478,11 @@ rs_status run_plain(rs_graph* g, PlainWorkspace& ws, const QueryPlan& qp, const 
           ncs[l].needed = h[2];
           ncs[l].ref_slots = h[3];
           ncs[l].ref_lead = h[4];
+          ncs[l].kept = h[5];
         }
         ncs[k] = ncs[k > 2 ? k - 1 : k];  // the last level needs only the window count
         if (k == 2) {  // no prefix level: count the windows alone
-          unsigned long long h[5] = {0, 0, 0, 0, 0};
+          unsigned long long h[6] = {0, 0, 0, 0, 0, 0};
           RS_HIP(launch_fill64(g->counts_dev.as<uint64_t>(), 0, 8, st));
           RS_HIP(launch_need_counts(G.hi.as<uint32_t>(), ws.lo.as<uint32_t>(), need_of(2), (uint32_t)m,
                                     g->counts_dev.as<unsigned long long>(), st));
@@ -427,9 +496,17 @@ rs_status run_plain(rs_graph* g, PlainWorkspace& ws, const QueryPlan& qp, const 
       }
     }
     {
+      // product rows: of the compacted lists' product entries (k >= 3), else
+      // of every edge, with the source and target constraints applied
       ProfScope ps(KC_QTABLE, st, (double)m * (12.0 + 8.0 * kq * (k - 1)), timed);
-      RS_HIP(launch_qtable(G.e_src.as<uint32_t>(), G.e_dst.as<uint32_t>(), G.e_t.as<uint32_t>(),
-                           ws.z.as<uint64_t>(), ws.q.as<uint64_t>(), (uint32_t)m, qp, st));
+      if (k >= 3) {
+        RS_HIP(launch_compact_rows(ca, ws.z.as<uint64_t>(), qp.seed, nullptr, smask, tmask, kq, st));
+      } else {
+        RS_HIP(launch_qtable(G.e_src.as<uint32_t>(), G.e_dst.as<uint32_t>(), G.e_t.as<uint32_t>(),
+                             ws.z.as<uint64_t>(), ws.q.as<uint64_t>(), (uint32_t)m, qp, st));
+        if (smask) RS_HIP(launch_mask_rows(ws.q.as<uint64_t>(), G.e_src.as<uint32_t>(), smask, (uint32_t)m, kq, st));
+        if (tmask) RS_HIP(launch_mask_rows(ws.q.as<uint64_t>(), G.e_dst.as<uint32_t>(), tmask, (uint32_t)m, kq, st));
+      }
     }
     if (tr) {
       const rs_status ts = trace("product rows", 0, 0, 0, false);
@@ -441,7 +518,6 @@ rs_status run_plain(rs_graph* g, PlainWorkspace& ws, const QueryPlan& qp, const 
       uint64_t* prev = ws.p0.as<uint64_t>();
       uint64_t* cur = ws.p1.as<uint64_t>();
       for (uint32_t l = 2; l <= k; ++l) {
-        const uint64_t* ql = ws.q.as<uint64_t>() + (uint64_t)(l - 2) * m * kq;
         const bool first = l == 2;
         if (l < k) {
           if (++ws.epoch >= (1u << 30)) {
@@ -449,12 +525,13 @@ rs_status run_plain(rs_graph* g, PlainWorkspace& ws, const QueryPlan& qp, const 
             RS_HIP(launch_fill64(ws.incl.as<uint64_t>(), 0, ws.incl.bytes / 8, st));
             ws.epoch = 1;
           }
+          const LevelList Lc = ca.list(l - 2);
           ScanArgs a;
-          a.e_src = G.e_src.as<uint32_t>();
-          a.e_out = G.e_out.as<uint32_t>();
-          a.hi = G.hi.as<uint32_t>();
-          a.lo = ws.lo.as<uint32_t>();
-          a.q = ql;
+          a.e_src = Lc.chi;  // level 2: the source of each entry
+          a.e_out = Lc.cslot;
+          a.hi = Lc.chi;
+          a.lo = Lc.clo;
+          a.q = Lc.cq;
           a.z = ws.z.as<uint64_t>();
           a.p_prev = prev;
           a.p_cur = cur;
@@ -466,9 +543,10 @@ rs_status run_plain(rs_graph* g, PlainWorkspace& ws, const QueryPlan& qp, const 
           a.epoch = ws.epoch;
           a.agg = ws.agg.as<uint64_t>();
           a.incl = ws.incl.as<uint64_t>();
-          a.need = need_of(l);
+          a.need = Lc.cflag;
           a.bounds = ws.run_bounds.as<uint32_t>() + (uint64_t)(l - 2) * run_stride;
           a.waves = first ? run_w2 : run_w3;
+          a.count = ca.count + (l - 2);
           if (tr) {
             RS_HIP(launch_fill64(ws.lb_stats.as<uint64_t>(), 0, 2, st));
             a.lb_stats = ws.lb_stats.as<unsigned long long>();
@@ -485,9 +563,18 @@ rs_status run_plain(rs_graph* g, PlainWorkspace& ws, const QueryPlan& qp, const 
         } else {
           TopArgs a;
           a.e_src = G.e_src.as<uint32_t>();
-          a.hi = G.hi.as<uint32_t>();
-          a.lo = ws.lo.as<uint32_t>();
-          a.q = ql;
+          if (k >= 3) {  // the compacted list of non-empty windows
+            const LevelList Lc = ca.list(k - 2);
+            a.hi = Lc.chi;
+            a.lo = Lc.clo;
+            a.q = Lc.cq;
+            a.count = ca.count + (k - 2);
+            a.ce = Lc.ce;
+          } else {
+            a.hi = G.hi.as<uint32_t>();
+            a.lo = ws.lo.as<uint32_t>();
+            a.q = ws.q.as<uint64_t>();
+          }
           a.z = ws.z.as<uint64_t>();
           a.p_prev = prev;
           a.p_stride = p_elems;
@@ -501,7 +588,10 @@ rs_status run_plain(rs_graph* g, PlainWorkspace& ws, const QueryPlan& qp, const 
           a.fsum = ws.fsum.as<uint64_t>();
           {
             ProfScope ps(KC_TOP, st, top_bytes(ncs[k], m, kq, gc, first), timed);
-            RS_HIP(launch_top(a, first, kq, gc, tu, st));
+            if (fine)
+              RS_HIP(launch_top_fine(a, first, kq, gc, tu, ws.fine_t.as<uint64_t>(), st));
+            else
+              RS_HIP(launch_top(a, first, kq, gc, tu, st));
           }
           if (tr) {
             const rs_status ts = trace("last", l, c0, gc, false);
@@ -509,6 +599,27 @@ rs_status run_plain(rs_graph* g, PlainWorkspace& ws, const QueryPlan& qp, const 
           }
         }
       }
+    }
+    if (fine) {
+      // zeta per slot, reach times; F = the XOR of the per-edge sums
+      RS_HIP(launch_fine_slots(G.e_dst.as<uint32_t>(), G.e_t.as<uint32_t>(), ws.fine_t.as<uint64_t>(), (uint32_t)m,
+                               ws.fine_z.as<uint64_t>(), ws.fine_r.as<uint32_t>(), st));
+      RS_HIP(launch_xor_reduce(ws.fine_t.as<uint64_t>(), 0, m, ws.out.as<uint64_t>(), st));
+      RS_HIP(hipMemcpyAsync(&F, ws.out.p, 8, hipMemcpyDeviceToHost, st));
+      RS_HIP(hipMemcpyAsync(ex->reach, ws.fine_r.p, 4 * n, hipMemcpyDeviceToHost, st));
+      if (ex->zeta) RS_HIP(hipMemcpyAsync(ex->zeta, ws.fine_z.p, 8 * m, hipMemcpyDeviceToHost, st));
+      if (timed) RS_HIP(hipEventRecord(ws.ev1, st));
+      RS_HIP(hipStreamSynchronize(st));
+      ex->reached = 0;
+      for (uint64_t u = 0; u < n; ++u) ex->reached += ex->reach[u] != 0xFFFFFFFFu;
+      float ms = 0;
+      if (timed) (void)hipEventElapsedTime(&ms, ws.ev0, ws.ev1);
+      if (profiling_on()) profile_flush();
+      r->fingerprint = F;
+      r->yes = ex->reached != 0;
+      r->status = RS_OK;
+      r->device_ms = ms;
+      return RS_OK;
     }
     RS_HIP(launch_xor_reduce(ws.fsum.as<uint64_t>(), qp.it_begin, qp.it_end, ws.out.as<uint64_t>(), st));
     RS_HIP(hipMemcpyAsync(&F, ws.out.p, 8, hipMemcpyDeviceToHost, st));
@@ -520,6 +631,12 @@ rs_status run_plain(rs_graph* g, PlainWorkspace& ws, const QueryPlan& qp, const 
   } else {
     if (per_it_host)
       for (uint64_t i = 0; i < span; ++i) per_it_host[i] = 0;
+    if (fine) {  // nothing reaches anything
+      for (uint64_t u = 0; u < n; ++u) ex->reach[u] = 0xFFFFFFFFu;
+      if (ex->zeta)
+        for (uint64_t e = 0; e < m; ++e) ex->zeta[e] = 0;
+      ex->reached = 0;
+    }
     if (timed) RS_HIP(hipEventRecord(ws.ev1, st));
     RS_HIP(hipStreamSynchronize(st));
   }
@@ -669,6 +786,11 @@ rs_status rs_run_ex(const rs_graph* gc, const rs_query* q, const rs_tuning* tune
     return s;
   }
   rs_graph* g = const_cast<rs_graph*>(gc);
+  if (tune && tune->edges_per_tile == 8 && g->g.m > kMaxEdgesE8) {
+    set_last_error("8-edge tiles are not accepted on graphs of more than 4e6 edges");
+    r->status = RS_EINVAL;
+    return RS_EINVAL;
+  }
   try {
     std::lock_guard<std::mutex> lk(g->mu);
     s = run_plain(g, g->ws, qp, resolve_tuning(g, qp.k, tune), per_iteration, r, (hipStream_t)hip_stream);
@@ -681,6 +803,121 @@ rs_status rs_run_ex(const rs_graph* gc, const rs_query* q, const rs_tuning* tune
 
 rs_status rs_run(const rs_graph* g, const rs_query* q, rs_result* r, void* hip_stream) {
   return rs_run_ex(g, q, nullptr, nullptr, r, hip_stream);
+}
+
+// Host masks and per-vertex resting times of a constraint set (validated).
+struct HostConstraints {
+  std::vector<uint8_t> smask, tmask;
+  QueryExtras ex;
+};
+static rs_status make_constraints(const rs_graph* g, const rs_constraints* c, HostConstraints& h) {
+  h.ex = QueryExtras();
+  if (!c) return RS_OK;
+  const uint32_t n = g->g.n;
+  if ((c->n_sources && !c->sources) || (c->n_targets && !c->targets)) return RS_EINVAL;
+  h.ex.delta_v = c->delta_per_vertex;
+  if (c->n_sources) {
+    h.smask.assign(std::max<uint32_t>(n, 1), 0);
+    for (uint32_t i = 0; i < c->n_sources; ++i) {
+      if (c->sources[i] >= n) return RS_EINVAL;
+      h.smask[c->sources[i]] = 1;
+    }
+    h.ex.smask = h.smask.data();
+  }
+  if (c->n_targets) {
+    h.tmask.assign(std::max<uint32_t>(n, 1), 0);
+    for (uint32_t i = 0; i < c->n_targets; ++i) {
+      if (c->targets[i] >= n) return RS_EINVAL;
+      h.tmask[c->targets[i]] = 1;
+    }
+    h.ex.tmask = h.tmask.data();
+  }
+  return RS_OK;
+}
+
+rs_status rs_run_constrained(const rs_graph* gc, const rs_query* q, const rs_constraints* c, uint64_t* per_iteration,
+                             rs_result* r, void* hip_stream) {
+  if (!r) return RS_EINVAL;
+  QueryPlan qp;
+  rs_status s = plan_query(gc, q, qp);
+  rs_graph* g = const_cast<rs_graph*>(gc);
+  try {
+    HostConstraints h;
+    if (s == RS_OK) s = make_constraints(g, c, h);
+    if (s == RS_OK) {
+      std::lock_guard<std::mutex> lk(g->mu);
+      s = run_plain(g, g->ws, qp, resolve_tuning(g, qp.k, nullptr), per_iteration, r, (hipStream_t)hip_stream, &h.ex);
+    }
+  } catch (...) {
+    s = RS_ENOMEM;
+  }
+  r->status = s;
+  return s;
+}
+
+rs_status rs_run_fine(const rs_graph* gc, const rs_query* q, const rs_constraints* c, uint32_t* reach_time,
+                      uint64_t* slot_zeta, rs_result* r, void* hip_stream) {
+  if (!r || !reach_time) return RS_EINVAL;
+  QueryPlan qp;
+  rs_status s = plan_query(gc, q, qp);
+  rs_graph* g = const_cast<rs_graph*>(gc);
+  try {
+    HostConstraints h;
+    if (s == RS_OK) s = make_constraints(g, c, h);
+    if (s == RS_OK) {
+      h.ex.fine = true;
+      h.ex.reach = reach_time;
+      h.ex.zeta = slot_zeta;
+      std::lock_guard<std::mutex> lk(g->mu);
+      s = run_plain(g, g->ws, qp, resolve_tuning(g, qp.k, nullptr), nullptr, r, (hipStream_t)hip_stream, &h.ex);
+    }
+  } catch (...) {
+    s = RS_ENOMEM;
+  }
+  r->status = s;
+  return s;
+}
+
+rs_status rs_reach_at_most(const rs_graph* gc, const rs_query* q, const rs_constraints* c, uint32_t* reach_time,
+                           uint32_t* reach_vertices, rs_result* r, void* hip_stream) {
+  if (!r || !reach_time || !q || q->motif_count || q->it_begin || q->it_end) return RS_EINVAL;
+  rs_graph* g = const_cast<rs_graph*>(gc);
+  rs_status s = RS_OK;
+  try {
+    const uint32_t n = gc ? gc->g.n : 0;
+    std::vector<uint32_t> rk(std::max<uint32_t>(n, 1));
+    for (uint32_t u = 0; u < n; ++u) {
+      reach_time[u] = 0xFFFFFFFFu;
+      if (reach_vertices) reach_vertices[u] = 0;
+    }
+    uint64_t F = 0;
+    float ms = 0;
+    uint64_t reached = 0;
+    for (uint32_t kk = 2; kk <= q->k && s == RS_OK; ++kk) {
+      rs_query qk = *q;
+      qk.k = kk;
+      rs_result rr{};
+      s = rs_run_fine(g, &qk, c, rk.data(), nullptr, &rr, hip_stream);
+      if (s != RS_OK) break;
+      F ^= rr.fingerprint;
+      ms += rr.device_ms;
+      for (uint32_t u = 0; u < n; ++u) {
+        if (rk[u] == 0xFFFFFFFFu) continue;
+        if (reach_vertices && reach_vertices[u] == 0) reach_vertices[u] = kk;
+        if (reach_time[u] == 0xFFFFFFFFu) ++reached;
+        reach_time[u] = std::min(reach_time[u], rk[u]);
+      }
+    }
+    if (s == RS_OK) {
+      r->fingerprint = F;
+      r->yes = reached != 0;
+      r->device_ms = ms;
+    }
+  } catch (...) {
+    s = RS_ENOMEM;
+  }
+  r->status = s;
+  return s;
 }
 
 rs_status rs_run_noalloc(const rs_graph* gc, const rs_query* q, uint64_t* per_iteration, rs_result* r,

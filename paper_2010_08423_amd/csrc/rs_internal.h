@@ -61,6 +61,11 @@ constexpr uint32_t kEdgePad = 64;
 constexpr uint32_t kFlagAgg = 1;   // record: XOR of the tile's open segment part
 constexpr uint32_t kFlagIncl = 2;  // record: full prefix of that segment
 
+// Largest graph (edges) on which 8-edge tiles are accepted: that shape ran
+// for over 140 s on a 10^7-edge query under an earlier look-back schedule and
+// has not been validated at that size since, so larger graphs reject it.
+constexpr uint64_t kMaxEdgesE8 = 4000000;
+
 struct Tuning {
   uint32_t edges_per_tile = 16;      // scan levels: 8 or 16
   uint32_t top_edges_per_tile = 64;  // last level: edges per wave's range
@@ -101,6 +106,8 @@ struct ScanArgs {
   unsigned long long* lb_stats = nullptr;  // null, or [2] look-back counters (see TileCtx)
   const uint32_t* bounds = nullptr;        // null, or [waves+1] work-balanced first tile of each run
   uint32_t waves = 0;                      // waves per chunk the bounds were cut for
+  const uint32_t* count = nullptr;         // null, or the device-side length of a compacted edge list
+                                           // (then m and n_tiles only bound it: record stride, grids)
 };
 // Blocks of a kernel with this block size and dynamic LDS that fit on the
 // whole GPU at once (cached).
@@ -139,6 +146,8 @@ struct TopArgs {
   uint32_t k;
   uint64_t* partial;  // [chunks][blocks][64] per-block sums
   uint64_t* fsum;     // [2^k] per-iteration sums
+  const uint32_t* count = nullptr;  // null, or the device-side length of the compacted last-level list
+  const uint32_t* ce = nullptr;     // compacted list: original edge of each entry (fine-grained outputs)
 };
 // Rows of `partial` one launch_top call writes per chunk.
 uint32_t top_blocks(const TopArgs& a, bool first_level, uint32_t kq, uint32_t chunks, const Tuning& tu);
@@ -146,8 +155,86 @@ uint32_t top_blocks(const TopArgs& a, bool first_level, uint32_t kq, uint32_t ch
 // Launchers (rs_kernels.hip). All enqueue on `st` and return hipGetLastError.
 hipError_t launch_ztable(uint64_t* z, uint32_t n, const QueryPlan& qp, const uint8_t* colour_d,
                          hipStream_t st);
+// delta_v: per-vertex resting times [n] on the device, or null (then delta).
 hipError_t launch_window(const uint32_t* e_src, const uint32_t* e_t, const uint32_t* in_off,
-                         uint32_t* lo, uint32_t m, uint32_t delta, hipStream_t st);
+                         uint32_t* lo, uint32_t m, uint32_t delta, const uint32_t* delta_v, hipStream_t st);
+
+// Entries per block of the block-wise prefix sums (tile costs, window cover,
+// list compaction): 256 threads x 4.
+constexpr uint32_t kCostBlock = 1024;
+
+// Weights of the work-balanced runs: per tile and per product, at level 2
+// and above it (fitted to per-wave clocks).
+constexpr uint32_t kTileCost = 5, kProductCost = 3;
+constexpr uint32_t kTileCostFirst = 7, kProductCostFirst = 4;
+
+// One level's compacted edge list (rs_compact.hip): the kept edges of the
+// level in edge order, with what a tile reads laid out contiguously.
+struct LevelList {
+  uint32_t* ce;     // original edge
+  uint32_t* cslot;  // P slot of the edge (prefix levels)
+  uint32_t* chi;    // window end slot (levels >= 3), or the source vertex (level 2)
+  uint32_t* clo;    // window start slot (levels >= 3)
+  uint8_t* cflag;   // bits 0..2 of the level's flags; bit 3: the running XOR restarts here
+  uint64_t* cq;     // [entries][kq] product rows of the entries that form a product
+};
+// The compacted lists of levels 2..k of one query (level index y = l - 2;
+// y = k - 2 is the last level), and what builds them.
+struct CompactArgs {
+  const uint32_t* e_src;
+  const uint32_t* e_dst;
+  const uint32_t* e_t;
+  const uint32_t* e_out;
+  const uint32_t* hi;
+  const uint32_t* lo;
+  const uint8_t* need;   // flags of prefix level l at need + (l - 2) * need_stride
+  uint64_t need_stride;
+  uint32_t m, k, kq;
+  uint32_t nb;           // blocks of kCostBlock edges
+  uint32_t* bsum;        // [k-1][nb] scratch: kept edges per block
+  uint32_t* boff;        // [k-1][nb] scratch: their exclusive prefix
+  uint32_t* count;       // [k-1] list lengths
+  uint32_t* u32;         // four u32 arrays per level: ce, cslot, chi, clo, each list_stride entries
+  uint8_t* u8;           // cflag per level, list_stride entries
+  uint64_t* rows;        // product rows per level, list_stride * kq entries
+  uint64_t list_stride;  // entries per list array (m + kEdgePad, rounded up)
+  __host__ __device__ LevelList list(uint32_t y) const {
+    uint32_t* b = u32 + (uint64_t)y * 4 * list_stride;
+    return LevelList{b, b + list_stride, b + 2 * list_stride, b + 3 * list_stride, u8 + (uint64_t)y * list_stride,
+                     rows + (uint64_t)y * list_stride * kq};
+  }
+};
+inline uint64_t list_stride(uint64_t m) { return (m + kEdgePad + 63) & ~63ull; }
+// Device bytes of the lists and their scratch for a query with k >= 3 levels.
+inline uint64_t compact_bytes(uint64_t m, uint32_t k, uint32_t kq) {
+  const uint64_t L = k - 1, st = list_stride(m), nb = (m + 1023) / 1024;
+  return L * (st * (16 + 1 + 8ull * kq)) + 4 * L * (2 * nb + 1) + 1024;
+}
+// Builds the lists (counts, offsets, scatter).
+hipError_t launch_compact(const CompactArgs& a, hipStream_t st);
+// Restart bits and per-tile costs of the prefix lists (tiles of E entries;
+// tiles_max bounds the tile count of every list): the inclusive cost prefix
+// within blocks, pre [k-2][tiles_max], its block totals and offsets, bsum and
+// boff [k-2][ceil(tiles_max / kCostBlock)].
+hipError_t launch_compact_costs(const CompactArgs& a, uint32_t E, uint32_t tiles_max, uint32_t* pre, uint32_t* bsum,
+                                uint32_t* boff, hipStream_t st);
+// The same, then the work-balanced run bounds [k-2][b_stride] for w_first
+// waves per chunk at level 2 and w_rest above it.
+hipError_t launch_compact_bounds(const CompactArgs& a, uint32_t E, uint32_t tiles_max, uint32_t w_first,
+                                 uint32_t w_rest, uint32_t* pre, uint32_t* bsum, uint32_t* boff, uint32_t* bounds,
+                                 uint32_t b_stride, hipStream_t st);
+// Product rows of the lists (seed dependent: seed, or *seed_p read on the
+// device when seed_p is not null). smask / tmask: device [n] masks of the
+// source and target vertices, or null.
+hipError_t launch_compact_rows(const CompactArgs& a, const uint64_t* z, uint64_t seed, const uint64_t* seed_p,
+                               const uint8_t* smask, const uint8_t* tmask, uint32_t kq, hipStream_t st);
+// Fine-grained last level and slot sums (rs_fine.hip).
+hipError_t launch_top_fine(const TopArgs& a, bool first_level, uint32_t kq, uint32_t chunks, const Tuning& tu,
+                           uint64_t* T, hipStream_t st);
+hipError_t launch_fine_slots(const uint32_t* e_dst, const uint32_t* e_t, const uint64_t* T, uint32_t m, uint64_t* zeta,
+                             uint32_t* reach, hipStream_t st);
+hipError_t launch_mask_rows(uint64_t* rows, const uint32_t* e_vertex, const uint8_t* mask, uint32_t m, uint32_t kq,
+                            hipStream_t st);
 // Edge counts of a query's windows and flags (graph and delta only), used to
 // state the algorithmic bytes of the level launches.
 struct NeedCounts {
@@ -156,9 +243,10 @@ struct NeedCounts {
   uint64_t needed = 0;       // edges whose product reaches a read slot
   uint64_t ref_slots = 0;    // edge slots that some window reads
   uint64_t ref_lead = 0;     // leading slots that some window reads
+  uint64_t kept = 0;         // edges in the level's compacted list
 };
-// counts[5] on the device, zeroed beforehand: live, live_needed, needed,
-// ref_slots, ref_lead.
+// counts[6] on the device, zeroed beforehand: live, live_needed, needed,
+// ref_slots, ref_lead, kept.
 hipError_t launch_need_counts(const uint32_t* hi, const uint32_t* lo, const uint8_t* need, uint32_t m,
                               unsigned long long* counts, hipStream_t st);
 // Store and product flags of prefix levels k-1 down to 2 (see mark_cover):
@@ -198,9 +286,20 @@ uint64_t table_z_bytes(uint64_t n, uint32_t kq);
 uint64_t table_q_bytes(uint64_t m, uint32_t k, uint32_t kq);
 uint64_t table_need_bytes(uint64_t m, uint32_t k);
 struct PlainWorkspace;
+// Constraints and fine-grained outputs of one plain-path query; every array
+// is host memory. Null / false: none.
+struct QueryExtras {
+  const uint32_t* delta_v = nullptr;  // [n] resting time per vertex (Sec. 2), replaces the scalar delta
+  const uint8_t* smask = nullptr;     // [n] source vertices: walks start only there (Sec. 3)
+  const uint8_t* tmask = nullptr;     // [n] target vertices: walks end only there (Sec. 3)
+  bool fine = false;                  // keep zeta per slot (Alg. 1, Sec. 4.5)
+  uint32_t* reach = nullptr;          // [n] fine: least reach time, 0xFFFFFFFF if none
+  uint64_t* zeta = nullptr;           // [m] fine, may be null: zeta of each canonical edge's slot
+  uint64_t reached = 0;               // fine, out: vertices with a reach time
+};
 // Plain path (rs_engine.hip): one query through workspace ws on stream st.
 rs_status run_plain(rs_graph* g, PlainWorkspace& ws, const QueryPlan& qp, const Tuning& tu, uint64_t* per_it_host,
-                    rs_result* r, hipStream_t st);
+                    rs_result* r, hipStream_t st, QueryExtras* ex = nullptr);
 rs_status plan_query(const rs_graph* g, const rs_query* q, QueryPlan& qp);
 Tuning resolve_tuning(const rs_graph* g, uint32_t k, const rs_tuning* t);
 // Batched path (rs_batch.hip). A batch workspace holds the device buffers and
@@ -253,6 +352,9 @@ struct PlainWorkspace {
   DevBuf lb_stats;  // look-back counters, allocated only while launches are traced
   DevBuf run_pre, run_bsum, run_boff, run_bounds;  // work-balanced runs of the prefix levels
   DevBuf cov_diff;  // window-cover scratch of the flags: difference array and block sums
+  DevBuf lists;     // compacted edge lists of levels 2..k and their scratch (k >= 3)
+  DevBuf dv, smask, tmask;         // constraints: per-vertex resting times, source and target masks
+  DevBuf fine_t, fine_z, fine_r;   // fine-grained outputs: per-edge sums, per-slot zeta, reach times
   uint32_t epoch = 0;
   uint64_t p_elems_per_chunk = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -260,15 +362,17 @@ struct PlainWorkspace {
   uint64_t scratch_bytes = 0;
   uint64_t bytes() const {
     uint64_t t = 0;
-    for (const DevBuf* b : {&lo, &z, &q, &p0, &p1, &partial, &agg, &incl, &fsum, &out, &ref, &need,
-                            &lb_stats, &run_pre, &run_bsum, &run_boff, &run_bounds, &cov_diff})
+    for (const DevBuf* b : {&lo, &z, &q, &p0, &p1, &partial, &agg, &incl, &fsum, &out, &ref, &need, &lb_stats,
+                            &run_pre, &run_bsum, &run_boff, &run_bounds, &cov_diff, &lists, &dv, &smask, &tmask,
+                            &fine_t, &fine_z, &fine_r})
       t += b->bytes;
     return t;
   }
   void release() {
     if (scratch) return;  // borrowed buffers are never freed
     for (DevBuf* b : {&lo, &z, &q, &p0, &p1, &partial, &agg, &incl, &fsum, &out, &ref, &need, &lb_stats,
-                      &run_pre, &run_bsum, &run_boff, &run_bounds, &cov_diff})
+                      &run_pre, &run_bsum, &run_boff, &run_bounds, &cov_diff, &lists, &dv, &smask, &tmask, &fine_t,
+                      &fine_z, &fine_r})
       b->release();
     if (ev0) (void)hipEventDestroy(ev0);
     if (ev1) (void)hipEventDestroy(ev1);
@@ -283,10 +387,14 @@ struct PlainWorkspace {
 struct PlainSizes {
   uint64_t lo, z, q, p, partial, fsum, ref, need, cover, records;
   uint64_t run_pre, run_bsum, run_boff, run_bounds;
+  uint64_t lists;                  // compacted lists (k >= 3; the q table is used only at k = 2)
+  uint64_t dv, smask, tmask;       // constraints (0 when absent)
+  uint64_t fine_t, fine_z, fine_r; // fine-grained outputs (0 when not asked)
   uint32_t run_w2, run_w3, run_stride;  // waves per chunk of level 2 and of levels >= 3; bounds stride
   uint64_t total() const;
 };
-PlainSizes plain_sizes(uint64_t m, uint64_t n, const QueryPlan& qp, const Tuning& tu);
+PlainSizes plain_sizes(uint64_t m, uint64_t n, const QueryPlan& qp, const Tuning& tu,
+                       const QueryExtras* ex = nullptr);
 // Largest query workspace of the no-allocation entry point (bytes of its
 // per-device scratch array).
 constexpr uint64_t kNoAllocScratchBytes = 256ull << 20;

@@ -27,7 +27,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
     const uint64_t* __restrict__ p_prev, uint64_t* __restrict__ p_cur, uint64_t p_stride,
     uint64_t chunk_base, uint32_t m, uint32_t n_tiles, uint32_t epoch,
     uint64_t* __restrict__ agg, uint64_t* __restrict__ incl, const uint8_t* __restrict__ need,
-    unsigned long long* __restrict__ lb_stats, const uint32_t* __restrict__ bounds) {
+    unsigned long long* __restrict__ lb_stats, const uint32_t* __restrict__ bounds, const uint32_t* __restrict__ count) {
   extern __shared__ uint64_t dyn_lds[];  // [waves][16][64]; starts at LDS address 0
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform for the compiler
@@ -47,8 +47,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
   c.pp = p_prev + (uint64_t)chunk * p_stride;
   c.pc = p_cur + (uint64_t)chunk * p_stride;
   c.cb = chunk_base + (uint64_t)chunk * kLanes;
-  c.m = m;
-  c.n_tiles = n_tiles;
+  // a compacted list's length is on the device; n_tiles stays the record stride
+  c.m = count ? __builtin_amdgcn_readfirstlane(*as_const(count)) : m;
+  c.n_tiles = count ? (c.m + E - 1) / E : n_tiles;
   c.epoch = epoch;
   c.row0 = (uint64_t)chunk * n_tiles;
   c.agg = agg;
@@ -70,8 +71,10 @@ __global__ __launch_bounds__(256) void k_top(
     const uint32_t* __restrict__ e_src, const uint32_t* __restrict__ hi_idx,
     const uint32_t* __restrict__ lo_idx, const uint64_t* __restrict__ q,
     const uint64_t* __restrict__ z, const uint64_t* __restrict__ p_prev, uint64_t p_stride,
-    uint64_t chunk_base, uint32_t m, uint32_t edges_per_wave, uint64_t* __restrict__ partial) {
+    uint64_t chunk_base, uint32_t m_max, uint32_t edges_per_wave, uint64_t* __restrict__ partial,
+    const uint32_t* __restrict__ count) {
   extern __shared__ uint64_t dyn_lds[];  // [waves][16][64]; starts at LDS address 0
+  const uint32_t m = count ? __builtin_amdgcn_readfirstlane(*as_const(count)) : m_max;  // compacted list length
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform for the compiler
   const uint32_t nw = blockDim.x >> 6;
@@ -165,17 +168,19 @@ __global__ __launch_bounds__(256) void k_ztable(uint64_t* __restrict__ z, uint32
   z[idx] = v;
 }
 
-// lo(e): slot of the first arrival at v = src(e) with time >= t(e) - delta.
+// lo(e): slot of the first arrival at v = src(e) with time >= t(e) - delta(v)
+// (delta(v) from delta_v when given, else the scalar delta).
 __global__ __launch_bounds__(256) void k_window(const uint32_t* __restrict__ e_src,
                                                 const uint32_t* __restrict__ e_t,
                                                 const uint32_t* __restrict__ in_off,
                                                 uint32_t* __restrict__ lo, uint32_t m,
-                                                uint32_t delta) {
+                                                uint32_t delta, const uint32_t* __restrict__ delta_v) {
   const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= m) return;
   const uint32_t v = e_src[e];
   const uint32_t t = e_t[e];
-  const uint32_t thr = t > delta ? t - delta : 0u;
+  const uint32_t dv = delta_v ? delta_v[v] : delta;
+  const uint32_t thr = t > dv ? t - dv : 0u;
   uint32_t a = in_off[v], b = in_off[v + 1];
   while (a < b) {
     const uint32_t mid = a + ((b - a) >> 1);
@@ -299,12 +304,10 @@ hipError_t launch_ztable(uint64_t* z, uint32_t n, const QueryPlan& qp, const uin
 // (level 2 + y); per level the arrays are pre[n_tiles], bsum[nb], boff[nb],
 // bounds[W+1], at the strides given.
 // ---------------------------------------------------------------------------
-// Weights of a tile and of a product, from per-wave clocks regressed on the
-// tiles and products of each wave's run (10^6-edge graph): levels >= 3 fit
-// 2.4 us per tile plus 1.3-1.4 us per product, level 2 2.1 us per tile plus
-// 1.2 us per product (level 2 gathers no windows).
-constexpr uint32_t kTileCost = 5, kProductCost = 3;
-constexpr uint32_t kTileCostFirst = 7, kProductCostFirst = 4;
+// The weights of a tile and of a product (kTileCost ...) come from per-wave
+// clocks regressed on the tiles and products of each wave's run (10^6-edge
+// graph): levels >= 3 fit 2.4 us per tile plus 1.3-1.4 us per product, level
+// 2 2.1 us per tile plus 1.2 us per product (level 2 gathers no windows).
 
 // The product bit of the flags already requires a non-empty window at levels
 // >= 3, and the flag bytes past m are zero, so a tile's products are a
@@ -399,10 +402,10 @@ hipError_t launch_run_bounds(const uint32_t* hi, const uint32_t* lo, const uint8
 __global__ __launch_bounds__(256) void k_need_counts(const uint32_t* __restrict__ hi, const uint32_t* __restrict__ lo,
                                                      const uint8_t* __restrict__ need, uint32_t m,
                                                      unsigned long long* __restrict__ counts) {
-  __shared__ unsigned long long part[5];
-  if (threadIdx.x < 5) part[threadIdx.x] = 0;
+  __shared__ unsigned long long part[6];
+  if (threadIdx.x < 6) part[threadIdx.x] = 0;
   __syncthreads();
-  uint32_t c[5] = {0, 0, 0, 0, 0};
+  uint32_t c[6] = {0, 0, 0, 0, 0, 0};
   for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (uint64_t)gridDim.x * blockDim.x) {
     const uint32_t f = need[e];
     const bool live = hi[e] != lo[e];
@@ -411,10 +414,11 @@ __global__ __launch_bounds__(256) void k_need_counts(const uint32_t* __restrict_
     c[2] += (f >> 2) & 1u;
     c[3] += f & 1u;
     c[4] += (f >> 1) & 1u;
+    c[5] += (f & 7u) != 0;  // kept in the level's compacted list
   }
-  for (int j = 0; j < 5; ++j) atomicAdd(&part[j], (unsigned long long)c[j]);
+  for (int j = 0; j < 6; ++j) atomicAdd(&part[j], (unsigned long long)c[j]);
   __syncthreads();
-  if (threadIdx.x < 5) atomicAdd(&counts[threadIdx.x], part[threadIdx.x]);
+  if (threadIdx.x < 6) atomicAdd(&counts[threadIdx.x], part[threadIdx.x]);
 }
 
 hipError_t launch_need_counts(const uint32_t* hi, const uint32_t* lo, const uint8_t* need, uint32_t m,
@@ -501,9 +505,9 @@ hipError_t launch_flags(const uint32_t* e_out, const uint32_t* hi, const uint32_
 }
 
 hipError_t launch_window(const uint32_t* e_src, const uint32_t* e_t, const uint32_t* in_off,
-                         uint32_t* lo, uint32_t m, uint32_t delta, hipStream_t st) {
+                         uint32_t* lo, uint32_t m, uint32_t delta, const uint32_t* delta_v, hipStream_t st) {
   if (!m) return hipSuccess;
-  hipLaunchKernelGGL(k_window, dim3(div_up(m, 256)), dim3(256), 0, st, e_src, e_t, in_off, lo, m, delta);
+  hipLaunchKernelGGL(k_window, dim3(div_up(m, 256)), dim3(256), 0, st, e_src, e_t, in_off, lo, m, delta, delta_v);
   return hipGetLastError();
 }
 
@@ -537,7 +541,7 @@ static void scan_one(const ScanArgs& a, uint32_t chunks, uint32_t wpb, hipStream
   dim3 g(gx, chunks), b(64 * wpb);
   hipLaunchKernelGGL((k_scan<KQ, E, FIRST>), g, b, lds, st, a.e_src, a.e_out, a.hi, a.lo, a.q, a.z,
                      a.p_prev, a.p_cur, a.p_stride, a.chunk_base, a.m, a.n_tiles, a.epoch, a.agg,
-                     a.incl, a.need, a.lb_stats, a.bounds);
+                     a.incl, a.need, a.lb_stats, a.bounds, a.count);
 }
 
 uint32_t scan_waves(uint32_t kq, uint32_t E, bool first, uint32_t n_tiles, uint32_t chunks, uint32_t wpb) {
@@ -603,10 +607,10 @@ static void top_kq(const TopArgs& a, bool first, uint32_t chunks, uint32_t wpb, 
   dim3 g(blocks, chunks), b(64 * wpb);
   if (first)
     hipLaunchKernelGGL((k_top<KQ, true>), g, b, lds, st, a.e_src, a.hi, a.lo, a.q, a.z, a.p_prev,
-                       a.p_stride, a.chunk_base, a.m, a.edges_per_wave, a.partial);
+                       a.p_stride, a.chunk_base, a.m, a.edges_per_wave, a.partial, a.count);
   else
     hipLaunchKernelGGL((k_top<KQ, false>), g, b, lds, st, a.e_src, a.hi, a.lo, a.q, a.z, a.p_prev,
-                       a.p_stride, a.chunk_base, a.m, a.edges_per_wave, a.partial);
+                       a.p_stride, a.chunk_base, a.m, a.edges_per_wave, a.partial, a.count);
 }
 
 uint32_t top_blocks(const TopArgs& a, bool first, uint32_t kq, uint32_t chunks, const Tuning& tu) {

@@ -276,17 +276,16 @@ __device__ __forceinline__ uint64_t edge_value(const TileCtx& c, uint32_t e, uin
 template <int KQ, int E, bool FIRST>
 __device__ uint64_t tile_open_part(const TileCtx& c, uint32_t j, uint32_t lane, const uint32_t (&mk)[6],
                                    uint64_t* tab, bool* started) {
-  cu32* e_out = as_const(c.e_out);
   cu32* hi_idx = as_const(c.hi);
   cu32* lo_idx = as_const(c.lo);
   cu32* e_src = as_const(c.e_src);
   const uint32_t e0 = j * (uint32_t)E;
   const uint32_t e1 = min(e0 + (uint32_t)E, c.m);
-  bool st = !(e0 > 0 && e_out[e0] == e_out[e0 - 1] + 1u);
+  bool st = e0 == 0 || (c.need[e0] & 8u);
   uint64_t acc = 0;
 #pragma unroll 1
   for (uint32_t e = e0; e < e1; ++e) {
-    if (e > e0 && e_out[e] != e_out[e - 1] + 1u) {
+    if (e > e0 && (c.need[e] & 8u)) {  // the running XOR restarts here
       acc = 0;
       st = true;
     }
@@ -451,10 +450,10 @@ __device__ __forceinline__ void scan_run(const TileCtx& c, uint32_t w, uint32_t 
   const uint32_t R = (c.n_tiles + W - 1) / W;  // tiles per run when the runs are of equal length
   const uint32_t t0 = run_begin(c, w, R), t1 = run_begin(c, w + 1, R);
   if (t0 >= t1) return;
-  cu32* e_out = as_const(c.e_out);
   const uint32_t m = c.m;
   const uint32_t e_begin = t0 * (uint32_t)E;
-  const bool cont = e_begin > 0 && e_out[e_begin] == e_out[e_begin - 1] + 1u;
+  // the run continues its predecessor's segment unless its first entry restarts
+  const bool cont = e_begin > 0 && !((c.need[e_begin] >> 3) & 1u);
   bool started = !cont;        // a segment starts in the run (its own first edge included)
   uint32_t open_end = e_begin; // edges [e_begin, open_end) precede the run's first segment start
   uint64_t acc = 0;
@@ -655,8 +654,8 @@ __device__ __forceinline__ void scan_runs(const TileCtx& c, uint32_t w, uint32_t
   }
 }
 
-// The schedule of a prefix level: interleaved runs at level 2, one
-// contiguous run per wave above it.
+// The schedule of a prefix level: interleaved runs at level 2 without run
+// bounds, one contiguous run per wave otherwise.
 template <int KQ, int E, bool FIRST>
 __device__ __forceinline__ void scan_level(const TileCtx& c, uint32_t w, uint32_t W, uint32_t lane,
                                            const uint32_t (&mk)[6], uint64_t* tab) {
@@ -752,9 +751,6 @@ __device__ __forceinline__ void top_range(const uint32_t* e_src_p, const uint32_
 // A prefix level forms the product of an edge only with bit 2 and stores only
 // slots with bit 0 / bit 1. The kEdgePad bytes past m are zero.
 
-// Entries per block of the block-wise prefix sums (tile costs, window cover):
-// 256 threads x 4.
-constexpr uint32_t kCostBlock = 1024;
 
 // Work-balanced runs: bounds[w] = the first tile whose exclusive cost prefix
 // reaches ceil(total * w / W), with pre[] the inclusive cost prefix within
