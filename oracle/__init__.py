@@ -256,3 +256,81 @@ def count_paths(n, src, dst, t, k, delta, colour=None, n_colours=0, motif=None) 
     if rc:
         raise ValueError(f"orc_count_paths rejected the query (rc={rc})")
     return cnt.value
+
+
+# --- fine-grained extraction (Sec. 4.7) --------------------------------------
+
+def extract(n, src, dst, t, k, delta, seed, colour=None, n_colours=0, motif=None, sources=None, targets=None,
+            threads=1):
+    """Extraction of an optimal solution with k fine-grained queries (Sec. 4.7,
+    "using fine-grained oracle"): a restless path with k vertices (agreeing
+    with the motif; from a source, to a target when given) whose largest
+    timestamp is least. Returns None when the first query finds no path,
+    else (vertices, times): vertices u_1..u_k of the path and times[j] the
+    timestamp of its edge (u_{j+1} -> u_{j+2}) (0-based j).
+
+    The queries follow the section's generalisation, with the source of the
+    reachability instance given directly (walks start only at the sources)
+    instead of through an added vertex s':
+      * query with k vertices on G: (u_k, i_k) = the slot with least i, then
+        least u, among those whose zeta != 0 (optimal: the last edge carries
+        the largest timestamp of a restless path);
+      * for l = k-1 .. 2: G^l = G without u_{l+1}, .., u_k (and their in- and
+        out-edges) and without the edges later than tau^l = i_{l+1}; M^l =
+        M^{l+1} minus the colour of u_{l+1}. The query with l vertices on G^l
+        gives zeta_{v,l,i}; u_l is the least in-neighbour v of u_{l+1} through
+        an edge (v, u_{l+1}, i_{l+1}) that has a slot (v, i) with zeta != 0 in
+        its waiting window i_{l+1} - delta(v) <= i <= i_{l+1}, and i_l the
+        least such i;
+      * u_1 is the least in-neighbour v of u_2 through an edge (v, u_2, i_2)
+        that is not removed, is a source, and has the one colour left in M^1.
+    Each step's zeta is non-zero only where a path exists, so the pieces join
+    into a restless path; a step that finds no candidate met a zero of a
+    non-zero polynomial (probability about 2^-57 per slot) and raises."""
+    cs, cd, ct = canonical_edges(src, dst, t)
+    dv = np.full(max(n, 1), int(delta), dtype=np.int64) if np.isscalar(delta) else np.asarray(delta, dtype=np.int64)
+    zeta, reach, _ = fine_grained(n, cs, cd, ct, k, delta, seed, colour, n_colours, motif, threads=threads,
+                                  sources=sources, targets=targets)
+    ends = range(n) if targets is None else sorted(set(int(x) for x in targets))
+    cand = [(int(reach[u]), u) for u in ends if reach[u] != UNREACHED]
+    if not cand:
+        return None
+    i_next, u_next = min(cand)
+    verts, times = [u_next], []
+    removed = set()
+    M = None if motif is None else [int(x) for x in motif]
+    src_ok = None if sources is None else set(int(x) for x in sources)
+    for l in range(k - 1, 0, -1):
+        removed.add(u_next)
+        if M is not None:
+            M[int(colour[u_next])] -= 1
+        # in-edges (v, u_next, i_next) of the last vertex found, in order of v
+        into = [int(cs[e]) for e in range(len(cs)) if cd[e] == u_next and ct[e] == i_next]
+        into = [v for v in sorted(into) if v not in removed]
+        if l == 1:
+            ok = [v for v in into if (src_ok is None or v in src_ok) and (M is None or M[int(colour[v])] == 1)]
+            if not ok:
+                raise RuntimeError("extraction: no start vertex for the last edge")
+            verts.append(ok[0])
+            times.append(i_next)
+            break
+        keep = np.array([cs[e] not in removed and cd[e] not in removed and ct[e] <= i_next for e in range(len(cs))],
+                        dtype=bool)
+        rs, rd, rt = cs[keep], cd[keep], ct[keep]
+        zl, _, _ = fine_grained(n, rs, rd, rt, l, delta, seed, colour, n_colours, M, threads=threads, sources=sources)
+        slot = {(int(rd[e]), int(rt[e])): int(zl[e]) for e in range(len(rd))}
+        pick = None
+        for v in into:
+            lo = max(1, i_next - int(dv[v]))
+            for i in range(lo, i_next + 1):
+                if slot.get((v, i), 0):
+                    pick = (v, i)
+                    break
+            if pick:
+                break
+        if pick is None:
+            raise RuntimeError(f"extraction: no predecessor at level {l}")
+        times.append(i_next)
+        u_next, i_next = pick
+        verts.append(u_next)
+    return verts[::-1], times[::-1]
