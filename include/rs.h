@@ -63,6 +63,9 @@ typedef int32_t rs_status;
 #define RS_ECANCELED (-5)  /* server: query cancelled */
 #define RS_ENOTFOUND (-6)  /* server: unknown ticket or graph id */
 #define RS_ETIMEOUT (-7)   /* server: poll wait expired before completion */
+#define RS_ERETRY (-8)     /* extraction: a query missed a path that exists (a
+                              zero of a non-zero polynomial, probability about
+                              2^-57 per slot); run again with another seed */
 
 #define RS_MAX_K 16
 #define RS_MAX_COLOURS 256
@@ -198,6 +201,14 @@ typedef struct {
                                        count (the destination d). NULL / 0 =
                                        any last vertex. */
   uint32_t n_targets;
+  const uint32_t* removed;          /* host array of n_removed vertex ids that
+                                       no path may pass through (the deleted
+                                       vertices of the extraction queries of
+                                       Sec. 4.7). NULL / 0 = none. */
+  uint32_t n_removed;
+  uint32_t t_max;                   /* only edges with timestamp <= t_max
+                                       (the time-truncated graph of Sec. 4.7);
+                                       0 = every edge. */
 } rs_constraints;
 
 /* rs_run_ex (automatic launch shape) under constraints c (NULL = none): F is
@@ -232,6 +243,25 @@ rs_status rs_run_fine(const rs_graph* g, const rs_query* q, const rs_constraints
  * the XOR of the k' fingerprints; r->yes says some vertex is reached. */
 rs_status rs_reach_at_most(const rs_graph* g, const rs_query* q, const rs_constraints* c, uint32_t* reach_time,
                            uint32_t* reach_vertices, rs_result* r, void* hip_stream);
+
+/* Extraction of an optimal solution with k fine-grained queries (Sec. 4.7):
+ * a restless path with q->k vertices (colour-agreeing with q->motif_count
+ * when given; from a source and to a target under c) whose largest
+ * timestamp is least. Query j = k, k-1, .., 2 runs the fine-grained sieve
+ * with j vertices on the graph without the vertices found so far and
+ * without the edges later than the last timestamp found, with the motif
+ * less their colours; the next vertex is the least in-neighbour v (through
+ * an edge at that timestamp) with a non-zero slot (v, i) in its waiting
+ * window [t - delta(v), t], and i the least such time; the first vertex is
+ * the least such in-neighbour that is a source of the remaining colour.
+ * On YES (r->yes = 1): path_vertices (host, k entries) receives u_1..u_k and
+ * path_times (host, k-1 entries) the timestamps of the edges u_j -> u_{j+1}.
+ * On NO (r->yes = 0) neither array is written. r->fingerprint is the first
+ * (k-vertex) query's, device_ms the sum over the queries. c->removed and
+ * c->t_max must be unset (RS_EINVAL), as must an iteration range. RS_ERETRY
+ * if a later query misses the path the earlier ones proved. */
+rs_status rs_extract(const rs_graph* g, const rs_query* q, const rs_constraints* c, uint32_t* path_vertices,
+                     uint32_t* path_times, rs_result* r, void* hip_stream);
 
 /* For callers that cannot allocate device memory (code under stream capture,
  * tight serving loops, harnesses that forbid hipMalloc): rs_run_ex without

@@ -22,6 +22,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librestless_sieve.so")
 
 RS_OK, RS_EINVAL, RS_ENOMEM, RS_EDEVICE, RS_EBUSY, RS_ECANCELED, RS_ENOTFOUND, RS_ETIMEOUT = 0, -1, -2, -3, -4, -5, -6, -7
+RS_ERETRY = -8
 RS_MAX_K = 16
 
 _u8p = ctypes.POINTER(ctypes.c_uint8)
@@ -60,7 +61,8 @@ class _Tuning(ctypes.Structure):
 
 class _Constraints(ctypes.Structure):
     _fields_ = [("delta_per_vertex", _u32p), ("sources", _u32p), ("n_sources", ctypes.c_uint32),
-                ("targets", _u32p), ("n_targets", ctypes.c_uint32)]
+                ("targets", _u32p), ("n_targets", ctypes.c_uint32), ("removed", _u32p),
+                ("n_removed", ctypes.c_uint32), ("t_max", ctypes.c_uint32)]
 
 
 class _GraphInfo(ctypes.Structure):
@@ -107,6 +109,8 @@ _SIGNATURES = {
                                      _u64p, ctypes.POINTER(_Result), ctypes.c_void_p]),
     "rs_reach_at_most": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(_Query), ctypes.POINTER(_Constraints), _u32p,
                                           _u32p, ctypes.POINTER(_Result), ctypes.c_void_p]),
+    "rs_extract": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(_Query), ctypes.POINTER(_Constraints), _u32p,
+                                    _u32p, ctypes.POINTER(_Result), ctypes.c_void_p]),
     "rs_run_noalloc": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(_Query), _u64p, ctypes.POINTER(_Result),
                                         ctypes.c_void_p]),
     "rs_run_batch": (ctypes.c_int32, [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(_Query), ctypes.c_uint32,
@@ -300,21 +304,25 @@ def footprint(graph: Graph, k, delta, seed=0, motif=None, it_begin=0, it_end=0) 
     return b.value
 
 
-def _constraints(delta, sources, targets):
-    """rs_constraints for a per-vertex delta array and source / target vertex
-    lists (None when there is nothing to constrain), and the arrays it points to."""
+def _constraints(delta, sources, targets, removed=None, t_max=0):
+    """rs_constraints for a per-vertex delta array, source / target / removed
+    vertex lists and a last timestamp (None when there is nothing to
+    constrain), and the arrays it points to."""
     per_vertex = not np.isscalar(delta)
-    if not per_vertex and sources is None and targets is None:
+    if not per_vertex and sources is None and targets is None and removed is None and not t_max:
         return None, None
     dv = np.ascontiguousarray(delta, dtype=np.uint32) if per_vertex else None
-    sv = None if sources is None else np.ascontiguousarray(np.asarray(sources).reshape(-1), dtype=np.uint32)
-    tv = None if targets is None else np.ascontiguousarray(np.asarray(targets).reshape(-1), dtype=np.uint32)
-    c = _Constraints(dv.ctypes.data_as(_u32p) if dv is not None else None,
-                     sv.ctypes.data_as(_u32p) if sv is not None and len(sv) else None,
-                     0 if sv is None else len(sv),
-                     tv.ctypes.data_as(_u32p) if tv is not None and len(tv) else None,
-                     0 if tv is None else len(tv))
-    return c, (dv, sv, tv)
+
+    def ids(x):
+        return None if x is None else np.ascontiguousarray(np.asarray(x).reshape(-1), dtype=np.uint32)
+
+    def ptr(a):
+        return a.ctypes.data_as(_u32p) if a is not None and len(a) else None
+
+    sv, tv, rv = ids(sources), ids(targets), ids(removed)
+    c = _Constraints(dv.ctypes.data_as(_u32p) if dv is not None else None, ptr(sv), 0 if sv is None else len(sv),
+                     ptr(tv), 0 if tv is None else len(tv), ptr(rv), 0 if rv is None else len(rv), int(t_max))
+    return c, (dv, sv, tv, rv)
 
 
 def run(graph: Graph, k, delta, seed, motif=None, it_begin=0, it_end=0, tuning: Tuning | None = None,
@@ -362,10 +370,12 @@ UNREACHED = 0xFFFFFFFF
 
 
 def run_fine(graph: Graph, k, delta, seed, motif=None, it_begin=0, it_end=0, sources=None, targets=None,
-             slots=True, stream=None) -> FineResult:
-    """rs_run_fine: per-slot zeta_{u,k,i} (Alg. 1), reach times and F."""
+             slots=True, stream=None, removed=None, t_max=0) -> FineResult:
+    """rs_run_fine: per-slot zeta_{u,k,i} (Alg. 1), reach times and F.
+    removed / t_max: vertices no path passes through and the last timestamp
+    of the edges used (0 = all)."""
     info = graph.info()
-    c, ckeep = _constraints(delta, sources, targets)
+    c, ckeep = _constraints(delta, sources, targets, removed, t_max)
     q, keep = _make_query(k, 0 if not np.isscalar(delta) else delta, seed, motif, it_begin, it_end)
     reach = np.zeros(max(graph.n, 1), dtype=np.uint32)
     zeta = np.zeros(max(info["m"], 1), dtype=np.uint64) if slots else None
@@ -377,6 +387,27 @@ def run_fine(graph: Graph, k, delta, seed, motif=None, it_begin=0, it_end=0, sou
     _check(s, "rs_run_fine")
     return FineResult(r.fingerprint, bool(r.yes), r.device_ms, reach[:graph.n],
                       zeta[:info["m"]] if zeta is not None else None)
+
+
+def extract(graph: Graph, k, delta, seed, motif=None, sources=None, targets=None, stream=None):
+    """rs_extract: an optimal restless path with k vertices from k
+    fine-grained queries (Sec. 4.7). Returns (vertices, times, Result) with
+    vertices u_1..u_k and times[j] the timestamp of edge u_{j+1} -> u_{j+2},
+    or (None, None, Result) when there is no path."""
+    c, ckeep = _constraints(delta, sources, targets)
+    q, keep = _make_query(k, 0 if not np.isscalar(delta) else delta, seed, motif)
+    verts = np.zeros(max(k, 1), dtype=np.uint32)
+    times = np.zeros(max(k - 1, 1), dtype=np.uint32)
+    r = _Result()
+    s = _load().rs_extract(graph.handle, ctypes.byref(q), ctypes.byref(c) if c is not None else None,
+                           verts.ctypes.data_as(_u32p), times.ctypes.data_as(_u32p), ctypes.byref(r),
+                           _stream_handle(stream))
+    del keep, ckeep
+    _check(s, "rs_extract")
+    res = Result(r.fingerprint, bool(r.yes), r.status, r.device_ms)
+    if not r.yes:
+        return None, None, res
+    return [int(v) for v in verts[:k]], [int(x) for x in times[:k - 1]], res
 
 
 def reach_at_most(graph: Graph, k, delta, seed, sources=None, targets=None, stream=None):

@@ -919,7 +919,7 @@ static rs_status batch_enqueue(BatchPlan& P, BatchWorkspace& W, hipStream_t st) 
       RS_HIP(launch_compact(ca, st));
       RS_HIP(launch_compact_costs(ca, E, (Q.m + E - 1) / E, Q.pre, Q.bsum, Q.boff, st));
       const uint64_t* seed_p = (const uint64_t*)((const char*)(dq + qi) + offsetof(BQuery, seed));
-      RS_HIP(launch_compact_rows(ca, Q.z, 0, seed_p, nullptr, nullptr, Q.kq, st));
+      RS_HIP(launch_compact_rows(ca, Q.z, 0, seed_p, EdgeFilter(), Q.kq, st));
     } else {
       switch (Q.kq) {
         case 4: hipLaunchKernelGGL(kb_qtable<4>, dim3((Q.m + 255) / 256), dim3(256), 0, st, dq, qi); break;

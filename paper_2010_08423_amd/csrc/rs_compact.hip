@@ -187,15 +187,12 @@ __global__ __launch_bounds__(256) void k_compact_bounds(const uint32_t* __restri
 }
 
 // Product rows of the kept edges that form a product (bit 2; every entry of
-// the last level): cq[j][i] = z_{dst,i} * y_{e,l-1}. A row of an edge that a
-// source or target constraint excludes (level 2: its source is not a source
-// vertex; last level: its destination is not a target vertex) is 0, so the
-// edge contributes nothing. Grid-stride over the entries of every level.
+// the last level): cq[j][i] = z_{dst,i} * y_{e,l-1}. A row of an edge that the
+// query's constraints exclude is 0, so the edge contributes nothing.
+// Grid-stride over the entries of every level.
 template <int KQ>
 __global__ __launch_bounds__(256) void k_compact_rows(CompactArgs a, const uint64_t* __restrict__ z, uint64_t seed_v,
-                                                      const uint64_t* __restrict__ seed_p,
-                                                      const uint8_t* __restrict__ smask,
-                                                      const uint8_t* __restrict__ tmask) {
+                                                      const uint64_t* __restrict__ seed_p, EdgeFilter f) {
   const uint64_t seed = seed_p ? *seed_p : seed_v;  // from a batch descriptor, read at run time
   __shared__ uint64_t lds[4][16][kLanes];
   const uint32_t lane = threadIdx.x & 63u;
@@ -210,8 +207,7 @@ __global__ __launch_bounds__(256) void k_compact_rows(CompactArgs a, const uint6
     const uint32_t e = L.ce[j];
     const uint32_t src = a.e_src[e], dst = a.e_dst[e], t = a.e_t[e];
     uint64_t* out = L.cq + (uint64_t)j * KQ;
-    const bool off = (l == 2 && smask && !smask[src]) || (l == a.k && tmask && !tmask[dst]);
-    if (off) {
+    if (edge_excluded(f, l, a.k, src, dst, t)) {
 #pragma unroll
       for (int i = 0; i < KQ; ++i) out[i] = 0;
       continue;
@@ -279,14 +275,14 @@ hipError_t launch_compact_bounds(const CompactArgs& a, uint32_t E, uint32_t tile
 }
 
 hipError_t launch_compact_rows(const CompactArgs& a, const uint64_t* z, uint64_t seed, const uint64_t* seed_p,
-                               const uint8_t* smask, const uint8_t* tmask, uint32_t kq, hipStream_t st) {
+                               const EdgeFilter& f, uint32_t kq, hipStream_t st) {
   if (!a.m || a.k < 3) return hipSuccess;
   const dim3 g(std::min<uint32_t>(cdiv(a.m, 256), 2048), a.k - 1), b(256);
   switch (kq) {
-    case 4: hipLaunchKernelGGL(k_compact_rows<4>, g, b, 0, st, a, z, seed, seed_p, smask, tmask); break;
-    case 8: hipLaunchKernelGGL(k_compact_rows<8>, g, b, 0, st, a, z, seed, seed_p, smask, tmask); break;
-    case 12: hipLaunchKernelGGL(k_compact_rows<12>, g, b, 0, st, a, z, seed, seed_p, smask, tmask); break;
-    case 16: hipLaunchKernelGGL(k_compact_rows<16>, g, b, 0, st, a, z, seed, seed_p, smask, tmask); break;
+    case 4: hipLaunchKernelGGL(k_compact_rows<4>, g, b, 0, st, a, z, seed, seed_p, f); break;
+    case 8: hipLaunchKernelGGL(k_compact_rows<8>, g, b, 0, st, a, z, seed, seed_p, f); break;
+    case 12: hipLaunchKernelGGL(k_compact_rows<12>, g, b, 0, st, a, z, seed, seed_p, f); break;
+    case 16: hipLaunchKernelGGL(k_compact_rows<16>, g, b, 0, st, a, z, seed, seed_p, f); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

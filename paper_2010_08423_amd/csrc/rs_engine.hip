@@ -248,6 +248,7 @@ PlainSizes plain_sizes(uint64_t m, uint64_t n, const QueryPlan& qp, const Tuning
   s.dv = ex && ex->delta_v ? 4 * n : 0;
   s.smask = ex && ex->smask ? n : 0;
   s.tmask = ex && ex->tmask ? n : 0;
+  s.rmask = ex && ex->rmask ? n : 0;
   const bool fine = ex && ex->fine;
   s.fine_t = fine ? 8 * m : 0;
   s.fine_z = fine ? 8 * m : 0;
@@ -257,7 +258,7 @@ PlainSizes plain_sizes(uint64_t m, uint64_t n, const QueryPlan& qp, const Tuning
 
 uint64_t PlainSizes::total() const {
   return lo + z + q + 2 * p + partial + fsum + 64 + ref + need + cover + 2 * records + run_pre + run_bsum + run_boff +
-         run_bounds + lists + dv + smask + tmask + fine_t + fine_z + fine_r;
+         run_bounds + lists + dv + smask + tmask + rmask + fine_t + fine_z + fine_r;
 }
 
 uint64_t plain_footprint(const rs_graph* g, const QueryPlan& qp, const Tuning& tu) {
@@ -299,6 +300,7 @@ static rs_status acquire_buffers(PlainWorkspace& ws, const PlainSizes& sz, uint6
     carve(ws.dv, sz.dv);
     carve(ws.smask, sz.smask);
     carve(ws.tmask, sz.tmask);
+    carve(ws.rmask, sz.rmask);
     carve(ws.fine_t, sz.fine_t);
     carve(ws.fine_z, sz.fine_z);
     carve(ws.fine_r, sz.fine_r);
@@ -329,6 +331,7 @@ static rs_status acquire_buffers(PlainWorkspace& ws, const PlainSizes& sz, uint6
       ws.run_boff.reserve(sz.run_boff, st, false) || ws.run_bounds.reserve(sz.run_bounds, st, false) ||
       (sz.lists && ws.lists.reserve(sz.lists, st, false)) || (sz.dv && ws.dv.reserve(sz.dv, st, false)) ||
       (sz.smask && ws.smask.reserve(sz.smask, st, false)) || (sz.tmask && ws.tmask.reserve(sz.tmask, st, false)) ||
+      (sz.rmask && ws.rmask.reserve(sz.rmask, st, false)) ||
       (sz.fine_t && ws.fine_t.reserve(sz.fine_t, st, false)) || (sz.fine_z && ws.fine_z.reserve(sz.fine_z, st, false)) ||
       (sz.fine_r && ws.fine_r.reserve(sz.fine_r, st, false)))
     return RS_ENOMEM;
@@ -366,18 +369,23 @@ rs_status run_plain(rs_graph* g, PlainWorkspace& ws, const QueryPlan& qp, const 
     RS_TRY(acquire_buffers(ws, sz, p_elems, st));
     // constraints (host arrays, copied in) and fine-grained output buffers
     const uint32_t* dv = nullptr;
-    const uint8_t *smask = nullptr, *tmask = nullptr;
+    EdgeFilter filt;
+    if (ex) filt.t_max = ex->t_max;
     if (sz.dv) {
       RS_HIP(hipMemcpyAsync(ws.dv.p, ex->delta_v, 4 * n, hipMemcpyHostToDevice, st));
       dv = ws.dv.as<uint32_t>();
     }
     if (sz.smask) {
       RS_HIP(hipMemcpyAsync(ws.smask.p, ex->smask, n, hipMemcpyHostToDevice, st));
-      smask = ws.smask.as<uint8_t>();
+      filt.smask = ws.smask.as<uint8_t>();
     }
     if (sz.tmask) {
       RS_HIP(hipMemcpyAsync(ws.tmask.p, ex->tmask, n, hipMemcpyHostToDevice, st));
-      tmask = ws.tmask.as<uint8_t>();
+      filt.tmask = ws.tmask.as<uint8_t>();
+    }
+    if (sz.rmask) {
+      RS_HIP(hipMemcpyAsync(ws.rmask.p, ex->rmask, n, hipMemcpyHostToDevice, st));
+      filt.rmask = ws.rmask.as<uint8_t>();
     }
     if (fine) {
       RS_HIP(launch_fill64(ws.fine_t.as<uint64_t>(), 0, m, st));
@@ -500,12 +508,13 @@ rs_status run_plain(rs_graph* g, PlainWorkspace& ws, const QueryPlan& qp, const 
       // of every edge, with the source and target constraints applied
       ProfScope ps(KC_QTABLE, st, (double)m * (12.0 + 8.0 * kq * (k - 1)), timed);
       if (k >= 3) {
-        RS_HIP(launch_compact_rows(ca, ws.z.as<uint64_t>(), qp.seed, nullptr, smask, tmask, kq, st));
+        RS_HIP(launch_compact_rows(ca, ws.z.as<uint64_t>(), qp.seed, nullptr, filt, kq, st));
       } else {
         RS_HIP(launch_qtable(G.e_src.as<uint32_t>(), G.e_dst.as<uint32_t>(), G.e_t.as<uint32_t>(),
                              ws.z.as<uint64_t>(), ws.q.as<uint64_t>(), (uint32_t)m, qp, st));
-        if (smask) RS_HIP(launch_mask_rows(ws.q.as<uint64_t>(), G.e_src.as<uint32_t>(), smask, (uint32_t)m, kq, st));
-        if (tmask) RS_HIP(launch_mask_rows(ws.q.as<uint64_t>(), G.e_dst.as<uint32_t>(), tmask, (uint32_t)m, kq, st));
+        if (filt.any())
+          RS_HIP(launch_mask_rows(ws.q.as<uint64_t>(), G.e_src.as<uint32_t>(), G.e_dst.as<uint32_t>(),
+                                  G.e_t.as<uint32_t>(), filt, (uint32_t)m, kq, st));
       }
     }
     if (tr) {
@@ -807,15 +816,25 @@ rs_status rs_run(const rs_graph* g, const rs_query* q, rs_result* r, void* hip_s
 
 // Host masks and per-vertex resting times of a constraint set (validated).
 struct HostConstraints {
-  std::vector<uint8_t> smask, tmask;
+  std::vector<uint8_t> smask, tmask, rmask;
   QueryExtras ex;
 };
 static rs_status make_constraints(const rs_graph* g, const rs_constraints* c, HostConstraints& h) {
   h.ex = QueryExtras();
   if (!c) return RS_OK;
   const uint32_t n = g->g.n;
-  if ((c->n_sources && !c->sources) || (c->n_targets && !c->targets)) return RS_EINVAL;
+  if ((c->n_sources && !c->sources) || (c->n_targets && !c->targets) || (c->n_removed && !c->removed))
+    return RS_EINVAL;
   h.ex.delta_v = c->delta_per_vertex;
+  h.ex.t_max = c->t_max;
+  if (c->n_removed) {
+    h.rmask.assign(std::max<uint32_t>(n, 1), 0);
+    for (uint32_t i = 0; i < c->n_removed; ++i) {
+      if (c->removed[i] >= n) return RS_EINVAL;
+      h.rmask[c->removed[i]] = 1;
+    }
+    h.ex.rmask = h.rmask.data();
+  }
   if (c->n_sources) {
     h.smask.assign(std::max<uint32_t>(n, 1), 0);
     for (uint32_t i = 0; i < c->n_sources; ++i) {

@@ -89,17 +89,17 @@ __global__ __launch_bounds__(256) void k_fine_slots(const uint32_t* __restrict__
   if (acc) atomicMin(&reach[u], t);
 }
 
-// Product rows of one level with the source / target constraints applied:
-// rows of edges whose source is not a source vertex (level 2) or whose
-// destination is not a target vertex (level k) are cleared, so those edges
-// contribute nothing (Sec. 3: paths from a source, paths to a destination).
-// rows: [m][kq] of one level.
-__global__ __launch_bounds__(256) void k_mask_rows(uint64_t* __restrict__ rows, const uint32_t* __restrict__ e_vertex,
-                                                   const uint8_t* __restrict__ mask, uint32_t m, uint32_t kq) {
+// Product rows [m][kq] of the one level of a k = 2 query with the query's
+// constraints applied: the rows of the edges they exclude are cleared, so
+// those edges contribute nothing (Sec. 3: paths from a source, paths to a
+// destination; Sec. 4.7: removed vertices, a last time).
+__global__ __launch_bounds__(256) void k_mask_rows(uint64_t* __restrict__ rows, const uint32_t* __restrict__ e_src,
+                                                   const uint32_t* __restrict__ e_dst, const uint32_t* __restrict__ e_t,
+                                                   EdgeFilter f, uint32_t m, uint32_t kq) {
   const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= (uint64_t)m * kq) return;
   const uint64_t e = i / kq;
-  if (!mask[e_vertex[e]]) rows[i] = 0;
+  if (edge_excluded(f, 2, 2, e_src[e], e_dst[e], e_t[e])) rows[i] = 0;
 }
 
 static inline uint32_t div_up32(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
@@ -140,11 +140,11 @@ hipError_t launch_fine_slots(const uint32_t* e_dst, const uint32_t* e_t, const u
   return hipGetLastError();
 }
 
-hipError_t launch_mask_rows(uint64_t* rows, const uint32_t* e_vertex, const uint8_t* mask, uint32_t m, uint32_t kq,
-                            hipStream_t st) {
+hipError_t launch_mask_rows(uint64_t* rows, const uint32_t* e_src, const uint32_t* e_dst, const uint32_t* e_t,
+                            const EdgeFilter& f, uint32_t m, uint32_t kq, hipStream_t st) {
   const uint64_t count = (uint64_t)m * kq;
   if (!count) return hipSuccess;
-  hipLaunchKernelGGL(k_mask_rows, dim3(div_up32(count, 256)), dim3(256), 0, st, rows, e_vertex, mask, m, kq);
+  hipLaunchKernelGGL(k_mask_rows, dim3(div_up32(count, 256)), dim3(256), 0, st, rows, e_src, e_dst, e_t, f, m, kq);
   return hipGetLastError();
 }
 

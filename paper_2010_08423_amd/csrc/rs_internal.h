@@ -223,18 +223,36 @@ hipError_t launch_compact_costs(const CompactArgs& a, uint32_t E, uint32_t tiles
 hipError_t launch_compact_bounds(const CompactArgs& a, uint32_t E, uint32_t tiles_max, uint32_t w_first,
                                  uint32_t w_rest, uint32_t* pre, uint32_t* bsum, uint32_t* boff, uint32_t* bounds,
                                  uint32_t b_stride, hipStream_t st);
+// Edges a query's constraints exclude (Sec. 3 and Sec. 4.7): at level 2 an
+// edge whose source is not a source vertex, at the last level one whose
+// destination is not a target vertex, at every level one that touches a
+// removed vertex or is later than t_max (0 = no limit). Their product rows
+// are 0, so they contribute nothing. Null masks exclude nothing.
+struct EdgeFilter {
+  const uint8_t* smask = nullptr;  // [n] source vertices
+  const uint8_t* tmask = nullptr;  // [n] target vertices
+  const uint8_t* rmask = nullptr;  // [n] removed vertices
+  uint32_t t_max = 0;
+  bool any() const { return smask || tmask || rmask || t_max; }
+};
+__device__ __forceinline__ bool edge_excluded(const EdgeFilter& f, uint32_t l, uint32_t k, uint32_t src, uint32_t dst,
+                                              uint32_t t) {
+  return (l == 2 && f.smask && !f.smask[src]) || (l == k && f.tmask && !f.tmask[dst]) ||
+         (f.rmask && (f.rmask[src] | f.rmask[dst])) || (f.t_max && t > f.t_max);
+}
 // Product rows of the lists (seed dependent: seed, or *seed_p read on the
-// device when seed_p is not null). smask / tmask: device [n] masks of the
-// source and target vertices, or null.
+// device when seed_p is not null), 0 for the edges f excludes.
 hipError_t launch_compact_rows(const CompactArgs& a, const uint64_t* z, uint64_t seed, const uint64_t* seed_p,
-                               const uint8_t* smask, const uint8_t* tmask, uint32_t kq, hipStream_t st);
+                               const EdgeFilter& f, uint32_t kq, hipStream_t st);
 // Fine-grained last level and slot sums (rs_fine.hip).
 hipError_t launch_top_fine(const TopArgs& a, bool first_level, uint32_t kq, uint32_t chunks, const Tuning& tu,
                            uint64_t* T, hipStream_t st);
 hipError_t launch_fine_slots(const uint32_t* e_dst, const uint32_t* e_t, const uint64_t* T, uint32_t m, uint64_t* zeta,
                              uint32_t* reach, hipStream_t st);
-hipError_t launch_mask_rows(uint64_t* rows, const uint32_t* e_vertex, const uint8_t* mask, uint32_t m, uint32_t kq,
-                            hipStream_t st);
+// Clears the rows [m][kq] of the one level of a k = 2 query (level 2 is
+// also the last) of the edges f excludes.
+hipError_t launch_mask_rows(uint64_t* rows, const uint32_t* e_src, const uint32_t* e_dst, const uint32_t* e_t,
+                            const EdgeFilter& f, uint32_t m, uint32_t kq, hipStream_t st);
 // Edge counts of a query's windows and flags (graph and delta only), used to
 // state the algorithmic bytes of the level launches.
 struct NeedCounts {
@@ -292,6 +310,8 @@ struct QueryExtras {
   const uint32_t* delta_v = nullptr;  // [n] resting time per vertex (Sec. 2), replaces the scalar delta
   const uint8_t* smask = nullptr;     // [n] source vertices: walks start only there (Sec. 3)
   const uint8_t* tmask = nullptr;     // [n] target vertices: walks end only there (Sec. 3)
+  const uint8_t* rmask = nullptr;     // [n] removed vertices: no walk passes through them (Sec. 4.7)
+  uint32_t t_max = 0;                 // edges later than this are left out (Sec. 4.7); 0 = none
   bool fine = false;                  // keep zeta per slot (Alg. 1, Sec. 4.5)
   uint32_t* reach = nullptr;          // [n] fine: least reach time, 0xFFFFFFFF if none
   uint64_t* zeta = nullptr;           // [m] fine, may be null: zeta of each canonical edge's slot
@@ -353,7 +373,7 @@ struct PlainWorkspace {
   DevBuf run_pre, run_bsum, run_boff, run_bounds;  // work-balanced runs of the prefix levels
   DevBuf cov_diff;  // window-cover scratch of the flags: difference array and block sums
   DevBuf lists;     // compacted edge lists of levels 2..k and their scratch (k >= 3)
-  DevBuf dv, smask, tmask;         // constraints: per-vertex resting times, source and target masks
+  DevBuf dv, smask, tmask, rmask;  // constraints: per-vertex resting times, source, target and removed masks
   DevBuf fine_t, fine_z, fine_r;   // fine-grained outputs: per-edge sums, per-slot zeta, reach times
   uint32_t epoch = 0;
   uint64_t p_elems_per_chunk = 0;
@@ -363,7 +383,7 @@ struct PlainWorkspace {
   uint64_t bytes() const {
     uint64_t t = 0;
     for (const DevBuf* b : {&lo, &z, &q, &p0, &p1, &partial, &agg, &incl, &fsum, &out, &ref, &need, &lb_stats,
-                            &run_pre, &run_bsum, &run_boff, &run_bounds, &cov_diff, &lists, &dv, &smask, &tmask,
+                            &run_pre, &run_bsum, &run_boff, &run_bounds, &cov_diff, &lists, &dv, &smask, &tmask, &rmask,
                             &fine_t, &fine_z, &fine_r})
       t += b->bytes;
     return t;
@@ -371,7 +391,7 @@ struct PlainWorkspace {
   void release() {
     if (scratch) return;  // borrowed buffers are never freed
     for (DevBuf* b : {&lo, &z, &q, &p0, &p1, &partial, &agg, &incl, &fsum, &out, &ref, &need, &lb_stats,
-                      &run_pre, &run_bsum, &run_boff, &run_bounds, &cov_diff, &lists, &dv, &smask, &tmask, &fine_t,
+                      &run_pre, &run_bsum, &run_boff, &run_bounds, &cov_diff, &lists, &dv, &smask, &tmask, &rmask, &fine_t,
                       &fine_z, &fine_r})
       b->release();
     if (ev0) (void)hipEventDestroy(ev0);
@@ -388,7 +408,7 @@ struct PlainSizes {
   uint64_t lo, z, q, p, partial, fsum, ref, need, cover, records;
   uint64_t run_pre, run_bsum, run_boff, run_bounds;
   uint64_t lists;                  // compacted lists (k >= 3; the q table is used only at k = 2)
-  uint64_t dv, smask, tmask;       // constraints (0 when absent)
+  uint64_t dv, smask, tmask, rmask;  // constraints (0 when absent)
   uint64_t fine_t, fine_z, fine_r; // fine-grained outputs (0 when not asked)
   uint32_t run_w2, run_w3, run_stride;  // waves per chunk of level 2 and of levels >= 3; bounds stride
   uint64_t total() const;
