@@ -68,6 +68,8 @@ def _load():
     lib.orc_fine_grained.restype = ctypes.c_int
     lib.orc_fine_grained.argtypes = graph_args + [_u8p, _u8p, u64, u64, u64, ctypes.c_int, _u64p, _u64p, _u32p,
                                                   _u64p]
+    lib.orc_fine_literal.restype = ctypes.c_int
+    lib.orc_fine_literal.argtypes = graph_args + [u64, u64, u64, ctypes.c_int, _u64p, _u64p, _u32p]
     lib.orc_closed_form_ex.restype = ctypes.c_int
     lib.orc_closed_form_ex.argtypes = graph_args + [_u8p, _u8p, u64, _u64p, _u64p, _u64p, _u64p, _u64p]
     lib.orc_count_paths.restype = ctypes.c_int
@@ -201,6 +203,24 @@ def fine_grained(n, src, dst, t, k, delta, seed, colour=None, n_colours=0, motif
     if rc:
         raise ValueError(f"orc_fine_grained rejected the query (rc={rc})")
     return zeta[:mc.value], reach[:n], F.value
+
+
+def fine_literal(n, src, dst, t, k, delta, seed, colour=None, n_colours=0, motif=None, it_begin=0, it_end=0,
+                 threads=1):
+    """Fine-grained outputs under the literal reading of Eq. (poly-enc:1)
+    (y indexed by the predecessor's arrival time): (zeta, reach) as in
+    fine_grained, per canonical edge's slot; no aggregate (it cancels)."""
+    args, keep = _graph_args(n, src, dst, t, colour, n_colours, k, delta, motif)
+    m = len(keep[0])
+    zeta = np.zeros(max(m, 1), dtype=np.uint64)
+    reach = np.zeros(max(n, 1), dtype=np.uint32)
+    mc = ctypes.c_uint64(0)
+    rc = _load().orc_fine_literal(*args, seed, it_begin, it_end, threads, _ptr(zeta, _u64p), ctypes.byref(mc),
+                                  _ptr(reach, _u32p))
+    del keep
+    if rc:
+        raise ValueError(f"orc_fine_literal rejected the query (rc={rc})")
+    return zeta[:mc.value], reach[:n]
 
 
 def closed_form_slots(n, src, dst, t, k, delta, seed, colour=None, n_colours=0, motif=None, sources=None,

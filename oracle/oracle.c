@@ -510,6 +510,149 @@ int orc_fine_grained(uint32_t n, uint64_t m, const uint32_t* src, const uint32_t
 }
 
 /* ---------------------------------------------------------------------------
+ * Literal reading of Eq. (poly-enc:1): the y variable of a window term is
+ * indexed by the edge's end points, the level and the predecessor's arrival
+ * time i - j (y_{uv, l-1, i-j}), not by the edge's own time, and level 1 is
+ * x_u at every time i in [tau], so a path also takes a term for each time it
+ * may have waited at its first vertex. Each window term has its own y, so an
+ * edge-update costs delta(v) + 1 products (the evaluation-cost lemma of
+ * Sec. 4.3). Two paths that differ only in the time of their last edge share
+ * every variable, so their terms cancel in a sum over end times; each slot
+ * (u, i) is therefore tested on its own (Alg. 1's per-slot test).
+ * ------------------------------------------------------------------------ */
+
+/* y_{uv, l, p}: the literal variable of the edge from v (src) to u (dst) at
+ * level l for a predecessor that arrived at v at time p. */
+static uint64_t orc_y_literal(uint64_t seed, uint32_t src, uint32_t dst, uint32_t p, uint32_t l) {
+  uint64_t w[2];
+  w[0] = (uint64_t)src | ((uint64_t)dst << 32);
+  w[1] = (uint64_t)p | ((uint64_t)l << 32);
+  return orc_hash(seed, 'P', w, 2);
+}
+
+/* chi_{v,l,p} of a level >= 2: the value of slot (v, p), or 0 when v has no
+ * arrival at time p. */
+static uint64_t orc_chi_at(const orc_graph* g, const uint64_t* chi, uint32_t v, uint32_t p) {
+  uint64_t lo = g->v_off[v], hi = g->v_off[v + 1];
+  while (lo < hi) {
+    uint64_t mid = (lo + hi) / 2;
+    if (g->slot_t[mid] < p)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return (lo < g->v_off[v + 1] && g->slot_t[lo] == p) ? chi[lo] : 0;
+}
+
+/* chi_{u,k,i} for every slot (u, i), for one subset L, by the literal
+ * recurrence: for each in-edge from v at time i and each j = 0..delta(v) with
+ * i - j > 0, the term y_{uv,l-1,i-j} chi_{v,l-1,i-j}; level 1 is z^L_v at
+ * every time. Returns the array that holds level k. */
+static uint64_t* orc_literal_levels_L(const orc_graph* g, const uint64_t* z, uint32_t k, const uint32_t* delta,
+                                      uint64_t seed, uint64_t L, uint64_t* zL, uint64_t* chi_a, uint64_t* chi_b) {
+  uint64_t* chi_prev = chi_a;
+  uint64_t* chi_cur = chi_b;
+  for (uint32_t u = 0; u < g->n; u++) {
+    uint64_t s = 0;
+    for (uint32_t j = 1; j <= k; j++)
+      if ((L >> (j - 1)) & 1) s ^= z[(uint64_t)u * k + (j - 1)];
+    zL[u] = s;
+  }
+  for (uint32_t l = 2; l <= k; l++) {
+    for (uint32_t u = 0; u < g->n; u++) {
+      for (uint64_t sl = g->v_off[u]; sl < g->v_off[u + 1]; sl++) {
+        const uint32_t i = g->slot_t[sl];
+        uint64_t acc = 0;
+        for (uint64_t ei = g->slot_e[sl]; ei < g->slot_e[sl + 1]; ei++) {
+          const uint32_t v = g->e[ei].src;
+          for (uint32_t j = 0; j <= delta[v] && j < i; j++) {
+            const uint64_t prev = l == 2 ? zL[v] : orc_chi_at(g, chi_prev, v, i - j);
+            acc ^= orc_gf_mul_nibble(orc_y_literal(seed, v, u, i - j, l - 1), prev);
+          }
+        }
+        chi_cur[sl] = orc_gf_mul_nibble(zL[u], acc);
+      }
+    }
+    uint64_t* tmp = chi_prev;
+    chi_prev = chi_cur;
+    chi_cur = tmp;
+  }
+  return chi_prev;
+}
+
+int orc_fine_literal(uint32_t n, uint64_t m, const uint32_t* src, const uint32_t* dst, const uint32_t* t,
+                     const uint8_t* colour, uint32_t n_colours, uint32_t k, const uint32_t* delta,
+                     const uint8_t* motif_count, uint64_t seed, uint64_t it_begin, uint64_t it_end, int threads,
+                     uint64_t* zeta_edge, uint64_t* m_canon_out, uint32_t* reach_out) {
+  if (!reach_out) return -1;
+  int rc = orc_check_query(n, colour, n_colours, k, delta, motif_count);
+  if (rc) return rc;
+  uint64_t total = 1ull << k;
+  if (it_begin == 0 && it_end == 0) it_end = total;
+  if (it_begin > it_end || it_end > total) return -1;
+  orc_graph g;
+  rc = orc_graph_build(n, m, src, dst, t, &g);
+  if (rc) return rc;
+  uint64_t* z = (uint64_t*)malloc(sizeof(uint64_t) * ((uint64_t)n * k + 1));
+  uint64_t* zeta = (uint64_t*)calloc(g.n_slots + 1, sizeof(uint64_t));
+  if (!z || !zeta) {
+    free(z);
+    free(zeta);
+    orc_graph_free(&g);
+    return -2;
+  }
+  rc = orc_z_table(n, colour, n_colours, k, motif_count, seed, z);
+  int nthr = threads > 1 ? threads : 1;
+  int failed = 0;
+  if (!rc) {
+#ifdef _OPENMP
+#pragma omp parallel num_threads(nthr) reduction(| : failed)
+#endif
+    {
+      uint64_t* zL = (uint64_t*)malloc(sizeof(uint64_t) * ((uint64_t)n + 1));
+      uint64_t* c0 = (uint64_t*)malloc(sizeof(uint64_t) * (g.n_slots + 1));
+      uint64_t* c1 = (uint64_t*)malloc(sizeof(uint64_t) * (g.n_slots + 1));
+      uint64_t* mine = (uint64_t*)calloc(g.n_slots + 1, sizeof(uint64_t));
+      if (!zL || !c0 || !c1 || !mine) {
+        failed = 1;
+      } else {
+#ifdef _OPENMP
+#pragma omp for schedule(dynamic, 1)
+#endif
+        for (int64_t it = (int64_t)it_begin; it < (int64_t)it_end; it++) {
+          const uint64_t* chi = orc_literal_levels_L(&g, z, k, delta, seed, (uint64_t)it, zL, c0, c1);
+          for (uint64_t sl = 0; sl < g.n_slots; sl++) mine[sl] ^= chi[sl];
+        }
+#ifdef _OPENMP
+#pragma omp critical
+#endif
+        for (uint64_t sl = 0; sl < g.n_slots; sl++) zeta[sl] ^= mine[sl];
+      }
+      free(zL);
+      free(c0);
+      free(c1);
+      free(mine);
+    }
+  }
+  if (!rc && !failed) {
+    for (uint32_t u = 0; u < n; u++) {
+      reach_out[u] = 0xFFFFFFFFu;
+      for (uint64_t sl = g.v_off[u]; sl < g.v_off[u + 1]; sl++)
+        if (zeta[sl] && g.slot_t[sl] < reach_out[u]) reach_out[u] = g.slot_t[sl];
+    }
+    if (zeta_edge)
+      for (uint64_t sl = 0; sl < g.n_slots; sl++)
+        for (uint64_t ei = g.slot_e[sl]; ei < g.slot_e[sl + 1]; ei++) zeta_edge[ei] = zeta[sl];
+    if (m_canon_out) *m_canon_out = g.m;
+  }
+  free(z);
+  free(zeta);
+  orc_graph_free(&g);
+  if (rc) return rc;
+  return failed ? -2 : 0;
+}
+
+/* ---------------------------------------------------------------------------
  * Determinants over GF(2^64).
  * ------------------------------------------------------------------------ */
 uint64_t orc_gf_det(const uint64_t* a, int k) {

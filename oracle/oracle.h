@@ -100,6 +100,16 @@ int orc_fine_grained(uint32_t n, uint64_t m, const uint32_t* src, const uint32_t
                      uint64_t it_begin, uint64_t it_end, int threads, uint64_t* zeta_edge,
                      uint64_t* m_canon_out, uint32_t* reach_out, uint64_t* F_out);
 
+/* Fine-grained outputs under the literal reading of Eq. (poly-enc:1): y of
+ * a window term indexed by (v, u, level, predecessor arrival time i - j),
+ * level 1 = z^L at every time, delta(v) + 1 products per edge-update. Outputs
+ * as orc_fine_grained (no masks, no aggregate: the sum over end times cancels
+ * paths that differ only in their last edge's time). */
+int orc_fine_literal(uint32_t n, uint64_t m, const uint32_t* src, const uint32_t* dst, const uint32_t* t,
+                     const uint8_t* colour, uint32_t n_colours, uint32_t k, const uint32_t* delta,
+                     const uint8_t* motif_count, uint64_t seed, uint64_t it_begin, uint64_t it_end, int threads,
+                     uint64_t* zeta_edge, uint64_t* m_canon_out, uint32_t* reach_out);
+
 /* Closed form: XOR over all restless paths P with k vertices (motif mode:
  * z from the shade sum, so colour-mismatched paths contribute det = 0) of
  * (prod_p y_{e_p,p}) * det Z_P. n_paths_out counts the paths enumerated
