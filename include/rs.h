@@ -263,6 +263,23 @@ rs_status rs_reach_at_most(const rs_graph* g, const rs_query* q, const rs_constr
 rs_status rs_extract(const rs_graph* g, const rs_query* q, const rs_constraints* c, uint32_t* path_vertices,
                      uint32_t* path_times, rs_result* r, void* hip_stream);
 
+/* Fine-grained sieve under the literal reading of Eq. (poly-enc:1): the y
+ * variable of each window term is keyed by the edge's end points, the level
+ * and the predecessor's arrival time i - j (y_{uv,l-1,i-j}), and level 1 is
+ * x_u at every time, so an edge-update costs one product per window term (up
+ * to delta(v) + 1; the evaluation-cost lemma of Sec. 4.3). Paths that differ
+ * only in their last edge's time share every variable and cancel in a sum over
+ * end times, so each slot is tested on its own (Alg. 1). Outputs as
+ * rs_run_fine: reach_time (host, n entries) = least i with zeta_{u,k,i} != 0
+ * or 0xFFFFFFFF; slot_zeta (host, info.m entries, or NULL) = the zeta of each
+ * canonical edge's slot; r->yes = some slot is non-zero; r->fingerprint = the
+ * XOR of the slot values (a checksum, not a decision value). delta_per_vertex:
+ * host array of n resting times or NULL for q->delta. The iteration range of
+ * q selects the iterations summed. The graph's slot structure is built on the
+ * first call (4 bytes per edge and per slot, kept with the graph). */
+rs_status rs_run_literal(const rs_graph* g, const rs_query* q, const uint32_t* delta_per_vertex,
+                         uint32_t* reach_time, uint64_t* slot_zeta, rs_result* r, void* hip_stream);
+
 /* For callers that cannot allocate device memory (code under stream capture,
  * tight serving loops, harnesses that forbid hipMalloc): rs_run_ex without
  * tuning knobs, whose query workspace (window indices, substitution and

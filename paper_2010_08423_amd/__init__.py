@@ -111,6 +111,8 @@ _SIGNATURES = {
                                           _u32p, ctypes.POINTER(_Result), ctypes.c_void_p]),
     "rs_extract": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(_Query), ctypes.POINTER(_Constraints), _u32p,
                                     _u32p, ctypes.POINTER(_Result), ctypes.c_void_p]),
+    "rs_run_literal": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(_Query), _u32p, _u32p, _u64p,
+                                        ctypes.POINTER(_Result), ctypes.c_void_p]),
     "rs_run_noalloc": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(_Query), _u64p, ctypes.POINTER(_Result),
                                         ctypes.c_void_p]),
     "rs_run_batch": (ctypes.c_int32, [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(_Query), ctypes.c_uint32,
@@ -385,6 +387,26 @@ def run_fine(graph: Graph, k, delta, seed, motif=None, it_begin=0, it_end=0, sou
                             ctypes.byref(r), _stream_handle(stream))
     del keep, ckeep
     _check(s, "rs_run_fine")
+    return FineResult(r.fingerprint, bool(r.yes), r.device_ms, reach[:graph.n],
+                      zeta[:info["m"]] if zeta is not None else None)
+
+
+def run_literal(graph: Graph, k, delta, seed, motif=None, it_begin=0, it_end=0, slots=True,
+                stream=None) -> FineResult:
+    """rs_run_literal: per-slot zeta_{u,k,i} under the literal reading of Eq.
+    (poly-enc:1) (y keyed by the predecessor's arrival time), reach times and
+    the XOR of the slot values."""
+    info = graph.info()
+    dv = None if np.isscalar(delta) else np.ascontiguousarray(delta, dtype=np.uint32)
+    q, keep = _make_query(k, delta if dv is None else 0, seed, motif, it_begin, it_end)
+    reach = np.zeros(max(graph.n, 1), dtype=np.uint32)
+    zeta = np.zeros(max(info["m"], 1), dtype=np.uint64) if slots else None
+    r = _Result()
+    s = _load().rs_run_literal(graph.handle, ctypes.byref(q), dv.ctypes.data_as(_u32p) if dv is not None else None,
+                               reach.ctypes.data_as(_u32p), zeta.ctypes.data_as(_u64p) if zeta is not None else None,
+                               ctypes.byref(r), _stream_handle(stream))
+    del keep
+    _check(s, "rs_run_literal")
     return FineResult(r.fingerprint, bool(r.yes), r.device_ms, reach[:graph.n],
                       zeta[:info["m"]] if zeta is not None else None)
 

@@ -73,7 +73,8 @@ void DevBuf::release() {
 // ---------------------------------------------------------------------------
 // Kernel timing
 // ---------------------------------------------------------------------------
-static const char* kClassNames[KC_COUNT] = {"level_scan", "level_first", "level_top", "qtable", "ztable", "window", "batch"};
+static const char* kClassNames[KC_COUNT] = {"level_scan", "level_first", "level_top", "qtable",
+                                            "ztable",     "window",      "batch",     "literal_level"};
 static std::mutex g_prof_mu;
 static std::atomic<bool> g_prof_on{false};
 struct PendingEv {
@@ -773,6 +774,7 @@ rs_status rs_graph_destroy(rs_graph* g) {
                     &g->counts_dev})
     b->release();
   g->ws.release();
+  g->lit.release();
   delete g;
   return RS_OK;
 }

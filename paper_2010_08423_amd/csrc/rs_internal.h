@@ -345,7 +345,7 @@ struct GraphDev {
 // ---------------------------------------------------------------------------
 // Profiling (rs_engine.hip)
 // ---------------------------------------------------------------------------
-enum KernelClass { KC_SCAN = 0, KC_FIRST, KC_TOP, KC_QTABLE, KC_ZTABLE, KC_WINDOW, KC_BATCH, KC_COUNT };
+enum KernelClass { KC_SCAN = 0, KC_FIRST, KC_TOP, KC_QTABLE, KC_ZTABLE, KC_WINDOW, KC_BATCH, KC_LITERAL, KC_COUNT };
 bool profiling_on();
 struct ProfScope {
   // Records events around one launch of class `kc` on `st` when profiling is
@@ -421,6 +421,28 @@ constexpr uint64_t kNoAllocScratchBytes = 256ull << 20;
 }  // namespace rs
 
 // Opaque graph handle.
+namespace rs {
+// State of the literal-reading fine-grained sieve on one graph (rs_literal.hip):
+// the slot structure (built on first use) and the query buffers.
+constexpr uint32_t kLiteralTile = 16;  // edges per wave in the literal level kernel
+struct LiteralState {
+  bool built = false;
+  uint64_t ns = 0;                  // slots (maximal runs of equal (dst, t))
+  DevBuf slot, slot_t, v_soff;      // slot of each edge [m], time of each slot [ns], first slot per vertex [n+1]
+  DevBuf wlo, whi, y2, need, z, zs, out, chi0, chi1, dv, reach, zeta_edge;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  void release() {
+    for (DevBuf* b : {&slot, &slot_t, &v_soff, &wlo, &whi, &y2, &need, &z, &zs, &out, &chi0, &chi1, &dv, &reach,
+                      &zeta_edge})
+      b->release();
+    if (ev0) (void)hipEventDestroy(ev0);
+    if (ev1) (void)hipEventDestroy(ev1);
+    ev0 = ev1 = nullptr;
+    built = false;
+  }
+};
+}  // namespace rs
+
 struct rs_graph {
   int device = 0;
   rs::GraphDev g;
@@ -439,4 +461,5 @@ struct rs_graph {
   std::mutex counts_mu;
   std::map<std::pair<uint32_t, uint32_t>, std::vector<rs::NeedCounts>> need_counts;  // by (delta, k), per level
   rs::DevBuf counts_dev;
+  rs::LiteralState lit;  // literal-reading sieve (rs_run_literal); guarded by mu
 };
