@@ -15,6 +15,8 @@ Prints one JSON line. Extra modes (not the driver's default):
   --mode serve   the continuous-batching server on four resident graphs vs
                  first-come first-served plain calls over the same arrivals
   --mode copy    a plain 1 GiB device copy, the reference for HBM byte counters
+  --mode literal the literal reading of Eq. (poly-enc:1) (rs_run_literal) on
+                 the 10^6-edge path query, against the VALU issue peak
 """
 from __future__ import annotations
 
@@ -43,7 +45,7 @@ def host_cores():
 
 # Sources whose change invalidates the committed HBM counter figures of the
 # level kernel (kernel code, launch shapes, defaults).
-KERNEL_SOURCES = ("rs_device.h", "rs_level.h", "rs_kernels.hip", "rs_engine.hip", "rs_internal.h")
+KERNEL_SOURCES = ("rs_device.h", "rs_level.h", "rs_kernels.hip", "rs_engine.hip", "rs_internal.h", "rs_compact.hip")
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "k_scan_chunglu_m1e6_k8_counters.md")
 SQ_FILE = os.path.join(ROOT, "profiles", "k_scan_chunglu_m1e6_k8_sq.md")
 
@@ -143,7 +145,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--mode", default="plain", choices=["plain", "batch", "serve", "copy"])
+    ap.add_argument("--mode", default="plain", choices=["plain", "batch", "serve", "copy", "literal"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="motif-scale", choices=sorted(WORKLOADS),
                     help="plain mode: the query timed (default: the 10^7-edge motif query)")

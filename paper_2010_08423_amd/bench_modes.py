@@ -1,4 +1,4 @@
-"""The batched and served benchmark modes of bench.py.
+"""The batched, served and literal-reading benchmark modes of bench.py.
 
 batch: 64 queries on the 1,000,000-edge Chung-Lu graph (k uniform in 4..12,
        delta uniform in 2..50, half path and half motif over 8 colours, seeds
@@ -217,7 +217,129 @@ def run_serve_mode(args):
     }
 
 
+# Wave64 VALU issue peak: 256 CUs x 4 SIMDs x 2.4 GHz, one wave64 instruction
+# per SIMD every 4 clocks, i.e. 3.93e13 32-bit lane operations per second.
+VALU_LANE_OPS_PEAK = 256 * 4 * 2.4e9 / 4 * 64
+# VALU instructions per product of the literal level kernel, counted in its
+# compiled gfx950 code: a window-term product (table of multiples of the
+# wave-uniform y, 16-nibble comb, reduction) and a slot product (the slot's
+# sum times z^L_u through a per-lane table, with the subset XOR of z_u).
+LITERAL_VALU_PER_TERM = 111
+LITERAL_VALU_PER_SLOT = 140
+
+
+def literal_work(src, dst, t, n, k, delta, chunks):
+    """Products of one literal-reading query on the canonical edge list, per
+    level (the work the level kernel performs), as {level: (window-term
+    products, slot products)} over all chunks: level 2 one term per edge of a
+    slot some window reads, levels 3..k-1 one per window slot of such edges,
+    level k one per window slot of every edge; one slot product per slot
+    whose sum is formed (a read slot at levels below k; at levels >= 3 only
+    if one of its edges has a non-empty window)."""
+    m = len(dst)
+    first = np.ones(m, bool)
+    first[1:] = (dst[1:] != dst[:-1]) | (t[1:] != t[:-1])
+    slot = np.cumsum(first) - 1
+    ns = int(slot[-1]) + 1 if m else 0
+    key = dst[first].astype(np.int64) * (1 << 32) + t[first].astype(np.int64)  # sorted slot keys
+    d = np.full(n, int(delta), np.int64) if np.isscalar(delta) else np.asarray(delta, np.int64)
+    ti = t.astype(np.int64)
+    lo_t = np.maximum(ti - d[src], 1)
+    lo = np.searchsorted(key, src.astype(np.int64) * (1 << 32) + lo_t, side="left")
+    hi = np.searchsorted(key, src.astype(np.int64) * (1 << 32) + ti, side="right")
+    win = hi - lo
+    cover = np.zeros(ns + 1, np.int64)
+    np.add.at(cover, lo, 1)
+    np.add.at(cover, hi, -1)
+    need = np.cumsum(cover)[:ns] > 0
+    in_need = need[slot]
+    fed = np.bincount(slot, weights=(win > 0), minlength=ns) > 0  # a slot with a non-empty window
+    work = {}
+    if k == 2:
+        work[2] = (m, ns)
+    else:
+        work[2] = (int(in_need.sum()), int(need.sum()))
+        for l in range(3, k):
+            work[l] = (int(win[in_need].sum()), int((need & fed).sum()))
+        work[k] = (int(win.sum()), int(fed.sum()))
+    return {l: (a * chunks, b * chunks) for l, (a, b) in work.items()}
+
+
+def run_literal_mode(args):
+    """The literal reading of Eq. (poly-enc:1) (rs_run_literal) on the
+    10^6-edge path query: whole queries timed, the level kernel's launches
+    timed live, its window-term products counted on the host."""
+    import torch
+
+    _log("generating graph")
+    g, q = inputs.config_path_scale()
+    gd = R.Graph.from_inputs(g)
+    info = gd.info()
+    m = info["m"]
+    upd = (1 << q.k) * (q.k - 1) * m
+    R.profile_enable(True)
+    for _ in range(max(args.warmup, 1)):
+        r = R.run_literal(gd, q.k, q.delta, q.seed, slots=False)
+    F = r.fingerprint
+    R.profile_reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        r = R.run_literal(gd, q.k, q.delta, q.seed, slots=False)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    n_lvl, ms_lvl, _ = R.profile_get("literal_level")
+    R.profile_enable(False)
+    if r.fingerprint != F:
+        raise SystemExit("slot checksum changed between runs")
+    ms = dt * 1e3 / args.steps
+    s, d, t = gd.edges()
+    chunks = (1 << q.k) // 64
+    work = literal_work(s, d, t, g.n, q.k, q.delta, chunks)
+    terms_per_query = sum(a for a, _ in work.values())
+    slots_per_query = sum(b for _, b in work.values())
+    nominal_terms = (1 << q.k) * (q.k - 1) * m * (q.delta + 1)
+    # every launch of the level kernel: one level of one group of chunks
+    launches_per_query = n_lvl / max(args.steps, 1)
+    # algorithmic VALU lane-operations of one query's products (each product
+    # is one wave64 instruction stream over the 64 iterations of a chunk)
+    lane_ops = 64 * (terms_per_query * LITERAL_VALU_PER_TERM + slots_per_query * LITERAL_VALU_PER_SLOT)
+    achieved = lane_ops / (ms_lvl * 1e-3 / max(args.steps, 1)) / 1e12
+    peak = VALU_LANE_OPS_PEAK / 1e12
+    return {
+        "metric": "GF(2^64) edge-updates/sec per sieve",
+        "value": upd / (ms * 1e-3),
+        "unit": "edge-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": "literal reading of Eq. (poly-enc:1) (y keyed by the predecessor's arrival time, "
+                               "per-slot outputs), k-RestlessPath, Chung-Lu(2.5) n=100000 m=1000000 t in [1,1000], "
+                               "delta=10, k=8 (256 iterations), seed 2",
+                   "n": info["n"], "m": m, "k": q.k, "delta": q.delta, "seed": q.seed,
+                   "edge_updates_per_query": upd, "slot_checksum": f"{r.fingerprint:#018x}",
+                   "reached_vertices": int((r.reach != R.UNREACHED).sum())},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TOP/s",
+                     "frac": achieved / peak, "traffic": None,
+                     "kernel": "k_lit_level (all levels; one launch per level and chunk group)",
+                     "avg_launch_ms": ms_lvl / max(n_lvl, 1), "launches_per_query": launches_per_query,
+                     "window_terms_per_query": terms_per_query, "slot_products_per_query": slots_per_query,
+                     "products_per_level": {str(l): list(v) for l, v in work.items()},
+                     "nominal_terms_per_query": nominal_terms,
+                     "valu_ops_per_term": LITERAL_VALU_PER_TERM, "valu_ops_per_slot": LITERAL_VALU_PER_SLOT},
+        "kernel_ms_per_query": ms_lvl / max(args.steps, 1),
+    }
+
+
 def run(args):
     if args.mode == "batch":
         return run_batch_mode(args)
+    if args.mode == "literal":
+        return run_literal_mode(args)
     return run_serve_mode(args)
