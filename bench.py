@@ -151,8 +151,8 @@ def main():
                     help="plain mode: the query timed (default: the 10^7-edge motif query)")
     # serve mode: offered load, arrival window, wall-clock cap, server budget
     ap.add_argument("--rate", type=float, default=200.0)
-    ap.add_argument("--window", type=float, default=5.0)
-    ap.add_argument("--cap", type=float, default=40.0)
+    ap.add_argument("--window", type=float, default=60.0)
+    ap.add_argument("--cap", type=float, default=75.0)
     ap.add_argument("--budget-gb", type=float, default=200.0)
     ap.add_argument("--group-updates", type=float, default=0, help="group work cap (0: the library default)")
     ap.add_argument("--streams", type=int, default=0)
@@ -267,6 +267,15 @@ def main():
                      "salu_frac": _float(committed_figures(sq_file).get("salu-frac")) if sq_file else None},
         "kernels": classes,
     }
+    # look-back events of one more (untimed) query: predecessor runs
+    # recomputed after the bounded wait, probe rounds that found no record
+    R.lookback_count(True)
+    rl = R.run(gd, q.k, q.delta, q.seed, motif=q.motif)
+    lb = R.lookback_get()
+    R.lookback_count(False)
+    if rl.fingerprint != F:
+        raise SystemExit("fingerprint changed with look-back counting on")
+    out["lookback_one_query"] = {"recomputed_predecessor_runs": lb[0], "unanswered_probe_rounds": lb[1]}
     exact = True
     if rank == 0 and not args.no_cpu_baseline:
         rec, a, per = cpu_baseline(g, q, m)

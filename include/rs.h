@@ -354,6 +354,17 @@ rs_status rs_profile_enable(int on);
  * diagnosing large queries: it serialises the launches with the host and so
  * changes timings. Results are unchanged. Never fails. */
 rs_status rs_trace_enable(int on);
+/* Look-back counters of the prefix levels (both paths). A level launch
+ * carries a segment's running XOR across runs of tiles through published
+ * per-run records; a run whose predecessor has not published within a
+ * bounded wait recomputes that predecessor's part itself. While counting is
+ * on (rs_lookback_count(1), which also zeroes the totals), every query and
+ * batch adds its numbers of recomputed predecessor runs and of probe rounds
+ * that found no record to process-wide totals, read by rs_lookback_get.
+ * Counting adds one device-side atomic per event and a small copy per call;
+ * results are unchanged. Never fails (rs_lookback_get: RS_EINVAL for NULL). */
+rs_status rs_lookback_count(int on);
+rs_status rs_lookback_get(uint64_t* recomputes, uint64_t* unanswered_rounds);
 rs_status rs_profile_reset(void);
 /* launches and summed milliseconds of a kernel class since the last reset. */
 rs_status rs_profile_get(const char* kernel_class, uint64_t* launches, double* total_ms,
@@ -377,9 +388,16 @@ typedef struct {
   uint32_t max_inflight;       /* queries running at once (0 = 256) */
   uint64_t group_edge_updates; /* work cap of one group, in edge-updates
                                   (iterations * (k-1) * m summed over its
-                                  queries; 0 = 4e9; a query whose own work
-                                  reaches the cap runs alone, so 1 turns
-                                  grouping off) */
+                                  queries; 0 = 4e9). A query whose remaining
+                                  work exceeds what is left of the cap joins
+                                  with a slice of whole 64-iteration chunks
+                                  (alone, through the plain kernels, when no
+                                  other query waits) and its rest rejoins the
+                                  queue in arrival order, so queries enter and
+                                  leave groups at chunk boundaries; a query
+                                  none of whose chunks fits runs alone, whole
+                                  (1 turns grouping off). Graphs above
+                                  group_max_edges always run whole and alone. */
   uint32_t streams;            /* worker threads and streams (0 = 2, at most 16);
                                   level kernels size their grids to fill the
                                   GPU, so more than two concurrent jobs mostly
@@ -396,6 +414,8 @@ typedef struct {
   double busy_ms;              /* wall time of jobs, summed over workers */
   uint64_t jobs;               /* jobs run (a group or a single query) */
   uint64_t held_bytes;         /* device bytes held by resident workspaces */
+  uint64_t slices;             /* pieces run of queries that ran in more than
+                                  one (work above the group cap) */
 } rs_server_stats;
 
 /* hbm_budget: bytes of HBM the server may hold for query workspaces. */

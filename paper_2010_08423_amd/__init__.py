@@ -82,7 +82,7 @@ class _ServerStats(ctypes.Structure):
                 ("deferred", ctypes.c_uint64), ("cancelled", ctypes.c_uint64), ("rejected", ctypes.c_uint64),
                 ("queued", ctypes.c_uint64), ("inflight", ctypes.c_uint64), ("qps", ctypes.c_double),
                 ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double), ("busy_ms", ctypes.c_double),
-                ("jobs", ctypes.c_uint64), ("held_bytes", ctypes.c_uint64)]
+                ("jobs", ctypes.c_uint64), ("held_bytes", ctypes.c_uint64), ("slices", ctypes.c_uint64)]
 
 
 # Every symbol include/rs.h declares, with its ctypes signature.
@@ -124,6 +124,8 @@ _SIGNATURES = {
     "rs_profile_enable": (ctypes.c_int32, [ctypes.c_int]),
     "rs_trace_enable": (ctypes.c_int32, [ctypes.c_int]),
     "rs_profile_reset": (ctypes.c_int32, []),
+    "rs_lookback_count": (ctypes.c_int32, [ctypes.c_int]),
+    "rs_lookback_get": (ctypes.c_int32, [_u64p, _u64p]),
     "rs_profile_get": (ctypes.c_int32, [ctypes.c_char_p, _u64p, ctypes.POINTER(ctypes.c_double),
                                         ctypes.POINTER(ctypes.c_double)]),
     "rs_server_create": (ctypes.c_int32, [ctypes.c_uint64, ctypes.POINTER(_ServerOpts),
@@ -529,6 +531,19 @@ def trace_enable(on=True):
 
 def profile_reset():
     _check(_load().rs_profile_reset(), "rs_profile_reset")
+
+
+def lookback_count(on: bool):
+    """rs_lookback_count: start (and zero) or stop counting look-back events."""
+    _check(_load().rs_lookback_count(1 if on else 0), "rs_lookback_count")
+
+
+def lookback_get():
+    """rs_lookback_get: (recomputed predecessor runs, probe rounds without a
+    record) since counting was turned on."""
+    a, b = ctypes.c_uint64(), ctypes.c_uint64()
+    _check(_load().rs_lookback_get(ctypes.byref(a), ctypes.byref(b)), "rs_lookback_get")
+    return a.value, b.value
 
 
 def profile_get(kernel_class: str):

@@ -91,6 +91,14 @@ def run_batch_mode(args):
     if got != plain:
         bad = [i for i in range(len(qs)) if got[i] != plain[i]]
         raise SystemExit(f"batched fingerprints differ from plain for queries {bad}")
+    # look-back events of one more (untimed) batch on the four stream lanes,
+    # whose rounds' waves are not guaranteed to be resident together
+    R.lookback_count(True)
+    res2, _ = R.run_batch(graphs, qs)
+    lb_batch = R.lookback_get()
+    R.lookback_count(False)
+    if [r.fingerprint for r in res2] != plain:
+        raise SystemExit("batched fingerprints changed with look-back counting on")
     return {
         "metric": "queries/s (batched vs plain, equal fingerprints)",
         "value": len(qs) / dt,
@@ -114,6 +122,7 @@ def run_batch_mode(args):
         "plain": {"queries_per_s": len(qs) / plain_s, "edge_updates_per_s": upd / plain_s, "s_total": plain_s},
         "speedup_vs_plain": plain_s / dt,
         "fingerprints_equal": True,
+        "lookback_one_batch": {"recomputed_predecessor_runs": lb_batch[0], "unanswered_probe_rounds": lb_batch[1]},
     }
 
 
@@ -154,8 +163,14 @@ def run_serve_mode(args):
     th = threading.Thread(target=submitter)
     th.start()
     th.join()
+    st_window = srv.stats()  # when the last arrival is in: the backlog the window leaves
+    t_window = time.perf_counter() - start
     lat, fps, done = [], {}, 0
+    _log(f"arrivals in after {t_window:.1f} s: {st_window['completed']} completed, "
+         f"{st_window['queued'] + st_window['inflight']} waiting or running")
     for i, tk in enumerate(tickets):
+        if i % 500 == 0:
+            _log(f"collecting results: {i}/{len(tickets)} at {time.perf_counter() - start:.1f} s")
         left_ms = int(max(0.0, start + cap - time.perf_counter()) * 1e3)
         r = srv.poll(tk, wait_ms=left_ms) if left_ms > 0 else srv.poll(tk, wait_ms=0)
         if r is not None and r.status == R.RS_OK:
@@ -165,6 +180,7 @@ def run_serve_mode(args):
     for i, tk in enumerate(tickets):
         if i not in fps:
             srv.cancel(tk)
+    cancelled = srv.stats()["cancelled"]
     srv.close()
     served_elapsed = end_served - start
     p50, p99 = st["p50_ms"], st["p99_ms"]
@@ -176,10 +192,14 @@ def run_serve_mode(args):
     torch.cuda.synchronize()
     start = time.perf_counter()
     plain_lat, plain_fp = [], {}
+    next_log = 10.0
     for i, (ta, gi, q) in enumerate(stream):
         now = time.perf_counter()
         if now - start >= cap:
             break
+        if now - start >= next_log:
+            _log(f"plain: {i} arrivals handled at {now - start:.1f} s")
+            next_log += 10.0
         if start + ta > now:
             time.sleep(start + ta - now)
         plain_fp[i] = R.run(gds[gi], q.k, q.delta, q.seed, motif=q.motif).fingerprint
@@ -209,8 +229,15 @@ def run_serve_mode(args):
                    "group_edge_updates": args.group_updates or 4e9, "streams": args.streams or 2},
         "served": {"completed": served_done, "queries_per_s": served_done / served_elapsed,
                    "edge_updates_per_s": done_updates / served_elapsed, "p50_ms": p50, "p99_ms": p99,
-                   "jobs": st["jobs"], "deferred": st["deferred"], "held_gb": st["held_bytes"] / 2**30,
-                   "elapsed_s": served_elapsed},
+                   "jobs": st["jobs"], "slices": st["slices"], "deferred": st["deferred"],
+                   "held_gb": st["held_bytes"] / 2**30, "elapsed_s": served_elapsed,
+                   # at the end of the arrival window: completed so far and the backlog left
+                   "at_window_end": {"t_s": t_window, "completed": st_window["completed"],
+                                     "backlog": st_window["queued"] + st_window["inflight"],
+                                     "queued": st_window["queued"], "inflight": st_window["inflight"],
+                                     "deferred": st_window["deferred"]},
+                   # at the cap: what had not completed is cancelled
+                   "backlog_at_cap": len(stream) - served_done, "cancelled_at_cap": cancelled},
         "plain": {"completed": len(plain_fp), "queries_per_s": len(plain_fp) / plain_elapsed,
                   "p50_ms": pp50, "p99_ms": pp99, "elapsed_s": plain_elapsed},
         "fingerprints_equal_on_common": len(common),

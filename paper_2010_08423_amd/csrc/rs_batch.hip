@@ -268,7 +268,7 @@ __device__ __forceinline__ uint32_t find_unit(cu32* ubegin, uint32_t from, uint3
 template <int KQ, int E, bool FIRST>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void kb_scan(const MUnit* __restrict__ units, const uint32_t* __restrict__ ubegin_p,
                                                uint32_t nunits, uint32_t total, uint64_t* __restrict__ agg,
-                                               uint64_t* __restrict__ incl) {
+                                               uint64_t* __restrict__ incl, unsigned long long* __restrict__ lb_stats) {
   extern __shared__ uint64_t dyn_lds[];  // [waves][16][64]; starts at LDS address 0
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform for the compiler
@@ -301,7 +301,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
   c.agg = agg;
   c.incl = incl;
   c.need = U.need;
-  c.lb_stats = nullptr;
+  c.lb_stats = lb_stats;  // null unless look-back counting is on
   c.bounds = U.bounds;
   scan_level<KQ, E, FIRST>(c, idx, U.waves, lane, mk, tab);
 }
@@ -374,6 +374,7 @@ constexpr uint32_t kBatchLanes = 4;
 struct BatchWorkspace {
   std::mutex mu;
   DevBuf qs, units, ubegin, per_query, parena, agg, incl, out, ref, cov, bounds;
+  DevBuf lb;  // look-back counters [2] (while counting is on)
   uint32_t epoch = 0;
   std::string key;  // shape of the captured graph
   hipGraphExec_t exec = nullptr;
@@ -401,7 +402,7 @@ struct BatchWorkspace {
   }
   void release() {
     drop_graph();
-    for (DevBuf* b : {&qs, &units, &ubegin, &per_query, &parena, &agg, &incl, &out, &ref, &cov, &bounds})
+    for (DevBuf* b : {&qs, &units, &ubegin, &per_query, &parena, &agg, &incl, &out, &ref, &cov, &bounds, &lb})
       b->release();
     epoch = 0;
   }
@@ -472,9 +473,20 @@ struct BatchPlan {
   std::vector<int32_t> unit_list;     // per unit: level index of its compacted list, or -1
   Tuning tu;
   std::string key;
+  bool count_lb = false;  // the prefix launches count look-back events into W.lb
 };
 
 static uint64_t align256(uint64_t b) { return (b + 255) & ~255ull; }
+
+// Per-query arena bytes of a query in a batch (the layout batch_plan gives
+// it), at the smallest tile size (most tiles).
+uint64_t batch_query_bytes(uint64_t m, uint64_t n, const QueryPlan& qp) {
+  const uint64_t levels = qp.k > 2 ? qp.k - 2 : 0, tiles = (m + 7) / 8, nb = (tiles + kCostBlock - 1) / kCostBlock;
+  return align256(table_lo_bytes(m)) + align256(table_z_bytes(n, qp.kq)) +
+         (qp.k == 2 ? align256(table_q_bytes(m, qp.k, qp.kq)) : 0) +
+         (qp.k >= 3 ? align256(compact_bytes(m, qp.k, qp.kq)) : 0) + align256(table_need_bytes(m, qp.k)) +
+         align256(4 * tiles * levels) + 2 * align256(4 * nb * levels) + align256(8 * (1ull << qp.k)) + 2048;
+}
 
 // Bytes one chunk holds while its round runs: two prefix-state arrays and
 // the look-back records of its tiles.
@@ -952,7 +964,8 @@ static rs_status batch_enqueue(BatchPlan& P, BatchWorkspace& W, hipStream_t st) 
                          P.tu.edges_per_tile);
       uint64_t* agg = W.agg.as<uint64_t>();
       uint64_t* incl = W.incl.as<uint64_t>();
-      void* args[] = {(void*)&u, (void*)&b, (void*)&L.nunits, (void*)&L.total, (void*)&agg, (void*)&incl};
+      unsigned long long* lb = P.count_lb ? W.lb.as<unsigned long long>() : nullptr;
+      void* args[] = {(void*)&u, (void*)&b, (void*)&L.nunits, (void*)&L.total, (void*)&agg, (void*)&incl, (void*)&lb};
       RS_HIP(hipLaunchKernel(kern, dim3(L.grid), dim3(64 * wpb), args, lds, lst));
     }
   }
@@ -1008,6 +1021,7 @@ rs_status run_batch_impl(const rs_graph* const* graphs, const rs_query* queries,
         return RS_EINVAL;
       }
   BatchPlan P;
+  P.count_lb = lookback_counting();
   // the lanes hold one round each at a time, so a round gets a lane's share
   // of the budget and the whole prefix arena stays within it
   const uint64_t budget = slot_budget ? slot_budget : default_slot_budget();
@@ -1042,6 +1056,13 @@ rs_status run_batch_impl(const rs_graph* const* graphs, const rs_query* queries,
   }
   RS_TRY(resolve_plan(P, W, W.epoch));
   size_grids(P);
+  if (P.count_lb) {
+    const void* before_lb = W.lb.p;
+    if (W.lb.reserve(16, st, true)) return RS_ENOMEM;
+    if (W.lb.p != before_lb) W.drop_graph();
+    RS_HIP(launch_fill64(W.lb.as<uint64_t>(), 0, 2, st));
+    P.key += "/lb";  // a captured graph holds the counter pointer
+  }
   {
     const void* before_b = W.bounds.p;
     if (W.bounds.reserve(4 * std::max<uint64_t>(P.bounds_words, 1), st, false)) return RS_ENOMEM;
@@ -1098,6 +1119,11 @@ rs_status run_batch_impl(const rs_graph* const* graphs, const rs_query* queries,
   RS_HIP(hipMemcpyAsync(F.data(), W.out.p, 8 * F.size(), hipMemcpyDeviceToHost, st));
   RS_HIP(hipEventRecord(W.ev1, st));
   RS_HIP(hipStreamSynchronize(st));
+  if (P.count_lb) {
+    unsigned long long h[2] = {0, 0};
+    RS_HIP(hipMemcpy(h, W.lb.p, sizeof(h), hipMemcpyDeviceToHost));
+    lookback_add(h[0], h[1]);
+  }
   if (profiling_on()) profile_flush();
   float ms = 0;
   (void)hipEventElapsedTime(&ms, W.ev0, W.ev1);

@@ -39,6 +39,14 @@ static bool trace_on() {
   return v > 0;
 }
 
+static std::atomic<bool> g_lb_on{false};
+static std::atomic<uint64_t> g_lb_recomputes{0}, g_lb_unanswered{0};
+bool lookback_counting() { return g_lb_on.load(std::memory_order_relaxed); }
+void lookback_add(uint64_t recomputes, uint64_t unanswered) {
+  g_lb_recomputes.fetch_add(recomputes);
+  g_lb_unanswered.fetch_add(unanswered);
+}
+
 static thread_local std::string g_last_error;
 void set_last_error(const std::string& s) { g_last_error = s; }
 
@@ -394,13 +402,16 @@ rs_status run_plain(rs_graph* g, PlainWorkspace& ws, const QueryPlan& qp, const 
     }
     auto need_of = [&](uint32_t l) { return ws.need.as<uint8_t>() + (uint64_t)(l - 2) * need_stride(m); };
     const bool tr = timed && trace_on();
-    if (tr && ws.lb_stats.reserve(16, st, true)) return RS_ENOMEM;
+    const bool count_lb = !tr && timed && lookback_counting();  // totals for the query, read at its end
+    if ((tr || count_lb) && ws.lb_stats.reserve(16, st, true)) return RS_ENOMEM;
+    if (count_lb) RS_HIP(launch_fill64(ws.lb_stats.as<uint64_t>(), 0, 2, st));
     auto t_last = std::chrono::steady_clock::now();
     // one trace line: waits for the launches so far, reads the counters
     auto trace = [&](const char* what, uint32_t l, uint64_t c0, uint32_t gc, bool counters) -> rs_status {
       RS_HIP(hipStreamSynchronize(st));
       unsigned long long h[2] = {0, 0};
       if (counters) RS_HIP(hipMemcpy(h, ws.lb_stats.p, sizeof(h), hipMemcpyDeviceToHost));
+      if (counters && lookback_counting()) lookback_add(h[0], h[1]);
       const auto now = std::chrono::steady_clock::now();
       fprintf(stderr, "[rs-trace] %s level %u chunks %llu..%llu: %.3f ms", what, l, (unsigned long long)c0,
               (unsigned long long)(c0 + gc), std::chrono::duration<double, std::milli>(now - t_last).count());
@@ -557,10 +568,8 @@ rs_status run_plain(rs_graph* g, PlainWorkspace& ws, const QueryPlan& qp, const 
           a.bounds = ws.run_bounds.as<uint32_t>() + (uint64_t)(l - 2) * run_stride;
           a.waves = first ? run_w2 : run_w3;
           a.count = ca.count + (l - 2);
-          if (tr) {
-            RS_HIP(launch_fill64(ws.lb_stats.as<uint64_t>(), 0, 2, st));
-            a.lb_stats = ws.lb_stats.as<unsigned long long>();
-          }
+          if (tr) RS_HIP(launch_fill64(ws.lb_stats.as<uint64_t>(), 0, 2, st));
+          if (tr || count_lb) a.lb_stats = ws.lb_stats.as<unsigned long long>();
           {
             ProfScope ps(first ? KC_FIRST : KC_SCAN, st, scan_bytes(ncs[l], m, kq, gc, first), timed);
             RS_HIP(launch_scan(a, first, kq, gc, tu, st));
@@ -620,6 +629,11 @@ rs_status run_plain(rs_graph* g, PlainWorkspace& ws, const QueryPlan& qp, const 
       if (ex->zeta) RS_HIP(hipMemcpyAsync(ex->zeta, ws.fine_z.p, 8 * m, hipMemcpyDeviceToHost, st));
       if (timed) RS_HIP(hipEventRecord(ws.ev1, st));
       RS_HIP(hipStreamSynchronize(st));
+      if (count_lb) {
+        unsigned long long h[2] = {0, 0};
+        RS_HIP(hipMemcpy(h, ws.lb_stats.p, sizeof(h), hipMemcpyDeviceToHost));
+        lookback_add(h[0], h[1]);
+      }
       ex->reached = 0;
       for (uint64_t u = 0; u < n; ++u) ex->reached += ex->reach[u] != 0xFFFFFFFFu;
       float ms = 0;
@@ -638,6 +652,11 @@ rs_status run_plain(rs_graph* g, PlainWorkspace& ws, const QueryPlan& qp, const 
                             hipMemcpyDeviceToHost, st));
     if (timed) RS_HIP(hipEventRecord(ws.ev1, st));
     RS_HIP(hipStreamSynchronize(st));
+    if (count_lb) {
+      unsigned long long h[2] = {0, 0};
+      RS_HIP(hipMemcpy(h, ws.lb_stats.p, sizeof(h), hipMemcpyDeviceToHost));
+      lookback_add(h[0], h[1]);
+    }
   } else {
     if (per_it_host)
       for (uint64_t i = 0; i < span; ++i) per_it_host[i] = 0;
@@ -970,6 +989,22 @@ rs_status rs_run_noalloc(const rs_graph* gc, const rs_query* q, uint64_t* per_it
 
 rs_status rs_trace_enable(int on) {
   g_trace.store(on != 0 ? 1 : 0);
+  return RS_OK;
+}
+
+rs_status rs_lookback_count(int on) {
+  if (on) {
+    g_lb_recomputes = 0;
+    g_lb_unanswered = 0;
+  }
+  g_lb_on.store(on != 0);
+  return RS_OK;
+}
+
+rs_status rs_lookback_get(uint64_t* recomputes, uint64_t* unanswered_rounds) {
+  if (!recomputes || !unanswered_rounds) return RS_EINVAL;
+  *recomputes = g_lb_recomputes.load();
+  *unanswered_rounds = g_lb_unanswered.load();
   return RS_OK;
 }
 

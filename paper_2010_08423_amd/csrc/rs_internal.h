@@ -327,6 +327,8 @@ Tuning resolve_tuning(const rs_graph* g, uint32_t k, const rs_tuning* t);
 // a time. ws = nullptr uses the process-wide workspace of rs_run_batch.
 struct BatchWorkspace;
 BatchWorkspace* batch_ws_create();
+// Per-query device bytes of a query in a batch (its tables and lists).
+uint64_t batch_query_bytes(uint64_t m, uint64_t n, const QueryPlan& qp);
 void batch_ws_destroy(BatchWorkspace* w);
 void batch_ws_release(BatchWorkspace* w);  // frees its device memory (synchronises the device)
 uint64_t batch_ws_bytes(BatchWorkspace* w);
@@ -347,6 +349,12 @@ struct GraphDev {
 // ---------------------------------------------------------------------------
 enum KernelClass { KC_SCAN = 0, KC_FIRST, KC_TOP, KC_QTABLE, KC_ZTABLE, KC_WINDOW, KC_BATCH, KC_LITERAL, KC_COUNT };
 bool profiling_on();
+// Look-back counters (rs_lookback_count / rs_lookback_get): while counting is
+// on, the level kernels of both paths count predecessor runs recomputed after
+// the bounded wait and probe rounds that found no record, and each query or
+// batch adds its counts to the process totals.
+bool lookback_counting();
+void lookback_add(uint64_t recomputes, uint64_t unanswered);
 struct ProfScope {
   // Records events around one launch of class `kc` on `st` when profiling is
   // on and the caller allows it (the no-allocation workspace does not).

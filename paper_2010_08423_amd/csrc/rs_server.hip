@@ -9,7 +9,13 @@
 //     to a work cap) and evaluated by the batched path in shared level
 //     launches, which removes their per-query launch and setup overhead;
 //     while a group runs, small-graph arrivals queue for the next group and
-//     idle workers take large-graph queries.
+//     idle workers take large-graph queries;
+//   * a query whose remaining work exceeds what is left of the cap joins a
+//     group with a slice of whole 64-iteration chunks (an iteration range:
+//     the sieve sums over iterations, so slice fingerprints XOR to the
+//     query's) and its rest rejoins the queue in arrival order. Queries thus
+//     enter and leave groups at chunk boundaries: an arrival waits for at
+//     most one group, not for the longest query of the one running.
 // Workers run concurrently, so queries overlap on the device. Admission is
 // by HBM: the resident plain workspaces, the group workspace and the growth
 // a job needs must stay within the budget; idle workspaces are freed when a
@@ -49,7 +55,12 @@ struct SQuery {
   Tuning tu;
   PlainSizes sizes;    // plain workspace buffers it needs
   uint64_t group_bytes;  // its per-query tables in a group
-  uint64_t work;         // edge-updates
+  uint64_t work;         // edge-updates of the remaining iterations
+  uint64_t per_it;       // edge-updates per iteration: (k-1) m
+  uint64_t next_it;      // first iteration not yet run
+  uint64_t acc_F = 0;    // XOR of the fingerprints of the slices run so far
+  bool admitted_once = false;
+  bool split = false;    // runs in more than one piece
   Clock::time_point t_submit;
   bool deferred_counted = false;
   bool done = false, cancelled = false;
@@ -66,6 +77,7 @@ struct PoolEntry {
 
 struct Job {
   std::vector<std::shared_ptr<SQuery>> qs;
+  std::vector<uint64_t> it_end;  // per query: end of the iterations this job runs
   PoolEntry* entry = nullptr;  // plain job
   uint64_t reserved = 0;       // bytes added to the held total for this job
   bool group = false;
@@ -108,7 +120,25 @@ static uint64_t growth(const PlainWorkspace& w, const PlainSizes& z) {
   auto g = [](const DevBuf& b, uint64_t need) { return need > b.bytes ? need - b.bytes : 0; };
   return g(w.lo, z.lo) + g(w.z, z.z) + g(w.q, z.q) + g(w.p0, z.p) + g(w.p1, z.p) + g(w.partial, z.partial) +
          g(w.fsum, z.fsum) + g(w.out, 64) + g(w.ref, z.ref) + g(w.need, z.need) + g(w.cov_diff, z.cover) +
-         g(w.agg, z.records) + g(w.incl, z.records);
+         g(w.agg, z.records) + g(w.incl, z.records) + g(w.run_pre, z.run_pre) + g(w.run_bsum, z.run_bsum) +
+         g(w.run_boff, z.run_boff) + g(w.run_bounds, z.run_bounds) + g(w.lists, z.lists);
+}
+
+// Puts a query back in the queue before the first query that arrived after
+// it (queries that have run slices keep their place in arrival order).
+static void requeue(rs_server* S, const std::shared_ptr<SQuery>& a) {
+  auto it = S->queued.begin();
+  while (it != S->queued.end() && (*it)->t_submit <= a->t_submit) ++it;
+  S->queued.insert(it, a);
+}
+
+// Iterations [next_it, end) of a that fit `room` edge-updates, ending at a
+// chunk boundary or at the query's end; end == next_it if no chunk fits.
+static uint64_t slice_end(const SQuery& a, uint64_t room) {
+  const uint64_t its = room / std::max<uint64_t>(a.per_it, 1);
+  if (a.next_it + its >= a.plan.it_end) return a.plan.it_end;
+  const uint64_t e = (a.next_it + its) / 64 * 64;  // 64-iteration chunks
+  return e > a.next_it ? e : a.next_it;
 }
 
 static uint64_t held(const rs_server* S) { return S->plain_held + S->batch_held; }
@@ -185,17 +215,20 @@ static bool take_job(rs_server* S, Job& job) {
     defer(S, *a);
     return false;
   }
-  if (is_small(S, *a) && S->opts.group_edge_updates > a->work) {
-    // a group: small-graph queries in arrival order while work, slots and memory allow
+  if (is_small(S, *a) && slice_end(*a, S->opts.group_edge_updates) > a->next_it) {
+    // a group: small-graph queries in arrival order while work, slots and
+    // memory allow, each with all its remaining iterations or a slice of them
     const uint64_t slot_share = S->budget / 4;  // prefix-state arena of the group's rounds
     uint64_t work = 0, bytes = slot_share;
     const uint64_t slots = S->opts.max_inflight - S->inflight;
-    std::vector<size_t> pick;  // queue positions, ascending
+    std::vector<size_t> pick;     // queue positions, ascending
+    std::vector<uint64_t> ends;   // iterations each picked query runs up to
     for (size_t j = (size_t)(it - S->queued.begin());
          j < S->queued.size() && pick.size() < std::min<uint64_t>(kMaxGroup, slots); ++j) {
       SQuery& b = *S->queued[j];
       if (b.cancelled || !is_small(S, b)) continue;
-      if (work + b.work > S->opts.group_edge_updates) break;
+      const uint64_t end = slice_end(b, S->opts.group_edge_updates - work);
+      if (end == b.next_it) break;  // not one chunk of it fits what is left
       const uint64_t nb = bytes + b.group_bytes;
       if (S->plain_held + std::max(S->batch_held, nb) > S->budget) {
         make_room(S, nb > S->batch_held ? nb - S->batch_held : 0, nullptr, UINT32_MAX);
@@ -204,19 +237,28 @@ static bool take_job(rs_server* S, Job& job) {
           break;
         }
       }
-      work += b.work;
+      work += (end - b.next_it) * b.per_it;
       bytes = nb;
       pick.push_back(j);
+      ends.push_back(end);
+      if (work >= S->opts.group_edge_updates) break;
     }
     if (pick.size() >= 2) {
-      for (size_t j : pick) job.qs.push_back(S->queued[j]);
+      for (size_t i = 0; i < pick.size(); ++i) {
+        auto& b = S->queued[pick[i]];
+        job.qs.push_back(b);
+        job.it_end.push_back(ends[i]);
+        if (!b->admitted_once) {
+          b->admitted_once = true;
+          S->st.admitted++;
+        }
+      }
       for (auto j = pick.rbegin(); j != pick.rend(); ++j) S->queued.erase(S->queued.begin() + *j);
       job.group = true;
       job.reserved = bytes > S->batch_held ? bytes - S->batch_held : 0;
       S->batch_held += job.reserved;
       S->group_running = true;
       S->inflight += job.qs.size();
-      S->st.admitted += job.qs.size();
       return true;
     }
   }
@@ -226,9 +268,17 @@ static bool take_job(rs_server* S, Job& job) {
     return false;
   }
   job.qs.push_back(a);
+  // a small-graph query runs alone a slice within the group cap, so that
+  // arrivals behind it join at its next chunk boundary (all of it when not
+  // one chunk fits the cap)
+  const uint64_t end = is_small(S, *a) ? slice_end(*a, S->opts.group_edge_updates) : a->plan.it_end;
+  job.it_end.push_back(end > a->next_it ? end : a->plan.it_end);
+  if (!a->admitted_once) {
+    a->admitted_once = true;
+    S->st.admitted++;
+  }
   S->queued.erase(it);
   S->inflight++;
-  S->st.admitted++;
   return true;
 }
 
@@ -249,16 +299,27 @@ static void worker_loop(rs_server* S) {
     if (s == RS_OK && !job.group) {
       SQuery& a = *job.qs[0];
       rs_graph* g = const_cast<rs_graph*>(S->graphs[a.graph_id]);
-      s = run_plain(g, job.entry->ws, a.plan, a.tu, nullptr, &res[0], st);
+      QueryPlan plan = a.plan;  // the iterations of this piece
+      if (a.next_it != plan.it_begin || job.it_end[0] != plan.it_end) {
+        rs_query q = a.q;
+        q.motif_count = a.has_motif ? a.motif : nullptr;
+        q.it_begin = a.next_it;
+        q.it_end = job.it_end[0];
+        s = plan_query(g, &q, plan);
+      }
+      if (s == RS_OK) s = run_plain(g, job.entry->ws, plan, a.tu, nullptr, &res[0], st);
       res[0].status = s;
     } else if (s == RS_OK) {
       std::vector<const rs_graph*> gl;
       std::vector<rs_query> qs;
-      for (auto& a : job.qs) {
-        rs_query q = a->q;
-        q.motif_count = a->has_motif ? a->motif : nullptr;
+      for (size_t i = 0; i < job.qs.size(); ++i) {
+        const SQuery& a = *job.qs[i];
+        rs_query q = a.q;
+        q.motif_count = a.has_motif ? a.motif : nullptr;
+        q.it_begin = a.next_it;
+        q.it_end = job.it_end[i];
         qs.push_back(q);
-        gl.push_back(S->graphs[a->graph_id]);
+        gl.push_back(S->graphs[a.graph_id]);
       }
       s = run_batch_impl(gl.data(), qs.data(), (uint32_t)qs.size(), res.data(), nullptr, st, false, S->budget / 4,
                          S->bws);
@@ -283,9 +344,25 @@ static void worker_loop(rs_server* S) {
       }
       const auto now = Clock::now();
       for (size_t i = 0; i < job.qs.size(); ++i) {
-        SQuery& a = *job.qs[i];
-        a.result = res[i];
-        if (s != RS_OK && a.result.status == RS_OK) a.result.status = s;
+        auto& ap = job.qs[i];
+        SQuery& a = *ap;
+        rs_result r = res[i];
+        if (s != RS_OK && r.status == RS_OK) r.status = s;
+        S->inflight--;
+        if (a.split || job.it_end[i] < a.plan.it_end) {
+          a.split = true;
+          S->st.slices++;
+        }
+        a.acc_F ^= r.fingerprint;
+        a.next_it = job.it_end[i];
+        a.work = (a.plan.it_end - a.next_it) * a.per_it;
+        if (r.status == RS_OK && !a.cancelled && a.next_it < a.plan.it_end) {
+          requeue(S, ap);  // the rest of its iterations joins a later group
+          continue;
+        }
+        a.result = r;
+        a.result.fingerprint = a.acc_F;
+        a.result.yes = a.acc_F != 0;
         if (a.cancelled) a.result.status = RS_ECANCELED;
         const double lat = std::chrono::duration<double, std::milli>(now - a.t_submit).count();
         a.result.device_ms = (float)lat;
@@ -294,7 +371,6 @@ static void worker_loop(rs_server* S) {
           S->st.completed++;
         }
         a.done = true;
-        S->inflight--;
       }
     }
     S->cv_done.notify_all();
@@ -374,8 +450,7 @@ rs_status rs_server_submit(rs_server* s, uint32_t graph_id, const rs_query* q, u
       s->st.rejected++;
       return RS_ENOMEM;
     }
-    a->group_bytes = table_lo_bytes(m) + table_z_bytes(n, a->plan.kq) + table_q_bytes(m, a->plan.k, a->plan.kq) +
-                     table_need_bytes(m, a->plan.k) + 8 * (1ull << a->plan.k) + 2048;
+    a->group_bytes = batch_query_bytes(m, n, a->plan);
     a->ticket = s->next_ticket++;
     a->graph_id = graph_id;
     a->q = *q;
@@ -384,7 +459,9 @@ rs_status rs_server_submit(rs_server* s, uint32_t graph_id, const rs_query* q, u
       memset(a->motif, 0, sizeof(a->motif));
       for (uint32_t c = 0; c < g->info.n_colours; ++c) a->motif[c] = q->motif_count[c];
     }
-    a->work = (a->plan.it_end - a->plan.it_begin) * (uint64_t)(a->plan.k - 1) * m;
+    a->per_it = (uint64_t)(a->plan.k - 1) * m;
+    a->next_it = a->plan.it_begin;
+    a->work = (a->plan.it_end - a->plan.it_begin) * a->per_it;
     a->t_submit = Clock::now();
     const bool trivial = m == 0 || a->plan.k > n || a->plan.it_end == a->plan.it_begin;
     if (trivial) {  // F = 0 exactly, nothing to run

@@ -249,3 +249,25 @@ def test_batch_config4_mix_vs_oracle():
         res, st = R.run_batch([gd] * len(qs), qs)
         assert st == R.RS_OK
         assert [r.fingerprint for r in res] == want, rep
+
+
+def test_lookback_counting_keeps_results():
+    """With look-back counting on, the batched path (eager and hipGraph) and
+    the plain path give the same fingerprints; the counters read back."""
+    gs = graphs()
+    gds = [R.Graph.from_inputs(g) for g in gs[:2]]
+    qs = mixed_queries(12, 4, seed=29, k_range=(3, 9))
+    which = [gds[i % 2] for i in range(len(qs))]
+    want = [plain(gd, q) for gd, q in zip(which, qs)]
+    R.lookback_count(True)
+    try:
+        for no_graph in (1, 0):
+            res, st = R.run_batch(which, qs, tuning=R.Tuning(no_graph=no_graph))
+            assert st == R.RS_OK and [r.fingerprint for r in res] == want
+        assert [plain(gd, q) for gd, q in zip(which, qs)] == want
+        rec, rounds = R.lookback_get()
+        assert rec >= 0 and rounds >= 0
+    finally:
+        R.lookback_count(False)
+    res, st = R.run_batch(which, qs)
+    assert [r.fingerprint for r in res] == want

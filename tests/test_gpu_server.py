@@ -189,3 +189,38 @@ def test_server_config5_stream_vs_oracle():
     st = srv.stats()
     assert st["completed"] == len(arrivals)
     srv.close()
+
+
+def test_server_chunk_boundary_slices():
+    """Queries whose work exceeds the group cap run as slices of whole
+    64-iteration chunks in successive groups (their fingerprints XOR to the
+    query's); a small query that arrives while a long one is being sliced
+    joins the next group and completes first. Every result equals the
+    oracle's and the plain path's."""
+    g = graphs()[0]  # m = 4000
+    gd = R.Graph.from_inputs(g)
+    r = np.random.default_rng(23)
+    qs = [inputs.Query(k=int(r.integers(7, 11)), delta=int(r.integers(0, 6)), seed=int(r.integers(0, 2**62)),
+                       motif=inputs.random_motif(8, 4, r) if i % 3 == 1 else None) for i in range(10)]
+    qs = [dataclasses.replace(q, k=8) if q.motif is not None else q for q in qs]
+    big = inputs.Query(k=12, delta=3, seed=5)
+    small = inputs.Query(k=4, delta=2, seed=6)
+    allq = qs + [big, small]
+    want = oracle_fps([(g, q) for q in allq])
+    assert [plain(gd, q) for q in allq] == want
+    say("[server] slices: 10 queries of k 7..10, then k=12 followed by k=4, cap 1e7 edge-updates")
+    srv = R.Server(hbm_budget=8 << 30, group_edge_updates=10_000_000, streams=1)
+    gid = srv.add_graph(gd)
+    tickets = [srv.submit(gid, q) for q in qs]
+    got = [srv.poll(t, wait_ms=60000) for t in tickets]
+    assert [x.fingerprint for x in got] == want[:10]
+    t_big = srv.submit(gid, big)
+    time.sleep(0.002)
+    t_small = srv.submit(gid, small)
+    r_small = srv.poll(t_small, wait_ms=60000)
+    r_big = srv.poll(t_big, wait_ms=60000)
+    assert r_big.fingerprint == want[10] and r_small.fingerprint == want[11]
+    assert r_small.device_ms < r_big.device_ms  # latencies: the small one finished first
+    st = srv.stats()
+    assert st["completed"] == 12 and st["slices"] > 12
+    srv.close()
