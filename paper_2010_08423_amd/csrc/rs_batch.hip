@@ -290,6 +290,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
   c.lo = U.lo;
   c.q = U.q;
   c.z = U.z;
+  c.d = nullptr;
   c.pp = U.pp + ch * U.p_stride;
   c.pc = U.pc + ch * U.p_stride;
   c.cb = U.cb + (uint64_t)ch * kLanes;

@@ -192,13 +192,14 @@ __global__ __launch_bounds__(256) void k_compact_bounds(const uint32_t* __restri
 // Grid-stride over the entries of every level.
 template <int KQ>
 __global__ __launch_bounds__(256) void k_compact_rows(CompactArgs a, const uint64_t* __restrict__ z, uint64_t seed_v,
-                                                      const uint64_t* __restrict__ seed_p, EdgeFilter f) {
+                                                      const uint64_t* __restrict__ seed_p, EdgeFilter f,
+                                                      uint32_t y_first) {
   const uint64_t seed = seed_p ? *seed_p : seed_v;  // from a batch descriptor, read at run time
   __shared__ uint64_t lds[4][16][kLanes];
   const uint32_t lane = threadIdx.x & 63u;
   uint64_t* tab = &lds[threadIdx.x >> 6][0][lane];
   tab[0] = 0;
-  const uint32_t y = blockIdx.y;
+  const uint32_t y = blockIdx.y + y_first;
   const uint32_t l = y + 2;
   const LevelList L = a.list(y);
   const uint32_t n = a.count[y];
@@ -275,14 +276,14 @@ hipError_t launch_compact_bounds(const CompactArgs& a, uint32_t E, uint32_t tile
 }
 
 hipError_t launch_compact_rows(const CompactArgs& a, const uint64_t* z, uint64_t seed, const uint64_t* seed_p,
-                               const EdgeFilter& f, uint32_t kq, hipStream_t st) {
-  if (!a.m || a.k < 3) return hipSuccess;
-  const dim3 g(std::min<uint32_t>(cdiv(a.m, 256), 2048), a.k - 1), b(256);
+                               const EdgeFilter& f, uint32_t kq, hipStream_t st, uint32_t y_first) {
+  if (!a.m || a.k < 3 || y_first >= a.k - 1) return hipSuccess;
+  const dim3 g(std::min<uint32_t>(cdiv(a.m, 256), 2048), a.k - 1 - y_first), b(256);
   switch (kq) {
-    case 4: hipLaunchKernelGGL(k_compact_rows<4>, g, b, 0, st, a, z, seed, seed_p, f); break;
-    case 8: hipLaunchKernelGGL(k_compact_rows<8>, g, b, 0, st, a, z, seed, seed_p, f); break;
-    case 12: hipLaunchKernelGGL(k_compact_rows<12>, g, b, 0, st, a, z, seed, seed_p, f); break;
-    case 16: hipLaunchKernelGGL(k_compact_rows<16>, g, b, 0, st, a, z, seed, seed_p, f); break;
+    case 4: hipLaunchKernelGGL(k_compact_rows<4>, g, b, 0, st, a, z, seed, seed_p, f, y_first); break;
+    case 8: hipLaunchKernelGGL(k_compact_rows<8>, g, b, 0, st, a, z, seed, seed_p, f, y_first); break;
+    case 12: hipLaunchKernelGGL(k_compact_rows<12>, g, b, 0, st, a, z, seed, seed_p, f, y_first); break;
+    case 16: hipLaunchKernelGGL(k_compact_rows<16>, g, b, 0, st, a, z, seed, seed_p, f, y_first); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -202,6 +202,12 @@ double scan_bytes(const NeedCounts& nc, uint64_t m, uint32_t kq, uint64_t chunks
   return (1024.0 * (double)nc.live_needed + stores) * (double)chunks + 13.0 * (double)nc.kept +
          8.0 * kq * (double)nc.live_needed;
 }
+// Level 3 from window rows: no gathers; the q, D and source z rows of the
+// product entries.
+double drows_bytes(const NeedCounts& nc, uint32_t kq, uint64_t chunks) {
+  const double stores = 512.0 * (double)(nc.ref_slots + nc.ref_lead);
+  return stores * (double)chunks + 13.0 * (double)nc.kept + 24.0 * kq * (double)nc.live_needed;
+}
 double top_bytes(const NeedCounts& nc, uint64_t m, uint32_t kq, uint64_t chunks, bool first) {
   if (first) return 8.0 * (double)m + 16.0 * kq * (double)m;
   return 1024.0 * (double)nc.live * (double)chunks + 8.0 * (double)nc.live + 8.0 * kq * (double)nc.live;
@@ -234,6 +240,7 @@ PlainSizes plain_sizes(uint64_t m, uint64_t n, const QueryPlan& qp, const Tuning
   // of their compacted lists
   s.q = k == 2 ? table_q_bytes(m, k, kq) : 0;
   s.lists = k >= 3 ? compact_bytes(m, k, kq) : 0;
+  s.rr = k >= 4 && m ? rrows_bytes(m, kq) : 0;
   s.p = 8 * (m + n) * 64 * cpl;
   s.partial = 8 * 64 * cpl * (uint64_t)tblocks;
   s.fsum = 8 * (1ull << k);
@@ -248,6 +255,9 @@ PlainSizes plain_sizes(uint64_t m, uint64_t n, const QueryPlan& qp, const Tuning
     const uint32_t E = tu.edges_per_tile;
     s.run_w2 = scan_waves(kq, E, true, (uint32_t)tiles, (uint32_t)cpl, tu.waves_per_block);
     s.run_w3 = scan_waves(kq, E, false, (uint32_t)tiles, (uint32_t)cpl, tu.waves_per_block);
+    // level 3 from window rows runs on the grid of levels >= 3: it must fit as well
+    if (k >= 4)
+      s.run_w3 = std::min(s.run_w3, scan_waves(kq, E, false, (uint32_t)tiles, (uint32_t)cpl, tu.waves_per_block, true));
     s.run_stride = std::max(s.run_w2, s.run_w3) + 1;
     const uint64_t levels = k - 2, nb = (tiles + 1023) / 1024;
     s.run_pre = 4 * tiles * levels;
@@ -267,7 +277,7 @@ PlainSizes plain_sizes(uint64_t m, uint64_t n, const QueryPlan& qp, const Tuning
 
 uint64_t PlainSizes::total() const {
   return lo + z + q + 2 * p + partial + fsum + 64 + ref + need + cover + 2 * records + run_pre + run_bsum + run_boff +
-         run_bounds + lists + dv + smask + tmask + rmask + fine_t + fine_z + fine_r;
+         run_bounds + lists + rr + dv + smask + tmask + rmask + fine_t + fine_z + fine_r;
 }
 
 uint64_t plain_footprint(const rs_graph* g, const QueryPlan& qp, const Tuning& tu) {
@@ -306,6 +316,7 @@ static rs_status acquire_buffers(PlainWorkspace& ws, const PlainSizes& sz, uint6
     carve(ws.run_boff, sz.run_boff);
     carve(ws.run_bounds, sz.run_bounds);
     carve(ws.lists, sz.lists);
+    carve(ws.rr, sz.rr);
     carve(ws.dv, sz.dv);
     carve(ws.smask, sz.smask);
     carve(ws.tmask, sz.tmask);
@@ -338,7 +349,7 @@ static rs_status acquire_buffers(PlainWorkspace& ws, const PlainSizes& sz, uint6
       ws.need.reserve(sz.need, st, false) || ws.cov_diff.reserve(sz.cover, st, false) ||
       ws.run_pre.reserve(sz.run_pre, st, false) || ws.run_bsum.reserve(sz.run_bsum, st, false) ||
       ws.run_boff.reserve(sz.run_boff, st, false) || ws.run_bounds.reserve(sz.run_bounds, st, false) ||
-      (sz.lists && ws.lists.reserve(sz.lists, st, false)) || (sz.dv && ws.dv.reserve(sz.dv, st, false)) ||
+      (sz.lists && ws.lists.reserve(sz.lists, st, false)) || (sz.rr && ws.rr.reserve(sz.rr, st, false)) || (sz.dv && ws.dv.reserve(sz.dv, st, false)) ||
       (sz.smask && ws.smask.reserve(sz.smask, st, false)) || (sz.tmask && ws.tmask.reserve(sz.tmask, st, false)) ||
       (sz.rmask && ws.rmask.reserve(sz.rmask, st, false)) ||
       (sz.fine_t && ws.fine_t.reserve(sz.fine_t, st, false)) || (sz.fine_z && ws.fine_z.reserve(sz.fine_z, st, false)) ||
@@ -375,6 +386,7 @@ rs_status run_plain(rs_graph* g, PlainWorkspace& ws, const QueryPlan& qp, const 
     const uint64_t tiles = (m + E - 1) / E;
     const uint64_t p_elems = (m + n) * 64;
     const PlainSizes sz = plain_sizes(m, n, qp, tu, ex);
+    const bool fold2 = sz.rr != 0;  // k >= 4: level 2 folded into level 3 (rs_rrows.hip)
     RS_TRY(acquire_buffers(ws, sz, p_elems, st));
     // constraints (host arrays, copied in) and fine-grained output buffers
     const uint32_t* dv = nullptr;
@@ -520,7 +532,11 @@ rs_status run_plain(rs_graph* g, PlainWorkspace& ws, const QueryPlan& qp, const 
       // of every edge, with the source and target constraints applied
       ProfScope ps(KC_QTABLE, st, (double)m * (12.0 + 8.0 * kq * (k - 1)), timed);
       if (k >= 3) {
-        RS_HIP(launch_compact_rows(ca, ws.z.as<uint64_t>(), qp.seed, nullptr, filt, kq, st));
+        // (level 2's own rows are not used when it is folded into level 3)
+        RS_HIP(launch_compact_rows(ca, ws.z.as<uint64_t>(), qp.seed, nullptr, filt, kq, st, fold2 ? 1 : 0));
+        // level 2 as iteration-independent prefix rows, level 3's window rows
+        if (fold2) RS_HIP(launch_rrows(ca, G.in_off.as<uint32_t>(), ws.z.as<uint64_t>(), qp.seed, filt, kq,
+                                       ws.rr.as<uint8_t>(), st));
       } else {
         RS_HIP(launch_qtable(G.e_src.as<uint32_t>(), G.e_dst.as<uint32_t>(), G.e_t.as<uint32_t>(),
                              ws.z.as<uint64_t>(), ws.q.as<uint64_t>(), (uint32_t)m, qp, st));
@@ -540,6 +556,8 @@ rs_status run_plain(rs_graph* g, PlainWorkspace& ws, const QueryPlan& qp, const 
       uint64_t* cur = ws.p1.as<uint64_t>();
       for (uint32_t l = 2; l <= k; ++l) {
         const bool first = l == 2;
+        if (fold2 && first) continue;  // folded into level 3's window rows
+        const bool drows = fold2 && l == 3;
         if (l < k) {
           if (++ws.epoch >= (1u << 30)) {
             RS_HIP(launch_fill64(ws.agg.as<uint64_t>(), 0, ws.agg.bytes / 8, st));
@@ -548,7 +566,7 @@ rs_status run_plain(rs_graph* g, PlainWorkspace& ws, const QueryPlan& qp, const 
           }
           const LevelList Lc = ca.list(l - 2);
           ScanArgs a;
-          a.e_src = Lc.chi;  // level 2: the source of each entry
+          a.e_src = Lc.chi;  // level 2, and level 3 from window rows: the source of each entry
           a.e_out = Lc.cslot;
           a.hi = Lc.chi;
           a.lo = Lc.clo;
@@ -568,10 +586,12 @@ rs_status run_plain(rs_graph* g, PlainWorkspace& ws, const QueryPlan& qp, const 
           a.bounds = ws.run_bounds.as<uint32_t>() + (uint64_t)(l - 2) * run_stride;
           a.waves = first ? run_w2 : run_w3;
           a.count = ca.count + (l - 2);
+          if (drows) a.d = ca.list(0).cq;  // the D rows, indexed like level 3's entries
           if (tr) RS_HIP(launch_fill64(ws.lb_stats.as<uint64_t>(), 0, 2, st));
           if (tr || count_lb) a.lb_stats = ws.lb_stats.as<unsigned long long>();
           {
-            ProfScope ps(first ? KC_FIRST : KC_SCAN, st, scan_bytes(ncs[l], m, kq, gc, first), timed);
+            ProfScope ps(first || drows ? KC_FIRST : KC_SCAN, st,
+                         drows ? drows_bytes(ncs[l], kq, gc) : scan_bytes(ncs[l], m, kq, gc, first), timed);
             RS_HIP(launch_scan(a, first, kq, gc, tu, st));
           }
           if (tr) {

@@ -91,7 +91,8 @@ struct ScanArgs {
   const uint32_t* hi;     // P slot of the window end
   const uint32_t* lo;     // P slot of the window start
   const uint64_t* q;      // [m][kq] products z_{dst,j} * y_{e,l-1} for this level
-  const uint64_t* z;      // [n][kq] (level 2 only)
+  const uint64_t* z;      // [n][kq] (level 2, and level 3 from window rows)
+  const uint64_t* d = nullptr;  // level 3 from window rows: [entries][kq] D rows (else null)
   const uint64_t* p_prev; // [(m+n)*64] per chunk
   uint64_t* p_cur;
   uint64_t p_stride;      // elements between consecutive chunks' P arrays
@@ -114,7 +115,8 @@ struct ScanArgs {
 uint32_t resident_blocks(const void* kern, uint32_t threads, size_t lds);
 // Waves per chunk of a prefix-level launch of this shape (grid width times
 // waves per block).
-uint32_t scan_waves(uint32_t kq, uint32_t E, bool first, uint32_t n_tiles, uint32_t chunks, uint32_t wpb);
+uint32_t scan_waves(uint32_t kq, uint32_t E, bool first, uint32_t n_tiles, uint32_t chunks, uint32_t wpb,
+                    bool drows = false);
 // Work-balanced run bounds of the prefix levels 2 .. 2 + levels - 1 of a
 // query: per level (need flags at need + y * need_stride_b) the per-tile
 // costs, their prefix (scratch pre[levels][n_tiles], bsum and boff
@@ -240,10 +242,18 @@ __device__ __forceinline__ bool edge_excluded(const EdgeFilter& f, uint32_t l, u
   return (l == 2 && f.smask && !f.smask[src]) || (l == k && f.tmask && !f.tmask[dst]) ||
          (f.rmask && (f.rmask[src] | f.rmask[dst])) || (f.t_max && t > f.t_max);
 }
-// Product rows of the lists (seed dependent: seed, or *seed_p read on the
-// device when seed_p is not null), 0 for the edges f excludes.
+// Level 2 folded into level 3 (k >= 4; rs_rrows.hip): the iteration-
+// independent prefix rows of level 2 and, for level 3's product entries, their
+// window rows D written over list(0)'s row array, with each level-3 entry's
+// source written over list(1)'s window-end array. buf holds rrows_bytes(m, kq).
+uint64_t rrows_bytes(uint64_t m, uint32_t kq);
+hipError_t launch_rrows(const CompactArgs& ca, const uint32_t* in_off, const uint64_t* z, uint64_t seed,
+                        const EdgeFilter& f, uint32_t kq, uint8_t* buf, hipStream_t st);
+// Product rows of the lists from level index y_first on (seed dependent: seed,
+// or *seed_p read on the device when seed_p is not null), 0 for the edges f
+// excludes.
 hipError_t launch_compact_rows(const CompactArgs& a, const uint64_t* z, uint64_t seed, const uint64_t* seed_p,
-                               const EdgeFilter& f, uint32_t kq, hipStream_t st);
+                               const EdgeFilter& f, uint32_t kq, hipStream_t st, uint32_t y_first = 0);
 // Fine-grained last level and slot sums (rs_fine.hip).
 hipError_t launch_top_fine(const TopArgs& a, bool first_level, uint32_t kq, uint32_t chunks, const Tuning& tu,
                            uint64_t* T, hipStream_t st);
@@ -381,6 +391,7 @@ struct PlainWorkspace {
   DevBuf run_pre, run_bsum, run_boff, run_bounds;  // work-balanced runs of the prefix levels
   DevBuf cov_diff;  // window-cover scratch of the flags: difference array and block sums
   DevBuf lists;     // compacted edge lists of levels 2..k and their scratch (k >= 3)
+  DevBuf rr;        // level-2 prefix rows (k >= 4)
   DevBuf dv, smask, tmask, rmask;  // constraints: per-vertex resting times, source, target and removed masks
   DevBuf fine_t, fine_z, fine_r;   // fine-grained outputs: per-edge sums, per-slot zeta, reach times
   uint32_t epoch = 0;
@@ -391,7 +402,7 @@ struct PlainWorkspace {
   uint64_t bytes() const {
     uint64_t t = 0;
     for (const DevBuf* b : {&lo, &z, &q, &p0, &p1, &partial, &agg, &incl, &fsum, &out, &ref, &need, &lb_stats,
-                            &run_pre, &run_bsum, &run_boff, &run_bounds, &cov_diff, &lists, &dv, &smask, &tmask, &rmask,
+                            &run_pre, &run_bsum, &run_boff, &run_bounds, &cov_diff, &lists, &rr, &dv, &smask, &tmask, &rmask,
                             &fine_t, &fine_z, &fine_r})
       t += b->bytes;
     return t;
@@ -399,7 +410,7 @@ struct PlainWorkspace {
   void release() {
     if (scratch) return;  // borrowed buffers are never freed
     for (DevBuf* b : {&lo, &z, &q, &p0, &p1, &partial, &agg, &incl, &fsum, &out, &ref, &need, &lb_stats,
-                      &run_pre, &run_bsum, &run_boff, &run_bounds, &cov_diff, &lists, &dv, &smask, &tmask, &rmask, &fine_t,
+                      &run_pre, &run_bsum, &run_boff, &run_bounds, &cov_diff, &lists, &rr, &dv, &smask, &tmask, &rmask, &fine_t,
                       &fine_z, &fine_r})
       b->release();
     if (ev0) (void)hipEventDestroy(ev0);
@@ -416,6 +427,7 @@ struct PlainSizes {
   uint64_t lo, z, q, p, partial, fsum, ref, need, cover, records;
   uint64_t run_pre, run_bsum, run_boff, run_bounds;
   uint64_t lists;                  // compacted lists (k >= 3; the q table is used only at k = 2)
+  uint64_t rr;                     // level 2 folded into level 3 (k >= 4): prefix rows and block carries
   uint64_t dv, smask, tmask, rmask;  // constraints (0 when absent)
   uint64_t fine_t, fine_z, fine_r; // fine-grained outputs (0 when not asked)
   uint32_t run_w2, run_w3, run_stride;  // waves per chunk of level 2 and of levels >= 3; bounds stride

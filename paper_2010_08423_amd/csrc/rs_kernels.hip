@@ -19,11 +19,11 @@ namespace rs {
 // ends, through the look-back records. A run whose predecessor has not
 // published after a bounded wait recomputes that run's tail (see look_back).
 // ---------------------------------------------------------------------------
-template <int KQ, int E, bool FIRST>
+template <int KQ, int E, bool FIRST, bool DR = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_scan(
     const uint32_t* __restrict__ e_src, const uint32_t* __restrict__ e_out,
     const uint32_t* __restrict__ hi_idx, const uint32_t* __restrict__ lo_idx,
-    const uint64_t* __restrict__ q, const uint64_t* __restrict__ z,
+    const uint64_t* __restrict__ q, const uint64_t* __restrict__ z, const uint64_t* __restrict__ d,
     const uint64_t* __restrict__ p_prev, uint64_t* __restrict__ p_cur, uint64_t p_stride,
     uint64_t chunk_base, uint32_t m, uint32_t n_tiles, uint32_t epoch,
     uint64_t* __restrict__ agg, uint64_t* __restrict__ incl, const uint8_t* __restrict__ need,
@@ -44,6 +44,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
   c.lo = lo_idx;
   c.q = q;
   c.z = z;
+  c.d = d;
   c.pp = p_prev + (uint64_t)chunk * p_stride;
   c.pc = p_cur + (uint64_t)chunk * p_stride;
   c.cb = chunk_base + (uint64_t)chunk * kLanes;
@@ -58,7 +59,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
   c.lb_stats = lb_stats;
   c.bounds = bounds;
   const uint32_t waves = gridDim.x * (blockDim.x >> 6);
-  scan_level<KQ, E, FIRST>(c, blockIdx.x * (blockDim.x >> 6) + wv, waves, lane, mk, tab);
+  scan_level<KQ, E, FIRST, DR>(c, blockIdx.x * (blockDim.x >> 6) + wv, waves, lane, mk, tab);
 }
 
 // ---------------------------------------------------------------------------
@@ -526,33 +527,38 @@ hipError_t launch_qtable(const uint32_t* e_src, const uint32_t* e_dst, const uin
   return hipGetLastError();
 }
 
-template <int KQ, int E, bool FIRST>
+template <int KQ, int E, bool FIRST, bool DR = false>
 static uint32_t scan_blocks_one(uint32_t n_tiles, uint32_t chunks, uint32_t wpb) {
   const size_t lds = (size_t)wpb * 16 * kLanes * 8;
-  const uint32_t fit = std::max(1u, resident_blocks((const void*)k_scan<KQ, E, FIRST>, 64 * wpb, lds) / chunks);
+  const uint32_t fit =
+      std::max(1u, resident_blocks((const void*)k_scan<KQ, E, FIRST, DR>, 64 * wpb, lds) / chunks);
   return std::min(div_up(n_tiles, wpb), fit);
 }
 
-template <int KQ, int E, bool FIRST>
+template <int KQ, int E, bool FIRST, bool DR = false>
 static void scan_one(const ScanArgs& a, uint32_t chunks, uint32_t wpb, hipStream_t st) {
   const size_t lds = (size_t)wpb * 16 * kLanes * 8;
   // with run bounds the grid is the one the bounds were cut for
-  const uint32_t gx = a.bounds ? a.waves / wpb : scan_blocks_one<KQ, E, FIRST>(a.n_tiles, chunks, wpb);
+  const uint32_t gx = a.bounds ? a.waves / wpb : scan_blocks_one<KQ, E, FIRST, DR>(a.n_tiles, chunks, wpb);
   dim3 g(gx, chunks), b(64 * wpb);
-  hipLaunchKernelGGL((k_scan<KQ, E, FIRST>), g, b, lds, st, a.e_src, a.e_out, a.hi, a.lo, a.q, a.z,
+  hipLaunchKernelGGL((k_scan<KQ, E, FIRST, DR>), g, b, lds, st, a.e_src, a.e_out, a.hi, a.lo, a.q, a.z, a.d,
                      a.p_prev, a.p_cur, a.p_stride, a.chunk_base, a.m, a.n_tiles, a.epoch, a.agg,
                      a.incl, a.need, a.lb_stats, a.bounds, a.count);
 }
 
-uint32_t scan_waves(uint32_t kq, uint32_t E, bool first, uint32_t n_tiles, uint32_t chunks, uint32_t wpb) {
+uint32_t scan_waves(uint32_t kq, uint32_t E, bool first, uint32_t n_tiles, uint32_t chunks, uint32_t wpb,
+                    bool drows) {
   uint32_t b = 0;
   auto pick = [&](auto kqc) {
     constexpr int K = decltype(kqc)::value;
     if (E == 8)
-      b = first ? scan_blocks_one<K, 8, true>(n_tiles, chunks, wpb) : scan_blocks_one<K, 8, false>(n_tiles, chunks, wpb);
+      b = first ? scan_blocks_one<K, 8, true>(n_tiles, chunks, wpb)
+                : (drows ? scan_blocks_one<K, 8, false, true>(n_tiles, chunks, wpb)
+                         : scan_blocks_one<K, 8, false>(n_tiles, chunks, wpb));
     else
       b = first ? scan_blocks_one<K, 16, true>(n_tiles, chunks, wpb)
-                : scan_blocks_one<K, 16, false>(n_tiles, chunks, wpb);
+                : (drows ? scan_blocks_one<K, 16, false, true>(n_tiles, chunks, wpb)
+                         : scan_blocks_one<K, 16, false>(n_tiles, chunks, wpb));
   };
   switch (kq) {
     case 4: pick(std::integral_constant<int, 4>{}); break;
@@ -567,9 +573,13 @@ template <int KQ>
 static bool scan_kq(const ScanArgs& a, bool first, uint32_t E, uint32_t chunks, uint32_t wpb,
                     hipStream_t st) {
   if (E == 8) {
-    if (first) scan_one<KQ, 8, true>(a, chunks, wpb, st); else scan_one<KQ, 8, false>(a, chunks, wpb, st);
+    if (first) scan_one<KQ, 8, true>(a, chunks, wpb, st);
+    else if (a.d) scan_one<KQ, 8, false, true>(a, chunks, wpb, st);
+    else scan_one<KQ, 8, false>(a, chunks, wpb, st);
   } else if (E == 16) {
-    if (first) scan_one<KQ, 16, true>(a, chunks, wpb, st); else scan_one<KQ, 16, false>(a, chunks, wpb, st);
+    if (first) scan_one<KQ, 16, true>(a, chunks, wpb, st);
+    else if (a.d) scan_one<KQ, 16, false, true>(a, chunks, wpb, st);
+    else scan_one<KQ, 16, false>(a, chunks, wpb, st);
   } else {
     return false;
   }

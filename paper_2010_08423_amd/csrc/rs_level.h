@@ -114,7 +114,8 @@ struct TileCtx {
   const uint32_t* hi;
   const uint32_t* lo;
   const uint64_t* q;   // this level's [m][KQ] rows
-  const uint64_t* z;   // [n][KQ] rows (level 2)
+  const uint64_t* z;   // [n][KQ] rows (level 2; level 3 from window rows)
+  const uint64_t* d;   // level 3 from window rows: [entries][KQ] L-independent window rows
   const uint64_t* pp;  // previous level, this chunk
   uint64_t* pc;        // this level, this chunk
   uint64_t cb;         // first iteration of the chunk
@@ -259,12 +260,15 @@ __device__ __forceinline__ void tile_inputs(const TileCtx& c, uint32_t e0, uint3
   }
 }
 
-// c_l(e) for edge i of the tile.
-template <int KQ, int E, bool FIRST>
+// c_l(e) for edge i of the tile. DR (level 3 from window rows): the window
+// is z^L_a * D^L(e), formed from the source's z row and the entry's D row.
+template <int KQ, int E, bool FIRST, bool DR = false>
 __device__ __forceinline__ uint64_t edge_value(const TileCtx& c, uint32_t e, uint32_t a, uint64_t w,
                                                const uint32_t (&mk)[6], uint64_t* tab) {
   const uint64_t aL = subset_xor<KQ>(as_const(c.q) + (uint64_t)e * KQ, c.cb, mk);
-  const uint64_t wv = FIRST ? subset_xor<KQ>(as_const(c.z) + (uint64_t)a * KQ, c.cb, mk) : w;
+  uint64_t wv = w;
+  if (FIRST || DR) wv = subset_xor<KQ>(as_const(c.z) + (uint64_t)a * KQ, c.cb, mk);
+  if (DR) wv = gf_mul(tab, wv, subset_xor<KQ>(as_const(c.d) + (uint64_t)e * KQ, c.cb, mk));
   return gf_mul(tab, aL, wv);
 }
 
@@ -273,7 +277,7 @@ __device__ __forceinline__ uint64_t edge_value(const TileCtx& c, uint32_t e, uin
 // inside the tile, else from the tile start). *started tells whether a
 // segment starts inside the tile, i.e. whether the value is inclusive. A
 // rarely taken path, written edge by edge to keep register use low.
-template <int KQ, int E, bool FIRST>
+template <int KQ, int E, bool FIRST, bool DR = false>
 __device__ uint64_t tile_open_part(const TileCtx& c, uint32_t j, uint32_t lane, const uint32_t (&mk)[6],
                                    uint64_t* tab, bool* started) {
   cu32* hi_idx = as_const(c.hi);
@@ -289,12 +293,12 @@ __device__ uint64_t tile_open_part(const TileCtx& c, uint32_t j, uint32_t lane, 
       acc = 0;
       st = true;
     }
-    if (!FIRST && hi_idx[e] == lo_idx[e]) continue;  // empty window: contributes zero
-    if (!(c.need[e] & 4u)) continue;                  // reaches no read slot
-    const uint64_t w = FIRST ? 0
-                             : p_load(c.pp + (uint64_t)hi_idx[e] * kLanes + lane) ^
-                                   p_load(c.pp + (uint64_t)lo_idx[e] * kLanes + lane);
-    acc ^= edge_value<KQ, E, FIRST>(c, e, FIRST ? e_src[e] : 0u, w, mk, tab);
+    if (!FIRST && !DR && hi_idx[e] == lo_idx[e]) continue;  // empty window: contributes zero
+    if (!(c.need[e] & 4u)) continue;                         // reaches no read slot
+    const uint64_t w = (FIRST || DR) ? 0
+                                     : p_load(c.pp + (uint64_t)hi_idx[e] * kLanes + lane) ^
+                                           p_load(c.pp + (uint64_t)lo_idx[e] * kLanes + lane);
+    acc ^= edge_value<KQ, E, FIRST, DR>(c, e, (FIRST || DR) ? e_src[e] : 0u, w, mk, tab);
   }
   *started = st;
   return acc;
@@ -320,7 +324,7 @@ constexpr uint32_t kFallbackSpins = 4096;
 // d/64 memory round trips. A predecessor that stays unpublished is recomputed
 // here, tile by tile from the end of its run, so every wait is bounded
 // whatever order the waves run in.
-template <int KQ, int E, bool FIRST>
+template <int KQ, int E, bool FIRST, bool DR = false>
 __device__ uint64_t look_back(const TileCtx& c, uint32_t run, uint32_t len, uint32_t lane, const uint32_t (&mk)[6],
                               uint64_t* tab) {
   uint64_t carry = 0;
@@ -398,7 +402,7 @@ __device__ uint64_t look_back(const TileCtx& c, uint32_t run, uint32_t len, uint
       bool started = false;
       const int64_t first = run_begin(c, top, len);
       for (int64_t j = (int64_t)run_begin(c, top + 1, len) - 1; j >= first && !started; --j)
-        carry ^= tile_open_part<KQ, E, FIRST>(c, (uint32_t)j, lane, mk, tab, &started);
+        carry ^= tile_open_part<KQ, E, FIRST, DR>(c, (uint32_t)j, lane, mk, tab, &started);
       if (started) break;
       --top;
       spins = 0;
@@ -417,18 +421,20 @@ template <int KQ, int E>
 struct TileIn {
   uint32_t slot[E], ia[E];
   uint64_t w[E];
-  RowBlock<KQ, E> qr, zr;  // product rows; substitution rows (level 2)
+  RowBlock<KQ, E> qr, zr;  // product rows; substitution rows of the sources (level 2, level 3 from D rows)
+  RowBlock<KQ, E> dr;      // level 3 from window rows: the entries' D rows
   IdxN<E / 4> need;        // store flags, four edges per word
 };
 
-template <int KQ, int E, bool FIRST>
+template <int KQ, int E, bool FIRST, bool DR = false>
 __device__ __forceinline__ void load_tile(const TileCtx& c, uint32_t tile, uint32_t lane, TileIn<KQ, E>& in) {
   const uint32_t e0 = tile * (uint32_t)E;
   const uint32_t ne = min((uint32_t)E, c.m - e0);
   in.need = load_idx<E / 4>((const uint32_t*)(c.need + e0));
   load_qrows<KQ, E>(in.qr, c.q, e0, lane);
-  if (FIRST) load_zrows<KQ, E>(in.zr, c.z, c.e_src, e0, ne, lane);
-  tile_inputs<KQ, E, FIRST>(c, e0, ne, lane, in.need, in.slot, in.ia, in.w);
+  if (FIRST || DR) load_zrows<KQ, E>(in.zr, c.z, c.e_src, e0, ne, lane);
+  if (DR) load_qrows<KQ, E>(in.dr, c.d, e0, lane);
+  tile_inputs<KQ, E, FIRST || DR>(c, e0, ne, lane, in.need, in.slot, in.ia, in.w);
 }
 
 // One prefix level (2..k-1) over the run of tiles of wave w of W: the tiles
@@ -444,7 +450,7 @@ __device__ __forceinline__ void load_tile(const TileCtx& c, uint32_t tile, uint3
 // slot) holds 0; writing it here lets P buffers be reused across graphs
 // without clearing. Only slots that some window of the next level reads are
 // stored; empty windows gather the zero row.
-template <int KQ, int E, bool FIRST>
+template <int KQ, int E, bool FIRST, bool DR = false>
 __device__ __forceinline__ void scan_run(const TileCtx& c, uint32_t w, uint32_t W, uint32_t lane,
                                          const uint32_t (&mk)[6], uint64_t* tab) {
   const uint32_t R = (c.n_tiles + W - 1) / W;  // tiles per run when the runs are of equal length
@@ -460,7 +466,7 @@ __device__ __forceinline__ void scan_run(const TileCtx& c, uint32_t w, uint32_t 
   auto slot_ptr = [&](uint32_t slot) { return c.pc + (uint64_t)slot * kLanes + lane; };
 
   TileIn<KQ, E> cur;
-  load_tile<KQ, E, FIRST>(c, t0, lane, cur);
+  load_tile<KQ, E, FIRST, DR>(c, t0, lane, cur);
   for (uint32_t tile = t0;;) {
     const uint32_t e0 = tile * (uint32_t)E;
     const TileIn<KQ, E>& in = cur;
@@ -488,14 +494,16 @@ __device__ __forceinline__ void scan_run(const TileCtx& c, uint32_t w, uint32_t 
         }
         if (needs(i)) {
           const uint64_t aL = subset_xor<KQ, E>(in.qr, i, c.cb, mk);
-          const uint64_t wv = FIRST ? subset_xor<KQ, E>(in.zr, i, c.cb, mk) : in.w[i];
+          uint64_t wv = in.w[i];
+          if (FIRST || DR) wv = subset_xor<KQ, E>(in.zr, i, c.cb, mk);
+          if (DR) wv = gf_mul(tab, wv, subset_xor<KQ, E>(in.dr, i, c.cb, mk));  // z^L_src * D^L
           acc ^= gf_mul(tab, aL, wv);
         }
         if (flag(i) & 1u) p_store(slot_ptr(in.slot[i]), acc);
       }
     }
     if (tile + 1 >= t1) break;
-    load_tile<KQ, E, FIRST>(c, tile + 1, lane, cur);
+    load_tile<KQ, E, FIRST, DR>(c, tile + 1, lane, cur);
     ++tile;
   }
   if (!started) open_end = min(t1 * (uint32_t)E, m);
@@ -506,7 +514,7 @@ __device__ __forceinline__ void scan_run(const TileCtx& c, uint32_t w, uint32_t 
   if (next_cont)
     publish(started ? c.incl : c.agg, fi, lane, acc, rec_tag(c.epoch, started ? kFlagIncl : kFlagAgg));
   if (!cont) return;
-  const uint64_t carry = look_back<KQ, E, FIRST>(c, w, R, lane, mk, tab);
+  const uint64_t carry = look_back<KQ, E, FIRST, DR>(c, w, R, lane, mk, tab);
   if (next_cont && !started) publish(c.incl, fi, lane, carry ^ acc, rec_tag(c.epoch, kFlagIncl));
   if (!carry) return;
   // the run's leading segment part: its stored slots get the carry (same lane
@@ -656,13 +664,16 @@ __device__ __forceinline__ void scan_runs(const TileCtx& c, uint32_t w, uint32_t
 
 // The schedule of a prefix level: interleaved runs at level 2 without run
 // bounds, one contiguous run per wave otherwise.
-template <int KQ, int E, bool FIRST>
+template <int KQ, int E, bool FIRST, bool DR = false>
 __device__ __forceinline__ void scan_level(const TileCtx& c, uint32_t w, uint32_t W, uint32_t lane,
                                            const uint32_t (&mk)[6], uint64_t* tab) {
-  if (FIRST && !c.bounds)
-    scan_runs<KQ, E, FIRST>(c, w, W, lane, mk, tab);
-  else
-    scan_run<KQ, E, FIRST>(c, w, W, lane, mk, tab);
+  if constexpr (FIRST) {
+    if (!c.bounds) {
+      scan_runs<KQ, E, FIRST>(c, w, W, lane, mk, tab);
+      return;
+    }
+  }
+  scan_run<KQ, E, FIRST, DR>(c, w, W, lane, mk, tab);
 }
 
 // Last level k over edges [e0, e1): unreduced per-lane sum of c_k(e) into r.

@@ -234,7 +234,9 @@ def test_trace_lines(capfd):
     lines = [ln for ln in err.splitlines() if ln.startswith("[rs-trace]")]
     assert Ft == F
     prefix = [ln for ln in lines if " prefix level " in ln]
-    assert len(prefix) == q.k - 2, lines  # levels 2..k-1, one chunk group (32 iterations)
+    # levels 3..k-1 (k >= 4 folds level 2 into level 3's window rows), one chunk group (32 iterations)
+    assert len(prefix) == q.k - 3, lines
+    assert not any(" prefix level 2 " in ln for ln in prefix)
     assert all("look-back recomputes" in ln for ln in prefix)
     assert sum(" last level " in ln for ln in lines) == 1
     R.run(gd, q.k, q.delta, q.seed)
