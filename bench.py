@@ -46,7 +46,7 @@ def host_cores():
 # Sources whose change invalidates the committed HBM counter figures of the
 # level kernel (kernel code, launch shapes, defaults).
 KERNEL_SOURCES = ("rs_device.h", "rs_level.h", "rs_kernels.hip", "rs_engine.hip", "rs_internal.h", "rs_compact.hip",
-                  "rs_rrows.hip")
+                  "rs_rrows.hip", "rs_group.hip")
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "k_scan_chunglu_m1e6_k8_counters.md")
 SQ_FILE = os.path.join(ROOT, "profiles", "k_scan_chunglu_m1e6_k8_sq.md")
 

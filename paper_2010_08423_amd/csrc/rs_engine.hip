@@ -208,9 +208,12 @@ double drows_bytes(const NeedCounts& nc, uint32_t kq, uint64_t chunks) {
   const double stores = 512.0 * (double)(nc.ref_slots + nc.ref_lead);
   return stores * (double)chunks + 13.0 * (double)nc.kept + 24.0 * kq * (double)nc.live_needed;
 }
-double top_bytes(const NeedCounts& nc, uint64_t m, uint32_t kq, uint64_t chunks, bool first) {
+// units: the entries the last level runs over (its windows, grouped or not;
+// 0 = every non-empty window).
+double top_bytes(const NeedCounts& nc, uint64_t m, uint32_t kq, uint64_t chunks, bool first, uint64_t units = 0) {
   if (first) return 8.0 * (double)m + 16.0 * kq * (double)m;
-  return 1024.0 * (double)nc.live * (double)chunks + 8.0 * (double)nc.live + 8.0 * kq * (double)nc.live;
+  const double u = units ? (double)units : (double)nc.live;
+  return 1024.0 * u * (double)chunks + 8.0 * u + 8.0 * kq * u;
 }
 
 uint64_t table_lo_bytes(uint64_t m) { return 4 * (m + kEdgePad); }
@@ -241,6 +244,10 @@ PlainSizes plain_sizes(uint64_t m, uint64_t n, const QueryPlan& qp, const Tuning
   s.q = k == 2 ? table_q_bytes(m, k, kq) : 0;
   s.lists = k >= 3 ? compact_bytes(m, k, kq) : 0;
   s.rr = k >= 4 && m ? rrows_bytes(m, kq) : 0;
+  // the last level by distinct windows pays for its sort (once per query)
+  // when the last level runs for at least two groups of chunks
+  const uint64_t groups = (nchunks + cpl - 1) / cpl;
+  s.grp = k >= 3 && m && groups >= 2 && !(ex && ex->fine) ? group_bytes(m, n, kq) : 0;
   s.p = 8 * (m + n) * 64 * cpl;
   s.partial = 8 * 64 * cpl * (uint64_t)tblocks;
   s.fsum = 8 * (1ull << k);
@@ -277,7 +284,7 @@ PlainSizes plain_sizes(uint64_t m, uint64_t n, const QueryPlan& qp, const Tuning
 
 uint64_t PlainSizes::total() const {
   return lo + z + q + 2 * p + partial + fsum + 64 + ref + need + cover + 2 * records + run_pre + run_bsum + run_boff +
-         run_bounds + lists + rr + dv + smask + tmask + rmask + fine_t + fine_z + fine_r;
+         run_bounds + lists + rr + grp + dv + smask + tmask + rmask + fine_t + fine_z + fine_r;
 }
 
 uint64_t plain_footprint(const rs_graph* g, const QueryPlan& qp, const Tuning& tu) {
@@ -317,6 +324,7 @@ static rs_status acquire_buffers(PlainWorkspace& ws, const PlainSizes& sz, uint6
     carve(ws.run_bounds, sz.run_bounds);
     carve(ws.lists, sz.lists);
     carve(ws.rr, sz.rr);
+    carve(ws.grp, sz.grp);
     carve(ws.dv, sz.dv);
     carve(ws.smask, sz.smask);
     carve(ws.tmask, sz.tmask);
@@ -349,7 +357,8 @@ static rs_status acquire_buffers(PlainWorkspace& ws, const PlainSizes& sz, uint6
       ws.need.reserve(sz.need, st, false) || ws.cov_diff.reserve(sz.cover, st, false) ||
       ws.run_pre.reserve(sz.run_pre, st, false) || ws.run_bsum.reserve(sz.run_bsum, st, false) ||
       ws.run_boff.reserve(sz.run_boff, st, false) || ws.run_bounds.reserve(sz.run_bounds, st, false) ||
-      (sz.lists && ws.lists.reserve(sz.lists, st, false)) || (sz.rr && ws.rr.reserve(sz.rr, st, false)) || (sz.dv && ws.dv.reserve(sz.dv, st, false)) ||
+      (sz.lists && ws.lists.reserve(sz.lists, st, false)) || (sz.rr && ws.rr.reserve(sz.rr, st, false)) ||
+      (sz.grp && ws.grp.reserve(sz.grp, st, false)) || (sz.dv && ws.dv.reserve(sz.dv, st, false)) ||
       (sz.smask && ws.smask.reserve(sz.smask, st, false)) || (sz.tmask && ws.tmask.reserve(sz.tmask, st, false)) ||
       (sz.rmask && ws.rmask.reserve(sz.rmask, st, false)) ||
       (sz.fine_t && ws.fine_t.reserve(sz.fine_t, st, false)) || (sz.fine_z && ws.fine_z.reserve(sz.fine_z, st, false)) ||
@@ -387,6 +396,9 @@ rs_status run_plain(rs_graph* g, PlainWorkspace& ws, const QueryPlan& qp, const 
     const uint64_t p_elems = (m + n) * 64;
     const PlainSizes sz = plain_sizes(m, n, qp, tu, ex);
     const bool fold2 = sz.rr != 0;  // k >= 4: level 2 folded into level 3 (rs_rrows.hip)
+    GroupView gv{};                  // the last level by distinct windows (rs_group.hip)
+    bool grouped = false;
+    uint64_t top_units = 0;          // the last level's entries, when counted (profiling)
     RS_TRY(acquire_buffers(ws, sz, p_elems, st));
     // constraints (host arrays, copied in) and fine-grained output buffers
     const uint32_t* dv = nullptr;
@@ -537,6 +549,20 @@ rs_status run_plain(rs_graph* g, PlainWorkspace& ws, const QueryPlan& qp, const 
         // level 2 as iteration-independent prefix rows, level 3's window rows
         if (fold2) RS_HIP(launch_rrows(ca, G.in_off.as<uint32_t>(), ws.z.as<uint64_t>(), qp.seed, filt, kq,
                                        ws.rr.as<uint8_t>(), st));
+        // the last level's entries grouped by window
+        if (sz.grp) {
+          uint32_t n_last = 0, n_groups = 0;
+          RS_HIP(hipMemcpyAsync(&n_last, ca.count + (k - 2), 4, hipMemcpyDeviceToHost, st));
+          RS_HIP(hipStreamSynchronize(st));
+          gv = group_view(ws.grp.as<uint8_t>(), m, kq);
+          RS_HIP(launch_group(ca.list(k - 2), ca.count + (k - 2), n_last, m + n, kq, gv, group_temp_bytes(m, n), st));
+          grouped = true;
+          if (profiling_on() && timed) {
+            RS_HIP(hipMemcpyAsync(&n_groups, gv.gcount, 4, hipMemcpyDeviceToHost, st));
+            RS_HIP(hipStreamSynchronize(st));
+            top_units = n_groups;
+          }
+        }
       } else {
         RS_HIP(launch_qtable(G.e_src.as<uint32_t>(), G.e_dst.as<uint32_t>(), G.e_t.as<uint32_t>(),
                              ws.z.as<uint64_t>(), ws.q.as<uint64_t>(), (uint32_t)m, qp, st));
@@ -602,7 +628,13 @@ rs_status run_plain(rs_graph* g, PlainWorkspace& ws, const QueryPlan& qp, const 
         } else {
           TopArgs a;
           a.e_src = G.e_src.as<uint32_t>();
-          if (k >= 3) {  // the compacted list of non-empty windows
+          if (grouped) {  // one entry per distinct window, its rows summed
+            a.hi = gv.ghi;
+            a.lo = gv.glo;
+            a.q = gv.gq;
+            a.count = gv.gcount;
+            a.ce = nullptr;
+          } else if (k >= 3) {  // the compacted list of non-empty windows
             const LevelList Lc = ca.list(k - 2);
             a.hi = Lc.chi;
             a.lo = Lc.clo;
@@ -626,7 +658,7 @@ rs_status run_plain(rs_graph* g, PlainWorkspace& ws, const QueryPlan& qp, const 
           a.partial = ws.partial.as<uint64_t>();
           a.fsum = ws.fsum.as<uint64_t>();
           {
-            ProfScope ps(KC_TOP, st, top_bytes(ncs[k], m, kq, gc, first), timed);
+            ProfScope ps(KC_TOP, st, top_bytes(ncs[k], m, kq, gc, first, top_units), timed);
             if (fine)
               RS_HIP(launch_top_fine(a, first, kq, gc, tu, ws.fine_t.as<uint64_t>(), st));
             else

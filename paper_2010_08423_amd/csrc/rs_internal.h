@@ -247,6 +247,22 @@ __device__ __forceinline__ bool edge_excluded(const EdgeFilter& f, uint32_t l, u
 // window rows D written over list(0)'s row array, with each level-3 entry's
 // source written over list(1)'s window-end array. buf holds rrows_bytes(m, kq).
 uint64_t rrows_bytes(uint64_t m, uint32_t kq);
+// The last level by distinct windows (rs_group.hip): the last level's list
+// sorted by (hi, lo), its q rows summed per group of equal windows.
+struct GroupView {
+  uint64_t *key_in, *key_out;
+  uint32_t *idx_in, *idx_out, *head, *gid, *gstart;
+  uint32_t *ghi, *glo;   // [groups] window slots
+  uint64_t* gq;          // [groups][kq] summed q rows
+  uint32_t* gcount;      // number of groups (device)
+  uint8_t* temp;         // sort and scan scratch
+};
+uint64_t group_temp_bytes(uint64_t m, uint64_t n);
+uint64_t group_bytes(uint64_t m, uint64_t n, uint32_t kq);
+GroupView group_view(uint8_t* buf, uint64_t m, uint32_t kq);
+// n_entries: the list's length (also at *count on the device); slots = m + n.
+hipError_t launch_group(const LevelList& Lk, const uint32_t* count, uint32_t n_entries, uint64_t slots, uint32_t kq,
+                        const GroupView& v, uint64_t temp_bytes, hipStream_t st);
 hipError_t launch_rrows(const CompactArgs& ca, const uint32_t* in_off, const uint64_t* z, uint64_t seed,
                         const EdgeFilter& f, uint32_t kq, uint8_t* buf, hipStream_t st);
 // Product rows of the lists from level index y_first on (seed dependent: seed,
@@ -392,6 +408,7 @@ struct PlainWorkspace {
   DevBuf cov_diff;  // window-cover scratch of the flags: difference array and block sums
   DevBuf lists;     // compacted edge lists of levels 2..k and their scratch (k >= 3)
   DevBuf rr;        // level-2 prefix rows (k >= 4)
+  DevBuf grp;       // last level grouped by window
   DevBuf dv, smask, tmask, rmask;  // constraints: per-vertex resting times, source, target and removed masks
   DevBuf fine_t, fine_z, fine_r;   // fine-grained outputs: per-edge sums, per-slot zeta, reach times
   uint32_t epoch = 0;
@@ -402,7 +419,7 @@ struct PlainWorkspace {
   uint64_t bytes() const {
     uint64_t t = 0;
     for (const DevBuf* b : {&lo, &z, &q, &p0, &p1, &partial, &agg, &incl, &fsum, &out, &ref, &need, &lb_stats,
-                            &run_pre, &run_bsum, &run_boff, &run_bounds, &cov_diff, &lists, &rr, &dv, &smask, &tmask, &rmask,
+                            &run_pre, &run_bsum, &run_boff, &run_bounds, &cov_diff, &lists, &rr, &grp, &dv, &smask, &tmask, &rmask,
                             &fine_t, &fine_z, &fine_r})
       t += b->bytes;
     return t;
@@ -410,7 +427,7 @@ struct PlainWorkspace {
   void release() {
     if (scratch) return;  // borrowed buffers are never freed
     for (DevBuf* b : {&lo, &z, &q, &p0, &p1, &partial, &agg, &incl, &fsum, &out, &ref, &need, &lb_stats,
-                      &run_pre, &run_bsum, &run_boff, &run_bounds, &cov_diff, &lists, &rr, &dv, &smask, &tmask, &rmask, &fine_t,
+                      &run_pre, &run_bsum, &run_boff, &run_bounds, &cov_diff, &lists, &rr, &grp, &dv, &smask, &tmask, &rmask, &fine_t,
                       &fine_z, &fine_r})
       b->release();
     if (ev0) (void)hipEventDestroy(ev0);
@@ -428,6 +445,7 @@ struct PlainSizes {
   uint64_t run_pre, run_bsum, run_boff, run_bounds;
   uint64_t lists;                  // compacted lists (k >= 3; the q table is used only at k = 2)
   uint64_t rr;                     // level 2 folded into level 3 (k >= 4): prefix rows and block carries
+  uint64_t grp;                    // last level by distinct windows (k >= 3, not fine-grained)
   uint64_t dv, smask, tmask, rmask;  // constraints (0 when absent)
   uint64_t fine_t, fine_z, fine_r; // fine-grained outputs (0 when not asked)
   uint32_t run_w2, run_w3, run_stride;  // waves per chunk of level 2 and of levels >= 3; bounds stride

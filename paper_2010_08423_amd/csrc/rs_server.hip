@@ -121,7 +121,7 @@ static uint64_t growth(const PlainWorkspace& w, const PlainSizes& z) {
   return g(w.lo, z.lo) + g(w.z, z.z) + g(w.q, z.q) + g(w.p0, z.p) + g(w.p1, z.p) + g(w.partial, z.partial) +
          g(w.fsum, z.fsum) + g(w.out, 64) + g(w.ref, z.ref) + g(w.need, z.need) + g(w.cov_diff, z.cover) +
          g(w.agg, z.records) + g(w.incl, z.records) + g(w.run_pre, z.run_pre) + g(w.run_bsum, z.run_bsum) +
-         g(w.run_boff, z.run_boff) + g(w.run_bounds, z.run_bounds) + g(w.lists, z.lists) + g(w.rr, z.rr);
+         g(w.run_boff, z.run_boff) + g(w.run_bounds, z.run_bounds) + g(w.lists, z.lists) + g(w.rr, z.rr) + g(w.grp, z.grp);
 }
 
 // Puts a query back in the queue before the first query that arrived after
