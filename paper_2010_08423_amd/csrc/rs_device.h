@@ -107,8 +107,10 @@ __device__ __forceinline__ void gf_comb_acc(uint32_t base, uint64_t a, Acc128& r
   for (int j = 7; j >= 0; --j) {
     const uint32_t s0 = (4 * j >= 9) ? (a0 >> (4 * j - 9)) : (a0 << (9 - 4 * j));
     const uint32_t s1 = (4 * j >= 9) ? (a1 >> (4 * j - 9)) : (a1 << (9 - 4 * j));
-    const uint64_t x = lds_load((s0 & 0x1E00u) | base);
-    const uint64_t y = lds_load((s1 & 0x1E00u) | base);
+    // base has bits 9..12 clear, so OR equals XOR and the address takes one
+    // three-input op after the shift
+    const uint64_t x = lds_load(and_xor(s0, 0x1E00u, base));
+    const uint64_t y = lds_load(and_xor(s1, 0x1E00u, base));
     d0 ^= lo32(x);
     d1 = xor3(d1, hi32(x), lo32(y));
     d2 ^= hi32(y);
