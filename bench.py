@@ -233,7 +233,13 @@ def main():
     # i.e. the bytes a dense evaluation of the levels would move; its rate
     # exceeds the HBM peak because the skipped updates are never done.
     kq = (q.k + 3) // 4 * 4
-    chunks_per_launch = max(1, min(4, (1 << q.k) // 64))
+    # chunks per launch, from the launches counted: levels 4..k-1 (level 2 is
+    # folded into level 3 at k >= 4, which has a class of its own) once per
+    # group of chunks
+    chunks = max(1, (1 << q.k) // 64)
+    per_query = n_scan / max(args.steps, 1)
+    groups = per_query / max(q.k - 4, 1) if q.k >= 5 else 1
+    chunks_per_launch = max(1, round(chunks / max(groups, 1)))
     dense_bytes = (1536.0 * chunks_per_launch + 12 + 8 * kq) * m
     dense = dense_bytes / (avg_scan_ms * 1e-3) / 1e9
     classes = {}
@@ -258,7 +264,7 @@ def main():
                    "edge_updates_per_query": upd, "fingerprint": f"{r.fingerprint:#018x}"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": committed_traffic(counters_file),
-                     "kernel": f"k_scan<kq={kq},E=16>, prefix levels 3..k-1, {chunks_per_launch} chunks per launch",
+                     "kernel": f"k_scan<kq={kq},E=16>, prefix levels 4..k-1, {chunks_per_launch} chunks per launch",
                      "avg_launch_ms": avg_scan_ms, "launches": n_scan,
                      "algorithmic_bytes_per_launch": alg_bytes,
                      # the dense evaluation's bytes at the same per-unit figure, and their rate
