@@ -89,8 +89,9 @@ struct MUnit {
   const uint32_t* boff;  // prefix-level units: this level's block offsets
   uint32_t* bounds;      // prefix-level units: [waves+1] first tile of each wave's run
   const uint32_t* count; // compacted list of this level (queries with k >= 3): its length; null otherwise
+  const uint64_t* d;     // level 3 of a query with k >= 4: its entries' window rows (level 2 folded in)
 };
-static_assert(sizeof(MUnit) == 176, "MUnit layout");
+static_assert(sizeof(MUnit) == 184, "MUnit layout");
 // Units are read through the constant address space: scalar loads into SGPRs.
 typedef __attribute__((address_space(4))) const MUnit cMUnit;
 
@@ -265,7 +266,7 @@ __device__ __forceinline__ uint32_t find_unit(cu32* ubegin, uint32_t from, uint3
 // the i-th of `waves` contiguous runs of tiles), so a run's predecessor is
 // the neighbouring wave of the same pair and no wave ever waits on another
 // pair.
-template <int KQ, int E, bool FIRST>
+template <int KQ, int E, bool FIRST, bool DR = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void kb_scan(const MUnit* __restrict__ units, const uint32_t* __restrict__ ubegin_p,
                                                uint32_t nunits, uint32_t total, uint64_t* __restrict__ agg,
                                                uint64_t* __restrict__ incl, unsigned long long* __restrict__ lb_stats) {
@@ -290,7 +291,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
   c.lo = U.lo;
   c.q = U.q;
   c.z = U.z;
-  c.d = nullptr;
+  c.d = DR ? U.d : nullptr;
   c.pp = U.pp + ch * U.p_stride;
   c.pc = U.pc + ch * U.p_stride;
   c.cb = U.cb + (uint64_t)ch * kLanes;
@@ -304,7 +305,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
   c.need = U.need;
   c.lb_stats = lb_stats;  // null unless look-back counting is on
   c.bounds = U.bounds;
-  scan_level<KQ, E, FIRST>(c, idx, U.waves, lane, mk, tab);
+  scan_level<KQ, E, FIRST, DR>(c, idx, U.waves, lane, mk, tab);
 }
 
 // Last level: flat index = (unit, edge range of top_edges edges). A wave keeps
@@ -445,7 +446,8 @@ static BatchWorkspace& batch_ws() {
 struct BLaunch {
   uint32_t lane;    // stream lane of the launch's round
   bool top;         // last-level launch (else prefix level)
-  bool first;       // level 2
+  bool first;       // level 2 (queries with k = 3; deeper ones fold it into level 3)
+  bool dr;          // level 3 from window rows (queries with k >= 4)
   uint32_t kq;
   uint32_t unit_off, nunits, total;
   uint32_t grid;    // blocks, set at enqueue time
@@ -470,6 +472,8 @@ struct BatchPlan {
   uint32_t lanes = 1;         // rounds run on this many streams at once
   uint64_t bounds_words = 0;  // run bounds of all prefix-level units
   std::vector<uint64_t> lists_off;    // per query: offset of its compacted lists (k >= 3)
+  std::vector<uint64_t> rr_off;       // per query: offset of its level-2 prefix rows (k >= 4)
+  std::vector<uint8_t*> rr;           // the same, resolved
   std::vector<CompactArgs> cargs;     // per query: its compacted lists (set by resolve_plan)
   std::vector<int32_t> unit_list;     // per unit: level index of its compacted list, or -1
   Tuning tu;
@@ -485,7 +489,8 @@ uint64_t batch_query_bytes(uint64_t m, uint64_t n, const QueryPlan& qp) {
   const uint64_t levels = qp.k > 2 ? qp.k - 2 : 0, tiles = (m + 7) / 8, nb = (tiles + kCostBlock - 1) / kCostBlock;
   return align256(table_lo_bytes(m)) + align256(table_z_bytes(n, qp.kq)) +
          (qp.k == 2 ? align256(table_q_bytes(m, qp.k, qp.kq)) : 0) +
-         (qp.k >= 3 ? align256(compact_bytes(m, qp.k, qp.kq)) : 0) + align256(table_need_bytes(m, qp.k)) +
+         (qp.k >= 3 ? align256(compact_bytes(m, qp.k, qp.kq)) : 0) +
+         (qp.k >= 4 ? align256(rrows_bytes(m, qp.kq)) : 0) + align256(table_need_bytes(m, qp.k)) +
          align256(4 * tiles * levels) + 2 * align256(4 * nb * levels) + align256(8 * (1ull << qp.k)) + 2048;
 }
 
@@ -555,6 +560,8 @@ rs_status batch_plan(const rs_graph* const* graphs, const rs_query* queries, uin
     if (qp.k == 2) pq_off += align256(table_q_bytes(m, qp.k, qp.kq));
     P.lists_off.push_back(pq_off);
     if (qp.k >= 3) pq_off += align256(compact_bytes(m, qp.k, qp.kq));
+    P.rr_off.push_back(pq_off);  // level 2 folded into level 3 (k >= 4)
+    if (qp.k >= 4) pq_off += align256(rrows_bytes(m, qp.kq));
     Q.need = (uint8_t*)(uintptr_t)pq_off;
     pq_off += align256(table_need_bytes(m, qp.k));
     {
@@ -650,6 +657,7 @@ rs_status batch_plan(const rs_graph* const* graphs, const rs_query* queries, uin
           L.lane = lane;
           L.top = top != 0;
           L.first = l == 2;
+          L.dr = !L.top && l == 3;
           L.kq = kq;
           L.unit_off = (uint32_t)P.units.size();
           L.nunits = 0;
@@ -659,6 +667,7 @@ rs_status batch_plan(const rs_graph* const* graphs, const rs_query* queries, uin
             const uint32_t qi = chunks[c].query;
             const BQuery& Q = P.qs[qi];
             if (Q.kq != kq || (top ? Q.k != l : Q.k <= l)) continue;
+            if (!top && l == 2 && Q.k >= 4) continue;  // folded into level 3's window rows
             // prefix levels: this and the following chunks of the same query
             // (consecutive in the round, their buffers and record rows at a
             // fixed stride) form one unit
@@ -706,7 +715,8 @@ rs_status batch_plan(const rs_graph* const* graphs, const rs_query* queries, uin
           if (L.nunits) {
             if (!L.top) ++P.scan_launches;
             P.launches.push_back(L);
-            key += "/" + std::to_string(L.top) + std::to_string(L.first) + ":" + std::to_string(kq) + ":" +
+            key += "/" + std::to_string(L.top) + std::to_string(L.first) + std::to_string(L.dr) + ":" +
+                   std::to_string(kq) + ":" +
                    std::to_string(L.nunits) + ":" + std::to_string(L.total);
           }
         }
@@ -782,6 +792,8 @@ static rs_status resolve_plan(BatchPlan& P, BatchWorkspace& W, uint32_t epoch0) 
       ca.count = ca.boff + L * ca.nb;
     }
     P.cargs.push_back(ca);
+    if (Q.k >= 4 && P.rr_off[i] + rrows_bytes(Q.m, Q.kq) > W.per_query.bytes) return RS_EINVAL;
+    P.rr.push_back(Q.k >= 4 ? (uint8_t*)(pq + P.rr_off[i]) : nullptr);
   }
   uint32_t scan_idx = 0;
   for (const BLaunch& L : P.launches) {
@@ -804,6 +816,7 @@ static rs_status resolve_plan(BatchPlan& P, BatchWorkspace& W, uint32_t epoch0) 
         U.lo = Lc.clo;
         U.q = Lc.cq;
         U.count = P.cargs[qi].count + y;
+        U.d = (y == 1 && Q.k >= 4) ? P.cargs[qi].list(0).cq : nullptr;  // the D rows
       } else {
         const uint64_t q_level = (uintptr_t)U.q;  // offset of this level's rows (k = 2)
         if (q_level + 8ull * Q.m * Q.kq > q_off[qi] + 8ull * Q.m * Q.kq * (Q.k - 1)) return RS_EINVAL;
@@ -835,24 +848,25 @@ static uint32_t resident_blocks_of(const void* kern, uint32_t threads, size_t ld
 }
 
 template <int KQ, int E>
-static const void* scan_kernel(bool first) {
+static const void* scan_kernel(bool first, bool dr) {
+  if (dr) return (const void*)kb_scan<KQ, E, false, true>;
   return first ? (const void*)kb_scan<KQ, E, true> : (const void*)kb_scan<KQ, E, false>;
 }
 
-static const void* pick_scan(uint32_t kq, uint32_t E, bool first) {
+static const void* pick_scan(uint32_t kq, uint32_t E, bool first, bool dr) {
   if (E == 8) {
     switch (kq) {
-      case 4: return scan_kernel<4, 8>(first);
-      case 8: return scan_kernel<8, 8>(first);
-      case 12: return scan_kernel<12, 8>(first);
-      default: return scan_kernel<16, 8>(first);
+      case 4: return scan_kernel<4, 8>(first, dr);
+      case 8: return scan_kernel<8, 8>(first, dr);
+      case 12: return scan_kernel<12, 8>(first, dr);
+      default: return scan_kernel<16, 8>(first, dr);
     }
   }
   switch (kq) {
-    case 4: return scan_kernel<4, 16>(first);
-    case 8: return scan_kernel<8, 16>(first);
-    case 12: return scan_kernel<12, 16>(first);
-    default: return scan_kernel<16, 16>(first);
+    case 4: return scan_kernel<4, 16>(first, dr);
+    case 8: return scan_kernel<8, 16>(first, dr);
+    case 12: return scan_kernel<12, 16>(first, dr);
+    default: return scan_kernel<16, 16>(first, dr);
   }
 }
 
@@ -877,7 +891,7 @@ static void size_grids(BatchPlan& P) {
   const uint32_t wpb = P.tu.waves_per_block;
   const size_t lds = (size_t)wpb * 16 * kLanes * 8;
   for (BLaunch& L : P.launches) {
-    const void* kern = L.top ? pick_top(L.kq, L.first) : pick_scan(L.kq, P.tu.edges_per_tile, L.first);
+    const void* kern = L.top ? pick_top(L.kq, L.first) : pick_scan(L.kq, P.tu.edges_per_tile, L.first, L.dr);
     const uint32_t resident = resident_blocks_of(kern, 64 * wpb, lds);
     if (!L.top) {
       uint64_t pairs = 0, tiles = 0;
@@ -932,7 +946,9 @@ static rs_status batch_enqueue(BatchPlan& P, BatchWorkspace& W, hipStream_t st) 
       RS_HIP(launch_compact(ca, st));
       RS_HIP(launch_compact_costs(ca, E, (Q.m + E - 1) / E, Q.pre, Q.bsum, Q.boff, st));
       const uint64_t* seed_p = (const uint64_t*)((const char*)(dq + qi) + offsetof(BQuery, seed));
-      RS_HIP(launch_compact_rows(ca, Q.z, 0, seed_p, EdgeFilter(), Q.kq, st));
+      RS_HIP(launch_compact_rows(ca, Q.z, 0, seed_p, EdgeFilter(), Q.kq, st, Q.k >= 4 ? 1 : 0));
+      // level 2 folded into level 3: the iteration-independent prefix rows
+      if (Q.k >= 4) RS_HIP(launch_rrows(ca, Q.in_off, Q.z, 0, seed_p, EdgeFilter(), Q.kq, P.rr[qi], st));
     } else {
       switch (Q.kq) {
         case 4: hipLaunchKernelGGL(kb_qtable<4>, dim3((Q.m + 255) / 256), dim3(256), 0, st, dq, qi); break;
@@ -954,7 +970,7 @@ static rs_status batch_enqueue(BatchPlan& P, BatchWorkspace& W, hipStream_t st) 
   for (uint32_t ln = 0; ln < P.lanes; ++ln) RS_HIP(hipStreamWaitEvent(W.lane_st[ln], W.fork, 0));
   for (BLaunch& L : P.launches) {
     hipStream_t lst = W.lane_st[L.lane];
-    const void* kern = L.top ? pick_top(L.kq, L.first) : pick_scan(L.kq, P.tu.edges_per_tile, L.first);
+    const void* kern = L.top ? pick_top(L.kq, L.first) : pick_scan(L.kq, P.tu.edges_per_tile, L.first, L.dr);
     const MUnit* u = du + L.unit_off;
     const uint32_t* b = db + L.unit_off;
     if (L.top) {

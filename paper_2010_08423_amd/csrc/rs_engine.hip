@@ -555,7 +555,7 @@ rs_status run_plain(rs_graph* g, PlainWorkspace& ws, const QueryPlan& qp, const 
         // (level 2's own rows are not used when it is folded into level 3)
         RS_HIP(launch_compact_rows(ca, ws.z.as<uint64_t>(), qp.seed, nullptr, filt, kq, st, fold2 ? 1 : 0));
         // level 2 as iteration-independent prefix rows, level 3's window rows
-        if (fold2) RS_HIP(launch_rrows(ca, G.in_off.as<uint32_t>(), ws.z.as<uint64_t>(), qp.seed, filt, kq,
+        if (fold2) RS_HIP(launch_rrows(ca, G.in_off.as<uint32_t>(), ws.z.as<uint64_t>(), qp.seed, nullptr, filt, kq,
                                        ws.rr.as<uint8_t>(), st));
         // the last level's entries grouped by window
         if (sz.grp) {

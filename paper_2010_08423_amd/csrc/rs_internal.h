@@ -246,6 +246,7 @@ __device__ __forceinline__ bool edge_excluded(const EdgeFilter& f, uint32_t l, u
 // independent prefix rows of level 2 and, for level 3's product entries, their
 // window rows D written over list(0)'s row array, with each level-3 entry's
 // source written over list(1)'s window-end array. buf holds rrows_bytes(m, kq).
+// The seed is *seed_p when seed_p is not null (read on the device).
 uint64_t rrows_bytes(uint64_t m, uint32_t kq);
 // The last level by distinct windows (rs_group.hip): the last level's list
 // sorted by (hi, lo), its q rows summed per group of equal windows.
@@ -264,7 +265,7 @@ GroupView group_view(uint8_t* buf, uint64_t m, uint32_t kq);
 hipError_t launch_group(const LevelList& Lk, const uint32_t* count, uint32_t n_entries, uint64_t slots, uint32_t kq,
                         const GroupView& v, uint64_t temp_bytes, hipStream_t st);
 hipError_t launch_rrows(const CompactArgs& ca, const uint32_t* in_off, const uint64_t* z, uint64_t seed,
-                        const EdgeFilter& f, uint32_t kq, uint8_t* buf, hipStream_t st);
+                        const uint64_t* seed_p, const EdgeFilter& f, uint32_t kq, uint8_t* buf, hipStream_t st);
 // Product rows of the lists from level index y_first on (seed dependent: seed,
 // or *seed_p read on the device when seed_p is not null), 0 for the edges f
 // excludes.

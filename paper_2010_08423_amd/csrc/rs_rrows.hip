@@ -43,11 +43,13 @@ struct RLocalShared {
 template <int KQ>
 __global__ __launch_bounds__(256) void k_r_local(const uint32_t* __restrict__ e_src, const uint32_t* __restrict__ e_dst,
                                                  const uint32_t* __restrict__ e_t, const uint8_t* __restrict__ need2,
-                                                 const uint64_t* __restrict__ z, uint64_t seed, EdgeFilter f,
+                                                 const uint64_t* __restrict__ z, uint64_t seed_v,
+                                                 const uint64_t* __restrict__ seed_p, EdgeFilter f,
                                                  uint32_t k, uint64_t m, uint64_t* __restrict__ R,
                                                  uint64_t* __restrict__ btail, uint32_t* __restrict__ bhead,
                                                  uint32_t* __restrict__ bfirst) {
   static_assert(256 * KQ <= 4 * 16 * kLanes, "tail rows fit the table buffer");
+  const uint64_t seed = seed_p ? *seed_p : seed_v;  // from a batch descriptor, read at run time
   __shared__ RLocalShared sh;  // the only static LDS of the kernel, so it starts at address 0
   auto& heads = sh.heads;
   auto& firsts = sh.firsts;
@@ -207,14 +209,14 @@ uint64_t rrows_bytes(uint64_t m, uint32_t kq) {
 
 template <int KQ>
 static hipError_t rrows_kq(const CompactArgs& ca, const uint32_t* in_off, const uint64_t* z, uint64_t seed,
-                           const EdgeFilter& f, uint8_t* buf, hipStream_t st) {
+                           const uint64_t* seed_p, const EdgeFilter& f, uint8_t* buf, hipStream_t st) {
   const uint64_t m = ca.m;
   const uint32_t nb = blocks_of(m, kRBlockEdges);
   uint64_t* R = (uint64_t*)buf;
   uint64_t* btail = R + (m + kEdgePad) * KQ;
   uint32_t* bhead = (uint32_t*)(btail + (uint64_t)nb * KQ);
   uint32_t* bfirst = bhead + nb;
-  hipLaunchKernelGGL(k_r_local<KQ>, dim3(nb), dim3(256), 0, st, ca.e_src, ca.e_dst, ca.e_t, ca.need, z, seed, f,
+  hipLaunchKernelGGL(k_r_local<KQ>, dim3(nb), dim3(256), 0, st, ca.e_src, ca.e_dst, ca.e_t, ca.need, z, seed, seed_p, f,
                      ca.k, m, R, btail, bhead, bfirst);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -228,13 +230,13 @@ static hipError_t rrows_kq(const CompactArgs& ca, const uint32_t* in_off, const 
 }
 
 hipError_t launch_rrows(const CompactArgs& ca, const uint32_t* in_off, const uint64_t* z, uint64_t seed,
-                        const EdgeFilter& f, uint32_t kq, uint8_t* buf, hipStream_t st) {
+                        const uint64_t* seed_p, const EdgeFilter& f, uint32_t kq, uint8_t* buf, hipStream_t st) {
   if (!ca.m || ca.k < 4) return hipSuccess;
   switch (kq) {
-    case 4: return rrows_kq<4>(ca, in_off, z, seed, f, buf, st);
-    case 8: return rrows_kq<8>(ca, in_off, z, seed, f, buf, st);
-    case 12: return rrows_kq<12>(ca, in_off, z, seed, f, buf, st);
-    case 16: return rrows_kq<16>(ca, in_off, z, seed, f, buf, st);
+    case 4: return rrows_kq<4>(ca, in_off, z, seed, seed_p, f, buf, st);
+    case 8: return rrows_kq<8>(ca, in_off, z, seed, seed_p, f, buf, st);
+    case 12: return rrows_kq<12>(ca, in_off, z, seed, seed_p, f, buf, st);
+    case 16: return rrows_kq<16>(ca, in_off, z, seed, seed_p, f, buf, st);
     default: return hipErrorInvalidValue;
   }
 }

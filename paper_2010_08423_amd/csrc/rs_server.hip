@@ -446,6 +446,14 @@ rs_status rs_server_submit(rs_server* s, uint32_t graph_id, const rs_query* q, u
     const uint64_t m = g->g.m, n = g->g.n;
     a->tu = resolve_tuning(g, a->plan.k, nullptr);
     a->sizes = plain_sizes(m, n, a->plan, a->tu);
+    // the wider launches of large queries are taken only where every worker
+    // can hold such a workspace at once, within three quarters of the budget:
+    // else idle workspaces would be freed and reallocated job after job
+    while (a->tu.chunks_per_launch > Tuning{}.chunks_per_launch &&
+           a->sizes.total() * s->opts.streams > s->budget / 4 * 3) {
+      a->tu.chunks_per_launch /= 2;
+      a->sizes = plain_sizes(m, n, a->plan, a->tu);
+    }
     if (a->sizes.total() > s->budget) {  // can never run alone
       s->st.rejected++;
       return RS_ENOMEM;
