@@ -126,7 +126,8 @@ __global__ __launch_bounds__(256) void k_compact_restart(CompactArgs a) {
 // Tiles past the list cost nothing.
 template <int E>
 __global__ __launch_bounds__(256) void k_compact_tiles(CompactArgs a, uint32_t tile_cost, uint32_t product_cost,
-                                                       uint32_t tile_cost_first, uint32_t product_cost_first,
+                                                       uint32_t store_cost, uint32_t tile_cost_first,
+                                                       uint32_t product_cost_first,
                                                        uint32_t* __restrict__ pre, uint32_t* __restrict__ bsum,
                                                        uint32_t tiles_max) {
   __shared__ uint32_t part[256];
@@ -142,10 +143,13 @@ __global__ __launch_bounds__(256) void k_compact_tiles(CompactArgs a, uint32_t t
     uint32_t cst = 0;
     if (t < n_tiles) {
       const uint32_t* wds = reinterpret_cast<const uint32_t*>(L.cflag + (uint64_t)t * E);
-      uint32_t np = 0;
+      uint32_t np = 0, ns = 0;
 #pragma unroll
-      for (int q = 0; q < E / 4; ++q) np += __popc(wds[q] & 0x04040404u);
-      cst = (y == 0 ? tile_cost_first : tile_cost) + (y == 0 ? product_cost_first : product_cost) * np;
+      for (int q = 0; q < E / 4; ++q) {
+        np += __popc(wds[q] & 0x04040404u);  // products (bit 2)
+        ns += __popc(wds[q] & 0x01010101u);  // stored slots (bit 0)
+      }
+      cst = y == 0 ? tile_cost_first + product_cost_first * np : tile_cost + product_cost * np + store_cost * ns;
     }
     sum += cst;
     cost[jt] = sum;
@@ -172,7 +176,8 @@ __global__ __launch_bounds__(256) void k_compact_bounds(const uint32_t* __restri
                                                         const uint32_t* __restrict__ pre,
                                                         const uint32_t* __restrict__ boff, uint32_t nb,
                                                         uint32_t tiles_max, uint32_t w_first, uint32_t w_rest,
-                                                        uint32_t b_stride, uint32_t* __restrict__ bounds) {
+                                                        float skew_first, float skew_rest, uint32_t b_stride,
+                                                        uint32_t* __restrict__ bounds) {
   const uint32_t y = blockIdx.y;
   const uint32_t n_tiles = (count[y] + E - 1) / E;
   const uint32_t W = y == 0 ? w_first : w_rest;
@@ -183,7 +188,9 @@ __global__ __launch_bounds__(256) void k_compact_bounds(const uint32_t* __restri
       for (uint32_t w = 0; w <= W; ++w) b[w] = 0;
     return;
   }
-  if (t < n_tiles) run_bounds_of_tile(pre + (uint64_t)y * tiles_max, boff + (uint64_t)y * nb, n_tiles, t, W, b);
+  if (t < n_tiles)
+    run_bounds_of_tile(pre + (uint64_t)y * tiles_max, boff + (uint64_t)y * nb, n_tiles, t, W, b,
+                       y == 0 ? skew_first : skew_rest);
 }
 
 // Product rows of the kept edges that form a product (bit 2; every entry of
@@ -249,17 +256,17 @@ hipError_t launch_compact_costs(const CompactArgs& a, uint32_t E, uint32_t tiles
   hipLaunchKernelGGL(k_compact_restart, dim3(std::min<uint32_t>(cdiv(a.m, 256), 4096), levels), dim3(256), 0, st, a);
   if (E == 8)
     hipLaunchKernelGGL(k_compact_tiles<8>, dim3(nbt, levels), dim3(256), 0, st, a, kTileCost, kProductCost,
-                       kTileCostFirst, kProductCostFirst, pre, bsum, tiles_max);
+                       kStoreCost, kTileCostFirst, kProductCostFirst, pre, bsum, tiles_max);
   else
     hipLaunchKernelGGL(k_compact_tiles<16>, dim3(nbt, levels), dim3(256), 0, st, a, kTileCost, kProductCost,
-                       kTileCostFirst, kProductCostFirst, pre, bsum, tiles_max);
+                       kStoreCost, kTileCostFirst, kProductCostFirst, pre, bsum, tiles_max);
   hipLaunchKernelGGL(k_compact_offsets, dim3(levels), dim3(1024), 0, st, bsum, nbt, boff);
   return hipGetLastError();
 }
 
 hipError_t launch_compact_bounds(const CompactArgs& a, uint32_t E, uint32_t tiles_max, uint32_t w_first,
-                                 uint32_t w_rest, uint32_t* pre, uint32_t* bsum, uint32_t* boff, uint32_t* bounds,
-                                 uint32_t b_stride, hipStream_t st) {
+                                 uint32_t w_rest, float skew_first, float skew_rest, uint32_t* pre, uint32_t* bsum,
+                                 uint32_t* boff, uint32_t* bounds, uint32_t b_stride, hipStream_t st) {
   if (!a.m || a.k < 3) return hipSuccess;
   hipError_t err = launch_compact_costs(a, E, tiles_max, pre, bsum, boff, st);
   if (err != hipSuccess) return err;
@@ -268,10 +275,10 @@ hipError_t launch_compact_bounds(const CompactArgs& a, uint32_t E, uint32_t tile
   const dim3 g(cdiv((uint64_t)tiles_max + 1, 256), levels);
   if (E == 8)
     hipLaunchKernelGGL(k_compact_bounds<8>, g, dim3(256), 0, st, a.count, pre, boff, nbt, tiles_max, w_first, w_rest,
-                       b_stride, bounds);
+                       skew_first, skew_rest, b_stride, bounds);
   else
     hipLaunchKernelGGL(k_compact_bounds<16>, g, dim3(256), 0, st, a.count, pre, boff, nbt, tiles_max, w_first,
-                       w_rest, b_stride, bounds);
+                       w_rest, skew_first, skew_rest, b_stride, bounds);
   return hipGetLastError();
 }
 

@@ -501,7 +501,8 @@ rs_status run_plain(rs_graph* g, PlainWorkspace& ws, const QueryPlan& qp, const 
       // (later groups launch the same width)
       if (k >= 3) {
         RS_HIP(launch_compact(ca, st));
-        RS_HIP(launch_compact_bounds(ca, E, (uint32_t)tiles, run_w2, run_w3, ws.run_pre.as<uint32_t>(),
+        RS_HIP(launch_compact_bounds(ca, E, (uint32_t)tiles, run_w2, run_w3, run_skew(run_w2, tu.waves_per_block),
+                                     run_skew(run_w3, tu.waves_per_block), ws.run_pre.as<uint32_t>(),
                                      ws.run_bsum.as<uint32_t>(), ws.run_boff.as<uint32_t>(),
                                      ws.run_bounds.as<uint32_t>(), run_stride, st));
       }

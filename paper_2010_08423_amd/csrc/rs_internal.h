@@ -117,21 +117,6 @@ uint32_t resident_blocks(const void* kern, uint32_t threads, size_t lds);
 // waves per block).
 uint32_t scan_waves(uint32_t kq, uint32_t E, bool first, uint32_t n_tiles, uint32_t chunks, uint32_t wpb,
                     bool drows = false);
-// Work-balanced run bounds of the prefix levels 2 .. 2 + levels - 1 of a
-// query: per level (need flags at need + y * need_stride_b) the per-tile
-// costs, their prefix (scratch pre[levels][n_tiles], bsum and boff
-// [levels][ceil(n_tiles / 1024)]) and bounds[levels][b_stride] for w_first
-// waves per chunk at level 2 and w_rest above it (b_stride > both).
-// The per-tile costs and their prefix only (no bounds), for callers that cut
-// the runs for several grid widths.
-hipError_t launch_tile_costs(const uint32_t* hi, const uint32_t* lo, const uint8_t* need, uint64_t need_stride_b,
-                             uint32_t m, uint32_t E, uint32_t levels, uint32_t* pre, uint32_t* bsum, uint32_t* boff,
-                             hipStream_t st);
-hipError_t launch_run_bounds(const uint32_t* hi, const uint32_t* lo, const uint8_t* need, uint64_t need_stride_b,
-                             uint32_t m, uint32_t E, uint32_t levels, uint32_t w_first, uint32_t w_rest,
-                             uint32_t* pre, uint32_t* bsum, uint32_t* boff, uint32_t* bounds, uint32_t b_stride,
-                             hipStream_t st);
-
 // Arguments of the last level k.
 struct TopArgs {
   const uint32_t* e_src;
@@ -165,10 +150,30 @@ hipError_t launch_window(const uint32_t* e_src, const uint32_t* e_t, const uint3
 // list compaction): 256 threads x 4.
 constexpr uint32_t kCostBlock = 1024;
 
-// Weights of the work-balanced runs: per tile and per product, at level 2
-// and above it (fitted to per-wave clocks).
-constexpr uint32_t kTileCost = 5, kProductCost = 3;
+// Weights of the work-balanced runs, fitted to per-wave clocks: at levels
+// >= 3 per tile, per product and per stored slot (per-wave clocks of the
+// 10^6-edge path query and the 10^7-edge motif query, least squares per
+// chunk: residual 3.8-5.8 % of a wave's time against 8-8.7 % for tile and
+// product weights alone); at level 2 per tile and per product. A tile costs
+// at most 2 + 16 * (7 + 1) = 130, so the level totals of any graph whose
+// prefix state fits in device memory stay below 2^32.
+constexpr uint32_t kTileCost = 2, kProductCost = 7, kStoreCost = 1;
 constexpr uint32_t kTileCostFirst = 7, kProductCostFirst = 4;
+
+// Waves of one launch run slower the later they were dispatched (on the
+// 10^7-edge motif query the chunk whose blocks come last took 17 % longer
+// than the first, and reversing the chunk order reversed the effect). The
+// level kernel therefore orders its runs by dispatch order (run index = age,
+// see k_scan) and the work-balanced split gives run r of W the share
+// 1 - kAgeSkew * r / W, normalised: the youngest wave gets kAgeSkew less.
+// (Measured there: 92.2 ms per query unskewed, 90.8 at 0.15, 90.7 at 0.2.)
+constexpr float kAgeSkew = 0.2f;
+
+// The skew of the split for a level launch of `waves` runs in blocks of wpb
+// waves: k_scan orders its runs by age when its grid width is a multiple of 8.
+inline float run_skew(uint32_t waves, uint32_t wpb) {
+  return wpb && waves % wpb == 0 && (waves / wpb) % 8 == 0 ? kAgeSkew : 0.0f;
+}
 
 // One level's compacted edge list (rs_compact.hip): the kept edges of the
 // level in edge order, with what a tile reads laid out contiguously.
@@ -223,8 +228,8 @@ hipError_t launch_compact_costs(const CompactArgs& a, uint32_t E, uint32_t tiles
 // The same, then the work-balanced run bounds [k-2][b_stride] for w_first
 // waves per chunk at level 2 and w_rest above it.
 hipError_t launch_compact_bounds(const CompactArgs& a, uint32_t E, uint32_t tiles_max, uint32_t w_first,
-                                 uint32_t w_rest, uint32_t* pre, uint32_t* bsum, uint32_t* boff, uint32_t* bounds,
-                                 uint32_t b_stride, hipStream_t st);
+                                 uint32_t w_rest, float skew_first, float skew_rest, uint32_t* pre, uint32_t* bsum,
+                                 uint32_t* boff, uint32_t* bounds, uint32_t b_stride, hipStream_t st);
 // Edges a query's constraints exclude (Sec. 3 and Sec. 4.7): at level 2 an
 // edge whose source is not a source vertex, at the last level one whose
 // destination is not a target vertex, at every level one that touches a

@@ -34,7 +34,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
   uint64_t* tab = dyn_lds + wv * 16 * kLanes + lane;
   tab[0] = 0;
 
-  const uint32_t chunk = blockIdx.y;
+  // Blocks start in linear order (x fastest) and alternate over the eight
+  // XCDs. With a grid width that is a multiple of 8, block L = (8 k + d) takes
+  // run block x = 8 (k / C) + d of chunk k mod C (C chunks): a run's chunks
+  // share an XCD (and its L2 copy of the run's indices and rows), and runs are
+  // in dispatch order, which the skewed split of the runs counts on.
+  uint32_t bx = blockIdx.x, chunk = blockIdx.y;
+  if ((gridDim.x & 7u) == 0) {
+    const uint32_t L = blockIdx.y * gridDim.x + blockIdx.x, k = L >> 3;
+    chunk = k % gridDim.y;
+    bx = (k / gridDim.y) * 8 + (L & 7u);
+  }
   uint32_t mk[6];
   lane_masks(lane, mk);
   TileCtx c;
@@ -59,7 +69,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
   c.lb_stats = lb_stats;
   c.bounds = bounds;
   const uint32_t waves = gridDim.x * (blockDim.x >> 6);
-  scan_level<KQ, E, FIRST, DR>(c, blockIdx.x * (blockDim.x >> 6) + wv, waves, lane, mk, tab);
+  scan_level<KQ, E, FIRST, DR>(c, bx * (blockDim.x >> 6) + wv, waves, lane, mk, tab);
 }
 
 // ---------------------------------------------------------------------------
@@ -297,107 +307,10 @@ hipError_t launch_ztable(uint64_t* z, uint32_t n, const QueryPlan& qp, const uin
   return hipGetLastError();
 }
 
-// ---------------------------------------------------------------------------
-// Work-balanced runs of the prefix levels. The cost of a tile is a weight per
-// tile plus a weight per edge that forms a product at that level (need bit
-// 2, and at levels >= 3 a non-empty window); runs are cut at equal shares of
-// the level's total cost. blockIdx.y is the level index
-// (level 2 + y); per level the arrays are pre[n_tiles], bsum[nb], boff[nb],
-// bounds[W+1], at the strides given.
-// ---------------------------------------------------------------------------
-// The weights of a tile and of a product (kTileCost ...) come from per-wave
-// clocks regressed on the tiles and products of each wave's run (10^6-edge
-// graph): levels >= 3 fit 2.4 us per tile plus 1.3-1.4 us per product, level
-// 2 2.1 us per tile plus 1.2 us per product (level 2 gathers no windows).
-
-// The product bit of the flags already requires a non-empty window at levels
-// >= 3, and the flag bytes past m are zero, so a tile's products are a
-// population count over its flag words.
-template <int E>
-__global__ __launch_bounds__(256) void k_tile_cost(const uint8_t* __restrict__ need, uint64_t need_stride_b,
-                                                   uint32_t m, uint32_t n_tiles, uint32_t* __restrict__ pre,
-                                                   uint32_t* __restrict__ bsum) {
-  __shared__ uint32_t part[256];
-  const uint32_t lvl = blockIdx.y;
-  const uint8_t* nd = need + (uint64_t)lvl * need_stride_b;
-  const uint32_t t_base = blockIdx.x * kCostBlock + threadIdx.x * 4;
-  uint32_t cost[4];
-  uint32_t sum = 0;
-  for (int j = 0; j < 4; ++j) {
-    const uint32_t t = t_base + j;
-    uint32_t c = 0;
-    if (t < n_tiles) {
-      c = lvl == 0 ? kTileCostFirst : kTileCost;
-      const uint32_t pc = lvl == 0 ? kProductCostFirst : kProductCost;
-      const uint32_t* w = reinterpret_cast<const uint32_t*>(nd + (uint64_t)t * E);
-      uint32_t np = 0;
-#pragma unroll
-      for (int q = 0; q < E / 4; ++q) np += __popc(w[q] & 0x04040404u);  // bit 2 of four flag bytes
-      c += pc * np;
-    }
-    sum += c;
-    cost[j] = sum;  // inclusive within the thread's four tiles
-  }
-  part[threadIdx.x] = sum;
-  __syncthreads();
-  for (uint32_t d = 1; d < 256; d <<= 1) {  // inclusive scan of the thread sums
-    const uint32_t v = threadIdx.x >= d ? part[threadIdx.x - d] : 0u;
-    __syncthreads();
-    part[threadIdx.x] += v;
-    __syncthreads();
-  }
-  const uint32_t before = threadIdx.x ? part[threadIdx.x - 1] : 0u;
-  uint32_t* pl = pre + (uint64_t)lvl * n_tiles;
-  for (int j = 0; j < 4; ++j)
-    if (t_base + j < n_tiles) pl[t_base + j] = before + cost[j];
-  if (threadIdx.x == 255) bsum[(uint64_t)lvl * gridDim.x + blockIdx.x] = part[255];
-}
-
 // Exclusive prefix of the block totals of each level (one block per level).
 __global__ __launch_bounds__(1024) void k_cost_block_offsets(const uint32_t* __restrict__ bsum, uint32_t nb,
                                                              uint32_t* __restrict__ boff) {
   block_offsets(bsum + (uint64_t)blockIdx.x * nb, nb, boff + (uint64_t)blockIdx.x * nb);
-}
-
-__global__ __launch_bounds__(256) void k_run_bounds(const uint32_t* __restrict__ pre, const uint32_t* __restrict__ boff,
-                                                    uint32_t nb, uint32_t n_tiles, uint32_t w_first,
-                                                    uint32_t w_rest, uint32_t b_stride,
-                                                    uint32_t* __restrict__ bounds) {
-  const uint32_t lvl = blockIdx.y;
-  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n_tiles) return;
-  run_bounds_of_tile(pre + (uint64_t)lvl * n_tiles, boff + (uint64_t)lvl * nb, n_tiles, t,
-                     lvl == 0 ? w_first : w_rest, bounds + (uint64_t)lvl * b_stride);
-}
-
-hipError_t launch_tile_costs(const uint32_t* hi, const uint32_t* lo, const uint8_t* need, uint64_t need_stride_b,
-                             uint32_t m, uint32_t E, uint32_t levels, uint32_t* pre, uint32_t* bsum, uint32_t* boff,
-                             hipStream_t st) {
-  if (!m || !levels) return hipSuccess;
-  const uint32_t n_tiles = div_up(m, E);
-  const uint32_t nb = div_up(n_tiles, kCostBlock);
-  if (E == 8)
-    hipLaunchKernelGGL(k_tile_cost<8>, dim3(nb, levels), dim3(256), 0, st, need, need_stride_b, m, n_tiles,
-                       pre, bsum);
-  else
-    hipLaunchKernelGGL(k_tile_cost<16>, dim3(nb, levels), dim3(256), 0, st, need, need_stride_b, m,
-                       n_tiles, pre, bsum);
-  hipLaunchKernelGGL(k_cost_block_offsets, dim3(levels), dim3(1024), 0, st, bsum, nb, boff);
-  return hipGetLastError();
-}
-
-hipError_t launch_run_bounds(const uint32_t* hi, const uint32_t* lo, const uint8_t* need, uint64_t need_stride_b,
-                             uint32_t m, uint32_t E, uint32_t levels, uint32_t w_first, uint32_t w_rest,
-                             uint32_t* pre, uint32_t* bsum, uint32_t* boff, uint32_t* bounds, uint32_t b_stride,
-                             hipStream_t st) {
-  if (!m || !levels) return hipSuccess;
-  const uint32_t n_tiles = div_up(m, E);
-  const uint32_t nb = div_up(n_tiles, kCostBlock);
-  hipError_t e = launch_tile_costs(hi, lo, need, need_stride_b, m, E, levels, pre, bsum, boff, st);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_run_bounds, dim3(div_up(n_tiles, 256), levels), dim3(256), 0, st, pre, boff, nb, n_tiles,
-                     w_first, w_rest, b_stride, bounds);
-  return hipGetLastError();
 }
 
 __global__ __launch_bounds__(256) void k_need_counts(const uint32_t* __restrict__ hi, const uint32_t* __restrict__ lo,

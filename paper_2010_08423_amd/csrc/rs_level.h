@@ -769,13 +769,26 @@ __device__ __forceinline__ void top_range(const uint32_t* e_src_p, const uint32_
 // the runs whose first tile it is; the last tile also writes bounds[w] =
 // n_tiles for the runs past it (empty) and for w = W.
 __device__ __forceinline__ void run_bounds_of_tile(const uint32_t* pre, const uint32_t* boff, uint32_t n_tiles,
-                                                   uint32_t t, uint32_t W, uint32_t* bounds) {
+                                                   uint32_t t, uint32_t W, uint32_t* bounds, float skew = 0.0f) {
   auto incl = [&](uint32_t i) { return (uint64_t)pre[i] + boff[i / kCostBlock]; };
   const uint64_t total = incl(n_tiles - 1);
   const uint64_t excl_t = t ? incl(t - 1) : 0;      // cost before tile t
   const uint64_t excl_p = t > 1 ? incl(t - 2) : 0;  // cost before tile t - 1
-  const uint64_t w_hi = excl_t * W / total;
-  const uint64_t w_lo = t ? excl_p * W / total + 1 : 0;
+  // the run in which cost x < total falls (below W). With a skew b, run
+  // u = r / W gets the share (1 - b u) / (1 - b / 2), whose cumulative
+  // F(u) = (u - b u^2 / 2) / (1 - b / 2) inverts to
+  // u = (1 - sqrt(1 - b (2 - b) x / total)) / b. Costs are integers below
+  // 2^32, so consecutive ones move u by more than 2^-33, far above the
+  // rounding error of these double operations: the runs stay monotone in x.
+  auto run_of = [&](uint64_t x) -> uint64_t {
+    if (skew <= 0.0f) return x * W / total;
+    const double b = skew, f = (double)x / (double)total;
+    const double u = (1.0 - __builtin_sqrt(1.0 - b * (2.0 - b) * f)) / b;
+    const uint64_t r = (uint64_t)(u * (double)W);
+    return r < W ? r : W - 1;
+  };
+  const uint64_t w_hi = run_of(excl_t);
+  const uint64_t w_lo = t ? run_of(excl_p) + 1 : 0;
   for (uint64_t w = w_lo; w <= w_hi && w < W; ++w) bounds[w] = t;
   if (t == n_tiles - 1)
     for (uint64_t w = w_hi + 1; w <= W; ++w) bounds[w] = n_tiles;
