@@ -267,7 +267,7 @@ __device__ __forceinline__ uint32_t find_unit(cu32* ubegin, uint32_t from, uint3
 // the neighbouring wave of the same pair and no wave ever waits on another
 // pair.
 template <int KQ, int E, bool FIRST, bool DR = false>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void kb_scan(const MUnit* __restrict__ units, const uint32_t* __restrict__ ubegin_p,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((FIRST || DR || E == 8) ? 5 : 4))) void kb_scan(const MUnit* __restrict__ units, const uint32_t* __restrict__ ubegin_p,
                                                uint32_t nunits, uint32_t total, uint64_t* __restrict__ agg,
                                                uint64_t* __restrict__ incl, unsigned long long* __restrict__ lb_stats) {
   extern __shared__ uint64_t dyn_lds[];  // [waves][16][64]; starts at LDS address 0

@@ -169,18 +169,20 @@ __global__ __launch_bounds__(256) void k_compact_tiles(CompactArgs a, uint32_t t
   if (threadIdx.x == 255) bsum[(uint64_t)y * gridDim.x + blockIdx.x] = part[255];
 }
 
-// Run bounds of the compacted prefix levels: as k_run_bounds, with the tile
-// count of each level read from its list length.
+// Work-balanced run bounds of the compacted prefix levels (one row of threads
+// per level, the tile count read from the level's list length): run w starts
+// at the first tile whose preceding cost reaches its share (run_bounds_of_tile).
 template <int E>
 __global__ __launch_bounds__(256) void k_compact_bounds(const uint32_t* __restrict__ count,
                                                         const uint32_t* __restrict__ pre,
                                                         const uint32_t* __restrict__ boff, uint32_t nb,
-                                                        uint32_t tiles_max, uint32_t w_first, uint32_t w_rest,
-                                                        float skew_first, float skew_rest, uint32_t b_stride,
+                                                        uint32_t tiles_max, uint32_t w_first, uint32_t w_second,
+                                                        uint32_t w_rest, float skew_first, float skew_second,
+                                                        float skew_rest, uint32_t b_stride,
                                                         uint32_t* __restrict__ bounds) {
   const uint32_t y = blockIdx.y;
   const uint32_t n_tiles = (count[y] + E - 1) / E;
-  const uint32_t W = y == 0 ? w_first : w_rest;
+  const uint32_t W = y == 0 ? w_first : (y == 1 ? w_second : w_rest);
   uint32_t* b = bounds + (uint64_t)y * b_stride;
   const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
   if (n_tiles == 0) {  // an empty level: every run is empty
@@ -190,7 +192,7 @@ __global__ __launch_bounds__(256) void k_compact_bounds(const uint32_t* __restri
   }
   if (t < n_tiles)
     run_bounds_of_tile(pre + (uint64_t)y * tiles_max, boff + (uint64_t)y * nb, n_tiles, t, W, b,
-                       y == 0 ? skew_first : skew_rest);
+                       y == 0 ? skew_first : (y == 1 ? skew_second : skew_rest));
 }
 
 // Product rows of the kept edges that form a product (bit 2; every entry of
@@ -265,8 +267,9 @@ hipError_t launch_compact_costs(const CompactArgs& a, uint32_t E, uint32_t tiles
 }
 
 hipError_t launch_compact_bounds(const CompactArgs& a, uint32_t E, uint32_t tiles_max, uint32_t w_first,
-                                 uint32_t w_rest, float skew_first, float skew_rest, uint32_t* pre, uint32_t* bsum,
-                                 uint32_t* boff, uint32_t* bounds, uint32_t b_stride, hipStream_t st) {
+                                 uint32_t w_second, uint32_t w_rest, float skew_first, float skew_second,
+                                 float skew_rest, uint32_t* pre, uint32_t* bsum, uint32_t* boff, uint32_t* bounds,
+                                 uint32_t b_stride, hipStream_t st) {
   if (!a.m || a.k < 3) return hipSuccess;
   hipError_t err = launch_compact_costs(a, E, tiles_max, pre, bsum, boff, st);
   if (err != hipSuccess) return err;
@@ -274,11 +277,11 @@ hipError_t launch_compact_bounds(const CompactArgs& a, uint32_t E, uint32_t tile
   const uint32_t nbt = cdiv(tiles_max, kCostBlock);
   const dim3 g(cdiv((uint64_t)tiles_max + 1, 256), levels);
   if (E == 8)
-    hipLaunchKernelGGL(k_compact_bounds<8>, g, dim3(256), 0, st, a.count, pre, boff, nbt, tiles_max, w_first, w_rest,
-                       skew_first, skew_rest, b_stride, bounds);
+    hipLaunchKernelGGL(k_compact_bounds<8>, g, dim3(256), 0, st, a.count, pre, boff, nbt, tiles_max, w_first, w_second,
+                       w_rest, skew_first, skew_second, skew_rest, b_stride, bounds);
   else
     hipLaunchKernelGGL(k_compact_bounds<16>, g, dim3(256), 0, st, a.count, pre, boff, nbt, tiles_max, w_first,
-                       w_rest, skew_first, skew_rest, b_stride, bounds);
+                       w_second, w_rest, skew_first, skew_second, skew_rest, b_stride, bounds);
   return hipGetLastError();
 }
 

@@ -264,16 +264,17 @@ PlainSizes plain_sizes(uint64_t m, uint64_t n, const QueryPlan& qp, const Tuning
   s.cover = 8 * (m + n + 1) + 8 * ((m + n + 1 + 1023) / 1024);  // two difference arrays and block sums
   s.records = 1024 * cpl * tiles;
   // work-balanced runs, cut for the grid width of a full chunk group
-  s.run_w2 = s.run_w3 = s.run_stride = 0;
+  s.run_w2 = s.run_w3 = s.run_w4 = s.run_stride = 0;
   s.run_pre = s.run_bsum = s.run_boff = s.run_bounds = 0;
   if (k >= 3 && m) {
     const uint32_t E = tu.edges_per_tile;
     s.run_w2 = scan_waves(kq, E, true, (uint32_t)tiles, (uint32_t)cpl, tu.waves_per_block);
-    s.run_w3 = scan_waves(kq, E, false, (uint32_t)tiles, (uint32_t)cpl, tu.waves_per_block);
-    // level 3 from window rows runs on the grid of levels >= 3: it must fit as well
-    if (k >= 4)
-      s.run_w3 = std::min(s.run_w3, scan_waves(kq, E, false, (uint32_t)tiles, (uint32_t)cpl, tu.waves_per_block, true));
-    s.run_stride = std::max(s.run_w2, s.run_w3) + 1;
+    // level 3 is formed from window rows when level 2 is folded (k >= 4); its
+    // kernel holds fewer registers than the gathering one of levels >= 4, so
+    // more of its waves fit
+    s.run_w3 = scan_waves(kq, E, false, (uint32_t)tiles, (uint32_t)cpl, tu.waves_per_block, s.rr != 0);
+    s.run_w4 = scan_waves(kq, E, false, (uint32_t)tiles, (uint32_t)cpl, tu.waves_per_block);
+    s.run_stride = std::max(std::max(s.run_w2, s.run_w3), s.run_w4) + 1;
     const uint64_t levels = k - 2, nb = (tiles + 1023) / 1024;
     s.run_pre = 4 * tiles * levels;
     s.run_bsum = s.run_boff = 4 * nb * levels;
@@ -461,7 +462,7 @@ rs_status run_plain(rs_graph* g, PlainWorkspace& ws, const QueryPlan& qp, const 
       ProfScope ps(KC_ZTABLE, st, 8.0 * n * kq, timed);
       RS_HIP(launch_ztable(ws.z.as<uint64_t>(), (uint32_t)n, qp, G.colour.as<uint8_t>(), st));
     }
-    const uint32_t run_w2 = sz.run_w2, run_w3 = sz.run_w3, run_stride = sz.run_stride;
+    const uint32_t run_w2 = sz.run_w2, run_w3 = sz.run_w3, run_w4 = sz.run_w4, run_stride = sz.run_stride;
     CompactArgs ca{};
     if (k >= 3) {
       const uint64_t L = k - 1, lst = list_stride(m);
@@ -501,8 +502,9 @@ rs_status run_plain(rs_graph* g, PlainWorkspace& ws, const QueryPlan& qp, const 
       // (later groups launch the same width)
       if (k >= 3) {
         RS_HIP(launch_compact(ca, st));
-        RS_HIP(launch_compact_bounds(ca, E, (uint32_t)tiles, run_w2, run_w3, run_skew(run_w2, tu.waves_per_block),
-                                     run_skew(run_w3, tu.waves_per_block), ws.run_pre.as<uint32_t>(),
+        const uint32_t wpb = tu.waves_per_block;
+        RS_HIP(launch_compact_bounds(ca, E, (uint32_t)tiles, run_w2, run_w3, run_w4, run_skew(run_w2, wpb),
+                                     run_skew(run_w3, wpb), run_skew(run_w4, wpb), ws.run_pre.as<uint32_t>(),
                                      ws.run_bsum.as<uint32_t>(), ws.run_boff.as<uint32_t>(),
                                      ws.run_bounds.as<uint32_t>(), run_stride, st));
       }
@@ -619,7 +621,7 @@ rs_status run_plain(rs_graph* g, PlainWorkspace& ws, const QueryPlan& qp, const 
           a.incl = ws.incl.as<uint64_t>();
           a.need = Lc.cflag;
           a.bounds = ws.run_bounds.as<uint32_t>() + (uint64_t)(l - 2) * run_stride;
-          a.waves = first ? run_w2 : run_w3;
+          a.waves = first ? run_w2 : (l == 3 ? run_w3 : run_w4);
           a.count = ca.count + (l - 2);
           if (drows) a.d = ca.list(0).cq;  // the D rows, indexed like level 3's entries
           if (tr) RS_HIP(launch_fill64(ws.lb_stats.as<uint64_t>(), 0, 2, st));

@@ -226,10 +226,12 @@ hipError_t launch_compact(const CompactArgs& a, hipStream_t st);
 hipError_t launch_compact_costs(const CompactArgs& a, uint32_t E, uint32_t tiles_max, uint32_t* pre, uint32_t* bsum,
                                 uint32_t* boff, hipStream_t st);
 // The same, then the work-balanced run bounds [k-2][b_stride] for w_first
-// waves per chunk at level 2 and w_rest above it.
+// waves per chunk at level 2, w_second at level 3 and w_rest above it, each
+// split with its skew (see run_skew).
 hipError_t launch_compact_bounds(const CompactArgs& a, uint32_t E, uint32_t tiles_max, uint32_t w_first,
-                                 uint32_t w_rest, float skew_first, float skew_rest, uint32_t* pre, uint32_t* bsum,
-                                 uint32_t* boff, uint32_t* bounds, uint32_t b_stride, hipStream_t st);
+                                 uint32_t w_second, uint32_t w_rest, float skew_first, float skew_second,
+                                 float skew_rest, uint32_t* pre, uint32_t* bsum, uint32_t* boff, uint32_t* bounds,
+                                 uint32_t b_stride, hipStream_t st);
 // Edges a query's constraints exclude (Sec. 3 and Sec. 4.7): at level 2 an
 // edge whose source is not a source vertex, at the last level one whose
 // destination is not a target vertex, at every level one that touches a
@@ -454,7 +456,8 @@ struct PlainSizes {
   uint64_t grp;                    // last level by distinct windows (k >= 3, not fine-grained)
   uint64_t dv, smask, tmask, rmask;  // constraints (0 when absent)
   uint64_t fine_t, fine_z, fine_r; // fine-grained outputs (0 when not asked)
-  uint32_t run_w2, run_w3, run_stride;  // waves per chunk of level 2 and of levels >= 3; bounds stride
+  // waves per chunk of level 2, of level 3 and of levels >= 4; bounds stride
+  uint32_t run_w2, run_w3, run_w4, run_stride;
   uint64_t total() const;
 };
 PlainSizes plain_sizes(uint64_t m, uint64_t n, const QueryPlan& qp, const Tuning& tu,

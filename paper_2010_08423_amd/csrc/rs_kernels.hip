@@ -20,7 +20,7 @@ namespace rs {
 // published after a bounded wait recomputes that run's tail (see look_back).
 // ---------------------------------------------------------------------------
 template <int KQ, int E, bool FIRST, bool DR = false>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_scan(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((FIRST || DR || E == 8) ? 5 : 4))) void k_scan(
     const uint32_t* __restrict__ e_src, const uint32_t* __restrict__ e_out,
     const uint32_t* __restrict__ hi_idx, const uint32_t* __restrict__ lo_idx,
     const uint64_t* __restrict__ q, const uint64_t* __restrict__ z, const uint64_t* __restrict__ d,

@@ -231,11 +231,16 @@ __device__ __forceinline__ uint64_t subset_xor(const RowBlock<KQ, N>& rb, int i,
 // zero), whose product no read slot needs, or that lies past the tile end
 // skips its gathers on a wave-uniform branch; with a sixth of the edges live
 // at levels >= 3, gathering a cached zero row for the others instead cost 13 %
-// of the launch (0.49 against 0.43 ms on the 10^6-edge graph).
+// of the launch (0.49 against 0.43 ms on the 10^6-edge graph; 11 % on the
+// 10^7-edge motif query). The two rows of a window land in separate registers
+// (w, w2) and are XORed at the product: XORed inside the branch, each live
+// edge waited for its own gathers before the next edge's were issued. Kept
+// apart they are all in flight together, at 115 VGPRs (four waves per SIMD):
+// levels 4..9 of the motif query 4.89 -> 4.72 ms per launch.
 template <int KQ, int E, bool FIRST>
 __device__ __forceinline__ void tile_inputs(const TileCtx& c, uint32_t e0, uint32_t ne, uint32_t lane,
                                             const IdxN<E / 4>& need, uint32_t (&slot)[E], uint32_t (&ia)[E],
-                                            uint64_t (&w)[E]) {
+                                            uint64_t (&w)[E], uint64_t (&w2)[E]) {
   const IdxN<E> so = load_idx<E>(c.e_out + e0);
 #pragma unroll
   for (int i = 0; i < E; ++i) slot[i] = so.v[i];
@@ -252,9 +257,13 @@ __device__ __forceinline__ void tile_inputs(const TileCtx& c, uint32_t e0, uint3
       // also requires a non-empty window and is zero past m
       const bool live = (need.v[i / 4] >> (8 * (i % 4) + 2)) & 1u;
       // wave-uniform branch: only live edges issue their two gathers
-      uint64_t v = 0;
-      if (live) v = p_load(c.pp + (uint64_t)h.v[i] * kLanes + lane) ^ p_load(c.pp + (uint64_t)l.v[i] * kLanes + lane);
+      uint64_t v = 0, v2 = 0;
+      if (live) {
+        v = p_load(c.pp + (uint64_t)h.v[i] * kLanes + lane);
+        v2 = p_load(c.pp + (uint64_t)l.v[i] * kLanes + lane);
+      }
       w[i] = v;
+      w2[i] = v2;
       ia[i] = live;
     }
   }
@@ -420,7 +429,7 @@ __device__ uint64_t look_back(const TileCtx& c, uint32_t run, uint32_t len, uint
 template <int KQ, int E>
 struct TileIn {
   uint32_t slot[E], ia[E];
-  uint64_t w[E];
+  uint64_t w[E], w2[E];
   RowBlock<KQ, E> qr, zr;  // product rows; substitution rows of the sources (level 2, level 3 from D rows)
   RowBlock<KQ, E> dr;      // level 3 from window rows: the entries' D rows
   IdxN<E / 4> need;        // store flags, four edges per word
@@ -434,7 +443,7 @@ __device__ __forceinline__ void load_tile(const TileCtx& c, uint32_t tile, uint3
   load_qrows<KQ, E>(in.qr, c.q, e0, lane);
   if (FIRST || DR) load_zrows<KQ, E>(in.zr, c.z, c.e_src, e0, ne, lane);
   if (DR) load_qrows<KQ, E>(in.dr, c.d, e0, lane);
-  tile_inputs<KQ, E, FIRST || DR>(c, e0, ne, lane, in.need, in.slot, in.ia, in.w);
+  tile_inputs<KQ, E, FIRST || DR>(c, e0, ne, lane, in.need, in.slot, in.ia, in.w, in.w2);
 }
 
 // One prefix level (2..k-1) over the run of tiles of wave w of W: the tiles
@@ -494,7 +503,7 @@ __device__ __forceinline__ void scan_run(const TileCtx& c, uint32_t w, uint32_t 
         }
         if (needs(i)) {
           const uint64_t aL = subset_xor<KQ, E>(in.qr, i, c.cb, mk);
-          uint64_t wv = in.w[i];
+          uint64_t wv = in.w[i] ^ in.w2[i];
           if (FIRST || DR) wv = subset_xor<KQ, E>(in.zr, i, c.cb, mk);
           if (DR) wv = gf_mul(tab, wv, subset_xor<KQ, E>(in.dr, i, c.cb, mk));  // z^L_src * D^L
           acc ^= gf_mul(tab, aL, wv);
