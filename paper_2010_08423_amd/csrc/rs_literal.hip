@@ -203,9 +203,13 @@ __global__ __launch_bounds__(256) void k_lit_level(LitArgs a) {
       const uint32_t lo = wlo[e], hi = whi[e];
       if (lo != hi) {
         const uint64_t h = lit_edge_key(a.hp, v, dst[e]);
+        // the next window slot's row is in flight during this slot's product
+        // (the last slot's row is loaded twice)
+        uint64_t xn = p_load(prev + (uint64_t)lo * kLanes + lane);
         for (uint32_t s = lo; s < hi; ++s) {
+          const uint64_t x = xn;
+          xn = p_load(prev + (uint64_t)(s + 1 < hi ? s + 1 : s) * kLanes + lane);
           const uint64_t y = lit_y(h, slot_t[s], a.level - 1);
-          const uint64_t x = p_load(prev + (uint64_t)s * kLanes + lane);
           acc ^= gf_mul_uniform(region, lane, y, x);
         }
       }
