@@ -1020,6 +1020,7 @@ rs_status run_batch_impl(const rs_graph* const* graphs, const rs_query* queries,
   // launch shape: explicit knobs, else the graph's autotuned batch shape, else defaults
   Tuning tu;
   tu.top_edges_per_tile = 128;
+  tu.waves_per_block = 2;
   if (graphs[0] && graphs[0]->has_batch_tuned) tu = graphs[0]->batch_tuned;
   if (tune) {
     if (tune->edges_per_tile) tu.edges_per_tile = tune->edges_per_tile;
@@ -1186,7 +1187,7 @@ rs_status autotune_impl(rs_graph* g, const rs_query* sample, uint32_t ns, rs_tun
           if (E == 8 && g->g.m > kMaxEdgesE8) continue;
           Tuning t;
           t.edges_per_tile = E;
-          t.waves_per_block = wpb;
+          t.waves_per_block = t.top_waves_per_block = wpb;
           t.top_edges_per_tile = top;
           t.chunks_per_launch = cpl;
           cands.push_back(t);

@@ -183,12 +183,14 @@ Tuning resolve_tuning(const rs_graph* g, uint32_t k, const rs_tuning* t) {
     if (t->edges_per_tile) tu.edges_per_tile = t->edges_per_tile;
     if (t->top_edges_per_tile) tu.top_edges_per_tile = t->top_edges_per_tile;
     if (t->chunks_per_launch) tu.chunks_per_launch = t->chunks_per_launch;
-    if (t->waves_per_block) tu.waves_per_block = t->waves_per_block;
+    if (t->waves_per_block) tu.waves_per_block = tu.top_waves_per_block = t->waves_per_block;
     if (t->max_slots) tu.max_slots = t->max_slots;
   }
   if (tu.edges_per_tile != 8 && tu.edges_per_tile != 16) tu.edges_per_tile = 16;
   tu.top_edges_per_tile = std::min(std::max(tu.top_edges_per_tile, 1u), 4096u);
-  if (tu.waves_per_block != 1 && tu.waves_per_block != 2 && tu.waves_per_block != 4) tu.waves_per_block = 2;
+  if (tu.waves_per_block != 1 && tu.waves_per_block != 2 && tu.waves_per_block != 4) tu.waves_per_block = 4;
+  if (tu.top_waves_per_block != 1 && tu.top_waves_per_block != 2 && tu.top_waves_per_block != 4)
+    tu.top_waves_per_block = 2;
   if (tu.chunks_per_launch < 1) tu.chunks_per_launch = 1;
   return tu;
 }

@@ -122,7 +122,7 @@ static void top_fine_kq(const TopArgs& a, bool first, uint32_t chunks, uint32_t 
 hipError_t launch_top_fine(const TopArgs& a, bool first_level, uint32_t kq, uint32_t chunks, const Tuning& tu,
                            uint64_t* T, hipStream_t st) {
   if (!a.m) return hipSuccess;
-  const uint32_t wpb = tu.waves_per_block;
+  const uint32_t wpb = tu.top_waves_per_block;
   switch (kq) {
     case 4: top_fine_kq<4>(a, first_level, chunks, wpb, T, st); break;
     case 8: top_fine_kq<8>(a, first_level, chunks, wpb, T, st); break;

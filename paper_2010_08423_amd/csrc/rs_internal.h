@@ -70,7 +70,14 @@ struct Tuning {
   uint32_t edges_per_tile = 16;      // scan levels: 8 or 16
   uint32_t top_edges_per_tile = 64;  // last level: edges per wave's range
   uint32_t chunks_per_launch = 4;
-  uint32_t waves_per_block = 2;
+  // Waves per block of the prefix levels and of the last level (one knob for
+  // both when set). The gathering level kernel holds four waves per SIMD;
+  // in blocks of four, one per SIMD, it ran levels 4..9 of the 10^7-edge
+  // motif query in 4.49 ms per launch against 4.68 in blocks of two, while
+  // the last level ran best in blocks of two (10^6-edge path query: 0.44
+  // against 0.47 ms).
+  uint32_t waves_per_block = 4;
+  uint32_t top_waves_per_block = 2;
   uint32_t max_slots = 0;  // batched path; 0 = as many as fit
 };
 

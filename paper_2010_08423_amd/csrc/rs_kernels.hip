@@ -538,17 +538,17 @@ static void top_kq(const TopArgs& a, bool first, uint32_t chunks, uint32_t wpb, 
 
 uint32_t top_blocks(const TopArgs& a, bool first, uint32_t kq, uint32_t chunks, const Tuning& tu) {
   switch (kq) {
-    case 4: return top_blocks_kq<4>(a, first, chunks, tu.waves_per_block);
-    case 8: return top_blocks_kq<8>(a, first, chunks, tu.waves_per_block);
-    case 12: return top_blocks_kq<12>(a, first, chunks, tu.waves_per_block);
-    default: return top_blocks_kq<16>(a, first, chunks, tu.waves_per_block);
+    case 4: return top_blocks_kq<4>(a, first, chunks, tu.top_waves_per_block);
+    case 8: return top_blocks_kq<8>(a, first, chunks, tu.top_waves_per_block);
+    case 12: return top_blocks_kq<12>(a, first, chunks, tu.top_waves_per_block);
+    default: return top_blocks_kq<16>(a, first, chunks, tu.top_waves_per_block);
   }
 }
 
 hipError_t launch_top(const TopArgs& a, bool first_level, uint32_t kq, uint32_t chunks,
                       const Tuning& tu, hipStream_t st) {
   if (!a.m) return hipSuccess;
-  const uint32_t wpb = tu.waves_per_block;
+  const uint32_t wpb = tu.top_waves_per_block;
   const uint32_t blocks = top_blocks(a, first_level, kq, chunks, tu);
   switch (kq) {
     case 4: top_kq<4>(a, first_level, chunks, wpb, blocks, st); break;
