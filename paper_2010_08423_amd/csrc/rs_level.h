@@ -479,6 +479,13 @@ __device__ __forceinline__ void scan_run(const TileCtx& c, uint32_t w, uint32_t 
   for (uint32_t tile = t0;;) {
     const uint32_t e0 = tile * (uint32_t)E;
     const TileIn<KQ, E>& in = cur;
+    // Wait once for all of this tile's rows and gathers. Without this the
+    // compiler, which cannot count the loads issued under the per-edge
+    // branches, put a full vmcnt(0) before every product, and that wait also
+    // covered the slot stores issued by the edges before it: each stored slot
+    // cost a store round trip before the next product. Levels 4..9 of the
+    // 10^7-edge motif query: 4.48 -> 4.06 ms per launch.
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0); expcnt, lgkmcnt at their maxima (no wait)
     // an edge needs a product when it reaches a read slot and, at levels >= 3,
     // its window is non-empty (need bit 2 says both). The flags of the edges
     // past m are zero, so the tile's edges need no range test: a segment
