@@ -194,7 +194,11 @@ __global__ __launch_bounds__(256) void k_lit_level(LitArgs a) {
   uint64_t acc = 0;
   for (uint64_t e = e0; e < e1; ++e) {
     const uint32_t sl = slot[e];
-    if (!LAST && !a.need[sl]) continue;  // no window reads this slot at the next level
+    // no window reads this slot at the next level. The flag byte is read with
+    // a scalar load of its word: a vector byte load here made every edge wait
+    // (vmcnt) for the slot stores of the edges before it.
+    if (!LAST && !((*(const __attribute__((address_space(4))) uint32_t*)(a.need + (sl & ~3u)) >> (8 * (sl & 3u))) & 0xFFu))
+      continue;
     const uint32_t v = src[e];
     if (FIRST) {
       const uint64_t zv = subset_xor<KQ>(as_const(a.z) + (uint64_t)v * KQ, cb, mk);
