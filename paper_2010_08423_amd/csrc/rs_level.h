@@ -693,7 +693,7 @@ __device__ __forceinline__ void scan_level(const TileCtx& c, uint32_t w, uint32_
 }
 
 // Last level k over edges [e0, e1): unreduced per-lane sum of c_k(e) into r.
-// Edges go in batches of 8: one scalar load per index array and batch. Two
+// Edges go in batches of 4: one scalar load per index array and batch. Two
 // batches alternate, so the next batch's gathers and rows are in flight
 // during this batch's products; the two rows of a window stay apart until
 // the product, so no load waits for its partner. Empty windows gather the
@@ -710,7 +710,7 @@ __device__ __forceinline__ void top_range(const uint32_t* e_src_p, const uint32_
                                           const uint32_t (&mk)[6], uint64_t* tab, Acc128& r) {
   if (e0 >= e1) return;
   const uint32_t base = lds_addr(tab);
-  constexpr int B = 8;
+  constexpr int B = 4;
   constexpr int P = RowBlock<KQ, B>::P;
   const uint64_t* zero = kZeroRow + lane;
   struct Batch {
@@ -759,13 +759,22 @@ __device__ __forceinline__ void top_range(const uint32_t* e_src_p, const uint32_
       }
     }
   };
+  // The empty asm statements are compiler barriers for memory operations
+  // (no instruction): without them the compiler sank the loads of the batch
+  // gathered ahead into the products that use them, so that batch's gathers
+  // waited one by one. Batches of 4 keep both in flight at 79 VGPRs (batches
+  // of 8 needed 112, four waves per SIMD, and ran slower): the last level of
+  // the 10^7-edge motif query 6.54 -> 6.45 ms per launch, of the 10^6-edge
+  // path query 0.429 -> 0.416 ms.
   Batch x, y;
   gather(e0, x);
   for (uint32_t eb = e0;; eb += 2 * B) {
     gather(eb + B, y);
+    asm volatile("" ::: "memory");
     compute(x);
     if (eb + B >= e1) break;
     gather(eb + 2 * B, x);
+    asm volatile("" ::: "memory");
     compute(y);
     if (eb + 2 * B >= e1) break;
   }
