@@ -148,6 +148,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--mode", default="plain", choices=["plain", "batch", "serve", "copy", "literal"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="--mode batch: the batched calls alone in the default shape (for kernel traces)")
     ap.add_argument("--workload", default="motif-scale", choices=sorted(WORKLOADS),
                     help="plain mode: the query timed (default: the 10^7-edge motif query)")
     # serve mode: offered load, arrival window, wall-clock cap, server budget

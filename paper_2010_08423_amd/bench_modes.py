@@ -47,6 +47,8 @@ def run_batch_mode(args):
     m = gd.info()["m"]
     qs = inputs.batch_mix()
     upd = sum(_updates(m, q) for q in qs)
+    if getattr(args, "batch_only", False):
+        return _batch_only(args, gd, qs, upd)
     # autotune on one query per k of the mix, each cut to its first four
     # 64-iteration chunks: every level structure of the mix is timed, and the
     # tuning time stays bounded
@@ -123,6 +125,42 @@ def run_batch_mode(args):
         "speedup_vs_plain": plain_s / dt,
         "fingerprints_equal": True,
         "lookback_one_batch": {"recomputed_predecessor_runs": lb_batch[0], "unanswered_probe_rounds": lb_batch[1]},
+    }
+
+
+def _batch_only(args, gd, qs, upd):
+    """The batched calls alone, in the default launch shape (no autotuner, no
+    plain reference): the run a kernel trace of the batched path profiles."""
+    import torch
+
+    graphs = [gd] * len(qs)
+    for _ in range(args.warmup):
+        R.run_batch(graphs, qs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        res, st = R.run_batch(graphs, qs)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    if st != R.RS_OK:
+        raise SystemExit(f"rs_run_batch failed: {st}")
+    return {
+        "metric": "queries/s (batched calls alone, default launch shape)",
+        "value": len(qs) / dt,
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": "64-query batch on Chung-Lu(2.5) n=100000 m=1000000 t in [1,1000]: k in 4..12, "
+                               "delta in 2..50, half motif over 8 colours, seeds 100..163",
+                   "edge_updates_per_step": upd},
+        "batched": {"queries_per_s": len(qs) / dt, "edge_updates_per_s": upd / dt, "s_per_batch": dt},
     }
 
 
