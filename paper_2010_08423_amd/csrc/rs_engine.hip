@@ -259,7 +259,7 @@ PlainSizes plain_sizes(uint64_t m, uint64_t n, const QueryPlan& qp, const Tuning
   const uint64_t groups = (nchunks + cpl - 1) / cpl;
   s.grp = k >= 3 && m && groups >= 2 && !(ex && ex->fine) ? group_bytes(m, n, kq) : 0;
   s.p = 8 * (m + n) * 64 * cpl;
-  s.partial = 8 * 64 * cpl * (uint64_t)tblocks;
+  s.partial = 8 * 64 * cpl * (uint64_t)tblocks + 4 * cpl;  // block rows, then one range ticket per chunk
   s.fsum = 8 * (1ull << k);
   s.ref = 2 * flag_ref_bytes(m, n);  // two levels' read marks, alternating
   s.need = table_need_bytes(m, k);
@@ -670,6 +670,17 @@ rs_status run_plain(rs_graph* g, PlainWorkspace& ws, const QueryPlan& qp, const 
           a.k = k;
           a.partial = ws.partial.as<uint64_t>();
           a.fsum = ws.fsum.as<uint64_t>();
+          // Ranges by tickets when a wave has many of them (the 10^7-edge motif
+          // query: about 270 per wave, 6.47 -> 6.28 ms per launch); with few
+          // per wave the atomics cost more than the balance gains (10^6-edge
+          // path query, about 14 per wave: 0.42 -> 0.47 ms). The tickets follow
+          // the block rows of a full chunk group.
+          const uint64_t t1 = top_blocks(a, first, kq, 1, tu);
+          const uint64_t top_waves = (uint64_t)top_blocks(a, first, kq, gc, tu) * tu.top_waves_per_block;
+          if (!fine && (m + tu.top_edges_per_tile - 1) / tu.top_edges_per_tile >= 32 * top_waves) {
+            a.ticket = reinterpret_cast<uint32_t*>(ws.partial.as<uint8_t>() + 8 * 64 * cpl * t1);
+            RS_HIP(launch_fill32(a.ticket, 0, gc, st));
+          }
           {
             ProfScope ps(KC_TOP, st, top_bytes(ncs[k], m, kq, gc, first, top_units), timed);
             if (fine)

@@ -139,6 +139,7 @@ struct TopArgs {
   uint32_t edges_per_wave;
   uint32_t k;
   uint64_t* partial;  // [chunks][blocks][64] per-block sums
+  uint32_t* ticket = nullptr;  // null (static ranges), or [chunks] zeroed next-range counters
   uint64_t* fsum;     // [2^k] per-iteration sums
   const uint32_t* count = nullptr;  // null, or the device-side length of the compacted last-level list
   const uint32_t* ce = nullptr;     // compacted list: original edge of each entry (fine-grained outputs)

@@ -83,7 +83,7 @@ __global__ __launch_bounds__(256) void k_top(
     const uint32_t* __restrict__ lo_idx, const uint64_t* __restrict__ q,
     const uint64_t* __restrict__ z, const uint64_t* __restrict__ p_prev, uint64_t p_stride,
     uint64_t chunk_base, uint32_t m_max, uint32_t edges_per_wave, uint64_t* __restrict__ partial,
-    const uint32_t* __restrict__ count) {
+    const uint32_t* __restrict__ count, uint32_t* __restrict__ ticket) {
   extern __shared__ uint64_t dyn_lds[];  // [waves][16][64]; starts at LDS address 0
   const uint32_t m = count ? __builtin_amdgcn_readfirstlane(*as_const(count)) : m_max;  // compacted list length
   const uint32_t lane = threadIdx.x & 63u;
@@ -97,11 +97,27 @@ __global__ __launch_bounds__(256) void k_top(
   lane_masks(lane, mk);
   const uint64_t waves = (uint64_t)gridDim.x * nw;
   Acc128 r = {0, 0, 0, 0};
-  for (uint64_t wave_id = (uint64_t)blockIdx.x * nw + wv; wave_id * edges_per_wave < m; wave_id += waves) {
-    const uint64_t e0 = wave_id * edges_per_wave;
-    const uint32_t e1 = (uint32_t)min((uint64_t)m, e0 + edges_per_wave);
-    top_range<KQ, FIRST>(e_src, hi_idx, lo_idx, q, z, p_prev + (uint64_t)chunk * p_stride, cb,
-                                (uint32_t)e0, e1, lane, mk, tab, r);
+  if (ticket) {
+    // ranges handed out in arrival order: waves dispatched later run slower,
+    // and a wave that finishes early takes the next range (the sum is an XOR,
+    // so the assignment does not change the result)
+    for (;;) {
+      uint32_t rid = 0;
+      if (lane == 0) rid = atomicAdd(ticket + chunk, 1u);
+      rid = __builtin_amdgcn_readfirstlane(rid);
+      const uint64_t e0 = (uint64_t)rid * edges_per_wave;
+      if (e0 >= m) break;
+      const uint32_t e1 = (uint32_t)min((uint64_t)m, e0 + edges_per_wave);
+      top_range<KQ, FIRST>(e_src, hi_idx, lo_idx, q, z, p_prev + (uint64_t)chunk * p_stride, cb,
+                                  (uint32_t)e0, e1, lane, mk, tab, r);
+    }
+  } else {
+    for (uint64_t wave_id = (uint64_t)blockIdx.x * nw + wv; wave_id * edges_per_wave < m; wave_id += waves) {
+      const uint64_t e0 = wave_id * edges_per_wave;
+      const uint32_t e1 = (uint32_t)min((uint64_t)m, e0 + edges_per_wave);
+      top_range<KQ, FIRST>(e_src, hi_idx, lo_idx, q, z, p_prev + (uint64_t)chunk * p_stride, cb,
+                                  (uint32_t)e0, e1, lane, mk, tab, r);
+    }
   }
   const uint64_t f = gf_reduce(r);
   // XOR the block's waves through LDS entry T[1] of each wave's table.
@@ -530,10 +546,10 @@ static void top_kq(const TopArgs& a, bool first, uint32_t chunks, uint32_t wpb, 
   dim3 g(blocks, chunks), b(64 * wpb);
   if (first)
     hipLaunchKernelGGL((k_top<KQ, true>), g, b, lds, st, a.e_src, a.hi, a.lo, a.q, a.z, a.p_prev,
-                       a.p_stride, a.chunk_base, a.m, a.edges_per_wave, a.partial, a.count);
+                       a.p_stride, a.chunk_base, a.m, a.edges_per_wave, a.partial, a.count, a.ticket);
   else
     hipLaunchKernelGGL((k_top<KQ, false>), g, b, lds, st, a.e_src, a.hi, a.lo, a.q, a.z, a.p_prev,
-                       a.p_stride, a.chunk_base, a.m, a.edges_per_wave, a.partial, a.count);
+                       a.p_stride, a.chunk_base, a.m, a.edges_per_wave, a.partial, a.count, a.ticket);
 }
 
 uint32_t top_blocks(const TopArgs& a, bool first, uint32_t kq, uint32_t chunks, const Tuning& tu) {
