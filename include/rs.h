@@ -158,6 +158,16 @@ typedef struct {
   uint32_t no_graph;           /* batched path: 1 = enqueue the launches
                                   directly instead of replaying a captured
                                   hipGraph */
+  uint32_t chunks_per_wave;    /* plain path: 1 or 2 chunks per wavefront
+                                  in the last level (2: one wavefront sums 128
+                                  iterations and forms each entry's indices and
+                                  row sums once for both chunks). It applies to
+                                  queries with k >= 7 whose iteration range
+                                  covers an even number of chunks from an even
+                                  chunk, with an even chunks_per_launch; the
+                                  fine-grained last level and any other query
+                                  run with 1. 0 = automatic (2 where it
+                                  applies). Results are identical. */
 } rs_tuning;
 
 /* HBM bytes rs_run needs for this query on this graph beyond the graph

@@ -56,7 +56,8 @@ class _Result(ctypes.Structure):
 class _Tuning(ctypes.Structure):
     _fields_ = [("edges_per_tile", ctypes.c_uint32), ("top_edges_per_tile", ctypes.c_uint32),
                 ("chunks_per_launch", ctypes.c_uint32), ("waves_per_block", ctypes.c_uint32),
-                ("max_slots", ctypes.c_uint32), ("no_graph", ctypes.c_uint32)]
+                ("max_slots", ctypes.c_uint32), ("no_graph", ctypes.c_uint32),
+                ("chunks_per_wave", ctypes.c_uint32)]
 
 
 class _Constraints(ctypes.Structure):
@@ -215,10 +216,11 @@ class Tuning:
     waves_per_block: int = 0
     max_slots: int = 0
     no_graph: int = 0
+    chunks_per_wave: int = 0
 
     def _c(self):
         return _Tuning(self.edges_per_tile, self.top_edges_per_tile, self.chunks_per_launch, self.waves_per_block,
-                       self.max_slots, self.no_graph)
+                       self.max_slots, self.no_graph, self.chunks_per_wave)
 
 
 class Graph:
@@ -501,7 +503,7 @@ def autotune_batch(graph: Graph, sample_queries) -> Tuning:
     _check(_load().rs_autotune_batch(graph.handle, qs, ns, ctypes.byref(out)), "rs_autotune_batch")
     del keep
     return Tuning(out.edges_per_tile, out.top_edges_per_tile, out.chunks_per_launch, out.waves_per_block,
-                  out.max_slots, out.no_graph)
+                  out.max_slots, out.no_graph, out.chunks_per_wave)
 
 
 def autotune(graph: Graph, sample_queries) -> Tuning:
@@ -515,7 +517,7 @@ def autotune(graph: Graph, sample_queries) -> Tuning:
     _check(_load().rs_autotune(graph.handle, qs, ns, ctypes.byref(out)), "rs_autotune")
     del keep
     return Tuning(out.edges_per_tile, out.top_edges_per_tile, out.chunks_per_launch, out.waves_per_block,
-                  out.max_slots, out.no_graph)
+                  out.max_slots, out.no_graph, out.chunks_per_wave)
 
 
 # --- kernel timing -------------------------------------------------------------

@@ -329,12 +329,12 @@ __global__ __launch_bounds__(256) void kb_top(const MUnit* __restrict__ units, c
   uint64_t* fsum = nullptr;
   uint64_t cb = 0, it_begin = 0, it_end = 0;
   uint32_t m = 0;
-  Acc128 r = {0, 0, 0, 0};
+  Acc128 r[1] = {{0, 0, 0, 0}};
   auto flush = [&]() {
-    const uint64_t f = gf_reduce(r);
+    const uint64_t f = gf_reduce(r[0]);
     const uint64_t it = cb + lane;
     if (it >= it_begin && it < it_end && f) atomicXor((unsigned long long*)&fsum[it], (unsigned long long)f);
-    r = Acc128{0, 0, 0, 0};
+    r[0] = Acc128{0, 0, 0, 0};
   };
   for (uint32_t t = blockIdx.x * (blockDim.x >> 6) + wv; t < total; t += waves) {
     if (t >= u_end) {
@@ -357,7 +357,7 @@ __global__ __launch_bounds__(256) void kb_top(const MUnit* __restrict__ units, c
     }
     const uint32_t e0 = (t - u_begin) * top_edges;
     const uint32_t e1 = min(m, e0 + top_edges);
-    top_range<KQ, FIRST>(e_src, hi, lo, q, z, pp, cb, e0, e1, lane, mk, tab, r);
+    top_range<KQ, FIRST>(e_src, hi, lo, q, z, pp, 0, cb, e0, e1, lane, mk, tab, r);
   }
   if (u_end != 0) flush();
 }

@@ -185,7 +185,9 @@ Tuning resolve_tuning(const rs_graph* g, uint32_t k, const rs_tuning* t) {
     if (t->chunks_per_launch) tu.chunks_per_launch = t->chunks_per_launch;
     if (t->waves_per_block) tu.waves_per_block = tu.top_waves_per_block = t->waves_per_block;
     if (t->max_slots) tu.max_slots = t->max_slots;
+    if (t->chunks_per_wave) tu.chunks_per_wave = t->chunks_per_wave;
   }
+  if (tu.chunks_per_wave != 1 && tu.chunks_per_wave != 2) tu.chunks_per_wave = 2;
   if (tu.edges_per_tile != 8 && tu.edges_per_tile != 16) tu.edges_per_tile = 16;
   tu.top_edges_per_tile = std::min(std::max(tu.top_edges_per_tile, 1u), 4096u);
   if (tu.waves_per_block != 1 && tu.waves_per_block != 2 && tu.waves_per_block != 4) tu.waves_per_block = 4;
@@ -196,6 +198,21 @@ Tuning resolve_tuning(const rs_graph* g, uint32_t k, const rs_tuning* t) {
 }
 
 static uint64_t chunks_of(const QueryPlan& qp) { return qp.chunk_last - qp.chunk_first; }
+
+// The launch shape a plain query runs with. The last level runs two chunks
+// per wave when every chunk group holds an even number of chunks from an even
+// chunk (so a pair's iterations differ only in bit 6) and the rows have at
+// least 7 entries (k >= 7, which two chunks imply for a full range); the
+// fine-grained last level reads one chunk per wave. (Two chunks per wave in
+// the prefix levels measured slower.) Idempotent.
+static Tuning query_tuning(Tuning tu, const QueryPlan& qp, bool fine) {
+  const uint64_t nch = chunks_of(qp);
+  const uint64_t cpl = std::min<uint64_t>(tu.chunks_per_launch, nch);
+  const bool pairs = tu.chunks_per_wave == 2 && !fine && qp.k >= 7 && nch >= 2 && nch % 2 == 0 &&
+                     qp.chunk_first % 2 == 0 && cpl % 2 == 0;
+  if (!pairs) tu.chunks_per_wave = 1;
+  return tu;
+}
 
 // Algorithmic HBM bytes of one level launch over `chunks` 64-iteration
 // chunks: what the exact computation has to move once edges whose window is
@@ -235,7 +252,8 @@ uint64_t table_need_bytes(uint64_t m, uint32_t k) { return (uint64_t)need_levels
 // Plain path: setup kernels, then per chunk group levels 2..k.
 // ---------------------------------------------------------------------------
 // Buffer sizes (bytes) one query needs in a plain workspace.
-PlainSizes plain_sizes(uint64_t m, uint64_t n, const QueryPlan& qp, const Tuning& tu, const QueryExtras* ex) {
+PlainSizes plain_sizes(uint64_t m, uint64_t n, const QueryPlan& qp, const Tuning& tu_in, const QueryExtras* ex) {
+  const Tuning tu = query_tuning(tu_in, qp, ex && ex->fine);
   PlainSizes s;
   const uint32_t k = qp.k, kq = qp.kq;
   const uint64_t nchunks = std::max<uint64_t>(chunks_of(qp), 1);
@@ -383,10 +401,11 @@ static rs_status acquire_buffers(PlainWorkspace& ws, const PlainSizes& sz, uint6
   return RS_OK;
 }
 
-rs_status run_plain(rs_graph* g, PlainWorkspace& ws, const QueryPlan& qp, const Tuning& tu, uint64_t* per_it_host,
+rs_status run_plain(rs_graph* g, PlainWorkspace& ws, const QueryPlan& qp, const Tuning& tu_in, uint64_t* per_it_host,
                     rs_result* r, hipStream_t st, QueryExtras* ex) {
   const GraphDev& G = g->g;
   const bool fine = ex && ex->fine;
+  const Tuning tu = query_tuning(tu_in, qp, fine);
   const uint64_t m = G.m, n = G.n;
   const uint64_t span = qp.it_end - qp.it_begin;
   const bool timed = !ws.scratch;  // the no-allocation workspace records no events

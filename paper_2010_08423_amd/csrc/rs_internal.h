@@ -79,6 +79,9 @@ struct Tuning {
   uint32_t waves_per_block = 4;
   uint32_t top_waves_per_block = 2;
   uint32_t max_slots = 0;  // batched path; 0 = as many as fit
+  // Plain path: chunks per wave of the last level (1 or 2; see query_tuning
+  // for when 2 applies).
+  uint32_t chunks_per_wave = 2;
 };
 
 struct QueryPlan {

@@ -75,9 +75,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((FIRST || D
 // ---------------------------------------------------------------------------
 // Last level k: grid-stride over edge ranges, per-lane sums XORed across the
 // block in LDS, one partial row per block (no contended atomics); k_top_fold
-// folds the rows into the per-iteration sums.
+// folds the rows into the per-iteration sums. With H = 2 a wave sums a chunk
+// pair (gridDim.y counts pairs) and writes both chunks' rows.
 // ---------------------------------------------------------------------------
-template <int KQ, bool FIRST>
+template <int KQ, bool FIRST, int H = 1>
 __global__ __launch_bounds__(256) void k_top(
     const uint32_t* __restrict__ e_src, const uint32_t* __restrict__ hi_idx,
     const uint32_t* __restrict__ lo_idx, const uint64_t* __restrict__ q,
@@ -91,12 +92,16 @@ __global__ __launch_bounds__(256) void k_top(
   const uint32_t nw = blockDim.x >> 6;
   uint64_t* tab = dyn_lds + wv * 16 * kLanes + lane;
   tab[0] = 0;
-  const uint32_t chunk = blockIdx.y;
-  const uint64_t cb = chunk_base + (uint64_t)chunk * kLanes;
+  const uint32_t chunk = blockIdx.y;  // chunk pair when H = 2
+  const uint64_t chunk0 = (uint64_t)chunk * H;
+  const uint64_t cb = chunk_base + chunk0 * kLanes;
+  const uint64_t* pp = p_prev + chunk0 * p_stride;
   uint32_t mk[6];
   lane_masks(lane, mk);
   const uint64_t waves = (uint64_t)gridDim.x * nw;
-  Acc128 r = {0, 0, 0, 0};
+  Acc128 r[H];
+#pragma unroll
+  for (int h = 0; h < H; ++h) r[h] = Acc128{0, 0, 0, 0};
   if (ticket) {
     // ranges handed out in arrival order: waves dispatched later run slower,
     // and a wave that finishes early takes the next range (the sum is an XOR,
@@ -108,26 +113,28 @@ __global__ __launch_bounds__(256) void k_top(
       const uint64_t e0 = (uint64_t)rid * edges_per_wave;
       if (e0 >= m) break;
       const uint32_t e1 = (uint32_t)min((uint64_t)m, e0 + edges_per_wave);
-      top_range<KQ, FIRST>(e_src, hi_idx, lo_idx, q, z, p_prev + (uint64_t)chunk * p_stride, cb,
-                                  (uint32_t)e0, e1, lane, mk, tab, r);
+      top_range<KQ, FIRST, H>(e_src, hi_idx, lo_idx, q, z, pp, p_stride, cb, (uint32_t)e0, e1, lane, mk, tab, r);
     }
   } else {
     for (uint64_t wave_id = (uint64_t)blockIdx.x * nw + wv; wave_id * edges_per_wave < m; wave_id += waves) {
       const uint64_t e0 = wave_id * edges_per_wave;
       const uint32_t e1 = (uint32_t)min((uint64_t)m, e0 + edges_per_wave);
-      top_range<KQ, FIRST>(e_src, hi_idx, lo_idx, q, z, p_prev + (uint64_t)chunk * p_stride, cb,
-                                  (uint32_t)e0, e1, lane, mk, tab, r);
+      top_range<KQ, FIRST, H>(e_src, hi_idx, lo_idx, q, z, pp, p_stride, cb, (uint32_t)e0, e1, lane, mk, tab, r);
     }
   }
-  const uint64_t f = gf_reduce(r);
-  // XOR the block's waves through LDS entry T[1] of each wave's table.
-  __syncthreads();
-  tab[kLanes] = f;
-  __syncthreads();
-  if (wv == 0) {
-    uint64_t s = 0;
-    for (uint32_t k2 = 0; k2 < nw; ++k2) s ^= dyn_lds[k2 * 16 * kLanes + kLanes + lane];
-    partial[((uint64_t)chunk * gridDim.x + blockIdx.x) * kLanes + lane] = s;
+  // XOR the block's waves through LDS entry T[1] of each wave's table, one
+  // chunk at a time.
+#pragma unroll
+  for (int h = 0; h < H; ++h) {
+    const uint64_t f = gf_reduce(r[h]);
+    __syncthreads();
+    tab[kLanes] = f;
+    __syncthreads();
+    if (wv == 0) {
+      uint64_t s = 0;
+      for (uint32_t k2 = 0; k2 < nw; ++k2) s ^= dyn_lds[k2 * 16 * kLanes + kLanes + lane];
+      partial[((chunk0 + h) * gridDim.x + blockIdx.x) * kLanes + lane] = s;
+    }
   }
 }
 
@@ -531,48 +538,68 @@ hipError_t launch_scan(const ScanArgs& a, bool first_level, uint32_t kq, uint32_
 }
 
 // Blocks of the last-level launch (also the number of partial rows per chunk).
+// With two chunks per wave the grid has a row per chunk pair.
 template <int KQ>
-static uint32_t top_blocks_kq(const TopArgs& a, bool first, uint32_t chunks, uint32_t wpb) {
+static uint32_t top_blocks_kq(const TopArgs& a, bool first, uint32_t chunks, uint32_t wpb, uint32_t cpw) {
   const uint32_t waves = div_up(a.m, a.edges_per_wave);
   const size_t lds = (size_t)wpb * 16 * kLanes * 8;
   const void* kern = first ? (const void*)k_top<KQ, true> : (const void*)k_top<KQ, false>;
-  const uint32_t fit = std::max(1u, resident_blocks(kern, 64 * wpb, lds) / chunks);
+  if constexpr (KQ > 6) {
+    if (cpw == 2 && !first) kern = (const void*)k_top<KQ, false, 2>;
+  }
+  const uint32_t rows = std::max(1u, cpw == 2 && !first ? chunks / 2 : chunks);
+  const uint32_t fit = std::max(1u, resident_blocks(kern, 64 * wpb, lds) / rows);
   return std::min(div_up(waves, wpb), fit);
 }
 
 template <int KQ>
-static void top_kq(const TopArgs& a, bool first, uint32_t chunks, uint32_t wpb, uint32_t blocks, hipStream_t st) {
+static bool top_kq(const TopArgs& a, bool first, uint32_t chunks, uint32_t wpb, uint32_t cpw, uint32_t blocks,
+                   hipStream_t st) {
   const size_t lds = (size_t)wpb * 16 * kLanes * 8;
-  dim3 g(blocks, chunks), b(64 * wpb);
+  dim3 b(64 * wpb);
+  if (cpw == 2) {
+    if constexpr (KQ > 6) {
+      if (first || chunks % 2) return false;
+      hipLaunchKernelGGL((k_top<KQ, false, 2>), dim3(blocks, chunks / 2), b, lds, st, a.e_src, a.hi, a.lo, a.q,
+                         a.z, a.p_prev, a.p_stride, a.chunk_base, a.m, a.edges_per_wave, a.partial, a.count,
+                         a.ticket);
+      return true;
+    }
+    return false;
+  }
+  dim3 g(blocks, chunks);
   if (first)
     hipLaunchKernelGGL((k_top<KQ, true>), g, b, lds, st, a.e_src, a.hi, a.lo, a.q, a.z, a.p_prev,
                        a.p_stride, a.chunk_base, a.m, a.edges_per_wave, a.partial, a.count, a.ticket);
   else
     hipLaunchKernelGGL((k_top<KQ, false>), g, b, lds, st, a.e_src, a.hi, a.lo, a.q, a.z, a.p_prev,
                        a.p_stride, a.chunk_base, a.m, a.edges_per_wave, a.partial, a.count, a.ticket);
+  return true;
 }
 
 uint32_t top_blocks(const TopArgs& a, bool first, uint32_t kq, uint32_t chunks, const Tuning& tu) {
+  const uint32_t wpb = tu.top_waves_per_block, cpw = tu.chunks_per_wave;
   switch (kq) {
-    case 4: return top_blocks_kq<4>(a, first, chunks, tu.top_waves_per_block);
-    case 8: return top_blocks_kq<8>(a, first, chunks, tu.top_waves_per_block);
-    case 12: return top_blocks_kq<12>(a, first, chunks, tu.top_waves_per_block);
-    default: return top_blocks_kq<16>(a, first, chunks, tu.top_waves_per_block);
+    case 4: return top_blocks_kq<4>(a, first, chunks, wpb, cpw);
+    case 8: return top_blocks_kq<8>(a, first, chunks, wpb, cpw);
+    case 12: return top_blocks_kq<12>(a, first, chunks, wpb, cpw);
+    default: return top_blocks_kq<16>(a, first, chunks, wpb, cpw);
   }
 }
 
 hipError_t launch_top(const TopArgs& a, bool first_level, uint32_t kq, uint32_t chunks,
                       const Tuning& tu, hipStream_t st) {
   if (!a.m) return hipSuccess;
-  const uint32_t wpb = tu.top_waves_per_block;
+  const uint32_t wpb = tu.top_waves_per_block, cpw = tu.chunks_per_wave;
   const uint32_t blocks = top_blocks(a, first_level, kq, chunks, tu);
+  bool ok = false;
   switch (kq) {
-    case 4: top_kq<4>(a, first_level, chunks, wpb, blocks, st); break;
-    case 8: top_kq<8>(a, first_level, chunks, wpb, blocks, st); break;
-    case 12: top_kq<12>(a, first_level, chunks, wpb, blocks, st); break;
-    case 16: top_kq<16>(a, first_level, chunks, wpb, blocks, st); break;
-    default: return hipErrorInvalidValue;
+    case 4: ok = top_kq<4>(a, first_level, chunks, wpb, cpw, blocks, st); break;
+    case 8: ok = top_kq<8>(a, first_level, chunks, wpb, cpw, blocks, st); break;
+    case 12: ok = top_kq<12>(a, first_level, chunks, wpb, cpw, blocks, st); break;
+    case 16: ok = top_kq<16>(a, first_level, chunks, wpb, cpw, blocks, st); break;
   }
+  if (!ok) return hipErrorInvalidValue;
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_top_fold, dim3(chunks), dim3(1024), 0, st, a.partial, blocks, a.chunk_base, a.it_begin,
