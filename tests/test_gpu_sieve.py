@@ -153,6 +153,40 @@ def test_iteration_ranges():
     assert acc == F
 
 
+def test_chunks_per_wave():
+    """The last level with one and two chunks per wave. The two-chunk form
+    applies only when every chunk group holds an even number of chunks from
+    an even chunk; the other cases fall back to one chunk per wave. Both
+    forms, over distinct windows (several chunk groups) and over edges (one
+    group), path and motif, against the oracle's per-iteration values."""
+    g = inputs.add_colours(_medium(seed=13, n=300, m=6000, t_max=40), 4, seed=13)
+    gd = R.Graph.from_inputs(g)
+    k, delta, seed = 9, 5, 777  # 512 iterations, 8 chunks
+    motif = np.array([3, 2, 2, 2], np.uint8)
+    cases = [  # chunks per wave, chunks per launch, iteration range
+        (2, 8, 0, 0),      # one group of 8: pairs
+        (2, 2, 0, 0),      # four groups of 2: pairs over distinct windows
+        (2, 4, 128, 384),  # chunks 2..5: pairs
+        (2, 3, 0, 0),      # odd groups: one chunk per wave
+        (2, 4, 64, 512),   # odd first chunk: one chunk per wave
+        (2, 4, 128, 320),  # three chunks: one chunk per wave
+        (1, 4, 0, 0),
+    ]
+    say("chunks per wave: oracle over all iterations")
+    ref = {None: oracle_per(g, inputs.Query(k=k, delta=delta, seed=seed), 0, 1 << k, threads=host_threads()),
+           "motif": oracle_per(g, inputs.Query(k=k, delta=delta, seed=seed + 1, motif=motif), 0, 1 << k,
+                               threads=host_threads())}
+    for cpw, cpl, a, b in cases:
+        say("chunks per wave", cpw, "per launch", cpl, "range", a, b)
+        tu = R.Tuning(chunks_per_wave=cpw, chunks_per_launch=cpl)
+        lo, hi = (a, b) if b else (0, 1 << k)
+        for key, s_, mot in ((None, seed, None), ("motif", seed + 1, motif)):
+            r = R.run(gd, k, delta, s_, motif=mot, tuning=tu, per_iteration=True, it_begin=a, it_end=b)
+            want = ref[key][lo:hi]
+            assert [int(x) for x in r.per_iteration] == [int(x) for x in want], (cpw, cpl, a, b, key)
+            assert r.fingerprint == int(np.bitwise_xor.reduce(want)), (cpw, cpl, a, b, key)
+
+
 def test_k_extremes():
     g = inputs.tiny_graph(7, n_max=8, m_max=30)
     gd = R.Graph.from_inputs(g)
