@@ -164,9 +164,10 @@ typedef struct {
                                   row sums once for both chunks). It applies to
                                   queries with k >= 7 whose iteration range
                                   covers an even number of chunks from an even
-                                  chunk, with an even chunks_per_launch; the
-                                  fine-grained last level and any other query
-                                  run with 1. 0 = automatic (2 where it
+                                  chunk and whose launches take an even number
+                                  of chunks (min(chunks_per_launch, chunks));
+                                  the fine-grained last level and any other
+                                  query run with 1. 0 = automatic (2 where it
                                   applies). Results are identical. */
 } rs_tuning;
 
