@@ -108,6 +108,20 @@ def test_constrained_plain_runs():
         r = R.run(gd, k, dv, seed, motif=motif, sources=sources, targets=targets, per_iteration=True)
         assert r.fingerprint == Fo, case
         assert np.array_equal(r.per_iteration, per), case
+    # k >= 7 over whole chunk pairs: the last level runs two chunks per wave
+    # over the target-restricted list
+    dv = rr.integers(0, 8, g.n).astype(np.uint32)
+    for case, (k, d, sources, targets, motif) in enumerate((
+            (8, dv, [3, 17, 40], list(range(0, g.n, 7)), None),
+            (9, 5, None, list(range(1, g.n, 3)), np.array([3, 3, 3], np.uint8)),
+            (9, dv, list(range(0, g.n, 11)), None, None))):
+        seed = 200 + case
+        say("constrained, two chunks per wave", case, k)
+        Fo, per = oracle.sieve(g.n, g.src, g.dst, g.t, k, d, seed, sources=sources, targets=targets,
+                               per_iteration=True, threads=host_threads(), **okw(g, motif))
+        r = R.run(gd, k, d, seed, motif=motif, sources=sources, targets=targets, per_iteration=True)
+        assert r.fingerprint == Fo, ("pairs", case)
+        assert np.array_equal(r.per_iteration, per), ("pairs", case)
 
 
 def test_reach_at_most_k():
