@@ -15,6 +15,9 @@ Prints one JSON line. Extra modes (not the driver's default):
   --mode serve   the continuous-batching server on four resident graphs vs
                  first-come first-served plain calls over the same arrivals
   --mode copy    a plain 1 GiB device copy, the reference for HBM byte counters
+  --mode rows    random 512-byte row reads, writes and both (rs_probe_rows) over
+                 an 8 GiB array: the practical ceiling of the prefix state's
+                 access pattern
   --mode literal the literal reading of Eq. (poly-enc:1) (rs_run_literal) on
                  the 10^6-edge path query, against the VALU issue peak
 """
@@ -146,7 +149,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--mode", default="plain", choices=["plain", "batch", "serve", "copy", "literal"])
+    ap.add_argument("--mode", default="plain", choices=["plain", "batch", "serve", "copy", "rows", "literal"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch-only", action="store_true",
                     help="--mode batch: the batched calls alone in the default shape (for kernel traces)")
@@ -185,6 +188,34 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"mode": "copy", "bytes_read_per_copy": n, "bytes_written_per_copy": n,
                           "copies": args.steps}), flush=True)
+        return
+    if args.mode == "rows":
+        # the prefix state's access pattern on its own: whole 512-byte rows at
+        # random rows of an array far larger than the caches
+        n_rows = 1 << 24
+        rows = torch.zeros((n_rows, 64), dtype=torch.int64, device="cuda")
+        steps, per_step = 128, {0: 16, 1: 16, 2: 24}
+        res = {}
+        for mode, name in ((0, "read"), (1, "write"), (2, "read2_write1")):
+            best = None
+            for waves in (4096, 8192):
+                out = torch.empty((waves, 64), dtype=torch.int64, device="cuda")
+                R.probe_rows(rows, out, waves, 4, mode)  # warm-up
+                times = []
+                for _ in range(max(args.steps // 4, 3)):
+                    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    a.record()
+                    R.probe_rows(rows, out, waves, steps, mode)
+                    b.record()
+                    b.synchronize()
+                    times.append(a.elapsed_time(b))
+                ms = sorted(times)[len(times) // 2]
+                gbps = waves * steps * per_step[mode] * 512 / (ms * 1e-3) / 1e9
+                if best is None or gbps > best["GBps"]:
+                    best = {"GBps": gbps, "waves": waves, "ms": ms}
+            res[name] = best
+        print(json.dumps({"mode": "rows", "row_bytes": 512, "array_bytes": n_rows * 512, "rows_per_step": per_step,
+                          "steps": steps, "results": res}), flush=True)
         return
     if args.mode != "plain":
         from paper_2010_08423_amd import bench_modes

@@ -381,6 +381,21 @@ rs_status rs_profile_reset(void);
 rs_status rs_profile_get(const char* kernel_class, uint64_t* launches, double* total_ms,
                          double* algorithmic_bytes);
 
+/* Measurement aid, not part of the sieve: the bandwidth of the prefix
+ * state's access pattern (whole 512-byte rows at random rows of a large
+ * array), the practical ceiling for the level kernels' HBM traffic.
+ * rows: device array of n_rows rows of 64 uint64 (n_rows a power of two);
+ * out: device array of waves rows of 64 uint64 (each wave's XOR of what it
+ * read). waves (a multiple of 4) wavefronts each take `steps` steps; a step
+ * moves 16 rows read (mode 0), 16 rows written (mode 1, rows is
+ * overwritten) or 16 rows read and 8 written (mode 2), at row indices hashed
+ * from (wave, step). Bytes moved: waves x steps x rows per step x 512.
+ * Enqueued on hip_stream; the caller times it. RS_EINVAL for null pointers,
+ * waves not a positive multiple of 4, n_rows not a power of two, or mode > 2;
+ * RS_EDEVICE if the launch fails. */
+rs_status rs_probe_rows(uint64_t* rows, uint64_t n_rows, uint64_t* out, uint32_t waves, uint32_t steps,
+                        uint32_t mode, void* hip_stream);
+
 /* ------------------------------------------------------------------------
  * Server: continuous batching over resident graphs.
  * Worker threads, each with its own HIP stream, take queued queries in

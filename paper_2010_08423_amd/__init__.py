@@ -129,6 +129,8 @@ _SIGNATURES = {
     "rs_lookback_get": (ctypes.c_int32, [_u64p, _u64p]),
     "rs_profile_get": (ctypes.c_int32, [ctypes.c_char_p, _u64p, ctypes.POINTER(ctypes.c_double),
                                         ctypes.POINTER(ctypes.c_double)]),
+    "rs_probe_rows": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_uint32,
+                                       ctypes.c_uint32, ctypes.c_uint32, ctypes.c_void_p]),
     "rs_server_create": (ctypes.c_int32, [ctypes.c_uint64, ctypes.POINTER(_ServerOpts),
                                           ctypes.POINTER(ctypes.c_void_p)]),
     "rs_server_add_graph": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, _u32p]),
@@ -546,6 +548,19 @@ def lookback_get():
     a, b = ctypes.c_uint64(), ctypes.c_uint64()
     _check(_load().rs_lookback_get(ctypes.byref(a), ctypes.byref(b)), "rs_lookback_get")
     return a.value, b.value
+
+
+def probe_rows(rows, out, waves, steps, mode, stream=None):
+    """rs_probe_rows: random 512-byte row reads (mode 0), writes (1) or both
+    (2) on device tensors rows [n_rows, 64] (n_rows a power of two) and out
+    [waves, 64] of 64-bit integers, enqueued on the stream; the caller times
+    it. Bytes moved: waves * steps * (16, 16 or 24) * 512."""
+    if rows.dim() != 2 or rows.shape[1] != 64 or rows.element_size() != 8 or not rows.is_contiguous():
+        raise ValueError("rows must be a contiguous [n_rows, 64] tensor of 64-bit elements")
+    if out.numel() < waves * 64 or out.element_size() != 8 or not out.is_contiguous():
+        raise ValueError("out must hold waves x 64 contiguous 64-bit elements")
+    _check(_load().rs_probe_rows(rows.data_ptr(), int(rows.shape[0]), out.data_ptr(), int(waves), int(steps),
+                                 int(mode), _stream_handle(stream)), "rs_probe_rows")
 
 
 def profile_get(kernel_class: str):

@@ -15,7 +15,7 @@ BUILD = os.path.join(HERE, "_build")
 SOURCES = ["rs_kernels.hip", "rs_graph.hip", "rs_engine.hip", "rs_batch.hip", "rs_server.hip", "rs_compact.hip",
            "rs_fine.hip", "rs_extract.hip",
            "rs_literal.hip", "rs_rrows.hip",
-           "rs_group.hip"]
+           "rs_group.hip", "rs_probe.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
