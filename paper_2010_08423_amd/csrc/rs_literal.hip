@@ -32,9 +32,40 @@
 
 namespace rs {
 
-// y * x with y wave-uniform: the multiples y*c, c = 0..15, go to column 0 of
-// this wave's table region (entry c at byte offset c * 512; lane c writes
-// entry c), then every lane combs its own x against that column.
+// As gf_comb_acc, against a table of 16 consecutive 8-byte entries that the
+// whole wave shares (base 128-byte aligned, entry v at base + 8 v): lanes that
+// look up different entries fall in different LDS banks.
+__device__ __forceinline__ void gf_comb_acc8(uint32_t base, uint64_t a, Acc128& r) {
+  const uint32_t a0 = lo32(a), a1 = hi32(a);
+  uint32_t d0 = 0, d1 = 0, d2 = 0, d3 = 0;
+#pragma unroll
+  for (int j = 7; j >= 0; --j) {
+    const uint32_t s0 = (4 * j >= 3) ? (a0 >> (4 * j - 3)) : (a0 << (3 - 4 * j));
+    const uint32_t s1 = (4 * j >= 3) ? (a1 >> (4 * j - 3)) : (a1 << (3 - 4 * j));
+    // base has bits 3..6 clear, so OR equals XOR
+    const uint64_t x = lds_load(and_xor(s0, 0x78u, base));
+    const uint64_t y = lds_load(and_xor(s1, 0x78u, base));
+    d0 ^= lo32(x);
+    d1 = xor3(d1, hi32(x), lo32(y));
+    d2 ^= hi32(y);
+    if (j) {
+      d3 = funnel(d3, d2, 28);
+      d2 = funnel(d2, d1, 28);
+      d1 = funnel(d1, d0, 28);
+      d0 <<= 4;
+    }
+  }
+  r.d0 ^= d0;
+  r.d1 ^= d1;
+  r.d2 ^= d2;
+  r.d3 ^= d3;
+}
+
+// y * x with y wave-uniform: the multiples y*c, c = 0..15, go to this wave's
+// 128-byte region (entry c at byte offset 8 c; lane c writes entry c), then
+// every lane combs its own x against it. (With the entries 512 bytes apart,
+// all sixteen fell in the same two LDS banks and the lanes' lookups of
+// different entries conflicted.)
 __device__ __forceinline__ uint64_t gf_mul_uniform(uint64_t* region, uint32_t lane, uint64_t y, uint64_t x) {
   uint32_t l1 = lo32(y), h1 = hi32(y);
   uint32_t l2 = l1, h2 = h1;
@@ -51,10 +82,10 @@ __device__ __forceinline__ uint64_t gf_mul_uniform(uint64_t* region, uint32_t la
   hi ^= (c & 4u) ? h4 : 0u;
   lo ^= (c & 8u) ? l8 : 0u;
   hi ^= (c & 8u) ? h8 : 0u;
-  if (lane < 16) region[c * kLanes] = mk64(lo, hi);
+  if (lane < 16) region[c] = mk64(lo, hi);
   __builtin_amdgcn_wave_barrier();
   Acc128 r = {0, 0, 0, 0};
-  gf_comb_acc(lds_addr(region), x, r);
+  gf_comb_acc8(lds_addr(region), x, r);
   __builtin_amdgcn_wave_barrier();
   return gf_reduce(r);
 }
@@ -168,11 +199,18 @@ __device__ __forceinline__ uint64_t wave_xor64(uint64_t v) {
 // Level a.level of every slot touched by this wave's tile of edges.
 template <int KQ, bool FIRST, bool LAST>
 __global__ __launch_bounds__(256) void k_lit_level(LitArgs a) {
-  __shared__ uint64_t lds[4][16][kLanes];
+  // The kernel's only static LDS object, so it starts at address 0: the
+  // per-lane tables (slot products) need bits 9..12 of their base clear, the
+  // wave-uniform tables (window terms) bits 3..6.
+  struct Tables {
+    uint64_t lane[4][16][kLanes];
+    uint64_t uniform[4][16];
+  };
+  __shared__ Tables sh;
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  uint64_t* region = &lds[wv][0][0];
-  uint64_t* tab = &lds[wv][0][lane];
+  uint64_t* region = &sh.uniform[wv][0];
+  uint64_t* tab = &sh.lane[wv][0][lane];
   const uint32_t chunk = blockIdx.y;
   const uint64_t cb = a.chunk_base + (uint64_t)chunk * kLanes;
   const uint64_t e0 = ((uint64_t)blockIdx.x * (blockDim.x >> 6) + wv) * a.tile;
