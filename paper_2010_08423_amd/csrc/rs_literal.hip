@@ -199,18 +199,18 @@ __device__ __forceinline__ uint64_t wave_xor64(uint64_t v) {
 // Level a.level of every slot touched by this wave's tile of edges.
 template <int KQ, bool FIRST, bool LAST>
 __global__ __launch_bounds__(256) void k_lit_level(LitArgs a) {
-  // The kernel's only static LDS object, so it starts at address 0: the
-  // per-lane tables (slot products) need bits 9..12 of their base clear, the
-  // wave-uniform tables (window terms) bits 3..6.
-  struct Tables {
-    uint64_t lane[4][16][kLanes];
-    uint64_t uniform[4][16];
-  };
-  __shared__ Tables sh;
+  // Per-lane tables of the slot products, [wave][entry][lane]; the kernel's
+  // only static LDS object, so it starts at address 0 (the comb needs bits
+  // 9..12 of a table's base clear). A wave's uniform table of the window
+  // terms (16 entries, bits 3..6 of its base clear) lives in entry row 1 of
+  // its region: a slot product rewrites rows 1..15 before it reads them, and
+  // the uniform table is rewritten for every window term, so they never
+  // overlap in time, and the block stays at 32 KB (five blocks per CU).
+  __shared__ uint64_t lds[4][16][kLanes];
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  uint64_t* region = &sh.uniform[wv][0];
-  uint64_t* tab = &sh.lane[wv][0][lane];
+  uint64_t* region = &lds[wv][1][0];
+  uint64_t* tab = &lds[wv][0][lane];
   const uint32_t chunk = blockIdx.y;
   const uint64_t cb = a.chunk_base + (uint64_t)chunk * kLanes;
   const uint64_t e0 = ((uint64_t)blockIdx.x * (blockDim.x >> 6) + wv) * a.tile;
